@@ -1,0 +1,176 @@
+"""Seeded synthetic inputs: manufactured solutions, forcing and viscosity fields.
+
+Problem data only -- analytic fields evaluated at given coordinates and seeded
+random draws.  It contains none of the solver's arithmetic; both the library's
+tests/benchmark and the CPU oracle take their inputs from here.
+
+Seeds: base 13513; workload k uses 13513 + 1000 k.  Host RNG is
+numpy.random.Generator(PCG64(seed)).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_BASE = 13513
+PI = np.pi
+
+
+@dataclass
+class Fields:
+    """u(x,y,z) -> (3, n), p(x,y,z) -> (n,), f(x,y,z) -> (3, n)."""
+    u: object
+    p: object
+    f: object
+    name: str = ""
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _z(x):
+    return np.zeros_like(np.asarray(x, dtype=float))
+
+
+def paper_cube():
+    """Analytic solution of the paper's cube benchmark (Sec. 5.1.1):
+    u = (-4 cos 4z, 8 cos 8x, -2 cos 2y), p = sin 4x sin 8y sin 2z, f = -lap u + grad p."""
+    def u(x, y, z):
+        return np.stack([-4 * np.cos(4 * z), 8 * np.cos(8 * x), -2 * np.cos(2 * y)])
+
+    def p(x, y, z):
+        return np.sin(4 * x) * np.sin(8 * y) * np.sin(2 * z)
+
+    def f(x, y, z):
+        return np.stack([
+            -64 * np.cos(4 * z) + 4 * np.cos(4 * x) * np.sin(8 * y) * np.sin(2 * z),
+            512 * np.cos(8 * x) + 8 * np.sin(4 * x) * np.cos(8 * y) * np.sin(2 * z),
+            -8 * np.cos(2 * y) + 2 * np.sin(4 * x) * np.sin(8 * y) * np.cos(2 * z)])
+    return Fields(u, p, f, "paper_cube")
+
+
+def sine_cube():
+    """Smooth divergence-free field with zero net boundary flux:
+    u = (s, s, sin(pi(x+y)) cos(pi z)), s = sin(pi x) sin(pi y) sin(pi z),
+    p = cos(pi x) cos(pi y) cos(pi z) (zero mean); f = 3 pi^2 u + grad p."""
+    def u(x, y, z):
+        s = np.sin(PI * x) * np.sin(PI * y) * np.sin(PI * z)
+        return np.stack([s, s, np.sin(PI * (x + y)) * np.cos(PI * z)])
+
+    def p(x, y, z):
+        return np.cos(PI * x) * np.cos(PI * y) * np.cos(PI * z)
+
+    def f(x, y, z):
+        uu = u(x, y, z)
+        gp = np.stack([-PI * np.sin(PI * x) * np.cos(PI * y) * np.cos(PI * z),
+                       -PI * np.cos(PI * x) * np.sin(PI * y) * np.cos(PI * z),
+                       -PI * np.cos(PI * x) * np.cos(PI * y) * np.sin(PI * z)])
+        return 3 * PI ** 2 * uu + gp
+    return Fields(u, p, f, "sine_cube")
+
+
+def quadratic_exact():
+    """u = (y^2, z^2, x^2), p = x + y + z - 3/2, f = (-1, -1, -1): inside the
+    Taylor-Hood space, so the discrete solution reproduces it."""
+    def u(x, y, z):
+        return np.stack([y * y, z * z, x * x])
+
+    def p(x, y, z):
+        return x + y + z - 1.5
+
+    def f(x, y, z):
+        return np.stack([-np.ones_like(x)] * 3)
+    return Fields(u, p, f, "quadratic_exact")
+
+
+def linear_exact():
+    """u = (y, z, x), p = 0, f = 0: reproduced by the P1-P1 discretisation."""
+    def u(x, y, z):
+        return np.stack([y, z, x])
+
+    def p(x, y, z):
+        return _z(x)
+
+    def f(x, y, z):
+        return np.stack([_z(x)] * 3)
+    return Fields(u, p, f, "linear_exact")
+
+
+def fourier_forcing(seed, modes=8, kmax=4):
+    """f = sum_m a_m sin(2 pi k_m . x + phi_m); k_m uniform in {-kmax..kmax}^3 \\ 0,
+    a_m ~ N(0,1)^3 / |k_m|^2, phi_m ~ U[0, 2 pi); u = 0 on the boundary, p unknown."""
+    g = rng(seed)
+    ks, amps, phis = [], [], []
+    while len(ks) < modes:
+        k = g.integers(-kmax, kmax + 1, size=3)
+        if np.any(k != 0):
+            ks.append(k)
+    for k in ks:
+        amps.append(g.standard_normal(3) / float(k @ k))
+        phis.append(g.uniform(0.0, 2 * PI))
+
+    def f(x, y, z):
+        out = np.zeros((3,) + np.shape(x))
+        for k, a, ph in zip(ks, amps, phis):
+            s = np.sin(2 * PI * (k[0] * x + k[1] * y + k[2] * z) + ph)
+            out += a.reshape((3,) + (1,) * np.ndim(s)) * s
+        return out
+
+    def u(x, y, z):
+        return np.stack([_z(x)] * 3)
+
+    def p(x, y, z):
+        return _z(x)
+    return Fields(u, p, f, f"fourier_{seed}")
+
+
+def gaussian_bump_viscosity(seed, bumps=8, width=0.15, ratio=100.0, N_ref=None):
+    """nu = exp(ln(ratio) (G - min G)/(max G - min G)), G = sum_b a_b exp(-|x-c_b|^2/(2 w^2)),
+    a_b ~ N(0,1), c_b ~ U[0,1]^3; min/max over the nodes of the lattice N_ref."""
+    g = rng(seed)
+    a = g.standard_normal(bumps)
+    c = g.uniform(0.0, 1.0, size=(bumps, 3))
+
+    def G(x, y, z):
+        out = np.zeros(np.shape(x))
+        for ab, cb in zip(a, c):
+            out += ab * np.exp(-((x - cb[0]) ** 2 + (y - cb[1]) ** 2 + (z - cb[2]) ** 2) / (2 * width ** 2))
+        return out
+
+    n = 32 if N_ref is None else N_ref
+    t = np.linspace(0.0, 1.0, n + 1)
+    X, Y, Z = np.meshgrid(t, t, t, indexing="ij")
+    GG = G(X, Y, Z)
+    gmin, gmax = float(GG.min()), float(GG.max())
+
+    def nu(x, y, z):
+        return np.exp(np.log(ratio) * (G(x, y, z) - gmin) / (gmax - gmin))
+    return nu
+
+
+def lognormal_viscosity(seed, modes=8, kmax=2, ratio=100.0):
+    """nu = exp(sigma G), G a unit-variance sum of `modes` Fourier modes,
+    sigma = ln(ratio) / 4."""
+    g = rng(seed)
+    ks, phis = [], []
+    while len(ks) < modes:
+        k = g.integers(-kmax, kmax + 1, size=3)
+        if np.any(k != 0):
+            ks.append(k)
+    amp = g.standard_normal(modes)
+    for _ in ks:
+        phis.append(g.uniform(0.0, 2 * PI))
+    scale = np.sqrt(2.0 / np.sum(amp ** 2))
+    sigma = np.log(ratio) / 4.0
+
+    def nu(x, y, z):
+        G = np.zeros(np.shape(x))
+        for k, a, ph in zip(ks, amp, phis):
+            G += a * np.sin(2 * PI * (k[0] * x + k[1] * y + k[2] * z) + ph)
+        return np.exp(sigma * scale * G)
+    return nu
+
+
+def normal_vector(seed, n):
+    """Seeded N(0,1) float64 vector."""
+    return rng(seed).standard_normal(n)

@@ -1,0 +1,279 @@
+"""Pins of the oracle's smoother, transfers, coarse solve, V-cycle and FMG."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import coarse, fe, mesh, multigrid as mg, smoother, transfer
+from oracle.stokes import Stokes
+from paper_2010_13513_amd import workloads as W
+
+
+# ------------------------------------------------------------------ colouring
+@pytest.mark.parametrize("vorder,N", [(1, 4), (2, 3)])
+def test_colouring_has_no_same_colour_coupling(vorder, N):
+    """Brute force over the assembled stiffness: no two distinct DoFs of one
+    colour are coupled (so a colour can be relaxed at once)."""
+    lev = fe.Level(N, vorder)
+    col = smoother.colours(lev)
+    A = lev.A.tocoo()
+    off = (A.row != A.col) & (np.abs(A.data) > 0)
+    assert not np.any(col[A.row[off]] == col[A.col[off]])
+    assert col.min() == 0 and col.max() == smoother.n_colours(vorder) - 1
+
+
+def _sequential_colour_sweep(U, us, f_us, p, order):
+    """Textbook Gauss-Seidel: one DoF at a time in the given order."""
+    lev = U.S.lev
+    A = lev.A.tocsr()
+    for i in order:
+        for d in range(3):
+            r = f_us[d][i] - A[i] @ us[d] - U.S.BT[d][i] @ p
+            us[d][i] += r[0] / lev.Adiag[i]
+
+
+@pytest.mark.parametrize("vorder,N", [(1, 3), (2, 2)])
+def test_multicolour_sweep_equals_pointwise_gauss_seidel(vorder, N):
+    """A colour-block sweep equals point Gauss-Seidel over the DoFs sorted by
+    colour, for any order inside each colour (order-independence)."""
+    S = Stokes(fe.Level(N, vorder))
+    U = smoother.Uzawa(S)
+    rng = np.random.default_rng(5)
+    us = [rng.standard_normal(S.nv) for _ in range(3)]
+    f_us = [rng.standard_normal(S.nv) for _ in range(3)]
+    p = rng.standard_normal(S.np_)
+    col = smoother.colours(S.lev)
+    ref = [u.copy() for u in us]
+    U.sweep(ref, f_us, p, forward=True)
+    for trial in range(2):
+        got = [u.copy() for u in us]
+        order = []
+        for c in range(U.ncol):
+            idx = np.nonzero((col == c) & S.lev.vint)[0]
+            order += list(rng.permutation(idx))
+        _sequential_colour_sweep(U, got, f_us, p, order)
+        for a, b in zip(ref, got):
+            assert np.abs(a - b).max() < 1e-13
+
+
+def test_forward_sweep_is_lower_triangular_solve():
+    """One forward sweep is u + (D + L)^{-1} (f - B^T p - A u) in colour order
+    (scipy's triangular solve as the reference)."""
+    S = Stokes(fe.Level(3, 2))
+    U = smoother.Uzawa(S)
+    lev = S.lev
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal(S.nv)
+    u[lev.vbnd] = rng.standard_normal(lev.vbnd.sum())
+    f = rng.standard_normal(S.nv)
+    col = smoother.colours(lev)
+    inner = np.nonzero(lev.vint)[0]
+    perm = inner[np.argsort(col[inner], kind="stable")]
+    A = lev.A.tocsr()
+    App = A[perm][:, perm]
+    DL = sp.tril(App, format="csr")
+    res = (f - A @ u)[perm]
+    want = u.copy()
+    want[perm] += spla.spsolve_triangular(DL, res, lower=True)
+    got = [u.copy(), np.zeros(S.nv), np.zeros(S.nv)]
+    U.sweep(got, [f, np.zeros(S.nv), np.zeros(S.nv)], np.zeros(S.np_), True)
+    assert np.abs(got[0] - want).max() < 1e-12
+
+
+@pytest.mark.parametrize("schur", ["ml", "sd"])
+def test_omega_power_iteration_matches_dense_eigenvalue(schur):
+    """eq. omega-eigenvalue-problem: the power-iteration estimate equals the
+    largest |eigenvalue| of the dense D^{-1}(C + B A_s^{-1} B^T) (numpy eig)."""
+    S = Stokes(fe.Level(2, 1))
+    U = smoother.Uzawa(S, schur)
+    n = S.np_
+    Mx = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        bt = [np.where(S.lev.vint, b, 0.0) for b in S.apply_BT(e)]
+        z = U.symmetric_sweep_solve(bt)
+        Mx[:, j] = (S.apply_C(e) + S.apply_B(z)) / U.D
+    lam = np.max(np.abs(np.linalg.eigvals(Mx)))
+    est = U.estimate_omega_inv(W.normal_vector(3, n), iters=300)
+    assert abs(est - lam) < 1e-6 * lam
+
+
+@pytest.mark.parametrize("vorder,Lmin,L,prob", [(1, 0, 2, W.sine_cube()), (2, 1, 2, W.paper_cube())])
+def test_uzawa_fixed_point_and_convergence(vorder, Lmin, L, prob):
+    """The discrete solution (sparse direct) is a fixed point of the Uzawa
+    iteration, and the iteration alone converges to it."""
+    H = mg.Hierarchy(vorder, Lmin, L, schur="sd")
+    xs = H.exact_discrete(L, prob)
+    b = H.rhs(L, prob)
+    U = H.U[L]
+    x1 = U.iterate(xs, b, "f", 2, 0.4)
+    assert np.abs(x1 - xs).max() < 1e-10 * np.abs(xs).max()   # residual rounding / D
+    x = H.initial(L, prob)
+    e0 = np.linalg.norm(H.S[L].mean_zero(x) - xs)
+    for _ in range(300):
+        x = U.iterate(x, b, "f", 2, 0.4)
+    assert np.linalg.norm(H.S[L].mean_zero(x) - xs) < 1e-3 * e0
+
+
+# ------------------------------------------------------------------- transfers
+@pytest.mark.parametrize("order", [1, 2])
+def test_prolongation_reproduces_polynomials(order):
+    Nc = 3
+    P = transfer.prolongation(Nc, order)
+    if order == 1:
+        cc, fc = mesh.p1_coords(Nc) / Nc, mesh.p1_coords(2 * Nc) / (2 * Nc)
+        q = lambda c: 1 + 2 * c[:, 0] - c[:, 1] + 0.5 * c[:, 2]
+    else:
+        cc, fc = mesh.p2_coords(Nc) / (2 * Nc), mesh.p2_coords(2 * Nc) / (4 * Nc)
+        q = lambda c: 1 + c[:, 0] * c[:, 1] - 2 * c[:, 2] ** 2 + 3 * c[:, 0] - c[:, 1] * c[:, 2]
+    assert np.abs(P @ q(cc) - q(fc)).max() < 1e-14
+
+
+def test_point_location_brute_force():
+    """Kuhn point location agrees with a search over all coarse tetrahedra."""
+    Nc = 2
+    tets = mesh.lattice_tets(Nc).astype(float)
+    pts = mesh.p2_coords(2 * Nc) / 4.0
+    V, lam = transfer.locate(Nc, pts)
+    for k in range(0, pts.shape[0], 7):
+        x = pts[k]
+        assert np.all(lam[k] > -1e-14) and abs(lam[k].sum() - 1) < 1e-14
+        assert np.allclose(lam[k] @ V[k], x)
+        found = False
+        for t in tets:
+            J = (t[1:] - t[0]).T
+            l = np.linalg.solve(J, x - t[0])
+            if np.all(l > -1e-12) and l.sum() < 1 + 1e-12:
+                found = True
+                break
+        assert found
+
+
+@pytest.mark.parametrize("vorder", [1, 2])
+def test_galerkin_identities(vorder):
+    """Nested spaces with exact integration: P^T A_f P = A_c, P_p^T B_f P_v =
+    B_c, P^T M_f P = M_c (independent of how P was built)."""
+    Nc = 2
+    lc, lf = fe.Level(Nc, vorder), fe.Level(2 * Nc, vorder)
+    Pv, Pp = transfer.prolongation(Nc, vorder), transfer.prolongation(Nc, 1)
+    assert abs(Pv.T @ lf.A @ Pv - lc.A).max() < 1e-13
+    assert abs(Pv.T @ lf.M @ Pv - lc.M).max() < 1e-15
+    for d in range(3):
+        assert abs(Pp.T @ lf.B[d] @ Pv - lc.B[d]).max() < 1e-14
+
+
+def test_restriction_is_transpose():
+    Sc, Sf = Stokes(fe.Level(2, 2)), Stokes(fe.Level(4, 2))
+    T = transfer.Transfer(Sc, Sf)
+    rng = np.random.default_rng(2)
+    xc = Sc.zero_boundary(rng.standard_normal(Sc.n))
+    rf = Sf.zero_boundary(rng.standard_normal(Sf.n))
+    rc = T.restrict(rf)
+    us, p = Sc.split(xc)
+    xc0 = Sc.join(us, p - p.mean())
+    assert abs(rc @ xc0 - rf @ T.prolong(xc0)) < 1e-12
+
+
+# ----------------------------------------------------------------- coarse
+@pytest.mark.parametrize("vorder,N", [(1, 1), (1, 4), (2, 2)])
+def test_coarse_pseudo_inverse(vorder, N):
+    """Rank n-1 (the (0, 1_p) direction); K^+ solves compatible systems and
+    agrees with scipy's sparse direct solve."""
+    S = Stokes(fe.Level(N, vorder))
+    cs = coarse.CoarseSolver(S)
+    assert cs.rank == cs.K.shape[0] - 1
+    rng = np.random.default_rng(4)
+    b = S.zero_boundary(rng.standard_normal(S.n))
+    us, p = S.split(b)
+    b = S.join(us, p - p.mean())                 # compatible: sum of g is 0
+    x = cs.solve(S.zeros(), b)
+    r = S.residual(x, b)
+    assert np.linalg.norm(r) < 1e-10 * np.linalg.norm(b)
+    idx = coarse.unknown_index(S)[:-1]
+    K = cs.K[:-1, :-1]
+    y = np.zeros(S.n)
+    y[idx] = np.linalg.solve(K, b[idx])
+    y = S.mean_zero(y)
+    assert np.abs(x - y).max() < 1e-10 * np.abs(y).max()
+
+
+def test_coarse_rank_taylor_hood_level0():
+    """Level 0 Taylor-Hood has 3 velocity against 8 pressure unknowns: the
+    coarse system is rank deficient beyond the constant (hence coarsest = 1)."""
+    cs = coarse.CoarseSolver(Stokes(fe.Level(1, 2)))
+    assert cs.K.shape == (11, 11)
+    assert cs.rank == 6
+
+
+# -------------------------------------------------------------- multigrid
+@pytest.mark.parametrize("vorder,Lmin,L,prob", [(1, 0, 3, W.linear_exact()), (2, 1, 3, W.quadratic_exact())])
+def test_exact_reproduction_through_fmg(vorder, Lmin, L, prob):
+    """Fields inside the discrete space are reproduced by FMG + V-cycles."""
+    H = mg.Hierarchy(vorder, Lmin, L, schur="sd")
+    prm = mg.Params(3, 3, 0, 1, "f", 1 if vorder == 1 else 3, 2.3)
+    x = H.fmg(prob, prm, cycles_on_finest=2)
+    xs = H.S[L].interpolate(prob.u, prob.p)
+    assert np.abs(x - xs).max() < 1e-11
+
+
+def test_sparse_direct_reproduces_exact_solutions():
+    H = mg.Hierarchy(2, 1, 2)
+    x = H.exact_discrete(2, W.quadratic_exact())
+    xs = H.S[2].interpolate(W.quadratic_exact().u, W.quadratic_exact().p)
+    assert np.abs(x - xs).max() < 1e-10
+
+
+@pytest.mark.slow
+def test_vcycle_rate_level_independent():
+    """Textbook multigrid: the V(3,3) residual reduction stays bounded as the
+    mesh is refined (P1-P1, levels 3..5)."""
+    prob = W.sine_cube()
+    rates = []
+    for L in (3, 4, 5):
+        H = mg.Hierarchy(1, 0, L, schur="sd")
+        om = H.U[L].estimate_omega_inv(W.normal_vector(1, H.S[L].np_), 50)
+        prm = mg.Params(3, 3, 0, 1, "f", 1, om)
+        b = H.rhs(L, prob)
+        x = H.fmg(prob, prm)
+        r0 = np.hypot(*H.residual_norms(L, x, b))
+        for _ in range(4):
+            x = H.S[L].mean_zero(H.vcycle(L, L, x, b, prm))
+        r = np.hypot(*H.residual_norms(L, x, b))
+        rates.append((r / r0) ** 0.25)
+    assert max(rates) < 0.45
+    assert rates[-1] < rates[0] + 0.15
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("vorder,Ls,order_u,order_p", [(1, (2, 3, 4), 2.0, 1.0), (2, (1, 2, 3), 3.0, 2.0)])
+def test_discretisation_orders(vorder, Ls, order_u, order_p):
+    """Textbook orders on a smooth manufactured solution: P1-P1 PSPG velocity
+    O(h^2), pressure at least O(h); P2-P1 velocity O(h^3), pressure O(h^2)."""
+    prob = W.sine_cube()
+    H = mg.Hierarchy(vorder, Ls[0] - 1 if vorder == 1 else 1, Ls[-1] + 1)
+    errs = []
+    for L in Ls:
+        x = H.exact_discrete(L, prob)
+        errs.append(mg.l2_errors(H.S[L + 1], H.T[L + 1], x, prob))
+    ou = np.log2(errs[-2][0] / errs[-1][0])
+    op = np.log2(errs[-2][1] / errs[-1][1])
+    assert ou > order_u - 0.2
+    assert op > order_p - 0.2
+
+
+@pytest.mark.slow
+def test_fmg_reaches_discretisation_accuracy():
+    """Sec. 5.1.1: FMG with the paper's minimal-work tuples brings gamma_u to
+    about 1 (P2-P1, Tab. fmg-table tuples)."""
+    prob = W.paper_cube()
+    L = 3
+    H = mg.Hierarchy(2, 1, L + 1, schur="sd")
+    om = H.U[L].estimate_omega_inv(W.normal_vector(1, H.S[L].np_), 100)
+    Hf = mg.Hierarchy(2, 1, L, schur="sd")
+    xd = H.exact_discrete(L, prob)
+    eud, epd = mg.l2_errors(H.S[L + 1], H.T[L + 1], xd, prob)
+    for s, gmax in [((1, 3, 2, 1, "f", 3), 1.1), ((1, 2, 1, 1, "f", 3), 1.1), ((0, 2, 1, 1, "f", 3), 2.0)]:
+        x = Hf.fmg(prob, mg.Params(*s, omega_inv=om))
+        eu, ep = mg.l2_errors(H.S[L + 1], H.T[L + 1], x, prob)
+        assert eu / eud < gmax, s
