@@ -1,0 +1,205 @@
+/*
+ * hhg.h -- C ABI of libhhg: matrix-free hierarchical-hybrid-grid multigrid for
+ * the Stokes system on MI355X (gfx950).
+ *
+ * Method: Kohl & Ruede, "Textbook efficiency: massively parallel matrix-free
+ * multigrid for the Stokes system".  Discrete problem: Sec. 2, eq.
+ * stokes-discrete (calA = [[A, B^T], [B, -C]], A = diag(A, A, A)), PSPG
+ * stabilisation eq. pspg (P1-P1) or C = 0 (P2-P1 Taylor-Hood).  Smoother:
+ * Sec. 3.2, eq. uzawa-iteration.  Transfer: Sec. 3.3.  Cycles: Alg. fmg.
+ *
+ * Domain and hierarchy.  The macro mesh is the unit cube split into the six
+ * Kuhn tetrahedra (macro_refine = 0) or the 48 tetrahedra of one Bey step of it
+ * (macro_refine = 1).  Bey refinement keeps Kuhn simplices, so level l is the
+ * Freudenthal lattice with N = 2^(l + macro_refine) intervals per cube edge and
+ * every macro-primitive's refined DoFs are sub-lattices of it.  Velocity is
+ * Dirichlet on the whole boundary; the pressure is fixed by int p = 0.
+ *
+ * Vectors.  All vectors are caller-owned device buffers holding every DoF of a
+ * level, Dirichlet velocity DoFs included (they carry the boundary data; the
+ * lifting of Sec. 2 comes from applying the operator to them).  Layout (in
+ * elements of the chosen precision), with n1 = N + 1 and nn = n1^3:
+ *   P1-P1: [u1 | u2 | u3 | p], each nn words, index i + n1 (j + n1 k).
+ *   P2-P1: [u1 | u2 | u3 | p], each velocity component 8 groups of nn words:
+ *          group 0 = vertex DoFs (doubled-lattice position 2(i,j,k)), groups
+ *          1..7 = edge DoFs of direction (1,0,0), (0,1,0), (0,0,1), (1,1,0),
+ *          (1,0,1), (0,1,1), (1,1,1) at position 2(i,j,k) + dir; entries whose
+ *          position leaves [0, 2N]^3 are padding and stay zero.
+ * hhg_vec_layout() reports the sizes; hhg_vec_from_lattice / _to_lattice
+ * convert to and from the plain lattice order (u1, u2, u3 over the velocity
+ * lattice X + (M+1)(Y + (M+1) Z), M = N or 2N, then p over the P1 lattice).
+ *
+ * Outputs: boundary velocity rows of every operator output are zero; pressure
+ * rows exist at every pressure node.
+ *
+ * Precision: HHG_F64 (double storage and arithmetic) and HHG_F32 (float
+ * storage, float accumulation).  Calls are asynchronous on the context's HIP
+ * stream unless they return host values.
+ *
+ * Errors: every call returns an hhg_status; hhg_last_error() gives a message for
+ * the calling thread.  No C++ exception crosses this interface.
+ */
+#ifndef HHG_H
+#define HHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hhg_status;
+enum {
+  HHG_OK = 0,
+  HHG_ERR_ARG = 1,            /* bad level, pointer, size or enum value          */
+  HHG_ERR_PREC = 2,           /* precision not supported for this call          */
+  HHG_ERR_HIP = 3,            /* a HIP runtime call failed                      */
+  HHG_ERR_OOM = 4,            /* device allocation failed                       */
+  HHG_ERR_NOT_CONVERGED = 5,  /* stopping test not met (stats still filled)     */
+  HHG_ERR_STATE = 6           /* call needs setup that has not been done        */
+};
+
+typedef struct hhg_ctx_s* hhg_ctx;
+typedef struct hhg_hier_s* hhg_hier;
+
+typedef enum { HHG_P1P1 = 0, HHG_P2P1 = 1 } hhg_disc;
+typedef enum { HHG_F64 = 0, HHG_F32 = 1 } hhg_prec;
+/* Operator blocks of eq. stokes-discrete; MASS = consistent velocity mass and
+ * P1 pressure mass (used for right-hand sides and error norms). */
+typedef enum { HHG_OP_FULL = 0, HHG_OP_A = 1, HHG_OP_BT = 2, HHG_OP_B = 3, HHG_OP_C = 4, HHG_OP_MASS = 5 } hhg_op;
+/* Velocity relaxation of eq. uzawa-velocity: A_f (forward Gauss-Seidel) or A_s
+ * (forward then backward). */
+typedef enum { HHG_GS_FWD = 0, HHG_GS_SYM = 1 } hhg_gs;
+/* Diagonal D of S_hat = omega^{-1} D in eq. uzawa-pressure.  SD: diag(C + B
+ * diag(A)^{-1} B^T) over interior velocity DoFs; ML: lumped P1 mass. */
+typedef enum { HHG_SCHUR_SD = 0, HHG_SCHUR_ML = 1 } hhg_schur;
+
+/* FMG(nu_pre, nu_post, nu_inc, kappa, A_hat, xi) of Alg. fmg plus omega^{-1}. */
+typedef struct {
+  int nu_pre, nu_post, nu_inc, kappa;
+  hhg_gs gs;
+  int xi;
+  double omega_inv;       /* S_hat = omega_inv * D                          */
+  int extra_cycles;       /* V-cycles on the finest level after FMG          */
+  double rtol;            /* > 0: instead of extra_cycles, cycle until
+                             ||r||_2 <= rtol ||b||_2 (max_cycles bound)       */
+  int max_cycles;
+} hhg_solver_params;
+
+typedef struct {
+  int cycles;             /* V-cycles on the finest level (FMG's included)  */
+  double res_u, res_p;    /* Euclidean norms of the final residual blocks    */
+  double rel_res;         /* ||r|| / ||b||                                   */
+  double work_units;      /* Sec. 4 model, in W(calA_L)                      */
+} hhg_stats;
+
+/* ---------------------------------------------------------------- context */
+/* Select device `device`; `stream` is a hipStream_t (NULL: the null stream).
+ * The context owns nothing else; destroy it after every hierarchy made on it. */
+hhg_status hhg_ctx_create(int device, void* stream, hhg_ctx* out);
+hhg_status hhg_ctx_set_stream(hhg_ctx ctx, void* stream);
+hhg_status hhg_ctx_destroy(hhg_ctx ctx);
+const char* hhg_last_error(void);
+
+/* ------------------------------------------------------------- hierarchy */
+/* Build levels lmin..lmax (lmin is the coarsest, solved directly) of one
+ * discretisation: lattice sizes, stencil weights (computed on the host from
+ * the element matrices of the six Kuhn tetrahedra, Sec. 2.1: constant per
+ * macro-primitive), the dense pseudo-inverse of the coarsest operator, and
+ * library work vectors (one residual per level plus the V-cycle and FMG
+ * vectors of the coarser levels), all in the given working precision.
+ * Limits: 0 <= lmin < lmax, N(lmax) <= 512 (P1-P1) or 256 (P2-P1), macro_refine
+ * in {0, 1};
+ * Taylor-Hood needs N(lmin) >= 2 (a level-0 Taylor-Hood system on six
+ * tetrahedra has spurious pressure modes).  Ownership: the hierarchy. */
+hhg_status hhg_hier_create(hhg_ctx ctx, hhg_disc disc, int macro_refine, int lmin, int lmax,
+                           hhg_schur schur, hhg_hier* out);
+hhg_status hhg_hier_destroy(hhg_hier h);
+
+/* Sizes of one level: N, words per lattice array (nn = (N+1)^3), words of a
+ * whole vector, words of the plain lattice-order vector. */
+hhg_status hhg_vec_layout(hhg_hier h, int level, int* N, size_t* nn, size_t* vec_words,
+                          size_t* lattice_words);
+
+/* Device-to-device conversion between the plain lattice order (always double)
+ * and the library layout in precision `prec` (double -> float rounds to
+ * nearest even).  Padding entries are written as zero. */
+hhg_status hhg_vec_from_lattice(hhg_hier h, int level, const double* src_lattice, void* dst, hhg_prec prec);
+hhg_status hhg_vec_to_lattice(hhg_hier h, int level, const void* src, double* dst_lattice, hhg_prec prec);
+
+/* ------------------------------------------------------------- operators */
+/* y = op x on `level` (eq. stokes-discrete blocks; FULL = calA).  A and BT
+ * fill the velocity part of y and zero its pressure part, B and C the
+ * reverse.  x and y must not overlap. */
+hhg_status hhg_apply(hhg_hier h, int level, hhg_op op, const void* x, void* y, hhg_prec prec);
+/* r = b - calA x (Alg. fmg defect; boundary velocity rows zero). */
+hhg_status hhg_residual(hhg_hier h, int level, const void* x, const void* b, void* r, hhg_prec prec);
+/* b = (M I(f) on interior velocity rows, 0 on pressure rows): the load vector
+ * of Sec. 2 with f given by its nodal values f_nodal (velocity part used). */
+hhg_status hhg_rhs(hhg_hier h, int level, const void* f_nodal, void* b, hhg_prec prec);
+/* `iters` inexact Uzawa iterations (eq. uzawa-iteration) in place on x:
+ * xi multicolour Gauss-Seidel sweeps (gs) on A u = f - B^T p_k, then
+ * p <- p - omega D^{-1} (g - B u + C p_k) with omega = 1 / omega_inv. */
+hhg_status hhg_smooth(hhg_hier h, int level, void* x, const void* b, int iters, hhg_gs gs, int xi,
+                      double omega_inv, hhg_prec prec);
+/* r_coarse = restriction of r_fine (transpose of hhg_prolong_add's
+ * interpolation, Sec. 3.3); fine boundary velocity rows are ignored, coarse
+ * boundary velocity rows set to zero, the coarse pressure part shifted to
+ * zero sum. */
+hhg_status hhg_restrict(hhg_hier h, int fine_level, const void* r_fine, void* r_coarse, hhg_prec prec);
+/* x_fine += I x_coarse: quadratic interpolation of P2 velocity, linear of
+ * P1 fields (Sec. 3.3). */
+hhg_status hhg_prolong_add(hhg_hier h, int coarse_level, const void* x_coarse, void* x_fine, hhg_prec prec);
+/* x <- x + calA_lmin^+ (b - calA x) on the unknowns of the coarsest level,
+ * then zero pressure mean.  F64 only. */
+hhg_status hhg_coarse_solve(hhg_hier h, void* x, const void* b, hhg_prec prec);
+/* p <- p - (m^T p / m^T 1), m_k = int psi_k (Sec. 2 mean-zero pressure). */
+hhg_status hhg_project_mean_zero(hhg_hier h, int level, void* x, hhg_prec prec);
+/* Copy the boundary velocity values of `src` (level `level`) into the
+ * boundary velocity DoFs of `dst` on level `level` (same level) */
+hhg_status hhg_copy_boundary(hhg_hier h, int level, const void* src, void* dst, hhg_prec prec);
+
+/* Largest eigenvalue of D^{-1}(C + B A_s^{-1} B^T) by `iters` power
+ * iterations (eq. omega-eigenvalue-problem; A_s^{-1}: one forward + one
+ * backward sweep from zero).  v0: caller-drawn start vector on the pressure
+ * nodes (device, double, nn words, P1 lattice order).  Synchronous. */
+hhg_status hhg_estimate_omega(hhg_hier h, int level, const double* v0, int iters, double* omega_inv);
+
+/* Euclidean norms of the velocity and pressure parts of x (synchronous). */
+hhg_status hhg_norms(hhg_hier h, int level, const void* x, double* norm_u, double* norm_p, hhg_prec prec);
+
+/* ------------------------------------------------------ host-only queries */
+/* The row stencil the library applies, at h = 1, computed on the host from
+ * the element matrices (no device needed).  kind: 'A' stiffness, 'M' velocity
+ * mass, 'T' B^T (velocity row -> pressure columns), 'B' (pressure row ->
+ * velocity columns), 'C' P1 stiffness (PSPG C = C-row * delta h_T^2 / h), 'P'
+ * P1 mass.  Row: velocity group `group` (0 for P1 / pressure rows) at index
+ * (i, j, k), summed over the lattice elements inside [0, nbox]^3.  Output
+ * entries: code[4 e .. 4 e + 3] = (column group, di, dj, dk), w[3 e .. 3 e +
+ * 2] = weights (three for 'T' and 'B', else w[3 e] only).  *n = number of
+ * entries; HHG_ERR_ARG if more than max_entries. */
+hhg_status hhg_query_stencil(hhg_disc disc, char kind, int group, int i, int j, int k, int nbox, int max_entries,
+                             int* n, int* code, double* w);
+/* Interpolation weights of Sec. 3.3 at a fine position inside one coarse
+ * lattice cube: t = (tx, ty, tz) / q with q = 2 (linear) or 4 (quadratic)
+ * and order 1 or 2.  Output: code[4 e ..] = (coarse group, di, dj, dk) from the
+ * cube origin, w[e]; at most 10 entries. */
+hhg_status hhg_query_interpolation(int order, int tx, int ty, int tz, int q, int* n, int* code, double* w);
+
+/* ----------------------------------------------------------------- cycles */
+/* One variable V-cycle of Alg. fmg on x (finest level `level`,
+ * l_fine = level).  F64. */
+hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_solver_params* prm);
+/* Alg. fmg on lmin..lmax.  b_levels[l - lmin]: right-hand sides of every level
+ * (hhg_rhs); x: finest-level vector whose boundary velocity DoFs hold the
+ * boundary data (interpolated to coarser levels by injection), overwritten by
+ * the solution.  Then extra_cycles V-cycles (or cycles to rtol).  Stats
+ * optional (NULL).  F64. */
+hhg_status hhg_fmg_solve(hhg_hier h, void* x, const void* const* b_levels, const hhg_solver_params* prm,
+                         hhg_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HHG_H */

@@ -1,0 +1,1045 @@
+// C ABI of libhhg: contexts, hierarchies, operators, cycles (include/hhg.h).
+//
+// Host-side driver of the paper's solver: Alg. fmg (FMG + variable V-cycle),
+// eq. uzawa-iteration (inexact Uzawa relaxation in multicolour order),
+// Sec. 3.3 (transfer), Sec. 2 (discrete Stokes operator).  Every numerical
+// step runs in the kernels of kernels.hip; this file builds tables, owns work
+// memory and sequences launches on the context stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <tuple>
+#include <unordered_map>
+
+#include "kernels.h"
+
+namespace hhg {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+const int kGroupDir[8][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1},
+                             {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
+
+int group_of_parity(int px, int py, int pz) {
+  for (int g = 0; g < 8; ++g)
+    if (kGroupDir[g][0] == px && kGroupDir[g][1] == py && kGroupDir[g][2] == pz) return g;
+  return -1;
+}
+
+// Device memory arena owned by a hierarchy.
+struct Arena {
+  std::vector<void*> ptrs;
+  template <typename T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw Error{HHG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) HHG_CHECK_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  ~Arena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+// Host staging of one stencil set before upload.
+struct HostStencil {
+  std::vector<int> off;
+  std::vector<double> w;  // nw per entry
+  std::vector<int> code;
+};
+
+template <typename T>
+DStencil<T> upload_stencil(Arena& a, const HostStencil& hs) {
+  std::vector<T> wt(hs.w.begin(), hs.w.end());
+  DStencil<T> d;
+  d.off = a.upload(hs.off);
+  d.w = a.upload(wt);
+  d.n = (int)hs.off.size();
+  return d;
+}
+
+int lin(int di, int dj, int dk, int n1) { return di + n1 * (dj + n1 * dk); }
+
+}  // namespace
+
+struct Level {
+  int l = 0;
+  Geom g{};
+  double h = 1.0;
+  int nbnd = 0;
+  int* bnd = nullptr;  // boundary pressure node list
+  Tables<double>* tb64 = nullptr;
+  Tables<float>* tb32 = nullptr;
+  TransferTables<double>* tt64 = nullptr;  // transfer from level l-1 to l
+  TransferTables<float>* tt32 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  size_t vec_words = 0;
+  // work vectors (float64): residual, V-cycle correction / rhs, FMG iterate, boundary data
+  double *r = nullptr, *cx = nullptr, *cb = nullptr, *xs = nullptr, *w = nullptr;
+  float* r32 = nullptr;
+  // host copies of the double tables (coarse assembly)
+  std::vector<HostStencil> hA, hBT, hB, hC;
+  double adiag[8] = {0};
+};
+
+}  // namespace hhg
+
+struct hhg_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+};
+
+struct hhg_hier_s {
+  hhg_ctx ctx = nullptr;
+  int disc = 0, mr = 0, lmin = 0, lmax = 0, schur = 0;
+  int G = 1;
+  hhg::Arena arena;
+  std::vector<hhg::Level> levels;
+  double* Kp = nullptr;
+  int* unk = nullptr;
+  int nunk = 0, rank = 0;
+  double* partial = nullptr;
+  double* sums = nullptr;   // device scratch for reductions (16 doubles)
+  double* hsums = nullptr;  // pinned host copy
+  hhg::Level& L(int l) { return levels[l - lmin]; }
+};
+
+namespace hhg {
+namespace {
+
+hipStream_t S(hhg_hier h) { return h->ctx->stream; }
+
+template <typename T>
+const Tables<T>* tables(Level& lv);
+template <>
+const Tables<double>* tables<double>(Level& lv) {
+  return lv.tb64;
+}
+template <>
+const Tables<float>* tables<float>(Level& lv) {
+  return lv.tb32;
+}
+template <typename T>
+const TransferTables<T>* ttables(Level& lv);
+template <>
+const TransferTables<double>* ttables<double>(Level& lv) {
+  return lv.tt64;
+}
+template <>
+const TransferTables<float>* ttables<float>(Level& lv) {
+  return lv.tt32;
+}
+template <typename T>
+const T* dinv(Level& lv);
+template <>
+const double* dinv<double>(Level& lv) {
+  return lv.dinv64;
+}
+template <>
+const float* dinv<float>(Level& lv) {
+  return lv.dinv32;
+}
+
+// --------------------------------------------------------- table building
+void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
+  const Geom& g = lv.g;
+  const int G = g.G, n1 = g.n1, nn = g.nn;
+  const double hh = lv.h;
+  const double sA = hh, sB = hh * hh, sM = hh * hh * hh;
+  const double sC = (h->disc == HHG_P1P1) ? (1.0 / 12.0) * std::pow(1.0 / 6.0, 2.0 / 3.0) * hh * hh * hh : 0.0;
+  auto prune = [](Row r, int nw) {
+    double mx = 0.0;
+    for (auto& e : r)
+      for (int d = 0; d < nw; ++d) mx = std::max(mx, std::fabs(e.w[d]));
+    Row out;
+    for (auto& e : r) {
+      bool keep = false;
+      for (int d = 0; d < nw; ++d) keep |= std::fabs(e.w[d]) > 1e-13 * mx;
+      if (keep) out.push_back(e);
+    }
+    return out;
+  };
+  Tables<double> t64{};
+  Tables<float> t32{};
+  Arena& a = h->arena;
+  lv.hA.assign(G, {});
+  lv.hBT.assign(G, {});
+  lv.hB.assign(27, {});
+  lv.hC.assign(27, {});
+  for (int gr = 0; gr < G; ++gr) {
+    const int c = 3;
+    HostStencil A, BT, Mv;
+    for (auto& e : prune(row_stencil(es, 'A', gr, c, c, c, 7), 1)) {
+      A.off.push_back((e.g - gr) * nn + lin(e.di, e.dj, e.dk, n1));
+      A.w.push_back(e.w[0] * sA);
+      if (e.g == gr && e.di == 0 && e.dj == 0 && e.dk == 0) lv.adiag[gr] = e.w[0] * sA;
+    }
+    for (auto& e : prune(row_stencil(es, 'T', gr, c, c, c, 7), 3)) {
+      BT.off.push_back(lin(e.di, e.dj, e.dk, n1));
+      for (int d = 0; d < 3; ++d) BT.w.push_back(e.w[d] * sB);
+    }
+    for (auto& e : prune(row_stencil(es, 'M', gr, c, c, c, 7), 1)) {
+      Mv.off.push_back((e.g - gr) * nn + lin(e.di, e.dj, e.dk, n1));
+      Mv.w.push_back(e.w[0] * sM);
+    }
+    HHG_REQUIRE(lv.adiag[gr] > 0.0, HHG_ERR_STATE, "stencil setup: missing diagonal");
+    t64.A[gr] = upload_stencil<double>(a, A);
+    t32.A[gr] = upload_stencil<float>(a, A);
+    t64.BT[gr] = upload_stencil<double>(a, BT);
+    t32.BT[gr] = upload_stencil<float>(a, BT);
+    t64.Mv[gr] = upload_stencil<double>(a, Mv);
+    t32.Mv[gr] = upload_stencil<float>(a, Mv);
+    t64.adiag_inv[gr] = 1.0 / lv.adiag[gr];
+    t32.adiag_inv[gr] = (float)(1.0 / lv.adiag[gr]);
+    lv.hA[gr] = A;
+    lv.hBT[gr] = BT;
+  }
+  const int rep[3] = {0, 2, 4};
+  for (int cls = 0; cls < 27; ++cls) {
+    const int ci = rep[cls % 3], cj = rep[(cls / 3) % 3], ck = rep[cls / 9];
+    HostStencil B, C;
+    for (auto& e : prune(row_stencil(es, 'B', 0, ci, cj, ck, 4), 3)) {
+      B.off.push_back(e.g * nn + lin(e.di, e.dj, e.dk, n1));
+      for (int d = 0; d < 3; ++d) B.w.push_back(e.w[d] * sB);
+      B.code.push_back(e.g | ((e.di + 2) << 4) | ((e.dj + 2) << 8) | ((e.dk + 2) << 12));
+    }
+    if (h->disc == HHG_P1P1) {
+      for (auto& e : prune(row_stencil(es, 'C', 0, ci, cj, ck, 4), 1)) {
+        C.off.push_back(lin(e.di, e.dj, e.dk, n1));
+        C.w.push_back(e.w[0] * sC);
+      }
+    }
+    double m = 0.0;
+    for (auto& e : row_stencil(es, 'P', 0, ci, cj, ck, 4)) m += e.w[0] * sM;
+    t64.B[cls] = upload_stencil<double>(a, B);
+    t32.B[cls] = upload_stencil<float>(a, B);
+    t64.C[cls] = upload_stencil<double>(a, C);
+    t32.C[cls] = upload_stencil<float>(a, C);
+    const int* code = a.upload(B.code);
+    t64.Bcode[cls] = code;
+    t32.Bcode[cls] = code;
+    t64.mclass[cls] = m;
+    t32.mclass[cls] = (float)m;
+    lv.hB[cls] = B;
+    lv.hC[cls] = C;
+  }
+  lv.dinv64 = a.alloc<double>(nn);
+  lv.dinv32 = a.alloc<float>(nn);
+  t64.dinv = lv.dinv64;
+  t32.dinv = lv.dinv32;
+  lv.tb64 = a.alloc<Tables<double>>(1);
+  lv.tb32 = a.alloc<Tables<float>>(1);
+  HHG_CHECK_HIP(hipMemcpy(lv.tb64, &t64, sizeof(t64), hipMemcpyHostToDevice));
+  HHG_CHECK_HIP(hipMemcpy(lv.tb32, &t32, sizeof(t32), hipMemcpyHostToDevice));
+  // boundary pressure nodes
+  std::vector<int> bnd;
+  for (int k = 0; k < n1; ++k)
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n1; ++i)
+        if (i == 0 || j == 0 || k == 0 || i == g.N || j == g.N || k == g.N) bnd.push_back(lin(i, j, k, n1));
+  lv.nbnd = (int)bnd.size();
+  lv.bnd = a.upload(bnd);
+  // Schur diagonal per node
+  launch_schur_diag<double>(S(h), g, lv.tb64, lv.bnd, lv.nbnd, h->schur, lv.dinv64);
+  launch_schur_diag<float>(S(h), g, lv.tb32, lv.bnd, lv.nbnd, h->schur, lv.dinv32);
+  HHG_CHECK_HIP(hipGetLastError());
+}
+
+// Kuhn point location inside the unit cube at t (in [0,1]^3): vertices (P1
+// offsets from the cube origin) and barycentric coordinates.
+void kuhn_locate(const double t[3], int V[4][3], double lam[4]) {
+  int ord[3] = {0, 1, 2};
+  std::stable_sort(ord, ord + 3, [&](int a, int b) { return t[a] > t[b]; });
+  lam[0] = 1.0 - t[ord[0]];
+  lam[1] = t[ord[0]] - t[ord[1]];
+  lam[2] = t[ord[1]] - t[ord[2]];
+  lam[3] = t[ord[2]];
+  for (int d = 0; d < 3; ++d) V[0][d] = 0;
+  for (int s = 0; s < 3; ++s) {
+    for (int d = 0; d < 3; ++d) V[s + 1][d] = V[s][d];
+    V[s + 1][ord[s]] += 1;
+  }
+}
+
+// Interpolation weights of a coarse element function at a point of a fine class.
+// order 1: P1 (coarse DoFs on the P1 lattice, group 0); order 2: P2 (groups).
+// Returns entries (coarse group, offset from cube origin in coarse index units, weight).
+std::vector<std::tuple<int, int, int, int, double>> interp_weights(int order, const double t[3]) {
+  int V[4][3];
+  double lam[4];
+  kuhn_locate(t, V, lam);
+  std::map<std::tuple<int, int, int, int>, double> acc;
+  if (order == 1) {
+    for (int a = 0; a < 4; ++a)
+      if (lam[a] != 0.0) acc[std::make_tuple(0, V[a][0], V[a][1], V[a][2])] += lam[a];
+  } else {
+    const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int a = 0; a < 4; ++a) {
+      const double v = lam[a] * (2.0 * lam[a] - 1.0);
+      if (v != 0.0) acc[std::make_tuple(0, V[a][0], V[a][1], V[a][2])] += v;
+    }
+    for (int e = 0; e < 6; ++e) {
+      const int p = E[e][0], q = E[e][1];
+      const double v = 4.0 * lam[p] * lam[q];
+      if (v == 0.0) continue;
+      int S[3];
+      for (int d = 0; d < 3; ++d) S[d] = V[p][d] + V[q][d];  // doubled coarse position rel. to 2*cube
+      const int gr = group_of_parity(S[0] & 1, S[1] & 1, S[2] & 1);
+      acc[std::make_tuple(gr, S[0] >> 1, S[1] >> 1, S[2] >> 1)] += v;
+    }
+  }
+  std::vector<std::tuple<int, int, int, int, double>> out;
+  for (auto& kv : acc)
+    if (std::fabs(kv.second) > 1e-15)
+      out.emplace_back(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                       kv.second);
+  return out;
+}
+
+void build_transfer(hhg_hier h, Level& lc, Level& lf) {
+  Arena& a = h->arena;
+  const int G = lf.g.G;
+  const int n1c = lc.g.n1, nnc = lc.g.nn, n1f = lf.g.n1, nnf = lf.g.nn;
+  // velocity prolongation classes
+  const int vorder = G == 1 ? 1 : 2;
+  const int vq = vorder == 1 ? 2 : 4;  // fine positions per coarse cube edge
+  const int ncls = vq * vq * vq;
+  std::vector<int> vp_off(ncls * 10, 0), vp_n(ncls, 0);
+  std::vector<double> vp_w(ncls * 10, 0.0);
+  // restriction accumulators per coarse group: (fine group, fine index offset) -> w
+  std::vector<std::map<std::tuple<int, int, int, int>, double>> racc(G);
+  for (int cz = 0; cz < vq; ++cz)
+    for (int cy = 0; cy < vq; ++cy)
+      for (int cx = 0; cx < vq; ++cx) {
+        const int cls = cx + vq * (cy + vq * cz);
+        const double t[3] = {(double)cx / vq, (double)cy / vq, (double)cz / vq};
+        auto ws = interp_weights(vorder, t);
+        HHG_REQUIRE(ws.size() <= 10, HHG_ERR_STATE, "transfer setup: too many weights");
+        int e = 0;
+        for (auto& w : ws) {
+          const int gc = std::get<0>(w), oi = std::get<1>(w), oj = std::get<2>(w), ok = std::get<3>(w);
+          vp_off[cls * 10 + e] = gc * nnc + lin(oi, oj, ok, n1c);
+          vp_w[cls * 10 + e] = std::get<4>(w);
+          ++e;
+          // transpose: fine site relative to the coarse site
+          const int c[3] = {cx, cy, cz};
+          const int o[3] = {oi, oj, ok};
+          int fofs[3];
+          int fpar[3];
+          for (int d = 0; d < 3; ++d) {
+            if (vorder == 2) {
+              const int delta = c[d] - 4 * o[d] - 2 * kGroupDir[gc][d];  // fine doubled, rel. to 2 S_c
+              fpar[d] = delta & 1;
+              fofs[d] = kGroupDir[gc][d] + (delta >> 1);  // fine index rel. to 2 (i,j,k)
+            } else {
+              fpar[d] = 0;
+              fofs[d] = c[d] - 2 * o[d];
+            }
+          }
+          const int fg = vorder == 2 ? group_of_parity(fpar[0], fpar[1], fpar[2]) : 0;
+          racc[gc][std::make_tuple(fg, fofs[0], fofs[1], fofs[2])] += std::get<4>(w);
+        }
+        vp_n[cls] = e;
+      }
+  // pressure (linear) prolongation classes and restriction
+  std::vector<int> pp_off(80, 0), pp_n(8, 0);
+  std::vector<double> pp_w(80, 0.0);
+  std::map<std::tuple<int, int, int>, double> pracc;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const int cls = cx + 2 * (cy + 2 * cz);
+        const double t[3] = {cx / 2.0, cy / 2.0, cz / 2.0};
+        auto ws = interp_weights(1, t);
+        int e = 0;
+        for (auto& w : ws) {
+          const int oi = std::get<1>(w), oj = std::get<2>(w), ok = std::get<3>(w);
+          pp_off[cls * 10 + e] = lin(oi, oj, ok, n1c);
+          pp_w[cls * 10 + e] = std::get<4>(w);
+          ++e;
+          pracc[std::make_tuple(cx - 2 * oi, cy - 2 * oj, cz - 2 * ok)] += std::get<4>(w);
+        }
+        pp_n[cls] = e;
+      }
+  auto mk = [&](auto& tt, auto tag) {
+    using T = decltype(tag);
+    std::vector<T> vw(vp_w.begin(), vp_w.end()), pw(pp_w.begin(), pp_w.end());
+    tt.vp_off = a.upload(vp_off);
+    tt.vp_w = a.upload(vw);
+    tt.vp_n = a.upload(vp_n);
+    tt.pp_off = a.upload(pp_off);
+    tt.pp_w = a.upload(pw);
+    tt.pp_n = a.upload(pp_n);
+    for (int gc = 0; gc < G; ++gc) {
+      HostStencil r;
+      for (auto& kv : racc[gc]) {
+        const int fg = std::get<0>(kv.first);
+        r.off.push_back(fg * nnf + lin(std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), n1f));
+        r.w.push_back(kv.second);
+      }
+      tt.r[gc] = upload_stencil<T>(a, r);
+    }
+    HostStencil rp;
+    std::vector<int> rpd;
+    for (auto& kv : pracc) {
+      const int di = std::get<0>(kv.first), dj = std::get<1>(kv.first), dk = std::get<2>(kv.first);
+      rp.off.push_back(lin(di, dj, dk, n1f));
+      rp.w.push_back(kv.second);
+      rpd.push_back((di + 2) | ((dj + 2) << 4) | ((dk + 2) << 8));
+    }
+    tt.rp = upload_stencil<T>(a, rp);
+    tt.rp_d = a.upload(rpd);
+  };
+  TransferTables<double> t64{};
+  TransferTables<float> t32{};
+  mk(t64, double());
+  mk(t32, float());
+  lf.tt64 = a.alloc<TransferTables<double>>(1);
+  lf.tt32 = a.alloc<TransferTables<float>>(1);
+  HHG_CHECK_HIP(hipMemcpy(lf.tt64, &t64, sizeof(t64), hipMemcpyHostToDevice));
+  HHG_CHECK_HIP(hipMemcpy(lf.tt32, &t32, sizeof(t32), hipMemcpyHostToDevice));
+}
+
+// Dense coarse operator on the unknowns (interior velocity DoFs, all pressure
+// DoFs) from the host stencil tables, and its pseudo-inverse.
+void build_coarse(hhg_hier h) {
+  Level& lv = h->L(h->lmin);
+  const Geom& g = lv.g;
+  const int N = g.N, n1 = g.n1, nn = g.nn, G = g.G;
+  std::vector<int> unk;
+  std::unordered_map<int, int> pos2u;
+  auto vint = [&](int gr, int i, int j, int k) {
+    const int dx = G == 1 ? 0 : kGroupDir[gr][0], dy = G == 1 ? 0 : kGroupDir[gr][1], dz = G == 1 ? 0 : kGroupDir[gr][2];
+    return i >= 1 - dx && j >= 1 - dy && k >= 1 - dz && i <= N - 1 && j <= N - 1 && k <= N - 1;
+  };
+  for (int d = 0; d < 3; ++d)
+    for (int gr = 0; gr < G; ++gr)
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i)
+            if (vint(gr, i, j, k)) {
+              const int p = d * g.vstride + gr * nn + lin(i, j, k, n1);
+              pos2u[p] = (int)unk.size();
+              unk.push_back(p);
+            }
+  for (int k = 0; k < n1; ++k)
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n1; ++i) {
+        const int p = 3 * g.vstride + lin(i, j, k, n1);
+        pos2u[p] = (int)unk.size();
+        unk.push_back(p);
+      }
+  const int n = (int)unk.size();
+  HHG_REQUIRE(n <= 2048, HHG_ERR_ARG, "coarsest level too large for the dense coarse solve (max 2048 unknowns)");
+  std::vector<double> K((size_t)n * n, 0.0);
+  auto add = [&](int r, int pos, double w) {
+    auto it = pos2u.find(pos);
+    if (it != pos2u.end()) K[(size_t)r * n + it->second] += w;
+  };
+  for (int r = 0; r < n; ++r) {
+    const int p = unk[r];
+    if (p < 3 * g.vstride) {
+      const int d = p / g.vstride, rem = p % g.vstride, gr = rem / nn, idx = rem % nn;
+      const HostStencil& A = lv.hA[gr];
+      for (size_t e = 0; e < A.off.size(); ++e) add(r, p + A.off[e], A.w[e]);
+      const HostStencil& BT = lv.hBT[gr];
+      for (size_t e = 0; e < BT.off.size(); ++e) add(r, 3 * g.vstride + idx + BT.off[e], BT.w[3 * e + d]);
+    } else {
+      const int idx = p - 3 * g.vstride;
+      const int i = idx % n1, j = (idx / n1) % n1, k = idx / (n1 * n1);
+      const int cls = bclass(i, j, k, N);
+      const HostStencil& B = lv.hB[cls];
+      for (size_t e = 0; e < B.off.size(); ++e)
+        for (int d = 0; d < 3; ++d) add(r, d * g.vstride + idx + B.off[e], B.w[3 * e + d]);
+      const HostStencil& C = lv.hC[cls];
+      for (size_t e = 0; e < C.off.size(); ++e) add(r, p + C.off[e], -C.w[e]);
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = r + 1; c < n; ++c) {
+      const double s = 0.5 * (K[(size_t)r * n + c] + K[(size_t)c * n + r]);
+      K[(size_t)r * n + c] = K[(size_t)c * n + r] = s;
+    }
+  std::vector<double> Kp;
+  h->rank = sym_pinv(n, K, Kp, 1e-12);
+  h->nunk = n;
+  h->Kp = h->arena.upload(Kp);
+  h->unk = h->arena.upload(unk);
+}
+
+// ---------------------------------------------------------------- ops
+template <typename T>
+void op_apply(hhg_hier h, int l, int opmask, const T* x, const T* b, T* y, bool has_b, bool vel, bool prs) {
+  Level& lv = h->L(l);
+  launch_apply<T>(S(h), lv.g, tables<T>(lv), x, b, y, opmask, has_b, vel, prs, lv.bnd, lv.nbnd);
+}
+
+int full_mask(hhg_hier h) { return h->disc == HHG_P1P1 ? 15 : 7; }
+
+template <typename T>
+T* rbuf(Level& lv);
+template <>
+double* rbuf<double>(Level& lv) {
+  return lv.r;
+}
+template <>
+float* rbuf<float>(Level& lv) {
+  return lv.r32;
+}
+
+template <typename T>
+void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, double omega) {
+  Level& lv = h->L(l);
+  const int ncol = h->G == 1 ? 4 : 11;
+  T* r = rbuf<T>(lv);
+  for (int it = 0; it < iters; ++it) {
+    for (int s = 0; s < xi; ++s) {
+      for (int c = 0; c < ncol; ++c) launch_gs_colour<T>(S(h), lv.g, tables<T>(lv), x, b, c);
+      if (gs == HHG_GS_SYM)
+        for (int c = ncol - 1; c >= 0; --c) launch_gs_colour<T>(S(h), lv.g, tables<T>(lv), x, b, c);
+    }
+    // r_p = g - B u + C p, then p -= omega D^{-1} r_p
+    op_apply<T>(h, l, full_mask(h) & 12, x, b, r, true, false, true);
+    launch_pressure_step<T>(S(h), lv.g, dinv<T>(lv), x, r, (T)omega);
+  }
+}
+
+template <typename T>
+void op_mean_zero(hhg_hier h, int l, T* x) {
+  Level& lv = h->L(l);
+  T* p = x + 3 * (size_t)lv.g.vstride;
+  launch_psum<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
+  launch_pshift<T>(S(h), lv.g, p, h->sums, 0);
+}
+
+template <typename T>
+void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
+  Level& f = h->L(lf);
+  Level& c = h->L(lf - 1);
+  launch_restrict<T>(S(h), f.g, c.g, ttables<T>(f), rf, rc);
+  T* p = rc + 3 * (size_t)c.g.vstride;
+  launch_psum<T>(S(h), c.g, tables<T>(c), p, h->partial, h->sums, 1);
+  launch_pshift<T>(S(h), c.g, p, h->sums, 1);
+}
+
+template <typename T>
+void op_prolong(hhg_hier h, int lc, const T* xc, T* xf, bool add, bool skip_bnd) {
+  Level& c = h->L(lc);
+  Level& f = h->L(lc + 1);
+  launch_prolong<T>(S(h), c.g, f.g, ttables<T>(f), xc, xf, add, skip_bnd);
+}
+
+void op_coarse(hhg_hier h, double* x, const double* b) {
+  Level& lv = h->L(h->lmin);
+  op_apply<double>(h, h->lmin, full_mask(h), x, b, lv.r, true, true, true);
+  launch_coarse(S(h), lv.g, h->Kp, h->unk, h->nunk, lv.r, x, nullptr);
+  op_mean_zero<double>(h, h->lmin, x);
+}
+
+void vcycle(hhg_hier h, int lf, int l, double* x, const double* b, const hhg_solver_params& p) {
+  if (l == h->lmin) {
+    op_coarse(h, x, b);
+    return;
+  }
+  Level& lv = h->L(l);
+  Level& lc = h->L(l - 1);
+  const double om = 1.0 / p.omega_inv;
+  op_smooth<double>(h, l, x, b, p.nu_pre + (lf - l) * p.nu_inc, p.gs, p.xi, om);
+  op_apply<double>(h, l, full_mask(h), x, b, lv.r, true, true, true);
+  op_restrict<double>(h, l, lv.r, lc.cb);
+  launch_fill<double>(S(h), lc.cx, lc.vec_words, 0.0);
+  vcycle(h, lf, l - 1, lc.cx, lc.cb, p);
+  op_prolong<double>(h, l - 1, lc.cx, x, true, true);
+  op_smooth<double>(h, l, x, b, p.nu_post + (lf - l) * p.nu_inc, p.gs, p.xi, om);
+}
+
+// Euclidean norms of velocity and pressure parts (synchronous).
+template <typename T>
+void norms(hhg_hier h, int l, const T* x, double* nu, double* np_) {
+  Level& lv = h->L(l);
+  launch_vsumsq<T>(S(h), lv.g, x, 3 * lv.g.vstride, h->partial, h->sums);
+  launch_vsumsq<T>(S(h), lv.g, x + 3 * (size_t)lv.g.vstride, lv.g.nn, h->partial + 2 * kPartials, h->sums + 2);
+  HHG_CHECK_HIP(hipMemcpyAsync(h->hsums, h->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, S(h)));
+  HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
+  *nu = std::sqrt(h->hsums[0]);
+  *np_ = std::sqrt(h->hsums[2]);
+}
+
+double fmg_work_units(const hhg_hier h, const hhg_solver_params& p) {
+  // Sec. 4: W(P^-1) = sweeps * W_A + 2 W_B + W_C (normalised), variable V-cycle
+  // bound 8/7 W(V_L^L) + 16/49 nu_inc W(P^-1), FMG bound 8 kappa / 7 W*.
+  double a, bb, c;
+  if (h->disc == HHG_P2P1) {
+    a = 46.0 / 72.0, bb = 13.0 / 72.0, c = 0.0;
+  } else {
+    a = 0.3, bb = 0.3, c = 0.1;
+  }
+  const double sweeps = p.xi * (p.gs == HHG_GS_SYM ? 2.0 : 1.0);
+  const double wp = sweeps * a + 2 * bb + c;
+  const double wv = (p.nu_pre + p.nu_post) * wp + 1.0;
+  const double wstar = 8.0 / 7.0 * wv + 16.0 / 49.0 * p.nu_inc * wp;
+  return 8.0 * p.kappa / 7.0 * wstar;
+}
+
+double vcycle_work_units(const hhg_hier h, const hhg_solver_params& p) {
+  double a, bb, c;
+  if (h->disc == HHG_P2P1) {
+    a = 46.0 / 72.0, bb = 13.0 / 72.0, c = 0.0;
+  } else {
+    a = 0.3, bb = 0.3, c = 0.1;
+  }
+  const double sweeps = p.xi * (p.gs == HHG_GS_SYM ? 2.0 : 1.0);
+  const double wp = sweeps * a + 2 * bb + c;
+  const double wv = (p.nu_pre + p.nu_post) * wp + 1.0;
+  return 8.0 / 7.0 * wv + 16.0 / 49.0 * p.nu_inc * wp;
+}
+
+hhg_hier check_level(hhg_hier h, int l) {
+  HHG_REQUIRE(h != nullptr, HHG_ERR_ARG, "null hierarchy");
+  HHG_REQUIRE(l >= h->lmin && l <= h->lmax, HHG_ERR_ARG, "level out of range");
+  return h;
+}
+
+template <typename F>
+hhg_status guard(F&& f) {
+  try {
+    f();
+    return HHG_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return HHG_ERR_STATE;
+  } catch (...) {
+    set_error("unknown error");
+    return HHG_ERR_STATE;
+  }
+}
+
+}  // namespace
+}  // namespace hhg
+
+using namespace hhg;
+
+extern "C" {
+
+const char* hhg_last_error(void) { return g_err.c_str(); }
+
+hhg_status hhg_ctx_create(int device, void* stream, hhg_ctx* out) {
+  return guard([&] {
+    HHG_REQUIRE(out != nullptr, HHG_ERR_ARG, "null output");
+    int n = 0;
+    HHG_CHECK_HIP(hipGetDeviceCount(&n));
+    HHG_REQUIRE(device >= 0 && device < n, HHG_ERR_ARG, "device out of range");
+    HHG_CHECK_HIP(hipSetDevice(device));
+    auto* c = new hhg_ctx_s;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+  });
+}
+
+hhg_status hhg_ctx_set_stream(hhg_ctx ctx, void* stream) {
+  return guard([&] {
+    HHG_REQUIRE(ctx != nullptr, HHG_ERR_ARG, "null context");
+    ctx->stream = (hipStream_t)stream;
+  });
+}
+
+hhg_status hhg_ctx_destroy(hhg_ctx ctx) {
+  return guard([&] { delete ctx; });
+}
+
+hhg_status hhg_hier_create(hhg_ctx ctx, hhg_disc disc, int macro_refine, int lmin, int lmax, hhg_schur schur,
+                           hhg_hier* out) {
+  return guard([&] {
+    HHG_REQUIRE(ctx && out, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(disc == HHG_P1P1 || disc == HHG_P2P1, HHG_ERR_ARG, "unknown discretisation");
+    HHG_REQUIRE(macro_refine == 0 || macro_refine == 1, HHG_ERR_ARG, "macro_refine must be 0 or 1");
+    HHG_REQUIRE(lmin >= 0 && lmin < lmax, HHG_ERR_ARG, "need 0 <= lmin < lmax");
+    HHG_REQUIRE((1 << (lmax + macro_refine)) <= (disc == HHG_P1P1 ? 512 : 256), HHG_ERR_ARG,
+                "finest level too large (N <= 512 for P1-P1, N <= 256 for P2-P1)");
+    HHG_REQUIRE(schur == HHG_SCHUR_SD || schur == HHG_SCHUR_ML, HHG_ERR_ARG, "unknown Schur option");
+    HHG_REQUIRE(disc == HHG_P1P1 || (1 << (lmin + macro_refine)) >= 2, HHG_ERR_ARG,
+                "Taylor-Hood needs at least 2 intervals on the coarsest level");
+    HHG_CHECK_HIP(hipSetDevice(ctx->device));
+    std::unique_ptr<hhg_hier_s> h(new hhg_hier_s);
+    h->ctx = ctx;
+    h->disc = disc;
+    h->mr = macro_refine;
+    h->lmin = lmin;
+    h->lmax = lmax;
+    h->schur = schur;
+    h->G = disc == HHG_P1P1 ? 1 : 8;
+    ElementSet es;
+    build_elements(disc == HHG_P1P1 ? 1 : 2, &es);
+    h->partial = h->arena.alloc<double>(4 * kPartials);
+    h->sums = h->arena.alloc<double>(16);
+    HHG_CHECK_HIP(hipHostMalloc((void**)&h->hsums, 16 * sizeof(double), hipHostMallocDefault));
+    h->levels.resize(lmax - lmin + 1);
+    for (int l = lmin; l <= lmax; ++l) {
+      Level& lv = h->L(l);
+      lv.l = l;
+      const int N = 1 << (l + macro_refine);
+      lv.g.N = N;
+      lv.g.n1 = N + 1;
+      lv.g.nn = (N + 1) * (N + 1) * (N + 1);
+      lv.g.G = h->G;
+      lv.g.vstride = h->G * lv.g.nn;
+      lv.h = 1.0 / N;
+      lv.vec_words = 3 * (size_t)lv.g.vstride + lv.g.nn;
+      build_level_tables(h.get(), lv, es);
+      lv.r = h->arena.alloc<double>(lv.vec_words);
+      lv.r32 = h->arena.alloc<float>(lv.vec_words);
+      lv.w = h->arena.alloc<double>(lv.vec_words);
+      lv.xs = h->arena.alloc<double>(lv.vec_words);
+      if (l < lmax) {
+        lv.cx = h->arena.alloc<double>(lv.vec_words);
+        lv.cb = h->arena.alloc<double>(lv.vec_words);
+      }
+      launch_fill<double>(ctx->stream, lv.r, lv.vec_words, 0.0);
+      launch_fill<float>(ctx->stream, lv.r32, lv.vec_words, 0.0f);
+      launch_fill<double>(ctx->stream, lv.w, lv.vec_words, 0.0);
+      launch_fill<double>(ctx->stream, lv.xs, lv.vec_words, 0.0);
+    }
+    for (int l = lmin + 1; l <= lmax; ++l) build_transfer(h.get(), h->L(l - 1), h->L(l));
+    build_coarse(h.get());
+    HHG_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    *out = h.release();
+  });
+}
+
+hhg_status hhg_hier_destroy(hhg_hier h) {
+  return guard([&] {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->ctx->stream);
+    if (h->hsums) (void)hipHostFree(h->hsums);
+    delete h;
+  });
+}
+
+hhg_status hhg_vec_layout(hhg_hier h, int level, int* N, size_t* nn, size_t* vec_words, size_t* lattice_words) {
+  return guard([&] {
+    check_level(h, level);
+    Level& lv = h->L(level);
+    if (N) *N = lv.g.N;
+    if (nn) *nn = lv.g.nn;
+    if (vec_words) *vec_words = lv.vec_words;
+    const size_t m1 = (h->G == 1 ? lv.g.N : 2 * lv.g.N) + 1;
+    if (lattice_words) *lattice_words = 3 * m1 * m1 * m1 + lv.g.nn;
+  });
+}
+
+#define HHG_DISPATCH(prec, F)                                              \
+  do {                                                                     \
+    if ((prec) == HHG_F64) {                                               \
+      using T = double;                                                    \
+      F;                                                                   \
+    } else if ((prec) == HHG_F32) {                                        \
+      using T = float;                                                     \
+      F;                                                                   \
+    } else {                                                               \
+      throw Error{HHG_ERR_PREC, "unsupported precision"};                  \
+    }                                                                      \
+  } while (0)
+
+hhg_status hhg_vec_from_lattice(hhg_hier h, int level, const double* src, void* dst, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(src && dst, HHG_ERR_ARG, "null vector");
+    Level& lv = h->L(level);
+    HHG_DISPATCH(prec, {
+      launch_fill<T>(S(h), (T*)dst, lv.vec_words, T(0));
+      launch_from_lattice<T>(S(h), lv.g, src, (T*)dst);
+    });
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_vec_to_lattice(hhg_hier h, int level, const void* src, double* dst, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(src && dst, HHG_ERR_ARG, "null vector");
+    Level& lv = h->L(level);
+    HHG_DISPATCH(prec, launch_to_lattice<T>(S(h), lv.g, (const T*)src, dst));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_apply(hhg_hier h, int level, hhg_op op, const void* x, void* y, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(x && y && x != y, HHG_ERR_ARG, "bad vectors");
+    Level& lv = h->L(level);
+    int mask = 0;
+    switch (op) {
+      case HHG_OP_FULL: mask = full_mask(h); break;
+      case HHG_OP_A: mask = 1; break;
+      case HHG_OP_BT: mask = 2; break;
+      case HHG_OP_B: mask = 4; break;
+      case HHG_OP_C: mask = 8 | 16; break;
+      default: throw Error{HHG_ERR_ARG, "operator not supported"};
+    }
+    if (op == HHG_OP_C && h->disc == HHG_P2P1) mask = 0;
+    HHG_DISPATCH(prec, {
+      op_apply<T>(h, level, mask, (const T*)x, nullptr, (T*)y, false, true, true);
+      (void)lv;
+    });
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_residual(hhg_hier h, int level, const void* x, const void* b, void* r, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(x && b && r && x != r && b != r, HHG_ERR_ARG, "bad vectors");
+    HHG_DISPATCH(prec, op_apply<T>(h, level, full_mask(h), (const T*)x, (const T*)b, (T*)r, true, true, true));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_rhs(hhg_hier h, int level, const void* f, void* b, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(f && b && f != b, HHG_ERR_ARG, "bad vectors");
+    Level& lv = h->L(level);
+    HHG_DISPATCH(prec, launch_rhs<T>(S(h), lv.g, tables<T>(lv), (const T*)f, (T*)b));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_smooth(hhg_hier h, int level, void* x, const void* b, int iters, hhg_gs gs, int xi, double omega_inv,
+                      hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(x && b && x != b, HHG_ERR_ARG, "bad vectors");
+    HHG_REQUIRE(iters >= 0 && xi >= 1 && omega_inv > 0.0, HHG_ERR_ARG, "bad smoother parameters");
+    HHG_REQUIRE(gs == HHG_GS_FWD || gs == HHG_GS_SYM, HHG_ERR_ARG, "bad Gauss-Seidel variant");
+    HHG_DISPATCH(prec, op_smooth<T>(h, level, (T*)x, (const T*)b, iters, gs, xi, 1.0 / omega_inv));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_restrict(hhg_hier h, int fine_level, const void* rf, void* rc, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, fine_level);
+    HHG_REQUIRE(fine_level > h->lmin, HHG_ERR_ARG, "no coarser level");
+    HHG_REQUIRE(rf && rc, HHG_ERR_ARG, "null vector");
+    HHG_DISPATCH(prec, op_restrict<T>(h, fine_level, (const T*)rf, (T*)rc));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_prolong_add(hhg_hier h, int coarse_level, const void* xc, void* xf, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, coarse_level);
+    HHG_REQUIRE(coarse_level < h->lmax, HHG_ERR_ARG, "no finer level");
+    HHG_REQUIRE(xc && xf, HHG_ERR_ARG, "null vector");
+    HHG_DISPATCH(prec, op_prolong<T>(h, coarse_level, (const T*)xc, (T*)xf, true, false));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_coarse_solve(hhg_hier h, void* x, const void* b, hhg_prec prec) {
+  return guard([&] {
+    HHG_REQUIRE(h && x && b && x != b, HHG_ERR_ARG, "bad arguments");
+    HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "coarse solve is float64");
+    op_coarse(h, (double*)x, (const double*)b);
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_project_mean_zero(hhg_hier h, int level, void* x, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(x, HHG_ERR_ARG, "null vector");
+    HHG_DISPATCH(prec, op_mean_zero<T>(h, level, (T*)x));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_copy_boundary(hhg_hier h, int level, const void* src, void* dst, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(src && dst, HHG_ERR_ARG, "null vector");
+    Level& lv = h->L(level);
+    HHG_DISPATCH(prec, launch_copy_boundary<T>(S(h), lv.g, (const T*)src, (T*)dst));
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_norms(hhg_hier h, int level, const void* x, double* nu, double* np_, hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(x && nu && np_, HHG_ERR_ARG, "null argument");
+    HHG_DISPATCH(prec, norms<T>(h, level, (const T*)x, nu, np_));
+  });
+}
+
+hhg_status hhg_estimate_omega(hhg_hier h, int level, const double* v0, int iters, double* omega_inv) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(v0 && omega_inv && iters >= 1, HHG_ERR_ARG, "bad arguments");
+    Level& lv = h->L(level);
+    const Geom& g = lv.g;
+    const size_t vs3 = 3 * (size_t)g.vstride;
+    double* v = lv.xs;   // pressure part holds v; velocity part zero
+    double* z = lv.w;    // velocity part: sweep iterate; pressure part: -v for C
+    double* y = lv.r;    // B^T v (velocity rows), then (B z + C v) (pressure rows)
+    hipStream_t s = S(h);
+    launch_fill<double>(s, v, lv.vec_words, 0.0);
+    HHG_CHECK_HIP(hipMemcpyAsync(v + vs3, v0, g.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    op_mean_zero<double>(h, level, v);
+    auto normalise = [&]() {
+      launch_vsumsq<double>(s, g, v + vs3, g.nn, h->partial, h->sums);
+      launch_scale<double>(s, v + vs3, g.nn, h->sums, 0);
+    };
+    normalise();
+    const int ncol = h->G == 1 ? 4 : 11;
+    for (int it = 0; it < iters; ++it) {
+      op_apply<double>(h, level, 2, v, nullptr, y, false, true, false);   // B^T v
+      launch_fill<double>(s, z, lv.vec_words, 0.0);
+      for (int c = 0; c < ncol; ++c) launch_gs_colour<double>(s, g, lv.tb64, z, y, c);
+      for (int c = ncol - 1; c >= 0; --c) launch_gs_colour<double>(s, g, lv.tb64, z, y, c);
+      launch_scaled_copy<double>(s, z + vs3, v + vs3, nullptr, g.nn, -1.0);
+      op_apply<double>(h, level, full_mask(h) & 12, z, nullptr, y, false, false, true);  // B z + C v
+      launch_scaled_copy<double>(s, v + vs3, y + vs3, lv.dinv64, g.nn, 1.0);         // w = D^{-1}(...)
+      launch_vsumsq<double>(s, g, v + vs3, g.nn, h->partial, h->sums);
+      if (it + 1 < iters) launch_scale<double>(s, v + vs3, g.nn, h->sums, 0);
+    }
+    HHG_CHECK_HIP(hipMemcpyAsync(h->hsums, h->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HHG_CHECK_HIP(hipStreamSynchronize(s));
+    *omega_inv = std::sqrt(h->hsums[0]);
+  });
+}
+
+hhg_status hhg_query_stencil(hhg_disc disc, char kind, int group, int i, int j, int k, int nbox, int max_entries,
+                             int* n, int* code, double* w) {
+  return guard([&] {
+    HHG_REQUIRE(disc == HHG_P1P1 || disc == HHG_P2P1, HHG_ERR_ARG, "unknown discretisation");
+    HHG_REQUIRE(n && code && w, HHG_ERR_ARG, "null output");
+    HHG_REQUIRE(std::strchr("AMTBCP", kind) != nullptr && kind != 0, HHG_ERR_ARG, "unknown stencil kind");
+    ElementSet es;
+    build_elements(disc == HHG_P1P1 ? 1 : 2, &es);
+    Row r = row_stencil(es, kind, group, i, j, k, nbox);
+    *n = (int)r.size();
+    HHG_REQUIRE((int)r.size() <= max_entries, HHG_ERR_ARG, "output too small");
+    for (size_t e = 0; e < r.size(); ++e) {
+      code[4 * e] = r[e].g, code[4 * e + 1] = r[e].di, code[4 * e + 2] = r[e].dj, code[4 * e + 3] = r[e].dk;
+      for (int d = 0; d < 3; ++d) w[3 * e + d] = r[e].w[d];
+    }
+  });
+}
+
+hhg_status hhg_query_interpolation(int order, int tx, int ty, int tz, int q, int* n, int* code, double* w) {
+  return guard([&] {
+    HHG_REQUIRE(order == 1 || order == 2, HHG_ERR_ARG, "order must be 1 or 2");
+    HHG_REQUIRE(q >= 1 && tx >= 0 && ty >= 0 && tz >= 0 && tx <= q && ty <= q && tz <= q, HHG_ERR_ARG,
+                "position outside the cube");
+    HHG_REQUIRE(n && code && w, HHG_ERR_ARG, "null output");
+    const double t[3] = {(double)tx / q, (double)ty / q, (double)tz / q};
+    auto ws = interp_weights(order, t);
+    *n = (int)ws.size();
+    for (size_t e = 0; e < ws.size(); ++e) {
+      code[4 * e] = std::get<0>(ws[e]);
+      code[4 * e + 1] = std::get<1>(ws[e]);
+      code[4 * e + 2] = std::get<2>(ws[e]);
+      code[4 * e + 3] = std::get<3>(ws[e]);
+      w[e] = std::get<4>(ws[e]);
+    }
+  });
+}
+
+hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_solver_params* prm) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(x && b && prm && prm->omega_inv > 0.0 && prm->xi >= 1, HHG_ERR_ARG, "bad arguments");
+    vcycle(h, level, level, (double*)x, (const double*)b, *prm);
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, const hhg_solver_params* prm,
+                         hhg_stats* stats) {
+  hhg_status st = guard([&] {
+    HHG_REQUIRE(h && xv && b_levels && prm, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(prm->omega_inv > 0.0 && prm->xi >= 1 && prm->kappa >= 1, HHG_ERR_ARG, "bad solver parameters");
+    for (int l = h->lmin; l <= h->lmax; ++l) HHG_REQUIRE(b_levels[l - h->lmin], HHG_ERR_ARG, "null rhs");
+    hipStream_t s = S(h);
+    double* x = (double*)xv;
+    const hhg_solver_params& p = *prm;
+    auto bl = [&](int l) { return (const double*)b_levels[l - h->lmin]; };
+    // boundary data on every level (nodal interpolation = injection)
+    Level& top = h->L(h->lmax);
+    launch_copy_boundary<double>(s, top.g, x, top.w);
+    for (int l = h->lmax - 1; l >= h->lmin; --l) launch_inject_boundary<double>(s, h->L(l + 1).g, h->L(l).g, h->L(l + 1).w, h->L(l).w);
+    Level& bot = h->L(h->lmin);
+    launch_fill<double>(s, bot.xs, bot.vec_words, 0.0);
+    launch_copy_boundary<double>(s, bot.g, bot.w, bot.xs);
+    op_coarse(h, bot.xs, bl(h->lmin));
+    for (int l = h->lmin + 1; l <= h->lmax; ++l) {
+      Level& lv = h->L(l);
+      double* X = l == h->lmax ? x : lv.xs;
+      op_prolong<double>(h, l - 1, h->L(l - 1).xs, X, false, false);
+      launch_copy_boundary<double>(s, lv.g, lv.w, X);
+      for (int c = 0; c < p.kappa; ++c) {
+        vcycle(h, l, l, X, bl(l), p);
+        op_mean_zero<double>(h, l, X);
+      }
+    }
+    int cycles = p.kappa;
+    double bu = 0, bp = 0, ru = 0, rp = 0;
+    const double* b = bl(h->lmax);
+    const bool want_norms = stats != nullptr || p.rtol > 0.0;
+    if (want_norms) norms<double>(h, h->lmax, b, &bu, &bp);
+    const double bn = std::sqrt(bu * bu + bp * bp);
+    if (p.rtol > 0.0) {
+      for (;;) {
+        op_apply<double>(h, h->lmax, full_mask(h), x, b, top.r, true, true, true);
+        norms<double>(h, h->lmax, top.r, &ru, &rp);
+        if (std::sqrt(ru * ru + rp * rp) <= p.rtol * bn || cycles >= p.max_cycles) break;
+        vcycle(h, h->lmax, h->lmax, x, b, p);
+        op_mean_zero<double>(h, h->lmax, x);
+        ++cycles;
+      }
+    } else {
+      for (int c = 0; c < p.extra_cycles; ++c) {
+        vcycle(h, h->lmax, h->lmax, x, b, p);
+        op_mean_zero<double>(h, h->lmax, x);
+        ++cycles;
+      }
+      if (stats) {
+        op_apply<double>(h, h->lmax, full_mask(h), x, b, top.r, true, true, true);
+        norms<double>(h, h->lmax, top.r, &ru, &rp);
+      }
+    }
+    HHG_CHECK_HIP(hipGetLastError());
+    if (stats) {
+      stats->cycles = cycles;
+      stats->res_u = ru;
+      stats->res_p = rp;
+      stats->rel_res = bn > 0 ? std::sqrt(ru * ru + rp * rp) / bn : 0.0;
+      stats->work_units = fmg_work_units(h, p) + (cycles - p.kappa) * vcycle_work_units(h, p);
+    }
+    if (p.rtol > 0.0 && std::sqrt(ru * ru + rp * rp) > p.rtol * bn)
+      throw Error{HHG_ERR_NOT_CONVERGED, "relative residual above rtol after max_cycles"};
+  });
+  return st;
+}
+
+}  // extern "C"

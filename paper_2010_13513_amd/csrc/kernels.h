@@ -1,0 +1,95 @@
+// Kernel-side declarations shared by the launchers (host) and kernels.hip.
+#pragma once
+#include "hhg_internal.h"
+
+namespace hhg {
+
+// Geometry of one level: N intervals, n1 = N + 1 nodes per edge, nn = n1^3
+// words per lattice array, G velocity groups (1: P1, 8: P2), vstride = G nn.
+struct Geom {
+  int N, n1, nn, G, vstride;
+};
+
+// Stencil tables of one level in one precision (device pointers inside).
+// Velocity rows exist only at interior velocity sites and use the unbounded
+// lattice stencil; pressure rows use one of 27 boundary classes.
+template <typename T>
+struct Tables {
+  DStencil<T> A[8];     // velocity row, group g -> velocity cols (offsets include group shift)
+  DStencil<T> BT[8];    // velocity row, group g -> pressure cols, 3 weights/entry
+  DStencil<T> Mv[8];    // velocity mass, interior rows
+  DStencil<T> B[27];    // pressure row, class -> velocity cols (offset from group-0 index), 3 weights
+  DStencil<T> C[27];    // pressure row, class -> pressure cols (PSPG; n = 0 for Taylor-Hood)
+  const int* Bcode[27]; // packed (g, di+2, dj+2, dk+2) of the B entries (setup only)
+  T adiag_inv[8];       // 1 / A_gg
+  T mclass[27];         // int psi_k per boundary class
+  const T* dinv;        // per pressure node 1 / D_k (Schur diagonal), nn words
+};
+
+// Transfer tables between level l-1 (coarse) and l (fine) for one field kind.
+// Prolongation: fine class (S & 3 per coordinate, 64 classes for quadratic,
+// 8 for linear on the P1 lattice) -> up to 10 (coarse offset, weight) pairs,
+// offsets relative to the coarse cube (S >> 2 or S >> 1) position in group 0.
+// Restriction: coarse group -> (fine offset, weight) relative to the fine index
+// 2 (i, j, k) in group 0.
+template <typename T>
+struct TransferTables {
+  const int* vp_off;   // velocity prolongation [ncls][10], ncls = 64 (P2) or 8 (P1)
+  const T* vp_w;
+  const int* vp_n;
+  const int* pp_off;   // P1 pressure prolongation [8][10]
+  const T* pp_w;
+  const int* pp_n;
+  DStencil<T> r[8];    // restriction per coarse velocity group (interior rows)
+  DStencil<T> rp;      // linear restriction of the P1 pressure (offsets into fine array)
+  const int* rp_d;     // packed (di+2, dj+2, dk+2) of rp entries, for clipping
+};
+
+// Launchers (kernels.hip).  All asynchronous on `s`.
+template <typename T>
+void launch_apply(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, const T* b, T* y, int opmask,
+                  bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd);
+template <typename T>
+void launch_gs_colour(hipStream_t s, const Geom& g, const Tables<T>* tb, T* x, const T* b, int colour);
+template <typename T>
+void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, const T* rp, T omega);
+template <typename T>
+void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const int* bnd, int nbnd, int mode,
+                       T* dinv);
+template <typename T>
+void launch_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* fnod, T* b);
+template <typename T>
+void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc);
+template <typename T>
+void launch_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, const T* xc, T* xf,
+                    bool add, bool skip_boundary);
+template <typename T>
+void launch_inject_boundary(hipStream_t s, const Geom& gf, const Geom& gc, const T* xf, T* xc);
+template <typename T>
+void launch_copy_boundary(hipStream_t s, const Geom& g, const T* src, T* dst);
+template <typename T>
+void launch_from_lattice(hipStream_t s, const Geom& g, const double* src, T* dst);
+template <typename T>
+void launch_to_lattice(hipStream_t s, const Geom& g, const T* src, double* dst);
+// sum over pressure nodes of (weights per class) * p, or of p^2, into out[slot]
+template <typename T>
+void launch_psum(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* p, double* partial, double* out,
+                 int mode);
+template <typename T>
+void launch_pshift(hipStream_t s, const Geom& g, T* p, const double* sums, int mode);
+template <typename T>
+void launch_vsumsq(hipStream_t s, const Geom& g, const T* x, int nwords, double* partial, double* out);
+void launch_coarse(hipStream_t s, const Geom& g, const double* Kp, const int* unk, int nunk, const double* r,
+                   double* x, const double* mweights);
+template <typename T>
+void launch_scale(hipStream_t s, T* x, size_t n, const double* sums, int slot);
+template <typename T>
+void launch_fill(hipStream_t s, T* x, size_t n, T v);
+template <typename T>
+void launch_scaled_copy(hipStream_t s, T* y, const T* x, const T* d, size_t n, T a);
+template <typename T>
+void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a);
+
+constexpr int kPartials = 1024;   // reduction partial slots
+
+}  // namespace hhg

@@ -1,0 +1,819 @@
+// HIP kernels of libhhg for gfx950: matrix-free stencil application,
+// multicolour Gauss-Seidel, Uzawa pressure step, grid transfer, reductions.
+//
+// Data layout (see include/hhg.h): every lattice array has nn = (N+1)^3 words
+// indexed i + n1 (j + n1 k); one thread per array index, consecutive threads
+// along i, so every stencil neighbour load of a wavefront is a contiguous run.
+// Stencil weights are constant per row type (paper Sec. 2.1) and are read from
+// small device tables with wavefront-uniform addresses (scalar loads).
+#include "kernels.h"
+
+namespace hhg {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void decode(int t, int n1, int& i, int& j, int& k) {
+  i = t % n1;
+  const int r = t / n1;
+  j = r % n1;
+  k = r / n1;
+}
+// parity class of velocity group g (0: vertex, 1..7: edge directions)
+__device__ __forceinline__ int gdx(int g) { return (0xB2 >> g) & 1; }
+__device__ __forceinline__ int gdy(int g) { return (0xD4 >> g) & 1; }
+__device__ __forceinline__ int gdz(int g) { return (0xE8 >> g) & 1; }
+
+template <int G>
+__device__ __forceinline__ bool vel_interior(int g, int i, int j, int k, int N) {
+  const int dx = G == 1 ? 0 : gdx(g), dy = G == 1 ? 0 : gdy(g), dz = G == 1 ? 0 : gdz(g);
+  return i >= 1 - dx && j >= 1 - dy && k >= 1 - dz && i <= N - 1 && j <= N - 1 && k <= N - 1;
+}
+// velocity site exists (not padding): doubled position 2(i,j,k) + dir inside [0, 2N]
+template <int G>
+__device__ __forceinline__ bool vel_exists(int g, int i, int j, int k, int N) {
+  if (G == 1) return true;
+  return i + gdx(g) <= N && j + gdy(g) <= N && k + gdz(g) <= N;
+}
+__device__ __forceinline__ int bcls3(int c, int N) { return c == 0 ? 0 : (c == N ? 2 : 1); }
+
+unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------- apply
+// y = [b -] op x on velocity rows of every group at (i,j,k) and on interior
+// pressure rows.  opmask bits: 1 A, 2 B^T, 4 B, 8 -C (the block of calA),
+// 16: +C instead (the matrix C alone).
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_apply(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
+                                                  const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                                  int vel_rows, int p_rows) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  int i, j, k;
+  decode(t, g.n1, i, j, k);
+  const int N = g.N;
+  const T* __restrict__ u0 = x;
+  const T* __restrict__ u1 = x + g.vstride;
+  const T* __restrict__ u2 = x + 2 * g.vstride;
+  const T* __restrict__ p = x + 3 * g.vstride;
+  if (vel_rows) {
+#pragma unroll
+    for (int gr = 0; gr < G; ++gr) {
+      const bool in = vel_interior<G>(gr, i, j, k, N);
+      const int pos = gr * g.nn + t;
+      T a0 = 0, a1 = 0, a2 = 0;
+      if (in) {
+        if (opmask & 1) {
+          const int n = tb->A[gr].n;
+          const int* __restrict__ off = tb->A[gr].off;
+          const T* __restrict__ w = tb->A[gr].w;
+          for (int e = 0; e < n; ++e) {
+            const int o = pos + off[e];
+            const T we = w[e];
+            a0 += we * u0[o];
+            a1 += we * u1[o];
+            a2 += we * u2[o];
+          }
+        }
+        if (opmask & 2) {
+          const int n = tb->BT[gr].n;
+          const int* __restrict__ off = tb->BT[gr].off;
+          const T* __restrict__ w = tb->BT[gr].w;
+          for (int e = 0; e < n; ++e) {
+            const T pv = p[t + off[e]];
+            a0 += w[3 * e] * pv;
+            a1 += w[3 * e + 1] * pv;
+            a2 += w[3 * e + 2] * pv;
+          }
+        }
+      }
+      T r0 = a0, r1 = a1, r2 = a2;
+      if (has_b) {
+        r0 = in ? b[pos] - a0 : T(0);
+        r1 = in ? b[g.vstride + pos] - a1 : T(0);
+        r2 = in ? b[2 * g.vstride + pos] - a2 : T(0);
+      }
+      y[pos] = r0;
+      y[g.vstride + pos] = r1;
+      y[2 * g.vstride + pos] = r2;
+    }
+  }
+  if (p_rows && i >= 1 && j >= 1 && k >= 1 && i <= N - 1 && j <= N - 1 && k <= N - 1) {
+    T acc = 0;
+    if (opmask & 4) {
+      const int n = tb->B[kInteriorClass].n;
+      const int* __restrict__ off = tb->B[kInteriorClass].off;
+      const T* __restrict__ w = tb->B[kInteriorClass].w;
+      for (int e = 0; e < n; ++e) {
+        const int o = t + off[e];
+        acc += w[3 * e] * u0[o] + w[3 * e + 1] * u1[o] + w[3 * e + 2] * u2[o];
+      }
+    }
+    if (opmask & 8) {
+      const int n = tb->C[kInteriorClass].n;
+      const int* __restrict__ off = tb->C[kInteriorClass].off;
+      const T* __restrict__ w = tb->C[kInteriorClass].w;
+      T c = 0;
+      for (int e = 0; e < n; ++e) c += w[e] * p[t + off[e]];
+      acc += (opmask & 16) ? c : -c;
+    }
+    const int pp = 3 * g.vstride + t;
+    y[pp] = has_b ? b[pp] - acc : acc;
+  }
+}
+
+// Pressure rows at boundary nodes (list), boundary-class stencils.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                                     const int* __restrict__ bnd, int nb) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nb) return;
+  const int node = bnd[t];
+  int i, j, k;
+  decode(node, g.n1, i, j, k);
+  const int cls = bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N);
+  const T* u0 = x;
+  const T* u1 = x + g.vstride;
+  const T* u2 = x + 2 * g.vstride;
+  const T* p = x + 3 * g.vstride;
+  T acc = 0;
+  if (opmask & 4) {
+    const DStencil<T> s = tb->B[cls];
+    for (int e = 0; e < s.n; ++e) {
+      const int o = node + s.off[e];
+      acc += s.w[3 * e] * u0[o] + s.w[3 * e + 1] * u1[o] + s.w[3 * e + 2] * u2[o];
+    }
+  }
+  if (opmask & 8) {
+    const DStencil<T> s = tb->C[cls];
+    T c = 0;
+    for (int e = 0; e < s.n; ++e) c += s.w[e] * p[node + s.off[e]];
+    acc += (opmask & 16) ? c : -c;
+  }
+  const int pp = 3 * g.vstride + node;
+  y[pp] = has_b ? b[pp] - acc : acc;
+}
+
+// ---------------------------------------------------------- Gauss-Seidel
+// One colour of the vertex group: interior nodes with (i+j+k) mod 4 == c.
+// u_d += (f_d - (A u_d) - (B^T p)_d) / a_gg for the three components.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, const Tables<T>* __restrict__ tb, T* __restrict__ x,
+                                                      const T* __restrict__ b, int c) {
+  const int N = g.N, nr = N - 1, ni = (nr + 3) >> 2;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= ni * nr * nr) return;
+  const int ip = t % ni, row = t / ni;
+  const int j = 1 + row % nr, k = 1 + row / nr;
+  const int i = 1 + ((((c - 1 - j - k) % 4) + 4) & 3) + 4 * ip;
+  if (i > N - 1) return;
+  const int pos = i + g.n1 * (j + g.n1 * k);
+  T* u0 = x;
+  T* u1 = x + g.vstride;
+  T* u2 = x + 2 * g.vstride;
+  const T* p = x + 3 * g.vstride;
+  T a0 = b[pos], a1 = b[g.vstride + pos], a2 = b[2 * g.vstride + pos];
+  {
+    const int n = tb->A[0].n;
+    const int* __restrict__ off = tb->A[0].off;
+    const T* __restrict__ w = tb->A[0].w;
+    for (int e = 0; e < n; ++e) {
+      const int o = pos + off[e];
+      const T we = w[e];
+      a0 -= we * u0[o];
+      a1 -= we * u1[o];
+      a2 -= we * u2[o];
+    }
+  }
+  {
+    const int n = tb->BT[0].n;
+    const int* __restrict__ off = tb->BT[0].off;
+    const T* __restrict__ w = tb->BT[0].w;
+    for (int e = 0; e < n; ++e) {
+      const T pv = p[pos + off[e]];
+      a0 -= w[3 * e] * pv;
+      a1 -= w[3 * e + 1] * pv;
+      a2 -= w[3 * e + 2] * pv;
+    }
+  }
+  const T di = tb->adiag_inv[0];
+  u0[pos] += a0 * di;
+  u1[pos] += a1 * di;
+  u2[pos] += a2 * di;
+}
+
+// One edge group (one colour) of the P2 velocity: all interior sites of group gr.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, const Tables<T>* __restrict__ tb, T* __restrict__ x,
+                                                    const T* __restrict__ b, int gr) {
+  const int N = g.N;
+  const int dx = gdx(gr), dy = gdy(gr), dz = gdz(gr);
+  const int cx = N - 1 + dx, cy = N - 1 + dy, cz = N - 1 + dz;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= cx * cy * cz) return;
+  const int i = 1 - dx + t % cx;
+  const int r = t / cx;
+  const int j = 1 - dy + r % cy;
+  const int k = 1 - dz + r / cy;
+  const int idx = i + g.n1 * (j + g.n1 * k);
+  const int pos = gr * g.nn + idx;
+  T* u0 = x;
+  T* u1 = x + g.vstride;
+  T* u2 = x + 2 * g.vstride;
+  const T* p = x + 3 * g.vstride;
+  T a0 = b[pos], a1 = b[g.vstride + pos], a2 = b[2 * g.vstride + pos];
+  {
+    const int n = tb->A[gr].n;
+    const int* __restrict__ off = tb->A[gr].off;
+    const T* __restrict__ w = tb->A[gr].w;
+    for (int e = 0; e < n; ++e) {
+      const int o = pos + off[e];
+      const T we = w[e];
+      a0 -= we * u0[o];
+      a1 -= we * u1[o];
+      a2 -= we * u2[o];
+    }
+  }
+  {
+    const int n = tb->BT[gr].n;
+    const int* __restrict__ off = tb->BT[gr].off;
+    const T* __restrict__ w = tb->BT[gr].w;
+    for (int e = 0; e < n; ++e) {
+      const T pv = p[idx + off[e]];
+      a0 -= w[3 * e] * pv;
+      a1 -= w[3 * e + 1] * pv;
+      a2 -= w[3 * e + 2] * pv;
+    }
+  }
+  const T di = tb->adiag_inv[gr];
+  u0[pos] += a0 * di;
+  u1[pos] += a1 * di;
+  u2[pos] += a2 * di;
+}
+
+// p <- p - omega * dinv * rp (eq. uzawa-pressure with S_hat = omega^{-1} D).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pstep(int nn, const T* __restrict__ dinv, T* __restrict__ p,
+                                                  const T* __restrict__ rp, T omega) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nn) return;
+  p[t] -= omega * dinv[t] * rp[t];
+}
+
+// Schur diagonal per pressure node: mode 0: C_kk + sum_d sum_{j interior}
+// B_dkj^2 / A_jj; mode 1: int psi_k.  Writes 1 / D_k.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_schur_diag(Geom g, const Tables<T>* __restrict__ tb, int mode,
+                                                       T* __restrict__ dinv) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  int i, j, k;
+  decode(t, g.n1, i, j, k);
+  const int N = g.N;
+  const int cls = bcls3(i, N) + 3 * bcls3(j, N) + 9 * bcls3(k, N);
+  double d = 0.0;
+  if (mode == 1) {
+    d = (double)tb->mclass[cls];
+  } else {
+    const DStencil<T> c = tb->C[cls];
+    for (int e = 0; e < c.n; ++e)
+      if (c.off[e] == 0) d += (double)c.w[e];
+    const DStencil<T> s = tb->B[cls];
+    const int* code = tb->Bcode[cls];
+    for (int e = 0; e < s.n; ++e) {
+      const int cc = code[e];
+      const int gr = cc & 15;
+      const int ii = i + ((cc >> 4) & 15) - 2, jj = j + ((cc >> 8) & 15) - 2, kk = k + ((cc >> 12) & 15) - 2;
+      if (!vel_interior<G>(gr, ii, jj, kk, N)) continue;
+      const double w0 = s.w[3 * e], w1 = s.w[3 * e + 1], w2 = s.w[3 * e + 2];
+      d += (w0 * w0 + w1 * w1 + w2 * w2) * (double)tb->adiag_inv[gr];
+    }
+  }
+  dinv[t] = (T)(1.0 / d);
+}
+
+// b = M f on interior velocity rows (velocity mass, interior stencil), 0 on
+// boundary rows and on the pressure part.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_rhs(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ f,
+                                                T* __restrict__ b) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  int i, j, k;
+  decode(t, g.n1, i, j, k);
+#pragma unroll
+  for (int gr = 0; gr < G; ++gr) {
+    const bool in = vel_interior<G>(gr, i, j, k, g.N);
+    const int pos = gr * g.nn + t;
+    T a0 = 0, a1 = 0, a2 = 0;
+    if (in) {
+      const DStencil<T> s = tb->Mv[gr];
+      for (int e = 0; e < s.n; ++e) {
+        const int o = pos + s.off[e];
+        a0 += s.w[e] * f[o];
+        a1 += s.w[e] * f[g.vstride + o];
+        a2 += s.w[e] * f[2 * g.vstride + o];
+      }
+    }
+    b[pos] = a0;
+    b[g.vstride + pos] = a1;
+    b[2 * g.vstride + pos] = a2;
+  }
+  b[3 * g.vstride + t] = 0;
+}
+
+// ---------------------------------------------------------------- transfer
+// Restriction (transpose of the prolongation): coarse thread gathers fine values.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const TransferTables<T>* __restrict__ tt,
+                                                     const T* __restrict__ rf, T* __restrict__ rc) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gc.nn) return;
+  int i, j, k;
+  decode(t, gc.n1, i, j, k);
+  const int fbase = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
+#pragma unroll
+  for (int gr = 0; gr < G; ++gr) {
+    const bool in = vel_interior<G>(gr, i, j, k, gc.N);
+    T a0 = 0, a1 = 0, a2 = 0;
+    if (in) {
+      const int n = tt->r[gr].n;
+      const int* __restrict__ off = tt->r[gr].off;
+      const T* __restrict__ w = tt->r[gr].w;
+      for (int e = 0; e < n; ++e) {
+        const int o = fbase + off[e];
+        a0 += w[e] * rf[o];
+        a1 += w[e] * rf[gf.vstride + o];
+        a2 += w[e] * rf[2 * gf.vstride + o];
+      }
+    }
+    const int pos = gr * gc.nn + t;
+    rc[pos] = a0;
+    rc[gc.vstride + pos] = a1;
+    rc[2 * gc.vstride + pos] = a2;
+  }
+  // pressure: linear restriction, clipped at the domain boundary
+  T acc = 0;
+  const int Nf = gf.N;
+  const int n = tt->rp.n;
+  for (int e = 0; e < n; ++e) {
+    const int cd = tt->rp_d[e];
+    const int fi = 2 * i + (cd & 15) - 2, fj = 2 * j + ((cd >> 4) & 15) - 2, fk = 2 * k + ((cd >> 8) & 15) - 2;
+    if (fi < 0 || fj < 0 || fk < 0 || fi > Nf || fj > Nf || fk > Nf) continue;
+    acc += tt->rp.w[e] * rf[3 * gf.vstride + fbase + tt->rp.off[e]];
+  }
+  rc[3 * gc.vstride + t] = acc;
+}
+
+// Prolongation: fine thread evaluates the coarse function at its sites.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
+                                                    const T* __restrict__ xc, T* __restrict__ xf, int add,
+                                                    int skip_boundary) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gf.nn) return;
+  int i, j, k;
+  decode(t, gf.n1, i, j, k);
+  const int Nf = gf.N;
+#pragma unroll
+  for (int gr = 0; gr < G; ++gr) {
+    if (!vel_exists<G>(gr, i, j, k, Nf)) continue;
+    if (skip_boundary && !vel_interior<G>(gr, i, j, k, Nf)) continue;
+    int cls, base;
+    if (G == 1) {
+      cls = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+      base = (i >> 1) + gc.n1 * ((j >> 1) + gc.n1 * (k >> 1));
+    } else {
+      const int X = 2 * i + gdx(gr), Y = 2 * j + gdy(gr), Z = 2 * k + gdz(gr);
+      cls = (X & 3) + 4 * (Y & 3) + 16 * (Z & 3);
+      base = (X >> 2) + gc.n1 * ((Y >> 2) + gc.n1 * (Z >> 2));
+    }
+    const int n = tt->vp_n[cls];
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int e = 0; e < n; ++e) {
+      const int o = base + tt->vp_off[cls * 10 + e];
+      const T w = tt->vp_w[cls * 10 + e];
+      a0 += w * xc[o];
+      a1 += w * xc[gc.vstride + o];
+      a2 += w * xc[2 * gc.vstride + o];
+    }
+    const int pos = gr * gf.nn + t;
+    if (add) {
+      xf[pos] += a0;
+      xf[gf.vstride + pos] += a1;
+      xf[2 * gf.vstride + pos] += a2;
+    } else {
+      xf[pos] = a0;
+      xf[gf.vstride + pos] = a1;
+      xf[2 * gf.vstride + pos] = a2;
+    }
+  }
+  const int cls = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+  const int base = (i >> 1) + gc.n1 * ((j >> 1) + gc.n1 * (k >> 1));
+  T a = 0;
+  const int n = tt->pp_n[cls];
+  for (int e = 0; e < n; ++e) a += tt->pp_w[cls * 10 + e] * xc[3 * gc.vstride + base + tt->pp_off[cls * 10 + e]];
+  const int pp = 3 * gf.vstride + t;
+  xf[pp] = add ? xf[pp] + a : a;
+}
+
+// Boundary velocity values of the coarse level from the coincident fine nodes.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_inject_boundary(Geom gf, Geom gc, const T* __restrict__ xf,
+                                                            T* __restrict__ xc) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gc.nn) return;
+  int i, j, k;
+  decode(t, gc.n1, i, j, k);
+#pragma unroll
+  for (int gr = 0; gr < G; ++gr) {
+    if (!vel_exists<G>(gr, i, j, k, gc.N) || vel_interior<G>(gr, i, j, k, gc.N)) continue;
+    int fi, fj, fk;
+    if (G == 1) {
+      fi = 2 * i, fj = 2 * j, fk = 2 * k;
+    } else {  // coarse doubled position S -> fine vertex index S
+      fi = 2 * i + gdx(gr), fj = 2 * j + gdy(gr), fk = 2 * k + gdz(gr);
+    }
+    const int fpos = fi + gf.n1 * (fj + gf.n1 * fk);
+    const int pos = gr * gc.nn + t;
+    xc[pos] = xf[fpos];
+    xc[gc.vstride + pos] = xf[gf.vstride + fpos];
+    xc[2 * gc.vstride + pos] = xf[2 * gf.vstride + fpos];
+  }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_copy_boundary(Geom g, const T* __restrict__ src, T* __restrict__ dst) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  int i, j, k;
+  decode(t, g.n1, i, j, k);
+#pragma unroll
+  for (int gr = 0; gr < G; ++gr) {
+    if (!vel_exists<G>(gr, i, j, k, g.N) || vel_interior<G>(gr, i, j, k, g.N)) continue;
+    const int pos = gr * g.nn + t;
+    dst[pos] = src[pos];
+    dst[g.vstride + pos] = src[g.vstride + pos];
+    dst[2 * g.vstride + pos] = src[2 * g.vstride + pos];
+  }
+}
+
+// ------------------------------------------------------------ conversions
+// Plain lattice order: velocity components over (M+1)^3, M = N (P1) or 2N (P2),
+// then pressure over (N+1)^3.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_lattice(Geom g, const double* __restrict__ lat, T* __restrict__ vec,
+                                                    double* __restrict__ lat_out, const T* __restrict__ vec_in,
+                                                    int to_lattice) {
+  const int M = G == 1 ? g.N : 2 * g.N;
+  const int m1 = M + 1;
+  const long nv = (long)m1 * m1 * m1;
+  const long tot = 3 * nv + g.nn;
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= tot) return;
+  long vpos;
+  if (t < 3 * nv) {
+    const int d = (int)(t / nv);
+    const int s = (int)(t % nv);
+    const int X = s % m1, r = s / m1, Y = r % m1, Z = r / m1;
+    int gr = 0, i = X, j = Y, k = Z;
+    if (G == 8) {
+      const int par = (X & 1) | ((Y & 1) << 1) | ((Z & 1) << 2);
+      // parity bits (x | y<<1 | z<<2) -> group index: only 3 <-> 4 differ
+      gr = par == 3 ? 4 : (par == 4 ? 3 : par);
+      i = X >> 1, j = Y >> 1, k = Z >> 1;
+    }
+    vpos = (long)d * g.vstride + (long)gr * g.nn + i + (long)g.n1 * (j + (long)g.n1 * k);
+  } else {
+    vpos = 3L * g.vstride + (t - 3 * nv);
+  }
+  if (to_lattice)
+    lat_out[t] = (double)vec_in[vpos];
+  else
+    vec[vpos] = (T)lat[t];
+}
+
+// ------------------------------------------------------------- reductions
+// Block partial sums of pressure quantities.  mode 0: sum m_cls p and sum
+// m_cls (two slots); mode 1: sum p; mode 2: sum p^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_psum(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ p,
+                                                 double* __restrict__ partial, int mode) {
+  __shared__ double sa[kBlock], sb[kBlock];
+  double a = 0.0, bsum = 0.0;
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < g.nn; t += gridDim.x * kBlock) {
+    const double v = (double)p[t];
+    if (mode == 0) {
+      int i, j, k;
+      decode(t, g.n1, i, j, k);
+      const double m = (double)tb->mclass[bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N)];
+      a += m * v;
+      bsum += m;
+    } else if (mode == 1) {
+      a += v;
+    } else {
+      a += v * v;
+    }
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = bsum;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sa[0];
+    partial[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sumsq(const T* __restrict__ x, long n, double* __restrict__ partial) {
+  __shared__ double sa[kBlock];
+  double a = 0.0;
+  for (long t = (long)blockIdx.x * kBlock + threadIdx.x; t < n; t += (long)gridDim.x * kBlock) {
+    const double v = (double)x[t];
+    a += v * v;
+  }
+  sa[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sa[threadIdx.x] += sa[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sa[0];
+    partial[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+// Fixed-order final sum of the block partials into out[0], out[1].
+__global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__ partial, int nparts,
+                                                      double* __restrict__ out) {
+  __shared__ double sa[kBlock], sb[kBlock];
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += kBlock) {
+    a += partial[2 * q];
+    b += partial[2 * q + 1];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sa[0];
+    out[1] = sb[0];
+  }
+}
+
+// mode 0: p -= s0 / s1 (weighted mean); mode 1: p -= s0 / nn (plain mean).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pshift(int nn, T* __restrict__ p, const double* __restrict__ sums,
+                                                   int mode) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nn) return;
+  const double mean = mode == 0 ? sums[0] / sums[1] : sums[0] / (double)nn;
+  p[t] = (T)((double)p[t] - mean);
+}
+
+// x *= 1 / sqrt(sums[slot])
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scale(T* __restrict__ x, long n, const double* __restrict__ sums,
+                                                  int slot) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  x[t] = (T)((double)x[t] / sqrt(sums[slot]));
+}
+
+// y = a * x (.* d if d != nullptr)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scaled_copy(T* __restrict__ y, const T* __restrict__ x,
+                                                        const T* __restrict__ d, long n, T a) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  y[t] = d ? a * x[t] * d[t] : a * x[t];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ x, long n, T v) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_axpy(T* __restrict__ y, const T* __restrict__ x, long n, T a) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) y[t] += a * x[t];
+}
+
+// Coarsest level: x[unk] += Kp r[unk] (one workgroup, unknowns staged in LDS).
+__global__ void __launch_bounds__(kBlock) k_coarse(const double* __restrict__ Kp, const int* __restrict__ unk, int n,
+                                                   const double* __restrict__ r, double* __restrict__ x) {
+  __shared__ double rs[2048];
+  for (int c = threadIdx.x; c < n; c += kBlock) rs[c] = r[unk[c]];
+  __syncthreads();
+  for (int row = threadIdx.x; row < n; row += kBlock) {
+    const double* kr = Kp + (size_t)row * n;
+    double acc = 0.0;
+    for (int c = 0; c < n; ++c) acc += kr[c] * rs[c];
+    x[unk[row]] += acc;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+#define HHG_LAUNCH(kernel, grid, stream, ...) hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__)
+
+template <typename T>
+void launch_apply(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, const T* b, T* y, int opmask,
+                  bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd) {
+  if (g.G == 1)
+    HHG_LAUNCH((k_apply<T, 1>), nblocks(g.nn), s, g, tb, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
+  else
+    HHG_LAUNCH((k_apply<T, 8>), nblocks(g.nn), s, g, tb, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
+  if (p_rows && nbnd > 0) HHG_LAUNCH((k_prow_bnd<T>), nblocks(nbnd), s, g, tb, x, b, y, opmask, (int)has_b, bnd, nbnd);
+}
+
+template <typename T>
+void launch_gs_colour(hipStream_t s, const Geom& g, const Tables<T>* tb, T* x, const T* b, int colour) {
+  const int N = g.N;
+  if (N < 2) return;
+  if (colour < 4) {
+    const int nr = N - 1, ni = (nr + 3) / 4;
+    if (g.G == 1)
+      HHG_LAUNCH((k_gs_vertex<T, 1>), nblocks((size_t)ni * nr * nr), s, g, tb, x, b, colour);
+    else
+      HHG_LAUNCH((k_gs_vertex<T, 8>), nblocks((size_t)ni * nr * nr), s, g, tb, x, b, colour);
+  } else {
+    const int gr = colour - 3;
+    const size_t n = (size_t)(N - 1 + ((0xB2 >> gr) & 1)) * (N - 1 + ((0xD4 >> gr) & 1)) * (N - 1 + ((0xE8 >> gr) & 1));
+    HHG_LAUNCH((k_gs_edge<T>), nblocks(n), s, g, tb, x, b, gr);
+  }
+}
+
+template <typename T>
+void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, const T* rp, T omega) {
+  HHG_LAUNCH((k_pstep<T>), nblocks(g.nn), s, g.nn, dinv, x + 3 * (size_t)g.vstride, rp + 3 * (size_t)g.vstride, omega);
+}
+
+template <typename T>
+void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const int*, int, int mode, T* dinv) {
+  if (g.G == 1)
+    HHG_LAUNCH((k_schur_diag<T, 1>), nblocks(g.nn), s, g, tb, mode, dinv);
+  else
+    HHG_LAUNCH((k_schur_diag<T, 8>), nblocks(g.nn), s, g, tb, mode, dinv);
+}
+
+template <typename T>
+void launch_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* f, T* b) {
+  if (g.G == 1)
+    HHG_LAUNCH((k_rhs<T, 1>), nblocks(g.nn), s, g, tb, f, b);
+  else
+    HHG_LAUNCH((k_rhs<T, 8>), nblocks(g.nn), s, g, tb, f, b);
+}
+
+template <typename T>
+void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc) {
+  if (gc.G == 1)
+    HHG_LAUNCH((k_restrict<T, 1>), nblocks(gc.nn), s, gf, gc, tt, rf, rc);
+  else
+    HHG_LAUNCH((k_restrict<T, 8>), nblocks(gc.nn), s, gf, gc, tt, rf, rc);
+}
+
+template <typename T>
+void launch_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, const T* xc, T* xf,
+                    bool add, bool skip_boundary) {
+  if (gf.G == 1)
+    HHG_LAUNCH((k_prolong<T, 1>), nblocks(gf.nn), s, gc, gf, tt, xc, xf, (int)add, (int)skip_boundary);
+  else
+    HHG_LAUNCH((k_prolong<T, 8>), nblocks(gf.nn), s, gc, gf, tt, xc, xf, (int)add, (int)skip_boundary);
+}
+
+template <typename T>
+void launch_inject_boundary(hipStream_t s, const Geom& gf, const Geom& gc, const T* xf, T* xc) {
+  if (gc.G == 1)
+    HHG_LAUNCH((k_inject_boundary<T, 1>), nblocks(gc.nn), s, gf, gc, xf, xc);
+  else
+    HHG_LAUNCH((k_inject_boundary<T, 8>), nblocks(gc.nn), s, gf, gc, xf, xc);
+}
+
+template <typename T>
+void launch_copy_boundary(hipStream_t s, const Geom& g, const T* src, T* dst) {
+  if (g.G == 1)
+    HHG_LAUNCH((k_copy_boundary<T, 1>), nblocks(g.nn), s, g, src, dst);
+  else
+    HHG_LAUNCH((k_copy_boundary<T, 8>), nblocks(g.nn), s, g, src, dst);
+}
+
+template <typename T>
+static size_t lattice_words(const Geom& g) {
+  const size_t m1 = (g.G == 1 ? g.N : 2 * g.N) + 1;
+  return 3 * m1 * m1 * m1 + (size_t)g.nn;
+}
+
+template <typename T>
+void launch_from_lattice(hipStream_t s, const Geom& g, const double* src, T* dst) {
+  const size_t n = lattice_words<T>(g);
+  if (g.G == 1)
+    HHG_LAUNCH((k_lattice<T, 1>), nblocks(n), s, g, src, dst, nullptr, nullptr, 0);
+  else
+    HHG_LAUNCH((k_lattice<T, 8>), nblocks(n), s, g, src, dst, nullptr, nullptr, 0);
+}
+
+template <typename T>
+void launch_to_lattice(hipStream_t s, const Geom& g, const T* src, double* dst) {
+  const size_t n = lattice_words<T>(g);
+  if (g.G == 1)
+    HHG_LAUNCH((k_lattice<T, 1>), nblocks(n), s, g, nullptr, nullptr, dst, src, 1);
+  else
+    HHG_LAUNCH((k_lattice<T, 8>), nblocks(n), s, g, nullptr, nullptr, dst, src, 1);
+}
+
+static int reduce_grid(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  return (int)(b < (size_t)kPartials ? (b == 0 ? 1 : b) : kPartials);
+}
+
+template <typename T>
+void launch_psum(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* p, double* partial, double* out,
+                 int mode) {
+  const int nb = reduce_grid(g.nn);
+  HHG_LAUNCH((k_psum<T>), nb, s, g, tb, p, partial, mode);
+  HHG_LAUNCH(k_final_sum, 1, s, partial, nb, out);
+}
+
+template <typename T>
+void launch_pshift(hipStream_t s, const Geom& g, T* p, const double* sums, int mode) {
+  HHG_LAUNCH((k_pshift<T>), nblocks(g.nn), s, g.nn, p, sums, mode);
+}
+
+template <typename T>
+void launch_vsumsq(hipStream_t s, const Geom&, const T* x, int nwords, double* partial, double* out) {
+  const int nb = reduce_grid((size_t)nwords);
+  HHG_LAUNCH((k_sumsq<T>), nb, s, x, (long)nwords, partial);
+  HHG_LAUNCH(k_final_sum, 1, s, partial, nb, out);
+}
+
+void launch_coarse(hipStream_t s, const Geom&, const double* Kp, const int* unk, int nunk, const double* r, double* x,
+                   const double*) {
+  HHG_LAUNCH(k_coarse, 1, s, Kp, unk, nunk, r, x);
+}
+
+template <typename T>
+void launch_scale(hipStream_t s, T* x, size_t n, const double* sums, int slot) {
+  HHG_LAUNCH((k_scale<T>), nblocks(n), s, x, (long)n, sums, slot);
+}
+
+template <typename T>
+void launch_scaled_copy(hipStream_t s, T* y, const T* x, const T* d, size_t n, T a) {
+  if (n) HHG_LAUNCH((k_scaled_copy<T>), nblocks(n), s, y, x, d, (long)n, a);
+}
+
+template <typename T>
+void launch_fill(hipStream_t s, T* x, size_t n, T v) {
+  if (n) HHG_LAUNCH((k_fill<T>), nblocks(n), s, x, (long)n, v);
+}
+
+template <typename T>
+void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
+  if (n) HHG_LAUNCH((k_axpy<T>), nblocks(n), s, y, x, (long)n, a);
+}
+
+#define HHG_INSTANTIATE(T)                                                                                          \
+  template void launch_apply<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, const T*, T*, int, bool, bool, \
+                                bool, const int*, int);                                                             \
+  template void launch_gs_colour<T>(hipStream_t, const Geom&, const Tables<T>*, T*, const T*, int);                 \
+  template void launch_pressure_step<T>(hipStream_t, const Geom&, const T*, T*, const T*, T);                       \
+  template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const int*, int, int, T*);         \
+  template void launch_rhs<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                            \
+  template void launch_restrict<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*);  \
+  template void launch_prolong<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*,    \
+                                  bool, bool);                                                                      \
+  template void launch_inject_boundary<T>(hipStream_t, const Geom&, const Geom&, const T*, T*);                     \
+  template void launch_copy_boundary<T>(hipStream_t, const Geom&, const T*, T*);                                    \
+  template void launch_from_lattice<T>(hipStream_t, const Geom&, const double*, T*);                                \
+  template void launch_to_lattice<T>(hipStream_t, const Geom&, const T*, double*);                                  \
+  template void launch_psum<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, double*, double*, int);        \
+  template void launch_pshift<T>(hipStream_t, const Geom&, T*, const double*, int);                                 \
+  template void launch_vsumsq<T>(hipStream_t, const Geom&, const T*, int, double*, double*);                        \
+  template void launch_scale<T>(hipStream_t, T*, size_t, const double*, int);                                       \
+  template void launch_fill<T>(hipStream_t, T*, size_t, T);                                                         \
+  template void launch_scaled_copy<T>(hipStream_t, T*, const T*, const T*, size_t, T);                              \
+  template void launch_axpy<T>(hipStream_t, T*, const T*, size_t, T);
+
+HHG_INSTANTIATE(double)
+HHG_INSTANTIATE(float)
+
+}  // namespace hhg

@@ -1,0 +1,239 @@
+"""Thin ctypes binding of libhhg (include/hhg.h).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name.  Device buffers are passed as torch CUDA tensors (or raw
+integer addresses); a non-zero status raises HHGError with the library's
+message.  Loading fails loudly when libhhg.so has not been built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhhg.so")
+
+HHG_OK, HHG_ERR_ARG, HHG_ERR_PREC, HHG_ERR_HIP, HHG_ERR_OOM, HHG_ERR_NOT_CONVERGED, HHG_ERR_STATE = range(7)
+HHG_P1P1, HHG_P2P1 = 0, 1
+HHG_F64, HHG_F32 = 0, 1
+HHG_OP_FULL, HHG_OP_A, HHG_OP_BT, HHG_OP_B, HHG_OP_C, HHG_OP_MASS = range(6)
+HHG_GS_FWD, HHG_GS_SYM = 0, 1
+HHG_SCHUR_SD, HHG_SCHUR_ML = 0, 1
+
+SYMBOLS = [
+    "hhg_ctx_create", "hhg_ctx_set_stream", "hhg_ctx_destroy", "hhg_last_error",
+    "hhg_hier_create", "hhg_hier_destroy", "hhg_vec_layout", "hhg_vec_from_lattice", "hhg_vec_to_lattice",
+    "hhg_apply", "hhg_residual", "hhg_rhs", "hhg_smooth", "hhg_restrict", "hhg_prolong_add",
+    "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
+    "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation",
+]
+
+
+class HHGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libhhg status {status}: {msg}")
+        self.status = status
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("nu_inc", ctypes.c_int),
+                ("kappa", ctypes.c_int), ("gs", ctypes.c_int), ("xi", ctypes.c_int),
+                ("omega_inv", ctypes.c_double), ("extra_cycles", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("res_u", ctypes.c_double), ("res_p", ctypes.c_double),
+                ("rel_res", ctypes.c_double), ("work_units", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhhg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "hhg_ctx_create": [I, P, P],
+        "hhg_ctx_set_stream": [P, P],
+        "hhg_ctx_destroy": [P],
+        "hhg_hier_create": [P, I, I, I, I, I, P],
+        "hhg_hier_destroy": [P],
+        "hhg_vec_layout": [P, I, P, P, P, P],
+        "hhg_vec_from_lattice": [P, I, P, P, I],
+        "hhg_vec_to_lattice": [P, I, P, P, I],
+        "hhg_apply": [P, I, I, P, P, I],
+        "hhg_residual": [P, I, P, P, P, I],
+        "hhg_rhs": [P, I, P, P, I],
+        "hhg_smooth": [P, I, P, P, I, I, I, D, I],
+        "hhg_restrict": [P, I, P, P, I],
+        "hhg_prolong_add": [P, I, P, P, I],
+        "hhg_coarse_solve": [P, P, P, I],
+        "hhg_project_mean_zero": [P, I, P, I],
+        "hhg_copy_boundary": [P, I, P, P, I],
+        "hhg_estimate_omega": [P, I, P, I, P],
+        "hhg_norms": [P, I, P, P, P, I],
+        "hhg_vcycle": [P, I, P, P, P],
+        "hhg_fmg_solve": [P, P, P, P, P],
+        "hhg_query_stencil": [I, ctypes.c_char, I, I, I, I, I, I, P, P, P],
+        "hhg_query_interpolation": [I, I, I, I, I, P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = I
+    lib.hhg_last_error.argtypes = []
+    lib.hhg_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, ctypes.c_void_p):
+        return x.value
+    return ctypes.cast(x, ctypes.c_void_p).value
+
+
+def _check(st):
+    if st != HHG_OK:
+        raise HHGError(st, load().hhg_last_error().decode())
+
+
+def hhg_last_error():
+    return load().hhg_last_error().decode()
+
+
+def hhg_ctx_create(device=0, stream=None):
+    out = ctypes.c_void_p()
+    _check(load().hhg_ctx_create(device, _ptr(stream), ctypes.byref(out)))
+    return out
+
+
+def hhg_ctx_set_stream(ctx, stream):
+    _check(load().hhg_ctx_set_stream(ctx, _ptr(stream)))
+
+
+def hhg_ctx_destroy(ctx):
+    _check(load().hhg_ctx_destroy(ctx))
+
+
+def hhg_hier_create(ctx, disc, macro_refine, lmin, lmax, schur=HHG_SCHUR_SD):
+    out = ctypes.c_void_p()
+    _check(load().hhg_hier_create(ctx, disc, macro_refine, lmin, lmax, schur, ctypes.byref(out)))
+    return out
+
+
+def hhg_hier_destroy(h):
+    _check(load().hhg_hier_destroy(h))
+
+
+def hhg_vec_layout(h, level):
+    N = ctypes.c_int()
+    nn, vw, lw = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().hhg_vec_layout(h, level, ctypes.byref(N), ctypes.byref(nn), ctypes.byref(vw), ctypes.byref(lw)))
+    return N.value, nn.value, vw.value, lw.value
+
+
+def hhg_vec_from_lattice(h, level, src, dst, prec=HHG_F64):
+    _check(load().hhg_vec_from_lattice(h, level, _ptr(src), _ptr(dst), prec))
+
+
+def hhg_vec_to_lattice(h, level, src, dst, prec=HHG_F64):
+    _check(load().hhg_vec_to_lattice(h, level, _ptr(src), _ptr(dst), prec))
+
+
+def hhg_apply(h, level, op, x, y, prec=HHG_F64):
+    _check(load().hhg_apply(h, level, op, _ptr(x), _ptr(y), prec))
+
+
+def hhg_residual(h, level, x, b, r, prec=HHG_F64):
+    _check(load().hhg_residual(h, level, _ptr(x), _ptr(b), _ptr(r), prec))
+
+
+def hhg_rhs(h, level, f, b, prec=HHG_F64):
+    _check(load().hhg_rhs(h, level, _ptr(f), _ptr(b), prec))
+
+
+def hhg_smooth(h, level, x, b, iters, gs, xi, omega_inv, prec=HHG_F64):
+    _check(load().hhg_smooth(h, level, _ptr(x), _ptr(b), iters, gs, xi, float(omega_inv), prec))
+
+
+def hhg_restrict(h, fine_level, rf, rc, prec=HHG_F64):
+    _check(load().hhg_restrict(h, fine_level, _ptr(rf), _ptr(rc), prec))
+
+
+def hhg_prolong_add(h, coarse_level, xc, xf, prec=HHG_F64):
+    _check(load().hhg_prolong_add(h, coarse_level, _ptr(xc), _ptr(xf), prec))
+
+
+def hhg_coarse_solve(h, x, b, prec=HHG_F64):
+    _check(load().hhg_coarse_solve(h, _ptr(x), _ptr(b), prec))
+
+
+def hhg_project_mean_zero(h, level, x, prec=HHG_F64):
+    _check(load().hhg_project_mean_zero(h, level, _ptr(x), prec))
+
+
+def hhg_copy_boundary(h, level, src, dst, prec=HHG_F64):
+    _check(load().hhg_copy_boundary(h, level, _ptr(src), _ptr(dst), prec))
+
+
+def hhg_estimate_omega(h, level, v0, iters=100):
+    out = ctypes.c_double()
+    _check(load().hhg_estimate_omega(h, level, _ptr(v0), iters, ctypes.byref(out)))
+    return out.value
+
+
+def hhg_norms(h, level, x, prec=HHG_F64):
+    nu, np_ = ctypes.c_double(), ctypes.c_double()
+    _check(load().hhg_norms(h, level, _ptr(x), ctypes.byref(nu), ctypes.byref(np_), prec))
+    return nu.value, np_.value
+
+
+def solver_params(nu_pre, nu_post, nu_inc, kappa, gs, xi, omega_inv, extra_cycles=0, rtol=0.0, max_cycles=100):
+    return SolverParams(nu_pre, nu_post, nu_inc, kappa, gs, xi, float(omega_inv), extra_cycles, float(rtol),
+                        max_cycles)
+
+
+def hhg_vcycle(h, level, x, b, prm):
+    _check(load().hhg_vcycle(h, level, _ptr(x), _ptr(b), ctypes.byref(prm)))
+
+
+def hhg_fmg_solve(h, x, b_levels, prm, want_stats=True):
+    arr = (ctypes.c_void_p * len(b_levels))(*[_ptr(b) for b in b_levels])
+    st = Stats()
+    _check(load().hhg_fmg_solve(h, _ptr(x), arr, ctypes.byref(prm), ctypes.byref(st) if want_stats else None))
+    return st
+
+
+def hhg_query_stencil(disc, kind, group, i, j, k, nbox, max_entries=256):
+    """Host-only: the library's row stencil at h = 1 as (codes (n, 4), weights (n, 3))."""
+    import numpy as np
+    n = ctypes.c_int()
+    code = (ctypes.c_int * (4 * max_entries))()
+    w = (ctypes.c_double * (3 * max_entries))()
+    _check(load().hhg_query_stencil(disc, kind.encode() if isinstance(kind, str) else kind, group, i, j, k, nbox,
+                                    max_entries, ctypes.byref(n), code, w))
+    m = n.value
+    return np.array(code[:4 * m]).reshape(m, 4), np.array(w[:3 * m]).reshape(m, 3)
+
+
+def hhg_query_interpolation(order, tx, ty, tz, q):
+    """Host-only: interpolation weights at (tx, ty, tz)/q in a coarse cube."""
+    import numpy as np
+    n = ctypes.c_int()
+    code = (ctypes.c_int * 40)()
+    w = (ctypes.c_double * 10)()
+    _check(load().hhg_query_interpolation(order, tx, ty, tz, q, ctypes.byref(n), code, w))
+    m = n.value
+    return np.array(code[:4 * m]).reshape(m, 4), np.array(w[:m])

@@ -1,0 +1,158 @@
+"""CPU tests of the HIP library's host side (no device needed): the C ABI
+loads and exports every declared symbol, and the stencil / interpolation
+tables the library builds on the host equal the oracle's assembled rows."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fe, mesh, transfer
+from paper_2010_13513_amd import hhg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+P1, P2 = hhg.HHG_P1P1, hhg.HHG_P2P1
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "hhg.h")).read()
+    return sorted(set(re.findall(r"\b(hhg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hhg.load()
+    decl = _declared_symbols()
+    assert len(decl) >= 20
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(hhg.SYMBOLS) == set(decl)
+
+
+def _oracle_row(lev, which, row, vorder_row_p2):
+    """Row of an oracle block as {(group, di, dj, dk): weights}."""
+    N = lev.N
+    out = {}
+    if which in ("A", "M"):
+        Mx = lev.A if which == "A" else lev.M
+        r = Mx.getrow(row)
+        cen = lev.vcoords[row]
+        for c, v in zip(r.indices, r.data):
+            pos = lev.vcoords[c]
+            key = _vkey(pos, cen, lev.vorder)
+            out[key] = np.array([v, 0, 0])
+    elif which == "T":
+        cen = lev.vcoords[row]
+        for d in range(3):
+            col = lev.B[d][:, row].tocoo()
+            for k, v in zip(col.row, col.data):
+                pos = lev.pcoords[k]
+                base = cen // 2 if lev.vorder == 2 else cen
+                key = (0,) + tuple(int(a) for a in pos - base)
+                out.setdefault(key, np.zeros(3))[d] += v
+    elif which == "B":
+        cen = lev.pcoords[row]
+        for d in range(3):
+            r = lev.B[d].getrow(row)
+            for c, v in zip(r.indices, r.data):
+                pos = lev.vcoords[c]
+                key = _vkey(pos, cen * lev.vorder, lev.vorder)
+                out.setdefault(key, np.zeros(3))[d] += v
+    elif which in ("C", "P"):
+        Mx = lev.C if which == "C" else lev.Mp
+        r = Mx.getrow(row)
+        cen = lev.pcoords[row]
+        for c, v in zip(r.indices, r.data):
+            out[(0,) + tuple(int(a) for a in lev.pcoords[c] - cen)] = np.array([v, 0, 0])
+    return out
+
+
+def _vkey(pos, cen, vorder):
+    if vorder == 1:
+        return (0,) + tuple(int(a) for a in pos - cen)
+    par = tuple(int(a) for a in pos % 2)
+    g = 0 if par == (0, 0, 0) else 1 + mesh.EDGE_DIRS.index(par)
+    return (g,) + tuple(int(a) for a in (pos // 2 - cen // 2))
+
+
+def _lib_row(disc, kind, g, i, j, k, nbox):
+    code, w = hhg.hhg_query_stencil(disc, kind, g, i, j, k, nbox)
+    return {tuple(int(a) for a in c): ww for c, ww in zip(code, w)}
+
+
+def _compare(lib, orc, scale, tol=1e-12):
+    keys = set(lib) | set(orc)
+    mx = max(np.abs(v).max() for v in orc.values())
+    for key in keys:
+        a = lib.get(key, np.zeros(3)) * scale
+        b = orc.get(key, np.zeros(3))
+        assert np.abs(a - b).max() <= tol * mx, (key, a, b)
+
+
+@pytest.mark.parametrize("vorder", [1, 2])
+@pytest.mark.parametrize("kind", ["A", "M", "T"])
+def test_interior_velocity_rows_match_oracle(vorder, kind):
+    N = 6
+    lev = fe.Level(N, vorder)
+    h = 1.0 / N
+    scale = {"A": h, "M": h ** 3, "T": h ** 2}[kind]
+    groups = [0] if vorder == 1 else range(8)
+    for g in groups:
+        i = j = k = 3
+        if vorder == 1:
+            row = mesh.p1_index(N, i, j, k)
+        else:
+            d = (0, 0, 0) if g == 0 else mesh.EDGE_DIRS[g - 1]
+            row = mesh.p2_index(N, 2 * i + d[0], 2 * j + d[1], 2 * k + d[2])
+        lib = _lib_row(P1 if vorder == 1 else P2, kind, g, i, j, k, 64)
+        _compare(lib, _oracle_row(lev, kind, row, vorder), scale)
+
+
+@pytest.mark.parametrize("vorder", [1, 2])
+@pytest.mark.parametrize("kind", ["B", "C", "P"])
+def test_pressure_rows_all_boundary_classes(vorder, kind):
+    if kind == "C" and vorder == 2:
+        pytest.skip("Taylor-Hood has C = 0")
+    N = 4
+    lev = fe.Level(N, vorder)
+    h = 1.0 / N
+    hT2 = (h ** 3 / 6.0) ** (2.0 / 3.0)
+    scale = {"B": h ** 2, "C": fe.DELTA_PSPG * hT2 * h, "P": h ** 3}[kind]
+    for cls in range(27):
+        ci, cj, ck = (0, 2, 4)[cls % 3], (0, 2, 4)[(cls // 3) % 3], (0, 2, 4)[cls // 9]
+        row = mesh.p1_index(N, ci, cj, ck)
+        lib = _lib_row(P1 if vorder == 1 else P2, kind, 0, ci, cj, ck, N)
+        _compare(lib, _oracle_row(lev, kind, row, vorder), scale)
+
+
+@pytest.mark.parametrize("order,q", [(1, 2), (2, 4)])
+def test_interpolation_weights_match_oracle(order, q):
+    """Library interpolation classes vs the oracle's prolongation rows."""
+    Nc = 2
+    P = transfer.prolongation(Nc, order)
+    nf1 = q * Nc + 1
+    ncm = Nc * order          # coarse lattice size in DoF units
+    for tz in range(q + 1):
+        for ty in range(q + 1):
+            for tx in range(q + 1):
+                # fine site inside coarse cube (0,0,0) at offset t / q
+                fi = tx + nf1 * (ty + nf1 * tz)
+                row = P.getrow(fi)
+                orc = {}
+                for c, v in zip(row.indices, row.data):
+                    X = c % (ncm + 1)
+                    Y = (c // (ncm + 1)) % (ncm + 1)
+                    Z = c // (ncm + 1) ** 2
+                    pos = np.array([X, Y, Z])
+                    orc[_vkey(pos, np.zeros(3, int), order)] = np.array([v, 0, 0])
+                code, w = hhg.hhg_query_interpolation(order, tx, ty, tz, q)
+                lib = {tuple(int(a) for a in c): np.array([ww, 0, 0]) for c, ww in zip(code, w)}
+                _compare(lib, orc, 1.0, tol=1e-14)
+
+
+def test_query_rejects_bad_arguments():
+    with pytest.raises(hhg.HHGError):
+        hhg.hhg_query_stencil(7, "A", 0, 1, 1, 1, 4)
+    with pytest.raises(hhg.HHGError):
+        hhg.hhg_query_interpolation(3, 0, 0, 0, 2)
+    with pytest.raises(hhg.HHGError):
+        hhg.hhg_query_stencil(P2, "A", 0, 3, 3, 3, 64, max_entries=4)
