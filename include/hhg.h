@@ -103,7 +103,10 @@ hhg_status hhg_ctx_destroy(hhg_ctx ctx);
 const char* hhg_last_error(void);
 
 /* ------------------------------------------------------------- hierarchy */
-/* Build levels lmin..lmax (lmin is the coarsest, solved directly) of one
+/* Build levels lmin..lmax (lmin is the coarsest, solved directly when it has
+ * at most 2048 unknowns; otherwise hhg_coarse_solve, hhg_vcycle and
+ * hhg_fmg_solve report HHG_ERR_STATE and the hierarchy serves operators and
+ * transfers only) of one
  * discretisation: lattice sizes, stencil weights (computed on the host from
  * the element matrices of the six Kuhn tetrahedra, Sec. 2.1: constant per
  * macro-primitive), the dense pseudo-inverse of the coarsest operator, and
@@ -131,7 +134,9 @@ hhg_status hhg_vec_to_lattice(hhg_hier h, int level, const void* src, double* ds
 /* ------------------------------------------------------------- operators */
 /* y = op x on `level` (eq. stokes-discrete blocks; FULL = calA).  A and BT
  * fill the velocity part of y and zero its pressure part, B and C the
- * reverse.  x and y must not overlap. */
+ * reverse (C = the PSPG matrix, i.e. minus the block of calA).  MASS: the
+ * consistent velocity mass on every velocity DoF (boundary rows included) and
+ * the P1 pressure mass.  x and y must not overlap. */
 hhg_status hhg_apply(hhg_hier h, int level, hhg_op op, const void* x, void* y, hhg_prec prec);
 /* r = b - calA x (Alg. fmg defect; boundary velocity rows zero). */
 hhg_status hhg_residual(hhg_hier h, int level, const void* x, const void* b, void* r, hhg_prec prec);
@@ -165,6 +170,23 @@ hhg_status hhg_copy_boundary(hhg_hier h, int level, const void* src, void* dst, 
  * backward sweep from zero).  v0: caller-drawn start vector on the pressure
  * nodes (device, double, nn words, P1 lattice order).  Synchronous. */
 hhg_status hhg_estimate_omega(hhg_hier h, int level, const double* v0, int iters, double* omega_inv);
+
+/* Dot products x.y of the velocity parts and of the pressure parts
+ * (synchronous); with y = hhg_apply(MASS) of x they are squared M-norms. */
+hhg_status hhg_dots(hhg_hier h, int level, const void* x, const void* y, double* dot_u, double* dot_p,
+                    hhg_prec prec);
+
+/* Kernel event timer (process-wide, for measurement).  hhg_timer_start
+ * enables HIP events around every launch of the kernel families in the mask
+ * (bit f = family f: 0 apply/residual, 1 boundary pressure rows, 2 vertex
+ * Gauss-Seidel colour, 3 edge-group Gauss-Seidel colour, 4 Uzawa pressure
+ * step, 5 restriction, 6 prolongation, 7 coarse solve, 8 reductions, 9 other)
+ * and clears earlier records; mask 0 disables it.  hhg_timer_read synchronises
+ * and returns, for one family since the last read, the summed event time in
+ * ms, the launches and the work units (sites processed: P2 sites or P1
+ * nodes for apply/transfers, updated sites for Gauss-Seidel colours). */
+hhg_status hhg_timer_start(unsigned family_mask);
+hhg_status hhg_timer_read(int family, double* total_ms, int* launches, double* units);
 
 /* Euclidean norms of the velocity and pressure parts of x (synchronous). */
 hhg_status hhg_norms(hhg_hier h, int level, const void* x, double* norm_u, double* norm_p, hhg_prec prec);

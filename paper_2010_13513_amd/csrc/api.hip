@@ -176,6 +176,7 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
   Tables<double> t64{};
   Tables<float> t32{};
   Arena& a = h->arena;
+  const int rep[3] = {0, 2, 4};
   lv.hA.assign(G, {});
   lv.hBT.assign(G, {});
   lv.hB.assign(27, {});
@@ -208,7 +209,6 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
     lv.hA[gr] = A;
     lv.hBT[gr] = BT;
   }
-  const int rep[3] = {0, 2, 4};
   for (int cls = 0; cls < 27; ++cls) {
     const int ci = rep[cls % 3], cj = rep[(cls / 3) % 3], ck = rep[cls / 9];
     HostStencil B, C;
@@ -236,6 +236,32 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
     t32.mclass[cls] = (float)m;
     lv.hB[cls] = B;
     lv.hC[cls] = C;
+  }
+  // full mass rows: velocity groups x boundary classes, pressure classes
+  for (int gr = 0; gr < G; ++gr)
+    for (int cls = 0; cls < 27; ++cls) {
+      const int cc[3] = {cls % 3, (cls / 3) % 3, cls / 9};
+      const int dir[3] = {G == 1 ? 0 : kGroupDir[gr][0], G == 1 ? 0 : kGroupDir[gr][1], G == 1 ? 0 : kGroupDir[gr][2]};
+      bool valid = true;
+      for (int d = 0; d < 3; ++d) valid &= !(dir[d] && cc[d] != 1);
+      HostStencil Mc;
+      if (valid) {
+        for (auto& e : prune(row_stencil(es, 'M', gr, rep[cc[0]], rep[cc[1]], rep[cc[2]], 4), 1)) {
+          Mc.off.push_back((e.g - gr) * nn + lin(e.di, e.dj, e.dk, n1));
+          Mc.w.push_back(e.w[0] * sM);
+        }
+      }
+      t64.Mfull[gr * 27 + cls] = upload_stencil<double>(a, Mc);
+      t32.Mfull[gr * 27 + cls] = upload_stencil<float>(a, Mc);
+    }
+  for (int cls = 0; cls < 27; ++cls) {
+    HostStencil Pc;
+    for (auto& e : prune(row_stencil(es, 'P', 0, rep[cls % 3], rep[(cls / 3) % 3], rep[cls / 9], 4), 1)) {
+      Pc.off.push_back(lin(e.di, e.dj, e.dk, n1));
+      Pc.w.push_back(e.w[0] * sM);
+    }
+    t64.Pm[cls] = upload_stencil<double>(a, Pc);
+    t32.Pm[cls] = upload_stencil<float>(a, Pc);
   }
   lv.dinv64 = a.alloc<double>(nn);
   lv.dinv32 = a.alloc<float>(nn);
@@ -444,7 +470,10 @@ void build_coarse(hhg_hier h) {
         unk.push_back(p);
       }
   const int n = (int)unk.size();
-  HHG_REQUIRE(n <= 2048, HHG_ERR_ARG, "coarsest level too large for the dense coarse solve (max 2048 unknowns)");
+  if (n > 2048) {  // no dense coarse solve: the hierarchy still applies operators and transfers
+    h->nunk = 0;
+    return;
+  }
   std::vector<double> K((size_t)n * n, 0.0);
   auto add = [&](int r, int pos, double w) {
     auto it = pos2u.find(pos);
@@ -544,6 +573,7 @@ void op_prolong(hhg_hier h, int lc, const T* xc, T* xf, bool add, bool skip_bnd)
 }
 
 void op_coarse(hhg_hier h, double* x, const double* b) {
+  HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "coarsest level has more than 2048 unknowns: no dense coarse solve");
   Level& lv = h->L(h->lmin);
   op_apply<double>(h, h->lmin, full_mask(h), x, b, lv.r, true, true, true);
   launch_coarse(S(h), lv.g, h->Kp, h->unk, h->nunk, lv.r, x, nullptr);
@@ -793,7 +823,13 @@ hhg_status hhg_apply(hhg_hier h, int level, hhg_op op, const void* x, void* y, h
       case HHG_OP_BT: mask = 2; break;
       case HHG_OP_B: mask = 4; break;
       case HHG_OP_C: mask = 8 | 16; break;
+      case HHG_OP_MASS: mask = -1; break;
       default: throw Error{HHG_ERR_ARG, "operator not supported"};
+    }
+    if (mask < 0) {
+      HHG_DISPATCH(prec, launch_mass<T>(S(h), lv.g, tables<T>(lv), (const T*)x, (T*)y));
+      HHG_CHECK_HIP(hipGetLastError());
+      return;
     }
     if (op == HHG_OP_C && h->disc == HHG_P2P1) mask = 0;
     HHG_DISPATCH(prec, {
@@ -925,6 +961,38 @@ hhg_status hhg_estimate_omega(hhg_hier h, int level, const double* v0, int iters
     HHG_CHECK_HIP(hipMemcpyAsync(h->hsums, h->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HHG_CHECK_HIP(hipStreamSynchronize(s));
     *omega_inv = std::sqrt(h->hsums[0]);
+  });
+}
+
+hhg_status hhg_dots(hhg_hier h, int level, const void* x, const void* y, double* dot_u, double* dot_p,
+                    hhg_prec prec) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(x && y && dot_u && dot_p, HHG_ERR_ARG, "null argument");
+    Level& lv = h->L(level);
+    const size_t nv = 3 * (size_t)lv.g.vstride;
+    HHG_DISPATCH(prec, {
+      launch_dot<T>(S(h), (const T*)x, (const T*)y, nv, h->partial, h->sums);
+      launch_dot<T>(S(h), (const T*)x + nv, (const T*)y + nv, lv.g.nn, h->partial + 2 * kPartials, h->sums + 2);
+    });
+    HHG_CHECK_HIP(hipMemcpyAsync(h->hsums, h->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, S(h)));
+    HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
+    *dot_u = h->hsums[0];
+    *dot_p = h->hsums[2];
+  });
+}
+
+hhg_status hhg_timer_start(unsigned family_mask) {
+  return guard([&] {
+    timer_set_mask(family_mask);
+    for (int f = 0; f < KF_COUNT; ++f) timer_read(f, nullptr, nullptr, nullptr);
+  });
+}
+
+hhg_status hhg_timer_read(int family, double* total_ms, int* launches, double* units) {
+  return guard([&] {
+    HHG_REQUIRE(family >= 0 && family < KF_COUNT, HHG_ERR_ARG, "unknown kernel family");
+    timer_read(family, total_ms, launches, units);
   });
 }
 

@@ -24,7 +24,28 @@ struct Tables {
   T adiag_inv[8];       // 1 / A_gg
   T mclass[27];         // int psi_k per boundary class
   const T* dinv;        // per pressure node 1 / D_k (Schur diagonal), nn words
+  DStencil<T> Mfull[8 * 27];  // velocity mass rows of every group and boundary class
+  DStencil<T> Pm[27];         // P1 pressure mass rows per boundary class
 };
+
+// Kernel families for the event timer (hhg_timer_*).
+enum KernelFamily {
+  KF_APPLY = 0,     // stencil apply / residual (interior pressure and all velocity rows)
+  KF_PROW_BND = 1,  // boundary pressure rows
+  KF_GS_VERTEX = 2, // Gauss-Seidel colour of the vertex group
+  KF_GS_EDGE = 3,   // Gauss-Seidel colour of one P2 edge group
+  KF_PSTEP = 4,     // Uzawa pressure step
+  KF_RESTRICT = 5,
+  KF_PROLONG = 6,
+  KF_COARSE = 7,
+  KF_REDUCE = 8,
+  KF_OTHER = 9,
+  KF_COUNT = 10
+};
+void timer_set_mask(unsigned mask);
+// Sum of event-measured durations (ms), launches and work units of one family
+// since the last read; synchronises the recorded events.
+void timer_read(int family, double* total_ms, int* launches, double* units);
 
 // Transfer tables between level l-1 (coarse) and l (fine) for one field kind.
 // Prolongation: fine class (S & 3 per coordinate, 64 classes for quadratic,
@@ -58,6 +79,10 @@ void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const 
                        T* dinv);
 template <typename T>
 void launch_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* fnod, T* b);
+template <typename T>
+void launch_mass(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, T* y);
+template <typename T>
+void launch_dot(hipStream_t s, const T* x, const T* y, size_t n, double* partial, double* out);
 template <typename T>
 void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc);
 template <typename T>

@@ -6,6 +6,8 @@
 // along i, so every stencil neighbour load of a wavefront is a contiguous run.
 // Stencil weights are constant per row type (paper Sec. 2.1) and are read from
 // small device tables with wavefront-uniform addresses (scalar loads).
+#include <vector>
+
 #include "kernels.h"
 
 namespace hhg {
@@ -38,6 +40,39 @@ __device__ __forceinline__ bool vel_exists(int g, int i, int j, int k, int N) {
 __device__ __forceinline__ int bcls3(int c, int N) { return c == 0 ? 0 : (c == N ? 2 : 1); }
 
 unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ------------------------------------------------------------ event timer
+struct TimerRec {
+  int fam;
+  hipEvent_t a, b;
+  double units;
+};
+struct Timer {
+  unsigned mask = 0;
+  std::vector<TimerRec> recs;
+};
+Timer& timer() {
+  static Timer t;
+  return t;
+}
+// Records HIP events on the launch stream around one kernel launch when its
+// family is enabled.
+struct KScope {
+  hipStream_t s_;
+  hipEvent_t b_ = nullptr;
+  KScope(hipStream_t s, int fam, double units) : s_(s) {
+    Timer& t = timer();
+    if (!((t.mask >> fam) & 1u)) return;
+    TimerRec r{fam, nullptr, nullptr, units};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, s);
+    b_ = r.b;
+    t.recs.push_back(r);
+  }
+  ~KScope() {
+    if (b_) (void)hipEventRecord(b_, s_);
+  }
+};
 
 // ---------------------------------------------------------------- apply
 // y = [b -] op x on velocity rows of every group at (i,j,k) and on interior
@@ -321,6 +356,66 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Geom g, const Tables<T>* __restr
     b[2 * g.vstride + pos] = a2;
   }
   b[3 * g.vstride + t] = 0;
+}
+
+// y = M x: consistent velocity mass on every velocity site (boundary rows
+// included, boundary-class stencils) and P1 pressure mass on every node.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_mass(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
+                                                 T* __restrict__ y) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  int i, j, k;
+  decode(t, g.n1, i, j, k);
+  const int N = g.N;
+#pragma unroll
+  for (int gr = 0; gr < G; ++gr) {
+    const int pos = gr * g.nn + t;
+    if (!vel_exists<G>(gr, i, j, k, N)) {
+      y[pos] = 0;
+      y[g.vstride + pos] = 0;
+      y[2 * g.vstride + pos] = 0;
+      continue;
+    }
+    const int dx = G == 1 ? 0 : gdx(gr), dy = G == 1 ? 0 : gdy(gr), dz = G == 1 ? 0 : gdz(gr);
+    const int cls = (dx ? 1 : bcls3(i, N)) + 3 * (dy ? 1 : bcls3(j, N)) + 9 * (dz ? 1 : bcls3(k, N));
+    const DStencil<T> st = tb->Mfull[gr * 27 + cls];
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int e = 0; e < st.n; ++e) {
+      const int o = pos + st.off[e];
+      a0 += st.w[e] * x[o];
+      a1 += st.w[e] * x[g.vstride + o];
+      a2 += st.w[e] * x[2 * g.vstride + o];
+    }
+    y[pos] = a0;
+    y[g.vstride + pos] = a1;
+    y[2 * g.vstride + pos] = a2;
+  }
+  const int cls = bcls3(i, N) + 3 * bcls3(j, N) + 9 * bcls3(k, N);
+  const DStencil<T> st = tb->Pm[cls];
+  T a = 0;
+  const T* p = x + 3 * g.vstride;
+  for (int e = 0; e < st.n; ++e) a += st.w[e] * p[t + st.off[e]];
+  y[3 * g.vstride + t] = a;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dot(const T* __restrict__ x, const T* __restrict__ y, long n,
+                                                double* __restrict__ partial) {
+  __shared__ double sa[kBlock];
+  double a = 0.0;
+  for (long t = (long)blockIdx.x * kBlock + threadIdx.x; t < n; t += (long)gridDim.x * kBlock)
+    a += (double)x[t] * (double)y[t];
+  sa[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sa[threadIdx.x] += sa[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sa[0];
+    partial[2 * blockIdx.x + 1] = 0.0;
+  }
 }
 
 // ---------------------------------------------------------------- transfer
@@ -636,14 +731,25 @@ __global__ void __launch_bounds__(kBlock) k_coarse(const double* __restrict__ Kp
 // ---------------------------------------------------------------- launchers
 #define HHG_LAUNCH(kernel, grid, stream, ...) hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__)
 
+static double p_sites(const Geom& g) {
+  const double m = g.G == 1 ? g.N + 1 : 2 * g.N + 1;
+  return m * m * m;
+}
+
 template <typename T>
 void launch_apply(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, const T* b, T* y, int opmask,
                   bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd) {
+  {
+  KScope ks(s, KF_APPLY, p_sites(g));
   if (g.G == 1)
     HHG_LAUNCH((k_apply<T, 1>), nblocks(g.nn), s, g, tb, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
   else
     HHG_LAUNCH((k_apply<T, 8>), nblocks(g.nn), s, g, tb, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
-  if (p_rows && nbnd > 0) HHG_LAUNCH((k_prow_bnd<T>), nblocks(nbnd), s, g, tb, x, b, y, opmask, (int)has_b, bnd, nbnd);
+  }
+  if (p_rows && nbnd > 0) {
+    KScope ks(s, KF_PROW_BND, nbnd);
+    HHG_LAUNCH((k_prow_bnd<T>), nblocks(nbnd), s, g, tb, x, b, y, opmask, (int)has_b, bnd, nbnd);
+  }
 }
 
 template <typename T>
@@ -652,6 +758,14 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const Tables<T>* tb, T* x, c
   if (N < 2) return;
   if (colour < 4) {
     const int nr = N - 1, ni = (nr + 3) / 4;
+    double cnt = 0;
+    if (timer().mask & (1u << KF_GS_VERTEX))
+      for (int k = 1; k <= nr; ++k)
+        for (int j = 1; j <= nr; ++j) {
+          const int i0 = 1 + (((colour - 1 - j - k) % 4) + 4) % 4;
+          if (i0 <= nr) cnt += (nr - i0) / 4 + 1;
+        }
+    KScope ks(s, KF_GS_VERTEX, cnt);
     if (g.G == 1)
       HHG_LAUNCH((k_gs_vertex<T, 1>), nblocks((size_t)ni * nr * nr), s, g, tb, x, b, colour);
     else
@@ -659,12 +773,14 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const Tables<T>* tb, T* x, c
   } else {
     const int gr = colour - 3;
     const size_t n = (size_t)(N - 1 + ((0xB2 >> gr) & 1)) * (N - 1 + ((0xD4 >> gr) & 1)) * (N - 1 + ((0xE8 >> gr) & 1));
+    KScope ks(s, KF_GS_EDGE, (double)n);
     HHG_LAUNCH((k_gs_edge<T>), nblocks(n), s, g, tb, x, b, gr);
   }
 }
 
 template <typename T>
 void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, const T* rp, T omega) {
+  KScope ks(s, KF_PSTEP, g.nn);
   HHG_LAUNCH((k_pstep<T>), nblocks(g.nn), s, g.nn, dinv, x + 3 * (size_t)g.vstride, rp + 3 * (size_t)g.vstride, omega);
 }
 
@@ -685,7 +801,26 @@ void launch_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* f, T
 }
 
 template <typename T>
+void launch_mass(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, T* y) {
+  KScope ks(s, KF_OTHER, p_sites(g));
+  if (g.G == 1)
+    HHG_LAUNCH((k_mass<T, 1>), nblocks(g.nn), s, g, tb, x, y);
+  else
+    HHG_LAUNCH((k_mass<T, 8>), nblocks(g.nn), s, g, tb, x, y);
+}
+
+template <typename T>
+void launch_dot(hipStream_t s, const T* x, const T* y, size_t n, double* partial, double* out) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  const int nb = (int)(b < (size_t)kPartials ? (b == 0 ? 1 : b) : kPartials);
+  KScope ks(s, KF_REDUCE, (double)n);
+  HHG_LAUNCH((k_dot<T>), nb, s, x, y, (long)n, partial);
+  HHG_LAUNCH(k_final_sum, 1, s, partial, nb, out);
+}
+
+template <typename T>
 void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc) {
+  KScope ks(s, KF_RESTRICT, p_sites(gf));
   if (gc.G == 1)
     HHG_LAUNCH((k_restrict<T, 1>), nblocks(gc.nn), s, gf, gc, tt, rf, rc);
   else
@@ -695,6 +830,7 @@ void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const Transf
 template <typename T>
 void launch_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, const T* xc, T* xf,
                     bool add, bool skip_boundary) {
+  KScope ks(s, KF_PROLONG, p_sites(gf));
   if (gf.G == 1)
     HHG_LAUNCH((k_prolong<T, 1>), nblocks(gf.nn), s, gc, gf, tt, xc, xf, (int)add, (int)skip_boundary);
   else
@@ -750,24 +886,28 @@ template <typename T>
 void launch_psum(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* p, double* partial, double* out,
                  int mode) {
   const int nb = reduce_grid(g.nn);
+  KScope ks(s, KF_REDUCE, g.nn);
   HHG_LAUNCH((k_psum<T>), nb, s, g, tb, p, partial, mode);
   HHG_LAUNCH(k_final_sum, 1, s, partial, nb, out);
 }
 
 template <typename T>
 void launch_pshift(hipStream_t s, const Geom& g, T* p, const double* sums, int mode) {
+  KScope ks(s, KF_REDUCE, g.nn);
   HHG_LAUNCH((k_pshift<T>), nblocks(g.nn), s, g.nn, p, sums, mode);
 }
 
 template <typename T>
 void launch_vsumsq(hipStream_t s, const Geom&, const T* x, int nwords, double* partial, double* out) {
   const int nb = reduce_grid((size_t)nwords);
+  KScope ks(s, KF_REDUCE, nwords);
   HHG_LAUNCH((k_sumsq<T>), nb, s, x, (long)nwords, partial);
   HHG_LAUNCH(k_final_sum, 1, s, partial, nb, out);
 }
 
 void launch_coarse(hipStream_t s, const Geom&, const double* Kp, const int* unk, int nunk, const double* r, double* x,
                    const double*) {
+  KScope ks(s, KF_COARSE, nunk);
   HHG_LAUNCH(k_coarse, 1, s, Kp, unk, nunk, r, x);
 }
 
@@ -798,6 +938,8 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
   template void launch_pressure_step<T>(hipStream_t, const Geom&, const T*, T*, const T*, T);                       \
   template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const int*, int, int, T*);         \
   template void launch_rhs<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                            \
+  template void launch_mass<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                           \
+  template void launch_dot<T>(hipStream_t, const T*, const T*, size_t, double*, double*);                           \
   template void launch_restrict<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*);  \
   template void launch_prolong<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*,    \
                                   bool, bool);                                                                      \
@@ -815,5 +957,35 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
 
 HHG_INSTANTIATE(double)
 HHG_INSTANTIATE(float)
+
+void timer_set_mask(unsigned mask) {
+  Timer& t = timer();
+  t.mask = mask;
+}
+
+void timer_read(int family, double* total_ms, int* launches, double* units) {
+  Timer& t = timer();
+  double ms = 0.0, u = 0.0;
+  int n = 0;
+  std::vector<TimerRec> keep;
+  for (auto& r : t.recs) {
+    if (r.fam != family) {
+      keep.push_back(r);
+      continue;
+    }
+    float e = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&e, r.a, r.b) == hipSuccess) {
+      ms += e;
+      u += r.units;
+      ++n;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  t.recs.swap(keep);
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (units) *units = u;
+}
 
 }  // namespace hhg

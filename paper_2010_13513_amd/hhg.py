@@ -23,8 +23,11 @@ SYMBOLS = [
     "hhg_hier_create", "hhg_hier_destroy", "hhg_vec_layout", "hhg_vec_from_lattice", "hhg_vec_to_lattice",
     "hhg_apply", "hhg_residual", "hhg_rhs", "hhg_smooth", "hhg_restrict", "hhg_prolong_add",
     "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
-    "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation",
+    "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation", "hhg_dots",
+    "hhg_timer_start", "hhg_timer_read",
 ]
+KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER = \
+    range(10)
 
 
 class HHGError(RuntimeError):
@@ -81,6 +84,9 @@ def load():
         "hhg_fmg_solve": [P, P, P, P, P],
         "hhg_query_stencil": [I, ctypes.c_char, I, I, I, I, I, I, P, P, P],
         "hhg_query_interpolation": [I, I, I, I, I, P, P, P],
+        "hhg_dots": [P, I, P, P, P, P, I],
+        "hhg_timer_start": [ctypes.c_uint],
+        "hhg_timer_read": [I, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -198,6 +204,22 @@ def hhg_norms(h, level, x, prec=HHG_F64):
     nu, np_ = ctypes.c_double(), ctypes.c_double()
     _check(load().hhg_norms(h, level, _ptr(x), ctypes.byref(nu), ctypes.byref(np_), prec))
     return nu.value, np_.value
+
+
+def hhg_dots(h, level, x, y, prec=HHG_F64):
+    du, dp = ctypes.c_double(), ctypes.c_double()
+    _check(load().hhg_dots(h, level, _ptr(x), _ptr(y), ctypes.byref(du), ctypes.byref(dp), prec))
+    return du.value, dp.value
+
+
+def hhg_timer_start(family_mask):
+    _check(load().hhg_timer_start(family_mask))
+
+
+def hhg_timer_read(family):
+    ms, n, u = ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+    _check(load().hhg_timer_read(family, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
+    return ms.value, n.value, u.value
 
 
 def solver_params(nu_pre, nu_post, nu_inc, kappa, gs, xi, omega_inv, extra_cycles=0, rtol=0.0, max_cycles=100):

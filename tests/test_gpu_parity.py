@@ -226,6 +226,38 @@ def test_float32_apply_error(libs, disc, L):
     assert rel_err(got, S.apply(x)) < 2e-5
 
 
+@pytest.mark.parametrize("disc,lmin,L", CASES)
+def test_mass_and_dots(libs, disc, lmin, L):
+    lib = libs(disc, lmin, L)
+    S = Stokes(fe.Level(2 ** L, _vorder(disc)))
+    x = _rand(S, 61)
+    dx = lib.from_lattice(L, x)
+    dy = lib.empty(L)
+    hhg.hhg_apply(lib.h, L, hhg.HHG_OP_MASS, dx, dy)
+    want = S.apply_block(x, "MASS")
+    assert rel_err(lib.to_lattice(L, dy), want) < 1e-12
+    du, dp = hhg.hhg_dots(lib.h, L, dx, dy)
+    us, p = S.split(x)
+    wu, wp = S.split(want)
+    assert abs(du - sum(a @ b for a, b in zip(us, wu))) < 1e-12 * abs(du)
+    assert abs(dp - p @ wp) < 1e-12 * abs(dp)
+
+
+def test_fmg_full_size_c2(libs):
+    """The benchmark workload at full size: P2-P1, 6 tets, level 5 (859,812
+    DoFs), paper cube solution, FMG(0,2,1,1,A_f,3) in the launch configuration
+    bench.py times; every DoF against the oracle's FMG."""
+    L = 5
+    lib = libs(P2, 1, L)
+    H = mg.Hierarchy(2, 1, L, schur="sd")
+    prob = W.paper_cube()
+    om = 2.3
+    want = H.fmg(prob, mg.Params(0, 2, 1, 1, "f", 3, om))
+    got, st = _fmg_gpu(lib, H, prob, L, None, hhg.solver_params(0, 2, 1, 1, hhg.HHG_GS_FWD, 3, om))
+    assert got.size == 859812
+    assert rel_err(got, want) < 1e-10
+
+
 def test_errors_are_reported(libs):
     lib = libs(P1, 0, 3)
     x = lib.empty(3)
