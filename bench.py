@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-apply-roofline", action="store_true")
+    ap.add_argument("--mode", choices=["fmg", "apply"], default="fmg",
+                    help="apply: only the operator-apply roofline (for counter runs)")
+    ap.add_argument("--apply-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
@@ -64,6 +67,19 @@ def main():
     prob = W.paper_cube()
 
     ctx = hhg.hhg_ctx_create(0, stream.cuda_stream)
+    if args.mode == "apply":
+        res = bench_apply(torch, hhg, dev, stream, ctx, reps=args.apply_reps)
+        # plain copy of a known size (calibration of the HBM byte counters)
+        n = 1 << 27
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written per launch")
+        print(json.dumps({"apply_roofline": res}), flush=True)
+        hhg.hhg_ctx_destroy(ctx)
+        return
     H = hhg.hhg_hier_create(ctx, hhg.HHG_P2P1, 0, lmin, L, hhg.HHG_SCHUR_SD)
     Ev = hhg.hhg_hier_create(ctx, hhg.HHG_P2P1, 0, L, L + 1, hhg.HHG_SCHUR_SD)   # error evaluation only
 

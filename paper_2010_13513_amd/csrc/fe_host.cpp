@@ -10,7 +10,7 @@
 #include <map>
 #include <tuple>
 
-#include "hhg_internal.h"
+#include "fe.h"
 
 namespace hhg {
 namespace {

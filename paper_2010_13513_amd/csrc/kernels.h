@@ -10,6 +10,15 @@ struct Geom {
   int N, n1, nn, G, vstride;
 };
 
+// Per-level constants of the generated interior stencils (weights at h = 1):
+// A scales by h, B and B^T by h^2, PSPG C by delta (1/6)^(2/3) h^3, masses by
+// h^3; ainv[g] = 1 / (a * A_gg).
+template <typename T>
+struct LevelConst {
+  T a, b, c, m;
+  T ainv[8];
+};
+
 // Stencil tables of one level in one precision (device pointers inside).
 // Velocity rows exist only at interior velocity sites and use the unbounded
 // lattice stencil; pressure rows use one of 27 boundary classes.
@@ -43,6 +52,7 @@ enum KernelFamily {
   KF_COUNT = 10
 };
 void timer_set_mask(unsigned mask);
+bool timer_enabled();
 // Sum of event-measured durations (ms), launches and work units of one family
 // since the last read; synchronises the recorded events.
 void timer_read(int family, double* total_ms, int* launches, double* units);
@@ -68,17 +78,17 @@ struct TransferTables {
 
 // Launchers (kernels.hip).  All asynchronous on `s`.
 template <typename T>
-void launch_apply(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, const T* b, T* y, int opmask,
-                  bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd);
+void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const Tables<T>* tb, const T* x, const T* b,
+                  T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd);
 template <typename T>
-void launch_gs_colour(hipStream_t s, const Geom& g, const Tables<T>* tb, T* x, const T* b, int colour);
+void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* x, const T* b, int colour);
 template <typename T>
 void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, const T* rp, T omega);
 template <typename T>
 void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const int* bnd, int nbnd, int mode,
                        T* dinv);
 template <typename T>
-void launch_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* fnod, T* b);
+void launch_rhs(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T* fnod, T* b);
 template <typename T>
 void launch_mass(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, T* y);
 template <typename T>

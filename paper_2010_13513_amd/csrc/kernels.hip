@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "generated/stencils.inc"
 
 namespace hhg {
 namespace {
@@ -74,84 +75,139 @@ struct KScope {
   }
 };
 
-// ---------------------------------------------------------------- apply
-// y = [b -] op x on velocity rows of every group at (i,j,k) and on interior
-// pressure rows.  opmask bits: 1 A, 2 B^T, 4 B, 8 -C (the block of calA),
-// 16: +C instead (the matrix C alone).
+// ------------------------------------------------------- generated stencils
+// Dispatch of the generated interior row stencils by velocity group (the group
+// is uniform per workgroup, so the switch is a scalar branch).
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_apply(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
-                                                  const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                                  int vel_rows, int p_rows) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= g.nn) return;
-  int i, j, k;
-  decode(t, g.n1, i, j, k);
-  const int N = g.N;
+struct Rows;
+
+template <typename T>
+struct Rows<T, 1> {
+  static __device__ __forceinline__ void A(int, const T* u0, const T* u1, const T* u2, int pos, int s1, int s2, int nn,
+                                           T& a0, T& a1, T& a2) {
+    gen::p1_A_g0<T>(u0, u1, u2, pos, s1, s2, nn, a0, a1, a2);
+  }
+  static __device__ __forceinline__ void M(int, const T* u0, const T* u1, const T* u2, int pos, int s1, int s2, int nn,
+                                           T& a0, T& a1, T& a2) {
+    gen::p1_M_g0<T>(u0, u1, u2, pos, s1, s2, nn, a0, a1, a2);
+  }
+  static __device__ __forceinline__ void BT(int, const T* p, int pos, int s1, int s2, T& a0, T& a1, T& a2) {
+    gen::p1_BT_g0<T>(p, pos, s1, s2, a0, a1, a2);
+  }
+  static __device__ __forceinline__ void B(const T* u0, const T* u1, const T* u2, int pos, int s1, int s2, int nn,
+                                           T& a) {
+    gen::p1_B<T>(u0, u1, u2, pos, s1, s2, nn, a);
+  }
+  static __device__ __forceinline__ void C(const T* p, int pos, int s1, int s2, T& a) {
+    gen::p1_C<T>(p, pos, s1, s2, a);
+  }
+};
+
+#define HHG_P2_CASES(F, ...)        \
+  switch (g) {                      \
+    case 0: gen::F##_g0<T>(__VA_ARGS__); break; \
+    case 1: gen::F##_g1<T>(__VA_ARGS__); break; \
+    case 2: gen::F##_g2<T>(__VA_ARGS__); break; \
+    case 3: gen::F##_g3<T>(__VA_ARGS__); break; \
+    case 4: gen::F##_g4<T>(__VA_ARGS__); break; \
+    case 5: gen::F##_g5<T>(__VA_ARGS__); break; \
+    case 6: gen::F##_g6<T>(__VA_ARGS__); break; \
+    default: gen::F##_g7<T>(__VA_ARGS__); break; \
+  }
+
+template <typename T>
+struct Rows<T, 8> {
+  static __device__ __forceinline__ void A(int g, const T* u0, const T* u1, const T* u2, int pos, int s1, int s2,
+                                           int nn, T& a0, T& a1, T& a2) {
+    HHG_P2_CASES(p2_A, u0, u1, u2, pos, s1, s2, nn, a0, a1, a2)
+  }
+  static __device__ __forceinline__ void M(int g, const T* u0, const T* u1, const T* u2, int pos, int s1, int s2,
+                                           int nn, T& a0, T& a1, T& a2) {
+    HHG_P2_CASES(p2_M, u0, u1, u2, pos, s1, s2, nn, a0, a1, a2)
+  }
+  static __device__ __forceinline__ void BT(int g, const T* p, int pos, int s1, int s2, T& a0, T& a1, T& a2) {
+    HHG_P2_CASES(p2_BT, p, pos, s1, s2, a0, a1, a2)
+  }
+  static __device__ __forceinline__ void B(const T* u0, const T* u1, const T* u2, int pos, int s1, int s2, int nn,
+                                           T& a) {
+    gen::p2_B<T>(u0, u1, u2, pos, s1, s2, nn, a);
+  }
+  static __device__ __forceinline__ void C(const T*, int, int, int, T&) {}
+};
+
+// ---------------------------------------------------------------- apply
+// Logical block index with a contiguous range of blocks per XCD: the 8 XCDs
+// receive workgroups round-robin, so block b runs on XCD b % 8; remapping
+// gives each XCD one contiguous slab of the lattice, and the k +- 1 planes a
+// stencil reads stay in that XCD's L2.  grid must be a multiple of 8.
+__device__ __forceinline__ int xcd_block() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+unsigned nblocks8(size_t n) { return (unsigned)(((n + kBlock - 1) / kBlock + 7) & ~(size_t)7); }
+
+// One velocity row type (group GR) of the apply at array index t.
+template <typename T, int G, int GR>
+__device__ __forceinline__ void apply_vrow(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                           const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b, int t,
+                                           int i, int j, int k) {
+  const int s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
   const T* __restrict__ u0 = x;
   const T* __restrict__ u1 = x + g.vstride;
   const T* __restrict__ u2 = x + 2 * g.vstride;
   const T* __restrict__ p = x + 3 * g.vstride;
-  if (vel_rows) {
-#pragma unroll
-    for (int gr = 0; gr < G; ++gr) {
-      const bool in = vel_interior<G>(gr, i, j, k, N);
-      const int pos = gr * g.nn + t;
-      T a0 = 0, a1 = 0, a2 = 0;
-      if (in) {
-        if (opmask & 1) {
-          const int n = tb->A[gr].n;
-          const int* __restrict__ off = tb->A[gr].off;
-          const T* __restrict__ w = tb->A[gr].w;
-          for (int e = 0; e < n; ++e) {
-            const int o = pos + off[e];
-            const T we = w[e];
-            a0 += we * u0[o];
-            a1 += we * u1[o];
-            a2 += we * u2[o];
-          }
-        }
-        if (opmask & 2) {
-          const int n = tb->BT[gr].n;
-          const int* __restrict__ off = tb->BT[gr].off;
-          const T* __restrict__ w = tb->BT[gr].w;
-          for (int e = 0; e < n; ++e) {
-            const T pv = p[t + off[e]];
-            a0 += w[3 * e] * pv;
-            a1 += w[3 * e + 1] * pv;
-            a2 += w[3 * e + 2] * pv;
-          }
-        }
-      }
-      T r0 = a0, r1 = a1, r2 = a2;
-      if (has_b) {
-        r0 = in ? b[pos] - a0 : T(0);
-        r1 = in ? b[g.vstride + pos] - a1 : T(0);
-        r2 = in ? b[2 * g.vstride + pos] - a2 : T(0);
-      }
-      y[pos] = r0;
-      y[g.vstride + pos] = r1;
-      y[2 * g.vstride + pos] = r2;
+  const bool in = vel_interior<G>(GR, i, j, k, g.N);
+  const int pos = GR * nn + t;
+  T r0 = 0, r1 = 0, r2 = 0;
+  if (in) {
+    T a0 = 0, a1 = 0, a2 = 0, c0 = 0, c1 = 0, c2 = 0;
+    if (opmask & 1) Rows<T, G>::A(GR, u0, u1, u2, pos, s1, s2, nn, a0, a1, a2);
+    if (opmask & 2) Rows<T, G>::BT(GR, p, t, s1, s2, c0, c1, c2);
+    r0 = lc.a * a0 + lc.b * c0;
+    r1 = lc.a * a1 + lc.b * c1;
+    r2 = lc.a * a2 + lc.b * c2;
+    if (has_b) {
+      r0 = b[pos] - r0;
+      r1 = b[g.vstride + pos] - r1;
+      r2 = b[2 * g.vstride + pos] - r2;
     }
   }
+  y[pos] = r0;
+  y[g.vstride + pos] = r1;
+  y[2 * g.vstride + pos] = r2;
+}
+
+template <typename T, int G, int GR>
+__device__ __forceinline__ void apply_vrows(const Geom& g, const LevelConst<T>& lc, const T* x, const T* b, T* y,
+                                            int opmask, int has_b, int t, int i, int j, int k) {
+  apply_vrow<T, G, GR>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
+  if constexpr (GR + 1 < G) apply_vrows<T, G, GR + 1>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
+}
+
+// y = [b -] op x on every row type at array index t: the G velocity groups
+// (zero rows where the site is not an interior velocity DoF) and the interior
+// pressure row (boundary pressure rows: k_prow_bnd).  opmask bits: 1 A, 2 B^T,
+// 4 B, 8 -C (block of calA), 16: +C instead.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, const T* __restrict__ x,
+                                                  const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                                  int vel_rows, int p_rows) {
+  const int t = xcd_block() * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  int i, j, k;
+  decode(t, g.n1, i, j, k);
+  const int N = g.N;
+  if (vel_rows) apply_vrows<T, G, 0>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
   if (p_rows && i >= 1 && j >= 1 && k >= 1 && i <= N - 1 && j <= N - 1 && k <= N - 1) {
-    T acc = 0;
-    if (opmask & 4) {
-      const int n = tb->B[kInteriorClass].n;
-      const int* __restrict__ off = tb->B[kInteriorClass].off;
-      const T* __restrict__ w = tb->B[kInteriorClass].w;
-      for (int e = 0; e < n; ++e) {
-        const int o = t + off[e];
-        acc += w[3 * e] * u0[o] + w[3 * e + 1] * u1[o] + w[3 * e + 2] * u2[o];
-      }
-    }
-    if (opmask & 8) {
-      const int n = tb->C[kInteriorClass].n;
-      const int* __restrict__ off = tb->C[kInteriorClass].off;
-      const T* __restrict__ w = tb->C[kInteriorClass].w;
-      T c = 0;
-      for (int e = 0; e < n; ++e) c += w[e] * p[t + off[e]];
-      acc += (opmask & 16) ? c : -c;
-    }
+    const int s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
+    const T* __restrict__ u0 = x;
+    const T* __restrict__ u1 = x + g.vstride;
+    const T* __restrict__ u2 = x + 2 * g.vstride;
+    const T* __restrict__ p = x + 3 * g.vstride;
+    T ab = 0, ac = 0;
+    if (opmask & 4) Rows<T, G>::B(u0, u1, u2, t, s1, s2, nn, ab);
+    if (opmask & 24) Rows<T, G>::C(p, t, s1, s2, ac);
+    const T acc = lc.b * ab + ((opmask & 16) ? lc.c * ac : -lc.c * ac);
     const int pp = 3 * g.vstride + t;
     y[pp] = has_b ? b[pp] - acc : acc;
   }
@@ -191,10 +247,29 @@ __global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __
 }
 
 // ---------------------------------------------------------- Gauss-Seidel
-// One colour of the vertex group: interior nodes with (i+j+k) mod 4 == c.
-// u_d += (f_d - (A u_d) - (B^T p)_d) / a_gg for the three components.
+// The generated row functions accumulate three components at once; the
+// Gauss-Seidel kernels give each velocity component its own thread
+// (blockIdx.y) so a colour of a small level spreads over three times as many
+// waves.  Component d reads u_d, p and writes u_d only (A is block diagonal).
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, const Tables<T>* __restrict__ tb, T* __restrict__ x,
+__device__ __forceinline__ void gs_update(const Geom& g, const LevelConst<T>& lc, T* __restrict__ x,
+                                          const T* __restrict__ b, int gr, int idx, int d) {
+  const int s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
+  const int pos = gr * nn + idx;
+  T* ud = x + d * g.vstride;
+  const T* p = x + 3 * g.vstride;
+  T a0 = 0, a1 = 0, a2 = 0, c0 = 0, c1 = 0, c2 = 0;
+  // same pointer for the three component slots: only slot d is used
+  Rows<T, G>::A(gr, ud, ud, ud, pos, s1, s2, nn, a0, a1, a2);
+  Rows<T, G>::BT(gr, p, idx, s1, s2, c0, c1, c2);
+  const T c = d == 0 ? c0 : (d == 1 ? c1 : c2);
+  ud[pos] += (b[d * g.vstride + pos] - lc.a * a0 - lc.b * c) * lc.ainv[gr];
+}
+
+// One colour of the vertex group: interior nodes with (i+j+k) mod 4 == c.
+// u_d += (f_d - (A u_d) - (B^T p)_d) / a_gg.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, LevelConst<T> lc, T* __restrict__ x,
                                                       const T* __restrict__ b, int c) {
   const int N = g.N, nr = N - 1, ni = (nr + 3) >> 2;
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -203,44 +278,12 @@ __global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, const Tables<T>* _
   const int j = 1 + row % nr, k = 1 + row / nr;
   const int i = 1 + ((((c - 1 - j - k) % 4) + 4) & 3) + 4 * ip;
   if (i > N - 1) return;
-  const int pos = i + g.n1 * (j + g.n1 * k);
-  T* u0 = x;
-  T* u1 = x + g.vstride;
-  T* u2 = x + 2 * g.vstride;
-  const T* p = x + 3 * g.vstride;
-  T a0 = b[pos], a1 = b[g.vstride + pos], a2 = b[2 * g.vstride + pos];
-  {
-    const int n = tb->A[0].n;
-    const int* __restrict__ off = tb->A[0].off;
-    const T* __restrict__ w = tb->A[0].w;
-    for (int e = 0; e < n; ++e) {
-      const int o = pos + off[e];
-      const T we = w[e];
-      a0 -= we * u0[o];
-      a1 -= we * u1[o];
-      a2 -= we * u2[o];
-    }
-  }
-  {
-    const int n = tb->BT[0].n;
-    const int* __restrict__ off = tb->BT[0].off;
-    const T* __restrict__ w = tb->BT[0].w;
-    for (int e = 0; e < n; ++e) {
-      const T pv = p[pos + off[e]];
-      a0 -= w[3 * e] * pv;
-      a1 -= w[3 * e + 1] * pv;
-      a2 -= w[3 * e + 2] * pv;
-    }
-  }
-  const T di = tb->adiag_inv[0];
-  u0[pos] += a0 * di;
-  u1[pos] += a1 * di;
-  u2[pos] += a2 * di;
+  gs_update<T, G>(g, lc, x, b, 0, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
 }
 
 // One edge group (one colour) of the P2 velocity: all interior sites of group gr.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, const Tables<T>* __restrict__ tb, T* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, LevelConst<T> lc, T* __restrict__ x,
                                                     const T* __restrict__ b, int gr) {
   const int N = g.N;
   const int dx = gdx(gr), dy = gdy(gr), dz = gdz(gr);
@@ -251,40 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, const Tables<T>* __r
   const int r = t / cx;
   const int j = 1 - dy + r % cy;
   const int k = 1 - dz + r / cy;
-  const int idx = i + g.n1 * (j + g.n1 * k);
-  const int pos = gr * g.nn + idx;
-  T* u0 = x;
-  T* u1 = x + g.vstride;
-  T* u2 = x + 2 * g.vstride;
-  const T* p = x + 3 * g.vstride;
-  T a0 = b[pos], a1 = b[g.vstride + pos], a2 = b[2 * g.vstride + pos];
-  {
-    const int n = tb->A[gr].n;
-    const int* __restrict__ off = tb->A[gr].off;
-    const T* __restrict__ w = tb->A[gr].w;
-    for (int e = 0; e < n; ++e) {
-      const int o = pos + off[e];
-      const T we = w[e];
-      a0 -= we * u0[o];
-      a1 -= we * u1[o];
-      a2 -= we * u2[o];
-    }
-  }
-  {
-    const int n = tb->BT[gr].n;
-    const int* __restrict__ off = tb->BT[gr].off;
-    const T* __restrict__ w = tb->BT[gr].w;
-    for (int e = 0; e < n; ++e) {
-      const T pv = p[idx + off[e]];
-      a0 -= w[3 * e] * pv;
-      a1 -= w[3 * e + 1] * pv;
-      a2 -= w[3 * e + 2] * pv;
-    }
-  }
-  const T di = tb->adiag_inv[gr];
-  u0[pos] += a0 * di;
-  u1[pos] += a1 * di;
-  u2[pos] += a2 * di;
+  gs_update<T, 8>(g, lc, x, b, gr, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
 }
 
 // p <- p - omega * dinv * rp (eq. uzawa-pressure with S_hat = omega^{-1} D).
@@ -331,29 +341,22 @@ __global__ void __launch_bounds__(kBlock) k_schur_diag(Geom g, const Tables<T>* 
 // b = M f on interior velocity rows (velocity mass, interior stencil), 0 on
 // boundary rows and on the pressure part.
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_rhs(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ f,
+__global__ void __launch_bounds__(kBlock) k_rhs(Geom g, LevelConst<T> lc, const T* __restrict__ f,
                                                 T* __restrict__ b) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= g.nn) return;
   int i, j, k;
   decode(t, g.n1, i, j, k);
-#pragma unroll
+  const int s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
+#pragma unroll 1
   for (int gr = 0; gr < G; ++gr) {
     const bool in = vel_interior<G>(gr, i, j, k, g.N);
-    const int pos = gr * g.nn + t;
+    const int pos = gr * nn + t;
     T a0 = 0, a1 = 0, a2 = 0;
-    if (in) {
-      const DStencil<T> s = tb->Mv[gr];
-      for (int e = 0; e < s.n; ++e) {
-        const int o = pos + s.off[e];
-        a0 += s.w[e] * f[o];
-        a1 += s.w[e] * f[g.vstride + o];
-        a2 += s.w[e] * f[2 * g.vstride + o];
-      }
-    }
-    b[pos] = a0;
-    b[g.vstride + pos] = a1;
-    b[2 * g.vstride + pos] = a2;
+    if (in) Rows<T, G>::M(gr, f, f + g.vstride, f + 2 * g.vstride, pos, s1, s2, nn, a0, a1, a2);
+    b[pos] = lc.m * a0;
+    b[g.vstride + pos] = lc.m * a1;
+    b[2 * g.vstride + pos] = lc.m * a2;
   }
   b[3 * g.vstride + t] = 0;
 }
@@ -737,14 +740,14 @@ static double p_sites(const Geom& g) {
 }
 
 template <typename T>
-void launch_apply(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, const T* b, T* y, int opmask,
-                  bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd) {
-  {
-  KScope ks(s, KF_APPLY, p_sites(g));
-  if (g.G == 1)
-    HHG_LAUNCH((k_apply<T, 1>), nblocks(g.nn), s, g, tb, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
-  else
-    HHG_LAUNCH((k_apply<T, 8>), nblocks(g.nn), s, g, tb, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
+void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const Tables<T>* tb, const T* x, const T* b,
+                  T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd) {
+  if (vel_rows || p_rows) {
+    KScope ks(s, KF_APPLY, p_sites(g));
+    if (g.G == 1)
+      HHG_LAUNCH((k_apply<T, 1>), nblocks8(g.nn), s, g, lc, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
+    else
+      HHG_LAUNCH((k_apply<T, 8>), nblocks8(g.nn), s, g, lc, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
   }
   if (p_rows && nbnd > 0) {
     KScope ks(s, KF_PROW_BND, nbnd);
@@ -753,7 +756,7 @@ void launch_apply(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x,
 }
 
 template <typename T>
-void launch_gs_colour(hipStream_t s, const Geom& g, const Tables<T>* tb, T* x, const T* b, int colour) {
+void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* x, const T* b, int colour) {
   const int N = g.N;
   if (N < 2) return;
   if (colour < 4) {
@@ -766,15 +769,16 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const Tables<T>* tb, T* x, c
           if (i0 <= nr) cnt += (nr - i0) / 4 + 1;
         }
     KScope ks(s, KF_GS_VERTEX, cnt);
+    const dim3 grid(nblocks((size_t)ni * nr * nr), 3);
     if (g.G == 1)
-      HHG_LAUNCH((k_gs_vertex<T, 1>), nblocks((size_t)ni * nr * nr), s, g, tb, x, b, colour);
+      hipLaunchKernelGGL((k_gs_vertex<T, 1>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
     else
-      HHG_LAUNCH((k_gs_vertex<T, 8>), nblocks((size_t)ni * nr * nr), s, g, tb, x, b, colour);
+      hipLaunchKernelGGL((k_gs_vertex<T, 8>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
   } else {
     const int gr = colour - 3;
     const size_t n = (size_t)(N - 1 + ((0xB2 >> gr) & 1)) * (N - 1 + ((0xD4 >> gr) & 1)) * (N - 1 + ((0xE8 >> gr) & 1));
     KScope ks(s, KF_GS_EDGE, (double)n);
-    HHG_LAUNCH((k_gs_edge<T>), nblocks(n), s, g, tb, x, b, gr);
+    hipLaunchKernelGGL((k_gs_edge<T>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, lc, x, b, gr);
   }
 }
 
@@ -793,11 +797,11 @@ void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const 
 }
 
 template <typename T>
-void launch_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* f, T* b) {
+void launch_rhs(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T* f, T* b) {
   if (g.G == 1)
-    HHG_LAUNCH((k_rhs<T, 1>), nblocks(g.nn), s, g, tb, f, b);
+    HHG_LAUNCH((k_rhs<T, 1>), nblocks(g.nn), s, g, lc, f, b);
   else
-    HHG_LAUNCH((k_rhs<T, 8>), nblocks(g.nn), s, g, tb, f, b);
+    HHG_LAUNCH((k_rhs<T, 8>), nblocks(g.nn), s, g, lc, f, b);
 }
 
 template <typename T>
@@ -932,12 +936,12 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
 }
 
 #define HHG_INSTANTIATE(T)                                                                                          \
-  template void launch_apply<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, const T*, T*, int, bool, bool, \
-                                bool, const int*, int);                                                             \
-  template void launch_gs_colour<T>(hipStream_t, const Geom&, const Tables<T>*, T*, const T*, int);                 \
+  template void launch_apply<T>(hipStream_t, const Geom&, const LevelConst<T>&, const Tables<T>*, const T*,        \
+                                const T*, T*, int, bool, bool, bool, const int*, int);                              \
+  template void launch_gs_colour<T>(hipStream_t, const Geom&, const LevelConst<T>&, T*, const T*, int);             \
   template void launch_pressure_step<T>(hipStream_t, const Geom&, const T*, T*, const T*, T);                       \
   template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const int*, int, int, T*);         \
-  template void launch_rhs<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                            \
+  template void launch_rhs<T>(hipStream_t, const Geom&, const LevelConst<T>&, const T*, T*);                        \
   template void launch_mass<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                           \
   template void launch_dot<T>(hipStream_t, const T*, const T*, size_t, double*, double*);                           \
   template void launch_restrict<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*);  \
@@ -962,6 +966,8 @@ void timer_set_mask(unsigned mask) {
   Timer& t = timer();
   t.mask = mask;
 }
+
+bool timer_enabled() { return timer().mask != 0; }
 
 void timer_read(int family, double* total_ms, int* launches, double* units) {
   Timer& t = timer();

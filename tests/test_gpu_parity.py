@@ -258,6 +258,32 @@ def test_fmg_full_size_c2(libs):
     assert rel_err(got, want) < 1e-10
 
 
+def test_fmg_graph_replay_matches_eager(libs):
+    """Fixed-work FMG calls (no stats, no tolerance) replay a captured HIP
+    graph; every replay, with eager library work and synchronisations in
+    between, equals the eager solve bit for bit."""
+    L = 4
+    lib = libs(P2, 1, L)
+    torch = lib.torch
+    H = mg.Hierarchy(2, 1, L, schur="sd")
+    prob = W.paper_cube()
+    bs = [lib.from_lattice(l, H.rhs(l, prob)) for l in range(1, L + 1)]
+    x0 = lib.from_lattice(L, H.initial(L, prob))
+    prm = hhg.solver_params(0, 2, 1, 1, hhg.HHG_GS_FWD, 3, 2.3, extra_cycles=1)
+    x = x0.clone()
+    hhg.hhg_fmg_solve(lib.h, x, bs, prm, want_stats=True)          # eager
+    want = lib.to_lattice(L, x)
+    for rep in range(4):
+        x.copy_(x0)
+        hhg.hhg_fmg_solve(lib.h, x, bs, prm, want_stats=False)      # graph (captured on rep 0)
+        torch.cuda.synchronize()
+        got = lib.to_lattice(L, x)
+        assert np.array_equal(got, want), rep
+        y = lib.empty(L)
+        hhg.hhg_apply(lib.h, L, hhg.HHG_OP_FULL, x, y)               # eager work between replays
+        hhg.hhg_norms(lib.h, L, y)
+
+
 def test_errors_are_reported(libs):
     lib = libs(P1, 0, 3)
     x = lib.empty(3)
