@@ -131,6 +131,15 @@ hhg_status hhg_vec_layout(hhg_hier h, int level, int* N, size_t* nn, size_t* vec
 hhg_status hhg_vec_from_lattice(hhg_hier h, int level, const double* src_lattice, void* dst, hhg_prec prec);
 hhg_status hhg_vec_to_lattice(hhg_hier h, int level, const void* src, double* dst_lattice, hhg_prec prec);
 
+/* Variable viscosity nu(x) on one level (not in the paper's experiments):
+ * the A block becomes sum_T nu_T int_T grad phi_i . grad phi_j per velocity
+ * component, nu_T the mean of nu at the four vertices of T.  nu: device,
+ * double, nn words, the nodal values at the P1 nodes of `level` (lattice
+ * order); copied.  Rebuilds the Gauss-Seidel diagonals, the Schur diagonal D
+ * and, on the coarsest level, the coarse pseudo-inverse.  Set it on every
+ * level of a solve.  Synchronous. */
+hhg_status hhg_set_viscosity(hhg_hier h, int level, const double* nu);
+
 /* ------------------------------------------------------------- operators */
 /* y = op x on `level` (eq. stokes-discrete blocks; FULL = calA).  A and BT
  * fill the velocity part of y and zero its pressure part, B and C the
@@ -220,6 +229,19 @@ hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_s
  * optional (NULL).  F64. */
 hhg_status hhg_fmg_solve(hhg_hier h, void* x, const void* const* b_levels, const hhg_solver_params* prm,
                          hhg_stats* stats);
+
+/* Defect correction (iterative refinement) in float64 around inner cycles in
+ * `inner_prec`: repeat r = b - calA x (float64); stop when ||r||_2 <= rtol
+ * ||b||_2 or after max_outer corrections; otherwise convert r to the inner
+ * precision (round to nearest even), run inner_cycles variable V-cycles
+ * (prm's smoothing parameters, arithmetic and storage in inner_prec, the
+ * coarsest-level pseudo-inverse applied in float64) on calA e = r from e = 0,
+ * x += e in float64 and project the pressure to zero mean in float64.  x holds
+ * the boundary data and the start vector.  Stats: cycles = inner V-cycles in
+ * total, residual norms of the final x.  HHG_ERR_NOT_CONVERGED if rtol is not
+ * reached. */
+hhg_status hhg_dc_solve(hhg_hier h, void* x, const void* b, const hhg_solver_params* prm, hhg_prec inner_prec,
+                        int inner_cycles, double rtol, int max_outer, hhg_stats* stats);
 
 #ifdef __cplusplus
 }

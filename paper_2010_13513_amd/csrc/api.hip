@@ -89,10 +89,17 @@ struct Level {
   float* dinv32 = nullptr;
   LevelConst<double> lc64{};
   LevelConst<float> lc32{};
+  // variable viscosity (allocated by hhg_set_viscosity)
+  double *nu64 = nullptr, *ainvs64 = nullptr;
+  float *nu32 = nullptr, *ainvs32 = nullptr;
   size_t vec_words = 0;
   // work vectors (float64): residual, V-cycle correction / rhs, FMG iterate, boundary data
   double *r = nullptr, *cx = nullptr, *cb = nullptr, *xs = nullptr, *w = nullptr;
   float* r32 = nullptr;
+  // float32 V-cycle vectors (allocated on first mixed-precision use)
+  float *cx32 = nullptr, *cb32 = nullptr;
+  // finest-level correction and right-hand side of a float64 inner solve
+  double *dc_e = nullptr, *dc_r = nullptr;
   // host copies of the double tables (coarse assembly)
   std::vector<HostStencil> hA, hBT, hB, hC;
   double adiag[8] = {0};
@@ -115,6 +122,7 @@ struct hhg_hier_s {
   double* Kp = nullptr;
   int* unk = nullptr;
   int nunk = 0, rank = 0;
+  std::vector<int> unk_host;
   double* partial = nullptr;
   double* sums = nullptr;   // device scratch for reductions (16 doubles)
   double* hsums = nullptr;  // pinned host copy
@@ -300,8 +308,8 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
   lv.nbnd = (int)bnd.size();
   lv.bnd = a.upload(bnd);
   // Schur diagonal per node
-  launch_schur_diag<double>(S(h), g, lv.tb64, lv.bnd, lv.nbnd, h->schur, lv.dinv64);
-  launch_schur_diag<float>(S(h), g, lv.tb32, lv.bnd, lv.nbnd, h->schur, lv.dinv32);
+  launch_schur_diag<double>(S(h), g, lv.tb64, nullptr, h->schur, lv.dinv64);
+  launch_schur_diag<float>(S(h), g, lv.tb32, nullptr, h->schur, lv.dinv32);
   HHG_CHECK_HIP(hipGetLastError());
 }
 
@@ -460,6 +468,8 @@ void build_transfer(hhg_hier h, Level& lc, Level& lf) {
   HHG_CHECK_HIP(hipMemcpy(lf.tt32, &t32, sizeof(t32), hipMemcpyHostToDevice));
 }
 
+int full_mask(hhg_hier h);
+
 // Dense coarse operator on the unknowns (interior velocity DoFs, all pressure
 // DoFs) from the host stencil tables, and its pseudo-inverse.
 void build_coarse(hhg_hier h) {
@@ -528,6 +538,37 @@ void build_coarse(hhg_hier h) {
   h->nunk = n;
   h->Kp = h->arena.upload(Kp);
   h->unk = h->arena.upload(unk);
+  h->unk_host = unk;
+}
+
+// Dense coarse operator from the device operator itself (columns = calA e_c
+// restricted to the unknowns), used when the coarsest level's rows depend on
+// data such as a variable viscosity; then its pseudo-inverse replaces Kp.
+void build_coarse_device(hhg_hier h) {
+  if (h->nunk == 0) return;
+  Level& lv = h->L(h->lmin);
+  const int n = h->nunk;
+  double* e = lv.cx;
+  double* y = lv.cb;
+  std::vector<double> K((size_t)n * n), col(lv.vec_words);
+  const double one = 1.0;
+  for (int c = 0; c < n; ++c) {
+    launch_fill<double>(S(h), e, lv.vec_words, 0.0);
+    HHG_CHECK_HIP(hipMemcpyAsync(e + h->unk_host[c], &one, sizeof(double), hipMemcpyHostToDevice, S(h)));
+    launch_apply<double>(S(h), lv.g, lv.lc64, lv.tb64, e, nullptr, y, full_mask(h), false, true, true, lv.bnd,
+                         lv.nbnd);
+    HHG_CHECK_HIP(hipMemcpyAsync(col.data(), y, lv.vec_words * sizeof(double), hipMemcpyDeviceToHost, S(h)));
+    HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
+    for (int r = 0; r < n; ++r) K[(size_t)r * n + c] = col[h->unk_host[r]];
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = r + 1; c < n; ++c) {
+      const double sym = 0.5 * (K[(size_t)r * n + c] + K[(size_t)c * n + r]);
+      K[(size_t)r * n + c] = K[(size_t)c * n + r] = sym;
+    }
+  std::vector<double> Kp;
+  h->rank = sym_pinv(n, K, Kp, 1e-12);
+  HHG_CHECK_HIP(hipMemcpy(h->Kp, Kp.data(), Kp.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
 // ---------------------------------------------------------------- ops
@@ -592,29 +633,80 @@ void op_prolong(hhg_hier h, int lc, const T* xc, T* xf, bool add, bool skip_bnd)
   launch_prolong<T>(S(h), c.g, f.g, ttables<T>(f), xc, xf, add, skip_bnd);
 }
 
-void op_coarse(hhg_hier h, double* x, const double* b) {
-  HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "coarsest level has more than 2048 unknowns: no dense coarse solve");
-  Level& lv = h->L(h->lmin);
-  op_apply<double>(h, h->lmin, full_mask(h), x, b, lv.r, true, true, true);
-  launch_coarse(S(h), lv.g, h->Kp, h->unk, h->nunk, lv.r, x, nullptr);
-  op_mean_zero<double>(h, h->lmin, x);
+template <typename T>
+T* cxbuf(Level& lv);
+template <>
+double* cxbuf<double>(Level& lv) {
+  return lv.cx;
+}
+template <>
+float* cxbuf<float>(Level& lv) {
+  return lv.cx32;
+}
+template <typename T>
+T* cbbuf(Level& lv);
+template <>
+double* cbbuf<double>(Level& lv) {
+  return lv.cb;
+}
+template <>
+float* cbbuf<float>(Level& lv) {
+  return lv.cb32;
 }
 
-void vcycle(hhg_hier h, int lf, int l, double* x, const double* b, const hhg_solver_params& p) {
+// Coarse solve x <- x + A0^+ (b - A0 x) on the unknowns (float64 GEMV for
+// either storage precision), then zero pressure mean.
+template <typename T>
+void op_coarse(hhg_hier h, T* x, const T* b) {
+  HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "coarsest level has more than 2048 unknowns: no dense coarse solve");
+  Level& lv = h->L(h->lmin);
+  T* r = rbuf<T>(lv);
+  op_apply<T>(h, h->lmin, full_mask(h), x, b, r, true, true, true);
+  launch_coarse<T>(S(h), h->Kp, h->unk, h->nunk, r, x);
+  op_mean_zero<T>(h, h->lmin, x);
+}
+
+// Variable V-cycle of Alg. fmg in storage/arithmetic precision T.
+template <typename T>
+void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_params& p) {
   if (l == h->lmin) {
-    op_coarse(h, x, b);
+    op_coarse<T>(h, x, b);
     return;
   }
   Level& lv = h->L(l);
   Level& lc = h->L(l - 1);
   const double om = 1.0 / p.omega_inv;
-  op_smooth<double>(h, l, x, b, p.nu_pre + (lf - l) * p.nu_inc, p.gs, p.xi, om);
-  op_apply<double>(h, l, full_mask(h), x, b, lv.r, true, true, true);
-  op_restrict<double>(h, l, lv.r, lc.cb);
-  launch_fill<double>(S(h), lc.cx, lc.vec_words, 0.0);
-  vcycle(h, lf, l - 1, lc.cx, lc.cb, p);
-  op_prolong<double>(h, l - 1, lc.cx, x, true, true);
-  op_smooth<double>(h, l, x, b, p.nu_post + (lf - l) * p.nu_inc, p.gs, p.xi, om);
+  T* r = rbuf<T>(lv);
+  op_smooth<T>(h, l, x, b, p.nu_pre + (lf - l) * p.nu_inc, p.gs, p.xi, om);
+  op_apply<T>(h, l, full_mask(h), x, b, r, true, true, true);
+  op_restrict<T>(h, l, r, cbbuf<T>(lc));
+  launch_fill<T>(S(h), cxbuf<T>(lc), lc.vec_words, T(0));
+  vcycle_t<T>(h, lf, l - 1, cxbuf<T>(lc), cbbuf<T>(lc), p);
+  op_prolong<T>(h, l - 1, cxbuf<T>(lc), x, true, true);
+  op_smooth<T>(h, l, x, b, p.nu_post + (lf - l) * p.nu_inc, p.gs, p.xi, om);
+}
+
+void vcycle(hhg_hier h, int lf, int l, double* x, const double* b, const hhg_solver_params& p) {
+  vcycle_t<double>(h, lf, l, x, b, p);
+}
+
+void ensure_f32_vectors(hhg_hier h) {
+  for (int l = h->lmin; l < h->lmax; ++l) {
+    Level& lv = h->L(l);
+    if (!lv.cx32) {
+      lv.cx32 = h->arena.alloc<float>(lv.vec_words);
+      lv.cb32 = h->arena.alloc<float>(lv.vec_words);
+      launch_fill<float>(S(h), lv.cx32, lv.vec_words, 0.0f);
+      launch_fill<float>(S(h), lv.cb32, lv.vec_words, 0.0f);
+    }
+  }
+  Level& top = h->L(h->lmax);
+  if (!top.cx32) {  // finest level: correction and right-hand side of the inner solve
+    top.cx32 = h->arena.alloc<float>(top.vec_words);
+    top.cb32 = h->arena.alloc<float>(top.vec_words);
+    launch_fill<float>(S(h), top.cx32, top.vec_words, 0.0f);
+    launch_fill<float>(S(h), top.cb32, top.vec_words, 0.0f);
+  }
 }
 
 // Euclidean norms of velocity and pressure parts (synchronous).
@@ -672,7 +764,7 @@ void fmg_body(hhg_hier h, double* x, BL bl, const hhg_solver_params& p) {
   Level& bot = h->L(h->lmin);
   launch_fill<double>(s, bot.xs, bot.vec_words, 0.0);
   launch_copy_boundary<double>(s, bot.g, bot.w, bot.xs);
-  op_coarse(h, bot.xs, bl(h->lmin));
+  op_coarse<double>(h, bot.xs, bl(h->lmin));
   for (int l = h->lmin + 1; l <= h->lmax; ++l) {
     Level& lv = h->L(l);
     double* X = l == h->lmax ? x : lv.xs;
@@ -951,7 +1043,7 @@ hhg_status hhg_coarse_solve(hhg_hier h, void* x, const void* b, hhg_prec prec) {
   return guard([&] {
     HHG_REQUIRE(h && x && b && x != b, HHG_ERR_ARG, "bad arguments");
     HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "coarse solve is float64");
-    op_coarse(h, (double*)x, (const double*)b);
+    op_coarse<double>(h, (double*)x, (const double*)b);
     HHG_CHECK_HIP(hipGetLastError());
   });
 }
@@ -1049,6 +1141,93 @@ hhg_status hhg_timer_read(int family, double* total_ms, int* launches, double* u
   return guard([&] {
     HHG_REQUIRE(family >= 0 && family < KF_COUNT, HHG_ERR_ARG, "unknown kernel family");
     timer_read(family, total_ms, launches, units);
+  });
+}
+
+hhg_status hhg_set_viscosity(hhg_hier h, int level, const double* nu) {
+  return guard([&] {
+    check_level(h, level);
+    HHG_REQUIRE(nu, HHG_ERR_ARG, "null viscosity");
+    Level& lv = h->L(level);
+    hipStream_t s = S(h);
+    const size_t nn = lv.g.nn;
+    if (!lv.nu64) {
+      lv.nu64 = h->arena.alloc<double>(nn);
+      lv.nu32 = h->arena.alloc<float>(nn);
+      lv.ainvs64 = h->arena.alloc<double>((size_t)lv.g.vstride);
+      lv.ainvs32 = h->arena.alloc<float>((size_t)lv.g.vstride);
+    }
+    HHG_CHECK_HIP(hipMemcpyAsync(lv.nu64, nu, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_to_f32(s, lv.nu64, lv.nu32, nn);
+    lv.lc64.nu = lv.nu64;
+    lv.lc32.nu = lv.nu32;
+    lv.lc64.ainv_site = lv.ainvs64;
+    lv.lc32.ainv_site = lv.ainvs32;
+    launch_nu_diag<double>(s, lv.g, lv.lc64, lv.ainvs64);
+    launch_nu_diag<float>(s, lv.g, lv.lc32, lv.ainvs32);
+    launch_schur_diag<double>(s, lv.g, lv.tb64, lv.ainvs64, h->schur, lv.dinv64);
+    launch_schur_diag<float>(s, lv.g, lv.tb32, lv.ainvs32, h->schur, lv.dinv32);
+    if (h->fmg_exec) {  // a captured solve holds the old operator
+      HHG_CHECK_HIP(hipGraphExecDestroy(h->fmg_exec));
+      h->fmg_exec = nullptr;
+      h->fmg_key.clear();
+    }
+    if (level == h->lmin) build_coarse_device(h);
+    HHG_CHECK_HIP(hipStreamSynchronize(s));
+  });
+}
+
+hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_params* prm, hhg_prec inner_prec,
+                        int inner_cycles, double rtol, int max_outer, hhg_stats* stats) {
+  return guard([&] {
+    HHG_REQUIRE(h && xv && bv && prm, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(inner_prec == HHG_F64 || inner_prec == HHG_F32, HHG_ERR_PREC, "inner precision must be F64 or F32");
+    HHG_REQUIRE(inner_cycles >= 1 && rtol > 0.0 && max_outer >= 1, HHG_ERR_ARG, "bad iteration parameters");
+    HHG_REQUIRE(prm->omega_inv > 0.0 && prm->xi >= 1, HHG_ERR_ARG, "bad solver parameters");
+    HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+    const int L = h->lmax;
+    Level& top = h->L(L);
+    hipStream_t s = S(h);
+    double* x = (double*)xv;
+    const double* b = (const double*)bv;
+    if (inner_prec == HHG_F32) ensure_f32_vectors(h);
+    double bu, bp, ru = 0, rp = 0;
+    norms<double>(h, L, b, &bu, &bp);
+    const double bn = std::sqrt(bu * bu + bp * bp);
+    int outer = 0, cycles = 0;
+    if (inner_prec == HHG_F64 && !top.dc_e) {
+      top.dc_e = h->arena.alloc<double>(top.vec_words);
+      top.dc_r = h->arena.alloc<double>(top.vec_words);
+    }
+    for (;;) {
+      op_apply<double>(h, L, full_mask(h), x, b, top.r, true, true, true);   // r = b - A x (float64)
+      norms<double>(h, L, top.r, &ru, &rp);
+      if (std::sqrt(ru * ru + rp * rp) <= rtol * bn || outer >= max_outer) break;
+      if (inner_prec == HHG_F32) {
+        launch_to_f32(s, top.r, top.cb32, top.vec_words);                     // RNE
+        launch_fill<float>(s, top.cx32, top.vec_words, 0.0f);
+        for (int c = 0; c < inner_cycles; ++c) vcycle_t<float>(h, L, L, top.cx32, top.cb32, *prm);
+        launch_add_f32_to_f64(s, x, top.cx32, top.vec_words);
+      } else {  // the V-cycle uses top.r as its own residual vector: keep the rhs apart
+        HHG_CHECK_HIP(hipMemcpyAsync(top.dc_r, top.r, top.vec_words * sizeof(double), hipMemcpyDeviceToDevice, s));
+        launch_fill<double>(s, top.dc_e, top.vec_words, 0.0);
+        for (int c = 0; c < inner_cycles; ++c) vcycle_t<double>(h, L, L, top.dc_e, top.dc_r, *prm);
+        launch_axpy<double>(s, x, top.dc_e, top.vec_words, 1.0);
+      }
+      op_mean_zero<double>(h, L, x);
+      ++outer;
+      cycles += inner_cycles;
+    }
+    HHG_CHECK_HIP(hipGetLastError());
+    if (stats) {
+      stats->cycles = cycles;
+      stats->res_u = ru;
+      stats->res_p = rp;
+      stats->rel_res = bn > 0 ? std::sqrt(ru * ru + rp * rp) / bn : 0.0;
+      stats->work_units = cycles * vcycle_work_units(h, *prm);
+    }
+    if (std::sqrt(ru * ru + rp * rp) > rtol * bn)
+      throw Error{HHG_ERR_NOT_CONVERGED, "relative residual above rtol after max_outer corrections"};
   });
 }
 

@@ -103,6 +103,96 @@ void emit_pp(FILE* f, const char* name, const Row& r) {
   std::fprintf(f, "  (void)nn;\n}\n// %zu entries\n\n", r.size());
 }
 
+// Variable viscosity (A weighted by nu_T = mean of nu at the element's four
+// vertices): the row of velocity group g at index (i,j,k) summed element by
+// element over the lattice elements containing it.  nu is read at P1 indices
+// relative to idx = i + s1 j + s2 k; u at group arrays relative to pos.
+struct ElemRow {
+  int vo[4][3];                 // element vertices, P1 offsets from (i,j,k)
+  std::vector<Entry> cols;      // element-local row: column (group, offset), weight
+  double diag;                  // K[a][a]
+};
+
+std::vector<ElemRow> element_rows(const ElementSet& es, int g) {
+  const int kDir[8][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
+  const int vs = es.vorder;
+  const int i = 3, j = 3, k = 3;
+  int rpos[3];
+  for (int d = 0; d < 3; ++d) rpos[d] = vs == 1 ? 3 : 2 * 3 + kDir[g][d];
+  std::vector<ElemRow> out;
+  for (int ck = k - 1; ck <= k + 1; ++ck)
+    for (int cj = j - 1; cj <= j + 1; ++cj)
+      for (int ci = i - 1; ci <= i + 1; ++ci)
+        for (int t = 0; t < 6; ++t) {
+          const int org[3] = {ci, cj, ck};
+          int a = -1;
+          for (int q = 0; q < es.nloc; ++q) {
+            bool m = true;
+            for (int d = 0; d < 3; ++d) m &= org[d] * vs + es.vpos[t][q][d] == rpos[d];
+            if (m) a = q;
+          }
+          if (a < 0) continue;
+          ElemRow er;
+          for (int v = 0; v < 4; ++v)
+            for (int d = 0; d < 3; ++d) er.vo[v][d] = org[d] + es.ppos[t][v][d] - (d == 0 ? i : d == 1 ? j : k);
+          er.diag = es.K[t][a][a];
+          for (int b = 0; b < es.nloc; ++b) {
+            if (es.K[t][a][b] == 0.0) continue;
+            Entry e{};
+            int sp[3];
+            for (int d = 0; d < 3; ++d) sp[d] = org[d] * vs + es.vpos[t][b][d];
+            if (vs == 1) {
+              e.g = 0;
+              e.di = sp[0] - i, e.dj = sp[1] - j, e.dk = sp[2] - k;
+            } else {
+              int par[3] = {sp[0] & 1, sp[1] & 1, sp[2] & 1};
+              for (int q = 0; q < 8; ++q)
+                if (kDir[q][0] == par[0] && kDir[q][1] == par[1] && kDir[q][2] == par[2]) e.g = q;
+              e.di = (sp[0] >> 1) - i, e.dj = (sp[1] >> 1) - j, e.dk = (sp[2] >> 1) - k;
+            }
+            e.w[0] = es.K[t][a][b];
+            er.cols.push_back(e);
+          }
+          out.push_back(er);
+        }
+  return out;
+}
+
+void emit_anu(FILE* f, const char* name, const std::vector<ElemRow>& rows, int g) {
+  std::fprintf(f,
+               "template <typename T>\n__device__ __forceinline__ void %s(const T* __restrict__ u0, const T* "
+               "__restrict__ u1, const T* __restrict__ u2, const T* __restrict__ nu, int pos, int idx, int s1, int s2, "
+               "int nn, T& a0, T& a1, T& a2) {\n",
+               name);
+  for (auto& er : rows) {
+    std::fprintf(f, "  {\n    const T nt = T(0.25) * (");
+    for (int v = 0; v < 4; ++v)
+      std::fprintf(f, "%snu[idx + (%d) + (%d) * s1 + (%d) * s2]", v ? " + " : "", er.vo[v][0], er.vo[v][1],
+                   er.vo[v][2]);
+    std::fprintf(f, ");\n    T b0 = 0, b1 = 0, b2 = 0;\n");
+    for (auto& e : er.cols)
+      std::fprintf(f, "    { const int o = pos + %s; const T w = T(%s); b0 += w * u0[o]; b1 += w * u1[o]; b2 += w * u2[o]; }\n",
+                   off_expr(e, g, true).c_str(), lit(e.w[0]).c_str());
+    std::fprintf(f, "    a0 += nt * b0; a1 += nt * b1; a2 += nt * b2;\n  }\n");
+  }
+  std::fprintf(f, "}\n// %zu elements\n\n", rows.size());
+}
+
+void emit_anu_diag(FILE* f, const char* name, const std::vector<ElemRow>& rows) {
+  std::fprintf(f,
+               "template <typename T>\n__device__ __forceinline__ T %s(const T* __restrict__ nu, int idx, int s1, int s2) "
+               "{\n  T d = 0;\n",
+               name);
+  for (auto& er : rows) {
+    std::fprintf(f, "  d += T(%s) * T(0.25) * (", lit(er.diag).c_str());
+    for (int v = 0; v < 4; ++v)
+      std::fprintf(f, "%snu[idx + (%d) + (%d) * s1 + (%d) * s2]", v ? " + " : "", er.vo[v][0], er.vo[v][1],
+                   er.vo[v][2]);
+    std::fprintf(f, ");\n");
+  }
+  std::fprintf(f, "  return d;\n}\n\n");
+}
+
 double diag_of(const Row& r, int g) {
   for (auto& e : r)
     if (e.g == g && e.di == 0 && e.dj == 0 && e.dk == 0) return e.w[0];
@@ -136,6 +226,11 @@ int main(int argc, char** argv) {
       std::snprintf(name, sizeof name, "%s_BT_g%d", D, g);
       emit_vp(f, name, BT);
       std::fprintf(f, "constexpr double %s_ADIAG_g%d = %s;\n\n", D, g, lit(diag_of(A, g)).c_str());
+      auto er = element_rows(es, g);
+      std::snprintf(name, sizeof name, "%s_Anu_g%d", D, g);
+      emit_anu(f, name, er, g);
+      std::snprintf(name, sizeof name, "%s_Anudiag_g%d", D, g);
+      emit_anu_diag(f, name, er);
     }
     Row B = pruned(es, 'B', 0, 3);
     std::snprintf(name, sizeof name, "%s_B", D);

@@ -13,10 +13,14 @@ struct Geom {
 // Per-level constants of the generated interior stencils (weights at h = 1):
 // A scales by h, B and B^T by h^2, PSPG C by delta (1/6)^(2/3) h^3, masses by
 // h^3; ainv[g] = 1 / (a * A_gg).
+// Variable viscosity: nu (P1 nodes, nn words) and ainv_site (1 / a_ii per
+// velocity site, G nn words); both null for the constant-coefficient rows.
 template <typename T>
 struct LevelConst {
   T a, b, c, m;
   T ainv[8];
+  const T* nu;
+  const T* ainv_site;
 };
 
 // Stencil tables of one level in one precision (device pointers inside).
@@ -85,8 +89,9 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* 
 template <typename T>
 void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, const T* rp, T omega);
 template <typename T>
-void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const int* bnd, int nbnd, int mode,
-                       T* dinv);
+void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* ainv_site, int mode, T* dinv);
+template <typename T>
+void launch_nu_diag(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* ainv_site);
 template <typename T>
 void launch_rhs(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T* fnod, T* b);
 template <typename T>
@@ -114,8 +119,10 @@ template <typename T>
 void launch_pshift(hipStream_t s, const Geom& g, T* p, const double* sums, int mode);
 template <typename T>
 void launch_vsumsq(hipStream_t s, const Geom& g, const T* x, int nwords, double* partial, double* out);
-void launch_coarse(hipStream_t s, const Geom& g, const double* Kp, const int* unk, int nunk, const double* r,
-                   double* x, const double* mweights);
+template <typename T>
+void launch_coarse(hipStream_t s, const double* Kp, const int* unk, int nunk, const T* r, T* x);
+void launch_to_f32(hipStream_t s, const double* x, float* y, size_t n);
+void launch_add_f32_to_f64(hipStream_t s, double* y, const float* e, size_t n);
 template <typename T>
 void launch_scale(hipStream_t s, T* x, size_t n, const double* sums, int slot);
 template <typename T>

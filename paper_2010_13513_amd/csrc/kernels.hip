@@ -101,6 +101,13 @@ struct Rows<T, 1> {
   static __device__ __forceinline__ void C(const T* p, int pos, int s1, int s2, T& a) {
     gen::p1_C<T>(p, pos, s1, s2, a);
   }
+  static __device__ __forceinline__ void Anu(int, const T* u0, const T* u1, const T* u2, const T* nu, int pos, int idx,
+                                             int s1, int s2, int nn, T& a0, T& a1, T& a2) {
+    gen::p1_Anu_g0<T>(u0, u1, u2, nu, pos, idx, s1, s2, nn, a0, a1, a2);
+  }
+  static __device__ __forceinline__ T Anudiag(int, const T* nu, int idx, int s1, int s2) {
+    return gen::p1_Anudiag_g0<T>(nu, idx, s1, s2);
+  }
 };
 
 #define HHG_P2_CASES(F, ...)        \
@@ -133,6 +140,24 @@ struct Rows<T, 8> {
     gen::p2_B<T>(u0, u1, u2, pos, s1, s2, nn, a);
   }
   static __device__ __forceinline__ void C(const T*, int, int, int, T&) {}
+  static __device__ __forceinline__ void Anu(int g, const T* u0, const T* u1, const T* u2, const T* nu, int pos,
+                                             int idx, int s1, int s2, int nn, T& a0, T& a1, T& a2) {
+    HHG_P2_CASES(p2_Anu, u0, u1, u2, nu, pos, idx, s1, s2, nn, a0, a1, a2)
+  }
+  static __device__ __forceinline__ T Anudiag(int g, const T* nu, int idx, int s1, int s2) {
+    T d = 0;
+    switch (g) {
+      case 0: d = gen::p2_Anudiag_g0<T>(nu, idx, s1, s2); break;
+      case 1: d = gen::p2_Anudiag_g1<T>(nu, idx, s1, s2); break;
+      case 2: d = gen::p2_Anudiag_g2<T>(nu, idx, s1, s2); break;
+      case 3: d = gen::p2_Anudiag_g3<T>(nu, idx, s1, s2); break;
+      case 4: d = gen::p2_Anudiag_g4<T>(nu, idx, s1, s2); break;
+      case 5: d = gen::p2_Anudiag_g5<T>(nu, idx, s1, s2); break;
+      case 6: d = gen::p2_Anudiag_g6<T>(nu, idx, s1, s2); break;
+      default: d = gen::p2_Anudiag_g7<T>(nu, idx, s1, s2); break;
+    }
+    return d;
+  }
 };
 
 // ---------------------------------------------------------------- apply
@@ -147,7 +172,7 @@ __device__ __forceinline__ int xcd_block() {
 unsigned nblocks8(size_t n) { return (unsigned)(((n + kBlock - 1) / kBlock + 7) & ~(size_t)7); }
 
 // One velocity row type (group GR) of the apply at array index t.
-template <typename T, int G, int GR>
+template <typename T, int G, int GR, bool VAR>
 __device__ __forceinline__ void apply_vrow(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
                                            const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b, int t,
                                            int i, int j, int k) {
@@ -161,7 +186,12 @@ __device__ __forceinline__ void apply_vrow(const Geom& g, const LevelConst<T>& l
   T r0 = 0, r1 = 0, r2 = 0;
   if (in) {
     T a0 = 0, a1 = 0, a2 = 0, c0 = 0, c1 = 0, c2 = 0;
-    if (opmask & 1) Rows<T, G>::A(GR, u0, u1, u2, pos, s1, s2, nn, a0, a1, a2);
+    if (opmask & 1) {
+      if constexpr (VAR)
+        Rows<T, G>::Anu(GR, u0, u1, u2, lc.nu, pos, t, s1, s2, nn, a0, a1, a2);
+      else
+        Rows<T, G>::A(GR, u0, u1, u2, pos, s1, s2, nn, a0, a1, a2);
+    }
     if (opmask & 2) Rows<T, G>::BT(GR, p, t, s1, s2, c0, c1, c2);
     r0 = lc.a * a0 + lc.b * c0;
     r1 = lc.a * a1 + lc.b * c1;
@@ -177,18 +207,18 @@ __device__ __forceinline__ void apply_vrow(const Geom& g, const LevelConst<T>& l
   y[2 * g.vstride + pos] = r2;
 }
 
-template <typename T, int G, int GR>
+template <typename T, int G, int GR, bool VAR>
 __device__ __forceinline__ void apply_vrows(const Geom& g, const LevelConst<T>& lc, const T* x, const T* b, T* y,
                                             int opmask, int has_b, int t, int i, int j, int k) {
-  apply_vrow<T, G, GR>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
-  if constexpr (GR + 1 < G) apply_vrows<T, G, GR + 1>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
+  apply_vrow<T, G, GR, VAR>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
+  if constexpr (GR + 1 < G) apply_vrows<T, G, GR + 1, VAR>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
 }
 
 // y = [b -] op x on every row type at array index t: the G velocity groups
 // (zero rows where the site is not an interior velocity DoF) and the interior
 // pressure row (boundary pressure rows: k_prow_bnd).  opmask bits: 1 A, 2 B^T,
 // 4 B, 8 -C (block of calA), 16: +C instead.
-template <typename T, int G>
+template <typename T, int G, bool VAR>
 __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, const T* __restrict__ x,
                                                   const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
                                                   int vel_rows, int p_rows) {
@@ -197,7 +227,7 @@ __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, cons
   int i, j, k;
   decode(t, g.n1, i, j, k);
   const int N = g.N;
-  if (vel_rows) apply_vrows<T, G, 0>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
+  if (vel_rows) apply_vrows<T, G, 0, VAR>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
   if (p_rows && i >= 1 && j >= 1 && k >= 1 && i <= N - 1 && j <= N - 1 && k <= N - 1) {
     const int s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
     const T* __restrict__ u0 = x;
@@ -251,7 +281,7 @@ __global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __
 // Gauss-Seidel kernels give each velocity component its own thread
 // (blockIdx.y) so a colour of a small level spreads over three times as many
 // waves.  Component d reads u_d, p and writes u_d only (A is block diagonal).
-template <typename T, int G>
+template <typename T, int G, bool VAR>
 __device__ __forceinline__ void gs_update(const Geom& g, const LevelConst<T>& lc, T* __restrict__ x,
                                           const T* __restrict__ b, int gr, int idx, int d) {
   const int s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
@@ -260,15 +290,22 @@ __device__ __forceinline__ void gs_update(const Geom& g, const LevelConst<T>& lc
   const T* p = x + 3 * g.vstride;
   T a0 = 0, a1 = 0, a2 = 0, c0 = 0, c1 = 0, c2 = 0;
   // same pointer for the three component slots: only slot d is used
-  Rows<T, G>::A(gr, ud, ud, ud, pos, s1, s2, nn, a0, a1, a2);
+  T ai;
+  if constexpr (VAR) {
+    Rows<T, G>::Anu(gr, ud, ud, ud, lc.nu, pos, idx, s1, s2, nn, a0, a1, a2);
+    ai = lc.ainv_site[pos];
+  } else {
+    Rows<T, G>::A(gr, ud, ud, ud, pos, s1, s2, nn, a0, a1, a2);
+    ai = lc.ainv[gr];
+  }
   Rows<T, G>::BT(gr, p, idx, s1, s2, c0, c1, c2);
   const T c = d == 0 ? c0 : (d == 1 ? c1 : c2);
-  ud[pos] += (b[d * g.vstride + pos] - lc.a * a0 - lc.b * c) * lc.ainv[gr];
+  ud[pos] += (b[d * g.vstride + pos] - lc.a * a0 - lc.b * c) * ai;
 }
 
 // One colour of the vertex group: interior nodes with (i+j+k) mod 4 == c.
 // u_d += (f_d - (A u_d) - (B^T p)_d) / a_gg.
-template <typename T, int G>
+template <typename T, int G, bool VAR>
 __global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, LevelConst<T> lc, T* __restrict__ x,
                                                       const T* __restrict__ b, int c) {
   const int N = g.N, nr = N - 1, ni = (nr + 3) >> 2;
@@ -278,11 +315,11 @@ __global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, LevelConst<T> lc, 
   const int j = 1 + row % nr, k = 1 + row / nr;
   const int i = 1 + ((((c - 1 - j - k) % 4) + 4) & 3) + 4 * ip;
   if (i > N - 1) return;
-  gs_update<T, G>(g, lc, x, b, 0, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
+  gs_update<T, G, VAR>(g, lc, x, b, 0, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
 }
 
 // One edge group (one colour) of the P2 velocity: all interior sites of group gr.
-template <typename T>
+template <typename T, bool VAR>
 __global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, LevelConst<T> lc, T* __restrict__ x,
                                                     const T* __restrict__ b, int gr) {
   const int N = g.N;
@@ -294,7 +331,7 @@ __global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, LevelConst<T> lc, T*
   const int r = t / cx;
   const int j = 1 - dy + r % cy;
   const int k = 1 - dz + r / cy;
-  gs_update<T, 8>(g, lc, x, b, gr, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
+  gs_update<T, 8, VAR>(g, lc, x, b, gr, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
 }
 
 // p <- p - omega * dinv * rp (eq. uzawa-pressure with S_hat = omega^{-1} D).
@@ -309,7 +346,8 @@ __global__ void __launch_bounds__(kBlock) k_pstep(int nn, const T* __restrict__ 
 // Schur diagonal per pressure node: mode 0: C_kk + sum_d sum_{j interior}
 // B_dkj^2 / A_jj; mode 1: int psi_k.  Writes 1 / D_k.
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_schur_diag(Geom g, const Tables<T>* __restrict__ tb, int mode,
+__global__ void __launch_bounds__(kBlock) k_schur_diag(Geom g, const Tables<T>* __restrict__ tb,
+                                                       const T* __restrict__ ainv_site, int mode,
                                                        T* __restrict__ dinv) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= g.nn) return;
@@ -332,10 +370,27 @@ __global__ void __launch_bounds__(kBlock) k_schur_diag(Geom g, const Tables<T>* 
       const int ii = i + ((cc >> 4) & 15) - 2, jj = j + ((cc >> 8) & 15) - 2, kk = k + ((cc >> 12) & 15) - 2;
       if (!vel_interior<G>(gr, ii, jj, kk, N)) continue;
       const double w0 = s.w[3 * e], w1 = s.w[3 * e + 1], w2 = s.w[3 * e + 2];
-      d += (w0 * w0 + w1 * w1 + w2 * w2) * (double)tb->adiag_inv[gr];
+      const double ai = ainv_site ? (double)ainv_site[gr * g.nn + ii + g.n1 * (jj + g.n1 * kk)]
+                                  : (double)tb->adiag_inv[gr];
+      d += (w0 * w0 + w1 * w1 + w2 * w2) * ai;
     }
   }
   dinv[t] = (T)(1.0 / d);
+}
+
+// 1 / a_ii for every interior velocity site with variable viscosity (0 elsewhere).
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_nu_diag(Geom g, LevelConst<T> lc, T* __restrict__ ainv_site) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  int i, j, k;
+  decode(t, g.n1, i, j, k);
+  for (int gr = 0; gr < G; ++gr) {
+    T v = 0;
+    if (vel_interior<G>(gr, i, j, k, g.N))
+      v = T(1) / (lc.a * Rows<T, G>::Anudiag(gr, lc.nu, t, g.n1, g.n1 * g.n1));
+    ainv_site[gr * g.nn + t] = v;
+  }
 }
 
 // b = M f on interior velocity rows (velocity mass, interior stencil), 0 on
@@ -715,18 +770,34 @@ __global__ void __launch_bounds__(kBlock) k_axpy(T* __restrict__ y, const T* __r
   if (t < n) y[t] += a * x[t];
 }
 
-// Coarsest level: x[unk] += Kp r[unk] (one workgroup, unknowns staged in LDS).
+// Coarsest level: x[unk] += Kp r[unk] (one workgroup, unknowns staged in LDS,
+// float64 arithmetic whatever the storage type T).
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse(const double* __restrict__ Kp, const int* __restrict__ unk, int n,
-                                                   const double* __restrict__ r, double* __restrict__ x) {
+                                                   const T* __restrict__ r, T* __restrict__ x) {
   __shared__ double rs[2048];
-  for (int c = threadIdx.x; c < n; c += kBlock) rs[c] = r[unk[c]];
+  for (int c = threadIdx.x; c < n; c += kBlock) rs[c] = (double)r[unk[c]];
   __syncthreads();
   for (int row = threadIdx.x; row < n; row += kBlock) {
     const double* kr = Kp + (size_t)row * n;
     double acc = 0.0;
     for (int c = 0; c < n; ++c) acc += kr[c] * rs[c];
-    x[unk[row]] += acc;
+    x[unk[row]] = (T)((double)x[unk[row]] + acc);
   }
+}
+
+// y (precision Y) = x (precision X), round to nearest even when narrowing.
+template <typename X, typename Y>
+__global__ void __launch_bounds__(kBlock) k_convert(const X* __restrict__ x, Y* __restrict__ y, long n) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) y[t] = (Y)x[t];
+}
+
+// y += (double) e
+template <typename X>
+__global__ void __launch_bounds__(kBlock) k_add_to_f64(double* __restrict__ y, const X* __restrict__ e, long n) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) y[t] += (double)e[t];
 }
 
 }  // namespace
@@ -744,10 +815,19 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
                   T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd) {
   if (vel_rows || p_rows) {
     KScope ks(s, KF_APPLY, p_sites(g));
-    if (g.G == 1)
-      HHG_LAUNCH((k_apply<T, 1>), nblocks8(g.nn), s, g, lc, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
-    else
-      HHG_LAUNCH((k_apply<T, 8>), nblocks8(g.nn), s, g, lc, x, b, y, opmask, (int)has_b, (int)vel_rows, (int)p_rows);
+    const unsigned nb = nblocks8(g.nn);
+    const int hb = has_b, vr = vel_rows, pr = p_rows;
+    if (g.G == 1) {
+      if (lc.nu)
+        HHG_LAUNCH((k_apply<T, 1, true>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+      else
+        HHG_LAUNCH((k_apply<T, 1, false>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+    } else {
+      if (lc.nu)
+        HHG_LAUNCH((k_apply<T, 8, true>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+      else
+        HHG_LAUNCH((k_apply<T, 8, false>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+    }
   }
   if (p_rows && nbnd > 0) {
     KScope ks(s, KF_PROW_BND, nbnd);
@@ -770,15 +850,25 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* 
         }
     KScope ks(s, KF_GS_VERTEX, cnt);
     const dim3 grid(nblocks((size_t)ni * nr * nr), 3);
-    if (g.G == 1)
-      hipLaunchKernelGGL((k_gs_vertex<T, 1>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
-    else
-      hipLaunchKernelGGL((k_gs_vertex<T, 8>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+    if (g.G == 1) {
+      if (lc.nu)
+        hipLaunchKernelGGL((k_gs_vertex<T, 1, true>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+      else
+        hipLaunchKernelGGL((k_gs_vertex<T, 1, false>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+    } else {
+      if (lc.nu)
+        hipLaunchKernelGGL((k_gs_vertex<T, 8, true>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+      else
+        hipLaunchKernelGGL((k_gs_vertex<T, 8, false>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+    }
   } else {
     const int gr = colour - 3;
     const size_t n = (size_t)(N - 1 + ((0xB2 >> gr) & 1)) * (N - 1 + ((0xD4 >> gr) & 1)) * (N - 1 + ((0xE8 >> gr) & 1));
     KScope ks(s, KF_GS_EDGE, (double)n);
-    hipLaunchKernelGGL((k_gs_edge<T>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, lc, x, b, gr);
+    if (lc.nu)
+      hipLaunchKernelGGL((k_gs_edge<T, true>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, lc, x, b, gr);
+    else
+      hipLaunchKernelGGL((k_gs_edge<T, false>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, lc, x, b, gr);
   }
 }
 
@@ -789,11 +879,19 @@ void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, con
 }
 
 template <typename T>
-void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const int*, int, int mode, T* dinv) {
+void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* ainv_site, int mode, T* dinv) {
   if (g.G == 1)
-    HHG_LAUNCH((k_schur_diag<T, 1>), nblocks(g.nn), s, g, tb, mode, dinv);
+    HHG_LAUNCH((k_schur_diag<T, 1>), nblocks(g.nn), s, g, tb, ainv_site, mode, dinv);
   else
-    HHG_LAUNCH((k_schur_diag<T, 8>), nblocks(g.nn), s, g, tb, mode, dinv);
+    HHG_LAUNCH((k_schur_diag<T, 8>), nblocks(g.nn), s, g, tb, ainv_site, mode, dinv);
+}
+
+template <typename T>
+void launch_nu_diag(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* ainv_site) {
+  if (g.G == 1)
+    HHG_LAUNCH((k_nu_diag<T, 1>), nblocks(g.nn), s, g, lc, ainv_site);
+  else
+    HHG_LAUNCH((k_nu_diag<T, 8>), nblocks(g.nn), s, g, lc, ainv_site);
 }
 
 template <typename T>
@@ -909,10 +1007,18 @@ void launch_vsumsq(hipStream_t s, const Geom&, const T* x, int nwords, double* p
   HHG_LAUNCH(k_final_sum, 1, s, partial, nb, out);
 }
 
-void launch_coarse(hipStream_t s, const Geom&, const double* Kp, const int* unk, int nunk, const double* r, double* x,
-                   const double*) {
+template <typename T>
+void launch_coarse(hipStream_t s, const double* Kp, const int* unk, int nunk, const T* r, T* x) {
   KScope ks(s, KF_COARSE, nunk);
-  HHG_LAUNCH(k_coarse, 1, s, Kp, unk, nunk, r, x);
+  HHG_LAUNCH((k_coarse<T>), 1, s, Kp, unk, nunk, r, x);
+}
+
+void launch_to_f32(hipStream_t s, const double* x, float* y, size_t n) {
+  if (n) HHG_LAUNCH((k_convert<double, float>), nblocks(n), s, x, y, (long)n);
+}
+
+void launch_add_f32_to_f64(hipStream_t s, double* y, const float* e, size_t n) {
+  if (n) HHG_LAUNCH((k_add_to_f64<float>), nblocks(n), s, y, e, (long)n);
 }
 
 template <typename T>
@@ -940,7 +1046,8 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
                                 const T*, T*, int, bool, bool, bool, const int*, int);                              \
   template void launch_gs_colour<T>(hipStream_t, const Geom&, const LevelConst<T>&, T*, const T*, int);             \
   template void launch_pressure_step<T>(hipStream_t, const Geom&, const T*, T*, const T*, T);                       \
-  template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const int*, int, int, T*);         \
+  template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, int, T*);                \
+  template void launch_nu_diag<T>(hipStream_t, const Geom&, const LevelConst<T>&, T*);                              \
   template void launch_rhs<T>(hipStream_t, const Geom&, const LevelConst<T>&, const T*, T*);                        \
   template void launch_mass<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                           \
   template void launch_dot<T>(hipStream_t, const T*, const T*, size_t, double*, double*);                           \
@@ -956,6 +1063,7 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
   template void launch_vsumsq<T>(hipStream_t, const Geom&, const T*, int, double*, double*);                        \
   template void launch_scale<T>(hipStream_t, T*, size_t, const double*, int);                                       \
   template void launch_fill<T>(hipStream_t, T*, size_t, T);                                                         \
+  template void launch_coarse<T>(hipStream_t, const double*, const int*, int, const T*, T*);                        \
   template void launch_scaled_copy<T>(hipStream_t, T*, const T*, const T*, size_t, T);                              \
   template void launch_axpy<T>(hipStream_t, T*, const T*, size_t, T);
 

@@ -24,7 +24,7 @@ SYMBOLS = [
     "hhg_apply", "hhg_residual", "hhg_rhs", "hhg_smooth", "hhg_restrict", "hhg_prolong_add",
     "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
     "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation", "hhg_dots",
-    "hhg_timer_start", "hhg_timer_read",
+    "hhg_timer_start", "hhg_timer_read", "hhg_dc_solve", "hhg_set_viscosity",
 ]
 KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER = \
     range(10)
@@ -87,6 +87,8 @@ def load():
         "hhg_dots": [P, I, P, P, P, P, I],
         "hhg_timer_start": [ctypes.c_uint],
         "hhg_timer_read": [I, P, P, P],
+        "hhg_dc_solve": [P, P, P, P, I, I, D, I, P],
+        "hhg_set_viscosity": [P, I, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -204,6 +206,21 @@ def hhg_norms(h, level, x, prec=HHG_F64):
     nu, np_ = ctypes.c_double(), ctypes.c_double()
     _check(load().hhg_norms(h, level, _ptr(x), ctypes.byref(nu), ctypes.byref(np_), prec))
     return nu.value, np_.value
+
+
+def hhg_set_viscosity(h, level, nu):
+    _check(load().hhg_set_viscosity(h, level, _ptr(nu)))
+
+
+def hhg_dc_solve(h, x, b, prm, inner_prec=HHG_F32, inner_cycles=1, rtol=1e-12, max_outer=100, check=True):
+    """Returns the stats; with check=False a tolerance miss (HHG_ERR_NOT_CONVERGED)
+    is reported in the stats instead of raised."""
+    st = Stats()
+    rc = load().hhg_dc_solve(h, _ptr(x), _ptr(b), ctypes.byref(prm), inner_prec, inner_cycles, float(rtol),
+                             max_outer, ctypes.byref(st))
+    if rc != HHG_OK and (check or rc != HHG_ERR_NOT_CONVERGED):
+        _check(rc)
+    return st
 
 
 def hhg_dots(h, level, x, y, prec=HHG_F64):

@@ -1,0 +1,111 @@
+"""GPU parity with variable viscosity (on-the-fly element-wise A rows) and
+the mixed-precision defect correction, against the float64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import fe, mesh, multigrid as mg, smoother as osm
+from oracle.stokes import Stokes
+from paper_2010_13513_amd import hhg, workloads as W
+from tests.gpu_util import Lib, rel_err
+
+pytestmark = pytest.mark.gpu
+
+P1, P2 = hhg.HHG_P1P1, hhg.HHG_P2P1
+NU = W.gaussian_bump_viscosity(W.SEED_BASE + 4000, N_ref=32)
+
+
+def _nu_nodes(N):
+    c = mesh.p1_coords(N) / float(N)
+    return NU(c[:, 0], c[:, 1], c[:, 2])
+
+
+def _set_nu(lib, lmin, lmax):
+    torch = lib.torch
+    for l in range(lmin, lmax + 1):
+        hhg.hhg_set_viscosity(lib.h, l, torch.from_numpy(_nu_nodes(2 ** l)).to(lib.dev))
+
+
+@pytest.fixture(scope="module")
+def libs():
+    cache = {}
+
+    def get(disc, lmin, lmax, varnu=True):
+        key = (disc, lmin, lmax, varnu)
+        if key not in cache:
+            lib = Lib(disc, lmin, lmax)
+            if varnu:
+                _set_nu(lib, lmin, lmax)
+            cache[key] = lib
+        return cache[key]
+    yield get
+    for lib in cache.values():
+        lib.close()
+
+
+@pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 3), (P1, 0, 4), (P2, 1, 3)])
+@pytest.mark.parametrize("op", ["FULL", "A"])
+def test_apply_variable_viscosity(libs, disc, lmin, L, op):
+    lib = libs(disc, lmin, L)
+    vo = 1 if disc == P1 else 2
+    S = Stokes(fe.Level(2 ** L, vo, _nu_nodes(2 ** L)))
+    x = W.normal_vector(300 + L, S.n)
+    dy = lib.empty(L)
+    hhg.hhg_apply(lib.h, L, hhg.HHG_OP_FULL if op == "FULL" else hhg.HHG_OP_A, lib.from_lattice(L, x), dy)
+    want = S.apply(x) if op == "FULL" else S.apply_block(x, "A")
+    assert rel_err(lib.to_lattice(L, dy), want) < 1e-12
+
+
+@pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 3), (P2, 1, 3)])
+def test_smooth_variable_viscosity(libs, disc, lmin, L):
+    lib = libs(disc, lmin, L)
+    vo = 1 if disc == P1 else 2
+    S = Stokes(fe.Level(2 ** L, vo, _nu_nodes(2 ** L)))
+    U = osm.Uzawa(S, "sd")
+    x = W.normal_vector(310, S.n)
+    b = S.zero_boundary(W.normal_vector(311, S.n))
+    want = x
+    for _ in range(2):
+        want = U.iterate(want, b, "f", 2, 0.5)
+    dx = lib.from_lattice(L, x)
+    hhg.hhg_smooth(lib.h, L, dx, lib.from_lattice(L, b), 2, hhg.HHG_GS_FWD, 2, 2.0)
+    assert rel_err(lib.to_lattice(L, dx), want) < 1e-10
+
+
+@pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 3), (P2, 1, 3)])
+def test_fmg_variable_viscosity(libs, disc, lmin, L):
+    """Whole FMG with variable viscosity (coarse pseudo-inverse rebuilt from
+    the device operator) against the oracle hierarchy with the same nu."""
+    lib = libs(disc, lmin, L)
+    vo = 1 if disc == P1 else 2
+    H = mg.Hierarchy(vo, lmin, L, nu_fn=NU, schur="sd")
+    prob = W.fourier_forcing(W.SEED_BASE + 2000)
+    s = (1, 2, 1, 1, "f", 2)
+    om = 2.3
+    want = H.fmg(prob, mg.Params(*s, omega_inv=om), cycles_on_finest=1)
+    bs = [lib.from_lattice(l, H.rhs(l, prob)) for l in range(lmin, L + 1)]
+    dx = lib.from_lattice(L, H.initial(L, prob))
+    hhg.hhg_fmg_solve(lib.h, dx, bs, hhg.solver_params(1, 2, 1, 1, hhg.HHG_GS_FWD, 2, om, extra_cycles=1))
+    assert rel_err(lib.to_lattice(L, dx), want) < 1e-9
+
+
+@pytest.mark.parametrize("disc,lmin,L,varnu", [(P1, 0, 3, False), (P2, 1, 3, True)])
+def test_defect_correction_float32(libs, disc, lmin, L, varnu):
+    """float32 inner V-cycles inside float64 defect correction reach the
+    float64 tolerance; the result equals the oracle's sparse direct solution
+    to the accuracy the tolerance implies, as does the all-float64 form."""
+    lib = libs(disc, lmin, L, varnu)
+    vo = 1 if disc == P1 else 2
+    H = mg.Hierarchy(vo, lmin, L, nu_fn=NU if varnu else None, schur="sd")
+    prob = W.fourier_forcing(W.SEED_BASE + 2000)
+    b = H.rhs(L, prob)
+    xd = H.exact_discrete(L, prob)
+    db = lib.from_lattice(L, b)
+    prm = hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 1 if disc == P1 else 3, 2.3)
+    out = {}
+    for prec in (hhg.HHG_F32, hhg.HHG_F64):
+        dx = lib.from_lattice(L, H.initial(L, prob))
+        st = hhg.hhg_dc_solve(lib.h, dx, db, prm, prec, 1, 1e-12, 200)
+        assert st.rel_res <= 1e-12
+        out[prec] = lib.to_lattice(L, dx)
+        assert rel_err(out[prec], xd) < 1e-7
+    assert rel_err(out[hhg.HHG_F32], out[hhg.HHG_F64]) < 1e-9
