@@ -62,6 +62,7 @@ enum {
 
 typedef struct hhg_ctx_s* hhg_ctx;
 typedef struct hhg_hier_s* hhg_hier;
+typedef struct hhg_mlp_s* hhg_mlp;
 
 typedef enum { HHG_P1P1 = 0, HHG_P2P1 = 1 } hhg_disc;
 typedef enum { HHG_F64 = 0, HHG_F32 = 1 } hhg_prec;
@@ -92,6 +93,7 @@ typedef struct {
   double res_u, res_p;    /* Euclidean norms of the final residual blocks    */
   double rel_res;         /* ||r|| / ||b||                                   */
   double work_units;      /* Sec. 4 model, in W(calA_L)                      */
+  int fallbacks;          /* learned coarse solve switched off (hhg_hier_set_mlp) */
 } hhg_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -242,6 +244,49 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* x, const void* const* b_levels, const
  * reached. */
 hhg_status hhg_dc_solve(hhg_hier h, void* x, const void* b, const hhg_solver_params* prm, hhg_prec inner_prec,
                         int inner_cycles, double rtol, int max_outer, hhg_stats* stats);
+
+/* ------------------------------------------------ learned coarse solve */
+/* Not in the paper: a dense network n_in -> H -> H -> H -> n_out (ReLU)
+ * that stands in for the exact coarse solve of Alg. fmg.  Weights and layer
+ * inputs are bfloat16 (round to nearest even), products run on the matrix
+ * cores with float32 accumulation, master weights and Adam moments are float32.
+ * Parameter order (host, float32): W1 (H x n_in, row-major), b1, W2, b2, W3,
+ * b3, W4 (n_out x H), b4.  max_batch bounds every batch.  The MLP belongs to a
+ * context; destroy it before the context. */
+hhg_status hhg_mlp_create(hhg_ctx ctx, int n_in, int n_hidden, int n_out, int max_batch, hhg_mlp* out);
+hhg_status hhg_mlp_destroy(hhg_mlp m);
+hhg_status hhg_mlp_num_params(hhg_mlp m, size_t* n);
+/* Copy parameters in (resets the Adam state) or out. */
+hhg_status hhg_mlp_set_params(hhg_mlp m, const float* host_params);
+hhg_status hhg_mlp_get_params(hhg_mlp m, float* host_params);
+/* y = net(x); x, y device float32, batch x n_in and batch x n_out. */
+hhg_status hhg_mlp_forward(hhg_mlp m, const float* x, int batch, float* y);
+/* Mean squared error over the n_out outputs of the batch and its gradient
+ * (host float32, parameter order) -- synchronous. */
+hhg_status hhg_mlp_loss_grad(hhg_mlp m, const float* x, const float* y, int batch, float* grad_host, double* loss);
+/* Adam (beta 0.9 / 0.999, eps 1e-8) over minibatches: for epoch e the samples
+ * order[e n_samples + i] (host, caller-drawn) are taken batch by batch; x, y
+ * device float32 datasets (n_samples rows).  last_loss: mean batch loss of the
+ * final epoch. */
+hhg_status hhg_mlp_train(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs, float lr,
+                         const int* order, double* last_loss);
+/* Feature and output sizes of the learned coarse solve of this hierarchy:
+ * n_out = coarse unknowns (interior velocity, then pressure), n_in = n_out +
+ * P1 nodes of the coarsest level. */
+hhg_status hhg_mlp_dims(hhg_hier h, int* n_in, int* n_out);
+/* One training pair from a coarsest-level vector r (device, float64, library
+ * layout): features = [r_unk / ||r_unk||, log nu at the coarse P1 nodes (0
+ * without viscosity)], target = (exact coarse correction)_unk / ||r_unk|| with
+ * the pressure at zero mean.  Outputs device float32. */
+hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* target);
+/* Attach (or detach with m = NULL) a network as the coarse solve of float64
+ * cycles: correction = ||r_unk|| net(features), then zero pressure mean.
+ * Fallback (hhg_fmg_solve with rtol > 0): a finest-level cycle whose residual
+ * ratio exceeds rho_plain (1 + tau), or is not finite, is undone and the rest
+ * of that solve uses the exact coarse solve (counted in stats->fallbacks).
+ * While a network is attached, hhg_set_viscosity on the coarsest level defers
+ * the pseudo-inverse rebuild to the first exact coarse solve. */
+hhg_status hhg_hier_set_mlp(hhg_hier h, hhg_mlp m, double rho_plain, double tau);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["api.hip", "kernels.hip", "fe_host.cpp"]
+SRC = ["api.hip", "kernels.hip", "mlp.hip", "fe_host.cpp"]
 GEN_SRC = ["gen_stencils.cpp", "fe_host.cpp"]
 GEN_OUT = os.path.join(HERE, "csrc", "generated", "stencils.inc")
 LIB = os.path.join(HERE, "libhhg.so")

@@ -11,9 +11,11 @@
 #include <map>
 #include <memory>
 #include <tuple>
+#include <type_traits>
 #include <unordered_map>
 
 #include "kernels.h"
+#include "mlp.h"
 
 namespace hhg {
 
@@ -107,6 +109,13 @@ struct Level {
 
 }  // namespace hhg
 
+struct hhg_mlp_s {
+  hhg_ctx ctx = nullptr;
+  hhg::Mlp net;
+  int* idx = nullptr;       // device minibatch indices
+  float *bx = nullptr, *by = nullptr;  // device minibatch
+};
+
 struct hhg_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -126,6 +135,15 @@ struct hhg_hier_s {
   double* partial = nullptr;
   double* sums = nullptr;   // device scratch for reductions (16 doubles)
   double* hsums = nullptr;  // pinned host copy
+  // learned coarse solve (optional)
+  hhg_mlp mlp = nullptr;
+  double rho_plain = 0.0, tau = 0.0;
+  bool mlp_off = false;      // fallback taken in the current solve
+  bool kp_stale = false;     // coarse pseudo-inverse not rebuilt for the current viscosity
+  float *feat = nullptr, *mlp_out = nullptr;
+  double* norm = nullptr;
+  double* bk = nullptr;      // copy of x before a monitored V-cycle
+  double *ce = nullptr, *cy = nullptr;  // coarse-operator assembly scratch
   // cached HIP graph of a fixed-work FMG solve (key: vectors + parameters)
   hipGraphExec_t fmg_exec = nullptr;
   std::vector<unsigned char> fmg_key;
@@ -548,8 +566,12 @@ void build_coarse_device(hhg_hier h) {
   if (h->nunk == 0) return;
   Level& lv = h->L(h->lmin);
   const int n = h->nunk;
-  double* e = lv.cx;
-  double* y = lv.cb;
+  if (!h->ce) {  // private vectors: callers may hold the coarse work vectors
+    h->ce = h->arena.alloc<double>(lv.vec_words);
+    h->cy = h->arena.alloc<double>(lv.vec_words);
+  }
+  double* e = h->ce;
+  double* y = h->cy;
   std::vector<double> K((size_t)n * n), col(lv.vec_words);
   const double one = 1.0;
   for (int c = 0; c < n; ++c) {
@@ -656,12 +678,32 @@ float* cbbuf<float>(Level& lv) {
 
 // Coarse solve x <- x + A0^+ (b - A0 x) on the unknowns (float64 GEMV for
 // either storage precision), then zero pressure mean.
+void build_coarse_device(hhg_hier h);
+
+// Coarse solve x <- x + A0^+ (b - A0 x) on the unknowns (float64 GEMV for
+// either storage precision), then zero pressure mean.  With an MLP attached
+// (float64 solves), the correction is ||r|| net([r / ||r||, log nu]) instead,
+// unless the fallback monitor has switched it off for this solve.
 template <typename T>
-void op_coarse(hhg_hier h, T* x, const T* b) {
+void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true) {
   HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "coarsest level has more than 2048 unknowns: no dense coarse solve");
   Level& lv = h->L(h->lmin);
   T* r = rbuf<T>(lv);
   op_apply<T>(h, h->lmin, full_mask(h), x, b, r, true, true, true);
+  if constexpr (std::is_same<T, double>::value) {
+    if (allow_mlp && h->mlp && !h->mlp_off) {
+      launch_coarse_features(S(h), r, h->unk, h->nunk, lv.nu64, lv.g.nn, h->feat, h->norm);
+      h->mlp->net.forward(S(h), h->feat, 1, h->mlp_out);
+      launch_coarse_scatter(S(h), h->mlp_out, h->unk, h->nunk, h->norm, x, nullptr);
+      op_mean_zero<T>(h, h->lmin, x);
+      return;
+    }
+  }
+  if (h->kp_stale) {
+    HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
+    build_coarse_device(h);
+    h->kp_stale = false;
+  }
   launch_coarse<T>(S(h), h->Kp, h->unk, h->nunk, r, x);
   op_mean_zero<T>(h, h->lmin, x);
 }
@@ -1172,7 +1214,13 @@ hhg_status hhg_set_viscosity(hhg_hier h, int level, const double* nu) {
       h->fmg_exec = nullptr;
       h->fmg_key.clear();
     }
-    if (level == h->lmin) build_coarse_device(h);
+    if (level == h->lmin) {
+      if (h->mlp) {
+        h->kp_stale = true;  // rebuilt only if the plain coarse solve is needed
+      } else {
+        build_coarse_device(h);
+      }
+    }
     HHG_CHECK_HIP(hipStreamSynchronize(s));
   });
 }
@@ -1225,9 +1273,159 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
       stats->res_p = rp;
       stats->rel_res = bn > 0 ? std::sqrt(ru * ru + rp * rp) / bn : 0.0;
       stats->work_units = cycles * vcycle_work_units(h, *prm);
+      stats->fallbacks = 0;
     }
     if (std::sqrt(ru * ru + rp * rp) > rtol * bn)
       throw Error{HHG_ERR_NOT_CONVERGED, "relative residual above rtol after max_outer corrections"};
+  });
+}
+
+hhg_status hhg_mlp_create(hhg_ctx ctx, int n_in, int n_hidden, int n_out, int max_batch, hhg_mlp* out) {
+  return guard([&] {
+    HHG_REQUIRE(ctx && out, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(n_in >= 1 && n_out >= 1 && n_hidden >= 16 && n_hidden % 16 == 0 && max_batch >= 1, HHG_ERR_ARG,
+                "bad MLP sizes (hidden width a multiple of 16)");
+    HHG_CHECK_HIP(hipSetDevice(ctx->device));
+    std::unique_ptr<hhg_mlp_s> m(new hhg_mlp_s);
+    m->ctx = ctx;
+    m->net.init(n_in, n_hidden, n_out, max_batch);
+    HHG_CHECK_HIP(hipMalloc(&m->idx, sizeof(int) * max_batch));
+    HHG_CHECK_HIP(hipMalloc(&m->bx, sizeof(float) * (size_t)max_batch * n_in));
+    HHG_CHECK_HIP(hipMalloc(&m->by, sizeof(float) * (size_t)max_batch * n_out));
+    *out = m.release();
+  });
+}
+
+hhg_status hhg_mlp_destroy(hhg_mlp m) {
+  return guard([&] {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(m->idx);
+    (void)hipFree(m->bx);
+    (void)hipFree(m->by);
+    delete m;
+  });
+}
+
+hhg_status hhg_mlp_num_params(hhg_mlp m, size_t* n) {
+  return guard([&] {
+    HHG_REQUIRE(m && n, HHG_ERR_ARG, "null argument");
+    *n = (size_t)m->net.host_params();
+  });
+}
+
+hhg_status hhg_mlp_set_params(hhg_mlp m, const float* host) {
+  return guard([&] {
+    HHG_REQUIRE(m && host, HHG_ERR_ARG, "null argument");
+    m->net.set_params(host);
+  });
+}
+
+hhg_status hhg_mlp_get_params(hhg_mlp m, float* host) {
+  return guard([&] {
+    HHG_REQUIRE(m && host, HHG_ERR_ARG, "null argument");
+    HHG_CHECK_HIP(hipStreamSynchronize(m->ctx->stream));
+    m->net.unpack(m->net.P, host);
+  });
+}
+
+hhg_status hhg_mlp_forward(hhg_mlp m, const float* x, int batch, float* y) {
+  return guard([&] {
+    HHG_REQUIRE(m && x && y, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(batch >= 1 && batch <= m->net.max_batch, HHG_ERR_ARG, "batch out of range");
+    m->net.forward(m->ctx->stream, x, batch, y);
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_mlp_loss_grad(hhg_mlp m, const float* x, const float* y, int batch, float* grad_host, double* loss) {
+  return guard([&] {
+    HHG_REQUIRE(m && x && y && grad_host && loss, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(batch >= 1 && batch <= m->net.max_batch, HHG_ERR_ARG, "batch out of range");
+    *loss = m->net.loss_grad(m->ctx->stream, x, y, batch);
+    HHG_CHECK_HIP(hipStreamSynchronize(m->ctx->stream));
+    m->net.unpack(m->net.Gr, grad_host);
+  });
+}
+
+hhg_status hhg_mlp_train(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs, float lr,
+                         const int* order, double* last_loss) {
+  return guard([&] {
+    HHG_REQUIRE(m && x && y && order, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(n_samples >= 1 && epochs >= 1 && lr > 0.f && batch >= 1 && batch <= m->net.max_batch, HHG_ERR_ARG,
+                "bad training parameters");
+    hipStream_t s = m->ctx->stream;
+    double tot = 0.0;
+    int nb = 0;
+    for (int e = 0; e < epochs; ++e) {
+      tot = 0.0, nb = 0;
+      for (int b0 = 0; b0 + batch <= n_samples; b0 += batch) {
+        const int* ord = order + (size_t)e * n_samples + b0;
+        for (int q = 0; q < batch; ++q)
+          HHG_REQUIRE(ord[q] >= 0 && ord[q] < n_samples, HHG_ERR_ARG, "sample index out of range");
+        HHG_CHECK_HIP(hipMemcpyAsync(m->idx, ord, sizeof(int) * batch, hipMemcpyHostToDevice, s));
+        launch_gather_rows(s, x, m->idx, batch, m->net.n_in, m->bx);
+        launch_gather_rows(s, y, m->idx, batch, m->net.n_out, m->by);
+        tot += m->net.train_step(s, m->bx, m->by, batch, lr);
+        ++nb;
+      }
+    }
+    if (last_loss) *last_loss = nb ? tot / nb : 0.0;
+  });
+}
+
+hhg_status hhg_mlp_dims(hhg_hier h, int* n_in, int* n_out) {
+  return guard([&] {
+    HHG_REQUIRE(h && n_in && n_out, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+    *n_in = h->nunk + h->L(h->lmin).g.nn;
+    *n_out = h->nunk;
+  });
+}
+
+static void ensure_coarse_buffers(hhg_hier h) {
+  if (!h->feat) {
+    h->feat = h->arena.alloc<float>((size_t)h->nunk + h->L(h->lmin).g.nn);
+    h->mlp_out = h->arena.alloc<float>(h->nunk);
+    h->norm = h->arena.alloc<double>(2);
+  }
+}
+
+hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* target) {
+  return guard([&] {
+    HHG_REQUIRE(h && r && features && target, HHG_ERR_ARG, "null argument");
+    HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+    ensure_coarse_buffers(h);
+    Level& lv = h->L(h->lmin);
+    HHG_REQUIRE(r != lv.r && r != lv.cx, HHG_ERR_ARG, "r must be a caller vector");
+    launch_coarse_features(S(h), r, h->unk, h->nunk, lv.nu64, lv.g.nn, features, h->norm);
+    double* c = lv.cx;
+    launch_fill<double>(S(h), c, lv.vec_words, 0.0);
+    op_coarse<double>(h, c, r, false);  // exact correction (plain coarse solve)
+    launch_coarse_scatter(S(h), nullptr, h->unk, h->nunk, h->norm, c, target);
+    HHG_CHECK_HIP(hipGetLastError());
+  });
+}
+
+hhg_status hhg_hier_set_mlp(hhg_hier h, hhg_mlp m, double rho_plain, double tau) {
+  return guard([&] {
+    HHG_REQUIRE(h, HHG_ERR_ARG, "null hierarchy");
+    if (m) {
+      HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+      HHG_REQUIRE(m->net.n_in == h->nunk + h->L(h->lmin).g.nn && m->net.n_out == h->nunk, HHG_ERR_ARG,
+                  "MLP sizes do not match the coarsest level");
+      HHG_REQUIRE(rho_plain > 0.0 && tau >= -1.0, HHG_ERR_ARG, "bad monitor parameters");
+      ensure_coarse_buffers(h);
+    }
+    h->mlp = m;
+    h->rho_plain = rho_plain;
+    h->tau = tau;
+    h->mlp_off = false;
+    if (h->fmg_exec) {
+      HHG_CHECK_HIP(hipGraphExecDestroy(h->fmg_exec));
+      h->fmg_exec = nullptr;
+      h->fmg_key.clear();
+    }
   });
 }
 
@@ -1331,18 +1529,41 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, cons
     fmg_body(h, x, bl, p);
     Level& top = h->L(h->lmax);
     int cycles = p.kappa + (p.rtol > 0.0 ? 0 : p.extra_cycles);
+    int fallbacks = 0;
     double bu = 0, bp = 0, ru = 0, rp = 0;
     const double* b = bl(h->lmax);
     norms<double>(h, h->lmax, b, &bu, &bp);
     const double bn = std::sqrt(bu * bu + bp * bp);
+    // Fallback monitor: with the learned coarse solve, a cycle whose residual
+    // reduction is worse than rho_plain (1 + tau) (or not finite) is undone and
+    // the rest of the solve uses the plain coarse solve.
+    const bool monitor = h->mlp && p.rtol > 0.0;
+    if (monitor && !h->bk) h->bk = h->arena.alloc<double>(top.vec_words);
+    double prev = -1.0;
     for (;;) {
       op_apply<double>(h, h->lmax, full_mask(h), x, b, top.r, true, true, true);
       norms<double>(h, h->lmax, top.r, &ru, &rp);
-      if (p.rtol <= 0.0 || std::sqrt(ru * ru + rp * rp) <= p.rtol * bn || cycles >= p.max_cycles) break;
+      const double rn = std::sqrt(ru * ru + rp * rp);
+      if (monitor && !h->mlp_off &&
+          (!std::isfinite(rn) || (prev > 0.0 && rn > h->rho_plain * (1.0 + h->tau) * prev))) {
+        h->mlp_off = true;
+        ++fallbacks;
+        if (prev > 0.0) {  // undo the last cycle
+          HHG_CHECK_HIP(hipMemcpyAsync(x, h->bk, top.vec_words * sizeof(double), hipMemcpyDeviceToDevice, S(h)));
+        } else {           // the FMG start itself is unusable: redo it with the exact coarse solve
+          fmg_body(h, x, bl, p);
+        }
+        continue;
+      }
+      if (p.rtol <= 0.0 || rn <= p.rtol * bn || cycles >= p.max_cycles) break;
+      if (monitor && !h->mlp_off)
+        HHG_CHECK_HIP(hipMemcpyAsync(h->bk, x, top.vec_words * sizeof(double), hipMemcpyDeviceToDevice, S(h)));
+      prev = rn;
       vcycle(h, h->lmax, h->lmax, x, b, p);
       op_mean_zero<double>(h, h->lmax, x);
       ++cycles;
     }
+    h->mlp_off = false;
     HHG_CHECK_HIP(hipGetLastError());
     if (stats) {
       stats->cycles = cycles;
@@ -1350,6 +1571,7 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, cons
       stats->res_p = rp;
       stats->rel_res = bn > 0 ? std::sqrt(ru * ru + rp * rp) / bn : 0.0;
       stats->work_units = fmg_work_units(h, p) + (cycles - p.kappa) * vcycle_work_units(h, p);
+      stats->fallbacks = fallbacks;
     }
     if (p.rtol > 0.0 && std::sqrt(ru * ru + rp * rp) > p.rtol * bn)
       throw Error{HHG_ERR_NOT_CONVERGED, "relative residual above rtol after max_cycles"};

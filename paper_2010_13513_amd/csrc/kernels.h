@@ -53,10 +53,19 @@ enum KernelFamily {
   KF_COARSE = 7,
   KF_REDUCE = 8,
   KF_OTHER = 9,
-  KF_COUNT = 10
+  KF_MLP = 10,      // MLP matrix products (work units: flops)
+  KF_COUNT = 11
 };
 void timer_set_mask(unsigned mask);
 bool timer_enabled();
+// Records HIP events on the launch stream around one kernel launch when its
+// family is enabled (kernels.hip).
+struct KScope {
+  hipStream_t s_;
+  hipEvent_t b_ = nullptr;
+  KScope(hipStream_t s, int fam, double units);
+  ~KScope();
+};
 // Sum of event-measured durations (ms), launches and work units of one family
 // since the last read; synchronises the recorded events.
 void timer_read(int family, double* total_ms, int* launches, double* units);
@@ -122,6 +131,11 @@ void launch_vsumsq(hipStream_t s, const Geom& g, const T* x, int nwords, double*
 template <typename T>
 void launch_coarse(hipStream_t s, const double* Kp, const int* unk, int nunk, const T* r, T* x);
 void launch_to_f32(hipStream_t s, const double* x, float* y, size_t n);
+void launch_coarse_features(hipStream_t s, const double* r, const int* unk, int nunk, const double* nu, int nn,
+                            float* f, double* norm);
+void launch_coarse_scatter(hipStream_t s, const float* y, const int* unk, int nunk, const double* norm, double* x,
+                           float* out);
+void launch_gather_rows(hipStream_t s, const float* src, const int* idx, int B, int w, float* dst);
 void launch_add_f32_to_f64(hipStream_t s, double* y, const float* e, size_t n);
 template <typename T>
 void launch_scale(hipStream_t s, T* x, size_t n, const double* sums, int slot);

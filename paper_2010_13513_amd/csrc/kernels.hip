@@ -56,24 +56,22 @@ Timer& timer() {
   static Timer t;
   return t;
 }
-// Records HIP events on the launch stream around one kernel launch when its
-// family is enabled.
-struct KScope {
-  hipStream_t s_;
-  hipEvent_t b_ = nullptr;
-  KScope(hipStream_t s, int fam, double units) : s_(s) {
-    Timer& t = timer();
-    if (!((t.mask >> fam) & 1u)) return;
-    TimerRec r{fam, nullptr, nullptr, units};
-    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
-    (void)hipEventRecord(r.a, s);
-    b_ = r.b;
-    t.recs.push_back(r);
-  }
-  ~KScope() {
-    if (b_) (void)hipEventRecord(b_, s_);
-  }
-};
+}  // namespace
+
+KScope::KScope(hipStream_t s, int fam, double units) : s_(s) {
+  Timer& t = timer();
+  if (!((t.mask >> fam) & 1u)) return;
+  TimerRec r{fam, nullptr, nullptr, units};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  (void)hipEventRecord(r.a, s);
+  b_ = r.b;
+  t.recs.push_back(r);
+}
+KScope::~KScope() {
+  if (b_) (void)hipEventRecord(b_, s_);
+}
+
+namespace {
 
 // ------------------------------------------------------- generated stencils
 // Dispatch of the generated interior row stencils by velocity group (the group
@@ -786,6 +784,50 @@ __global__ void __launch_bounds__(kBlock) k_coarse(const double* __restrict__ Kp
   }
 }
 
+// Coarse-level MLP features: f[c] = r[unk[c]] / ||r_unk||, c < nunk, then
+// log nu at the nn P1 nodes (0 without a viscosity); norm[0] = ||r_unk||.
+__global__ void __launch_bounds__(kBlock) k_coarse_features(const double* __restrict__ r, const int* __restrict__ unk,
+                                                            int nunk, const double* __restrict__ nu, int nn,
+                                                            float* __restrict__ f, double* __restrict__ norm) {
+  __shared__ double s[kBlock];
+  double a = 0.0;
+  for (int c = threadIdx.x; c < nunk; c += kBlock) {
+    const double v = r[unk[c]];
+    a += v * v;
+  }
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int k = kBlock / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double nr = sqrt(s[0]);
+  const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int c = threadIdx.x; c < nunk; c += kBlock) f[c] = (float)(r[unk[c]] * inv);
+  for (int q = threadIdx.x; q < nn; q += kBlock) f[nunk + q] = nu ? (float)log(nu[q]) : 0.f;
+  if (threadIdx.x == 0) norm[0] = nr;
+}
+
+// x[unk[c]] += norm * y[c] (the learned correction), or out[c] = x[unk[c]] / norm.
+__global__ void __launch_bounds__(kBlock) k_coarse_scatter(const float* __restrict__ y, const int* __restrict__ unk,
+                                                           int nunk, const double* __restrict__ norm,
+                                                           double* __restrict__ x, float* __restrict__ out) {
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < nunk; c += gridDim.x * kBlock) {
+    if (out)
+      out[c] = norm[0] > 0.0 ? (float)(x[unk[c]] / norm[0]) : 0.f;
+    else
+      x[unk[c]] += norm[0] * (double)y[c];
+  }
+}
+
+// Rows idx[0..B) of src (n x w floats) -> dst (B x w).
+__global__ void k_gather_rows(const float* __restrict__ src, const int* __restrict__ idx, int B, int w,
+                              float* __restrict__ dst) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)B * w) return;
+  dst[t] = src[(long)idx[t / w] * w + t % w];
+}
+
 // y (precision Y) = x (precision X), round to nearest even when narrowing.
 template <typename X, typename Y>
 __global__ void __launch_bounds__(kBlock) k_convert(const X* __restrict__ x, Y* __restrict__ y, long n) {
@@ -1011,6 +1053,22 @@ template <typename T>
 void launch_coarse(hipStream_t s, const double* Kp, const int* unk, int nunk, const T* r, T* x) {
   KScope ks(s, KF_COARSE, nunk);
   HHG_LAUNCH((k_coarse<T>), 1, s, Kp, unk, nunk, r, x);
+}
+
+void launch_coarse_features(hipStream_t s, const double* r, const int* unk, int nunk, const double* nu, int nn,
+                            float* f, double* norm) {
+  KScope ks(s, KF_COARSE, nunk);
+  HHG_LAUNCH(k_coarse_features, 1, s, r, unk, nunk, nu, nn, f, norm);
+}
+
+void launch_coarse_scatter(hipStream_t s, const float* y, const int* unk, int nunk, const double* norm, double* x,
+                           float* out) {
+  KScope ks(s, KF_COARSE, nunk);
+  HHG_LAUNCH(k_coarse_scatter, nblocks(nunk), s, y, unk, nunk, norm, x, out);
+}
+
+void launch_gather_rows(hipStream_t s, const float* src, const int* idx, int B, int w, float* dst) {
+  if ((long)B * w > 0) HHG_LAUNCH(k_gather_rows, nblocks((size_t)B * w), s, src, idx, B, w, dst);
 }
 
 void launch_to_f32(hipStream_t s, const double* x, float* y, size_t n) {

@@ -25,9 +25,11 @@ SYMBOLS = [
     "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
     "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation", "hhg_dots",
     "hhg_timer_start", "hhg_timer_read", "hhg_dc_solve", "hhg_set_viscosity",
+    "hhg_mlp_create", "hhg_mlp_destroy", "hhg_mlp_num_params", "hhg_mlp_set_params", "hhg_mlp_get_params",
+    "hhg_mlp_forward", "hhg_mlp_loss_grad", "hhg_mlp_train", "hhg_mlp_dims", "hhg_coarse_pair", "hhg_hier_set_mlp",
 ]
-KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER = \
-    range(10)
+KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER, \
+    KF_MLP = range(11)
 
 
 class HHGError(RuntimeError):
@@ -45,7 +47,7 @@ class SolverParams(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("res_u", ctypes.c_double), ("res_p", ctypes.c_double),
-                ("rel_res", ctypes.c_double), ("work_units", ctypes.c_double)]
+                ("rel_res", ctypes.c_double), ("work_units", ctypes.c_double), ("fallbacks", ctypes.c_int)]
 
 
 _lib = None
@@ -89,6 +91,17 @@ def load():
         "hhg_timer_read": [I, P, P, P],
         "hhg_dc_solve": [P, P, P, P, I, I, D, I, P],
         "hhg_set_viscosity": [P, I, P],
+        "hhg_mlp_create": [P, I, I, I, I, P],
+        "hhg_mlp_destroy": [P],
+        "hhg_mlp_num_params": [P, P],
+        "hhg_mlp_set_params": [P, P],
+        "hhg_mlp_get_params": [P, P],
+        "hhg_mlp_forward": [P, P, I, P],
+        "hhg_mlp_loss_grad": [P, P, P, I, P, P],
+        "hhg_mlp_train": [P, P, P, I, I, I, ctypes.c_float, P, P],
+        "hhg_mlp_dims": [P, P, P],
+        "hhg_coarse_pair": [P, P, P, P],
+        "hhg_hier_set_mlp": [P, P, D, D],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -276,3 +289,68 @@ def hhg_query_interpolation(order, tx, ty, tz, q):
     _check(load().hhg_query_interpolation(order, tx, ty, tz, q, ctypes.byref(n), code, w))
     m = n.value
     return np.array(code[:4 * m]).reshape(m, 4), np.array(w[:m])
+
+
+# ------------------------------------------------------------ learned coarse solve
+def hhg_mlp_create(ctx, n_in, n_hidden, n_out, max_batch):
+    out = ctypes.c_void_p()
+    _check(load().hhg_mlp_create(ctx, n_in, n_hidden, n_out, max_batch, ctypes.byref(out)))
+    return out
+
+
+def hhg_mlp_destroy(m):
+    _check(load().hhg_mlp_destroy(m))
+
+
+def hhg_mlp_num_params(m):
+    n = ctypes.c_size_t()
+    _check(load().hhg_mlp_num_params(m, ctypes.byref(n)))
+    return n.value
+
+
+def hhg_mlp_set_params(m, params_f32):
+    import numpy as np
+    a = np.ascontiguousarray(params_f32, dtype=np.float32)
+    _check(load().hhg_mlp_set_params(m, a.ctypes.data))
+
+
+def hhg_mlp_get_params(m):
+    import numpy as np
+    a = np.empty(hhg_mlp_num_params(m), dtype=np.float32)
+    _check(load().hhg_mlp_get_params(m, a.ctypes.data))
+    return a
+
+
+def hhg_mlp_forward(m, x, batch, y):
+    _check(load().hhg_mlp_forward(m, _ptr(x), batch, _ptr(y)))
+
+
+def hhg_mlp_loss_grad(m, x, y, batch):
+    import numpy as np
+    g = np.empty(hhg_mlp_num_params(m), dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(load().hhg_mlp_loss_grad(m, _ptr(x), _ptr(y), batch, g.ctypes.data, ctypes.byref(loss)))
+    return loss.value, g
+
+
+def hhg_mlp_train(m, x, y, n_samples, batch, epochs, lr, order):
+    import numpy as np
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    loss = ctypes.c_double()
+    _check(load().hhg_mlp_train(m, _ptr(x), _ptr(y), n_samples, batch, epochs, float(lr), o.ctypes.data,
+                                ctypes.byref(loss)))
+    return loss.value
+
+
+def hhg_mlp_dims(h):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(load().hhg_mlp_dims(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def hhg_coarse_pair(h, r, features, target):
+    _check(load().hhg_coarse_pair(h, _ptr(r), _ptr(features), _ptr(target)))
+
+
+def hhg_hier_set_mlp(h, m, rho_plain=1.0, tau=0.0):
+    _check(load().hhg_hier_set_mlp(h, m, float(rho_plain), float(tau)))
