@@ -47,8 +47,13 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-apply-roofline", action="store_true")
-    ap.add_argument("--mode", choices=["fmg", "apply"], default="fmg",
-                    help="apply: only the operator-apply roofline (for counter runs)")
+    ap.add_argument("--mode", choices=["fmg", "apply", "learned"], default="fmg",
+                    help="apply: only the operator-apply roofline (for counter runs); learned: the "
+                         "learned coarse-solve workload (pairs, GPU training, held-out evaluation)")
+    ap.add_argument("--pairs", type=int, default=20000)
+    ap.add_argument("--hidden", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--test-seeds", type=int, default=1000)
     ap.add_argument("--apply-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -67,6 +72,11 @@ def main():
     prob = W.paper_cube()
 
     ctx = hhg.hhg_ctx_create(0, stream.cuda_stream)
+    if args.mode == "learned":
+        res = bench_learned(torch, hhg, ctx, args)
+        print(json.dumps(res), flush=True)
+        hhg.hhg_ctx_destroy(ctx)
+        return
     if args.mode == "apply":
         res = bench_apply(torch, hhg, dev, stream, ctx, reps=args.apply_reps)
         # plain copy of a known size (calibration of the HBM byte counters)
@@ -248,6 +258,129 @@ def bench_apply(torch, hhg, dev, stream, ctx, level=7, reps=20):
     finally:
         hhg.hhg_hier_destroy(H)
     return res
+
+
+def bench_learned(torch, hhg, ctx, args, L=6, lmin=2):
+    """Learned coarse solve on P1-P1 PSPG, 6 macro-tets, level 6, coarsest
+    N = 4 (206 unknowns): pairs from plain V(3,3) solves over log-normal
+    viscosity seeds, GPU training, held-out pair errors, V-cycle rates (exact
+    / network / relaxation only) and the time of a solve with a new viscosity
+    (plain: pseudo-inverse rebuilt; network: none) at equal tolerance."""
+    from paper_2010_13513_amd import learned
+    from paper_2010_13513_amd.problem import Problem
+    P = Problem(torch, ctx, hhg.HHG_P1P1, lmin, L)
+    v33 = (3, 3, 0, 1, hhg.HHG_GS_FWD, 1)
+    # omega^{-1} by power iteration (eq. omega-eigenvalue-problem) for the
+    # first training field, used for every field
+    P.set_viscosity(learned.W.lognormal_viscosity(learned.TRAIN_BASE))
+    v0 = torch.from_numpy(W_normal(P, L)).to(P.dev)
+    om = hhg.hhg_estimate_omega(P.h, L, v0, 100)
+    log(f"[learned] omega_inv {om:.4f}")
+    # pairs: the first 16 coarse-grid visits (FMG, then V(3,3) cycles) of a
+    # plain solve per training field
+    prm_pairs = hhg.solver_params(*v33, om, extra_cycles=12)
+    out = {"mode": "learned", "workload": f"P1-P1 PSPG, 6 Kuhn macro-tets, level {L} ({P.dofs(L)} DoFs), "
+                                          f"coarsest level {lmin} (N=4, 206 unknowns), log-normal viscosity "
+                                          f"1:100, Fourier forcing, V(3,3)"}
+    m = None
+    try:
+        t0 = time.perf_counter()
+        F, T, used = learned.collect_pairs(P, [learned.TRAIN_BASE + s for s in range(100000)], prm_pairs, args.pairs,
+                                           per_seed=16, log=log)
+        out["pairs"] = {"n": int(F.shape[0]), "seeds": used, "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"[learned] {F.shape[0]} pairs from {used} seeds in {out['pairs']['seconds']} s")
+        hhg.hhg_timer_start(1 << hhg.KF_MLP)
+        t0 = time.perf_counter()
+        m, hist = learned.train(ctx, F, T, hidden=args.hidden, batch=256, epochs=args.epochs, lr=1e-3,
+                                lr_final=1e-4, stages=4, log=log)
+        t_train = time.perf_counter() - t0
+        ms, n, flops = hhg.hhg_timer_read(hhg.KF_MLP)
+        hhg.hhg_timer_start(0)
+        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        out["train"] = {"hidden": args.hidden, "epochs": args.epochs, "batch": 256, "seconds": round(t_train, 2),
+                        "loss_history": [round(h, 6) for h in hist]}
+        out["mlp_roofline"] = {"bound": "mfma", "kernel": "k_gemm_bf16", "achieved": round(tf, 2),
+                               "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 5),
+                               "avg_launch_us": round(1e3 * ms / max(n, 1), 2), "launches": n, "traffic": None}
+        log(f"[learned] training {t_train:.1f} s; MLP GEMMs {n} launches, {tf:.2f} TFLOP/s")
+        # held-out pairs: the coarse visits of FMG + one cycle on every held-out seed
+        prm_fmg = hhg.solver_params(*v33, om, extra_cycles=1)
+        t0 = time.perf_counter()
+        Fh, Th, used_h = learned.collect_pairs(P, [learned.TEST_BASE + s for s in range(args.test_seeds)], prm_fmg,
+                                               8 * args.test_seeds, log=log)
+        eh = learned.pair_errors(P, m, Fh, Th)
+        et = learned.pair_errors(P, m, F[:4096], T[:4096])
+        out["pair_error"] = {"held_out_seeds": used_h, "held_out_pairs": int(Fh.shape[0]),
+                             "held_out_median": round(float(np.median(eh)), 4),
+                             "held_out_p90": round(float(np.percentile(eh, 90)), 4),
+                             "train_median": round(float(np.median(et)), 4),
+                             "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"[learned] pair errors {out['pair_error']}")
+        # V(3,3) convergence rates on held-out fields
+        prm0 = hhg.solver_params(*v33, om)
+        prms = hhg.solver_params(*v33, om, coarse_smooth=2)
+        rates = {"exact": [], "network": [], "relax_only": []}
+        for s in range(10):
+            seed = learned.TEST_BASE + 5000 + s
+            rates["exact"].append(float(np.mean(learned.cycle_rates(P, seed, prm0, 12)[2:])))
+            rates["relax_only"].append(float(np.mean(learned.cycle_rates(P, seed, prms, 12)[2:])))
+            hhg.hhg_hier_set_mlp(P.h, m, 1.0, 0.0)
+            rates["network"].append(float(np.mean(learned.cycle_rates(P, seed, prm0, 12)[2:])))
+            hhg.hhg_hier_set_mlp(P.h, None)
+        out["vcycle_rate_mean"] = {k: round(float(np.mean(v)), 4) for k, v in rates.items()}
+        log(f"[learned] V(3,3) rates {out['vcycle_rate_mean']}")
+        # a solve per new viscosity to rtol 1e-8: setup (viscosity on every
+        # level, plain: + pseudo-inverse) + FMG and cycles
+        rho = float(np.max(rates["exact"]))    # monitor: plain rate of the worst held-out field
+        res = {"plain": [], "network": []}
+        prm_solve = hhg.solver_params(*v33, om, rtol=1e-8, max_cycles=200)
+        for s in range(10):
+            seed = learned.TEST_BASE + 6000 + s
+            xs = {}
+            for mode in ("plain", "network"):
+                if mode == "network":
+                    hhg.hhg_hier_set_mlp(P.h, m, rho, 0.5)
+                nu = learned.W.lognormal_viscosity(seed)
+                prob = learned.W.fourier_forcing(learned.forcing_seed(seed))
+                nus = {l: torch.from_numpy(nu(*P.p1_nodes(l))).to(P.dev) for l in range(lmin, L + 1)}
+                bs = P.rhs(prob)
+                x = P.boundary(prob)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for l in range(lmin, L + 1):
+                    hhg.hhg_set_viscosity(P.h, l, nus[l])
+                t1 = time.perf_counter()
+                st = hhg.hhg_fmg_solve(P.h, x, bs, prm_solve, check=False)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                res[mode].append((t1 - t0, t2 - t1, st.cycles, st.fallbacks, st.rel_res))
+                xs[mode] = x
+                if mode == "network":
+                    hhg.hhg_hier_set_mlp(P.h, None)
+            d = ((xs["network"] - xs["plain"]).abs().max() / xs["plain"].abs().max()).item()
+            res.setdefault("max_rel_diff", []).append(d)
+        summ = {}
+        for mode in ("plain", "network"):
+            a = np.array(res[mode])
+            summ[mode] = {"setup_ms": round(1e3 * float(np.median(a[:, 0])), 3),
+                          "solve_ms": round(1e3 * float(np.median(a[:, 1])), 3),
+                          "total_ms": round(1e3 * float(np.median(a[:, 0] + a[:, 1])), 3),
+                          "cycles_median": float(np.median(a[:, 2])), "fallbacks": int(a[:, 3].sum()),
+                          "max_rel_res": float(a[:, 4].max())}
+        summ["max_rel_diff_network_vs_plain"] = float(max(res["max_rel_diff"]))
+        out["new_viscosity_solve"] = summ
+        log(f"[learned] per new viscosity: {summ}")
+    finally:
+        if m is not None:
+            hhg.hhg_hier_set_mlp(P.h, None)
+            hhg.hhg_mlp_destroy(m)
+        P.close()
+    return out
+
+
+def W_normal(P, level):
+    from paper_2010_13513_amd import workloads as W
+    return W.normal_vector(W.SEED_BASE + 5000 + 1, (P.N(level) + 1) ** 3)
 
 
 def cpu_baseline(L, omega_inv, budget_s=15.0):

@@ -86,6 +86,10 @@ typedef struct {
   double rtol;            /* > 0: instead of extra_cycles, cycle until
                              ||r||_2 <= rtol ||b||_2 (max_cycles bound)       */
   int max_cycles;
+  int coarse_smooth;      /* > 0: no coarse solve; the coarsest level gets this
+                             many Uzawa iterations instead (comparison point
+                             for the learned coarse solve); 0: exact solve, or
+                             the attached network                           */
 } hhg_solver_params;
 
 typedef struct {
@@ -279,6 +283,15 @@ hhg_status hhg_mlp_dims(hhg_hier h, int* n_in, int* n_out);
  * without viscosity)], target = (exact coarse correction)_unk / ||r_unk|| with
  * the pressure at zero mean.  Outputs device float32. */
 hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* target);
+/* Training-pair recorder: while capacity > 0, every exact float64 coarse
+ * solve (inside hhg_vcycle, hhg_fmg_solve, hhg_dc_solve with F64 inner
+ * cycles) also writes the pair of its residual, as hhg_coarse_pair does, into
+ * row k of features (capacity x n_in) and targets (capacity x n_out), k = 0,
+ * 1, ... until capacity rows are filled.  Device float32 buffers owned by the
+ * caller and kept until recording stops (capacity 0).  Each call restarts the
+ * count; solves run eagerly (no HIP-graph replay) while recording. */
+hhg_status hhg_record_pairs(hhg_hier h, float* features, float* targets, int capacity);
+hhg_status hhg_recorded_pairs(hhg_hier h, int* count);
 /* Attach (or detach with m = NULL) a network as the coarse solve of float64
  * cycles: correction = ||r_unk|| net(features), then zero pressure mean.
  * Fallback (hhg_fmg_solve with rtol > 0): a finest-level cycle whose residual

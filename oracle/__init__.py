@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
 execute anything in this package: only the test-suite, the smoke check and the
 benchmark's ``cpu_baseline`` leg use it.  It shares no code with the HIP
 library (no kernels, headers, tables or constant generators); the only common
-module is ``tests/inputs.py``, which draws seeded random numbers and holds none
+module is ``paper_2010_13513_amd/workloads.py``, which holds problem data and seeded random draws and none
 of the method's arithmetic.
 
 Everything here is plain float64 numpy/scipy written from the paper's

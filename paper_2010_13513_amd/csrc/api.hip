@@ -143,6 +143,10 @@ struct hhg_hier_s {
   float *feat = nullptr, *mlp_out = nullptr;
   double* norm = nullptr;
   double* bk = nullptr;      // copy of x before a monitored V-cycle
+  // training-pair recorder of exact coarse solves (hhg_record_pairs)
+  float *rec_f = nullptr, *rec_t = nullptr;
+  int rec_cap = 0, rec_n = 0;
+  double* rc = nullptr;      // coarse correction of a recorded solve
   double *ce = nullptr, *cy = nullptr;  // coarse-operator assembly scratch
   // cached HIP graph of a fixed-work FMG solve (key: vectors + parameters)
   hipGraphExec_t fmg_exec = nullptr;
@@ -560,36 +564,48 @@ void build_coarse(hhg_hier h) {
 }
 
 // Dense coarse operator from the device operator itself (columns = calA e_c
-// restricted to the unknowns), used when the coarsest level's rows depend on
-// data such as a variable viscosity; then its pseudo-inverse replaces Kp.
+// restricted to the unknowns, all n columns applied back to back), used when
+// the coarsest level's rows depend on data such as a variable viscosity; then
+// its pseudo-inverse replaces Kp.  When the first (eigenvalue) pseudo-inverse
+// found exactly one null vector, that vector is the constant pressure (Sec. 2:
+// the pressure is fixed only up to a constant) and the rebuild uses
+// K^+ = (K + z z^T)^{-1} - z z^T instead of a new eigen-decomposition.
 void build_coarse_device(hhg_hier h) {
   if (h->nunk == 0) return;
   Level& lv = h->L(h->lmin);
   const int n = h->nunk;
+  const size_t vw = lv.vec_words;
   if (!h->ce) {  // private vectors: callers may hold the coarse work vectors
-    h->ce = h->arena.alloc<double>(lv.vec_words);
-    h->cy = h->arena.alloc<double>(lv.vec_words);
+    h->ce = h->arena.alloc<double>((size_t)n * vw);
+    h->cy = h->arena.alloc<double>((size_t)n * vw);
   }
-  double* e = h->ce;
-  double* y = h->cy;
-  std::vector<double> K((size_t)n * n), col(lv.vec_words);
-  const double one = 1.0;
-  for (int c = 0; c < n; ++c) {
-    launch_fill<double>(S(h), e, lv.vec_words, 0.0);
-    HHG_CHECK_HIP(hipMemcpyAsync(e + h->unk_host[c], &one, sizeof(double), hipMemcpyHostToDevice, S(h)));
-    launch_apply<double>(S(h), lv.g, lv.lc64, lv.tb64, e, nullptr, y, full_mask(h), false, true, true, lv.bnd,
-                         lv.nbnd);
-    HHG_CHECK_HIP(hipMemcpyAsync(col.data(), y, lv.vec_words * sizeof(double), hipMemcpyDeviceToHost, S(h)));
-    HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
-    for (int r = 0; r < n; ++r) K[(size_t)r * n + c] = col[h->unk_host[r]];
-  }
+  launch_fill<double>(S(h), h->ce, (size_t)n * vw, 0.0);
+  launch_unit_columns(S(h), h->ce, vw, h->unk, n);
+  for (int c = 0; c < n; ++c)
+    launch_apply<double>(S(h), lv.g, lv.lc64, lv.tb64, h->ce + c * vw, nullptr, h->cy + c * vw, full_mask(h), false,
+                         true, true, lv.bnd, lv.nbnd);
+  std::vector<double> cols((size_t)n * vw), K((size_t)n * n);
+  HHG_CHECK_HIP(hipMemcpyAsync(cols.data(), h->cy, cols.size() * sizeof(double), hipMemcpyDeviceToHost, S(h)));
+  HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
+  for (int c = 0; c < n; ++c)
+    for (int r = 0; r < n; ++r) K[(size_t)r * n + c] = cols[c * vw + h->unk_host[r]];
   for (int r = 0; r < n; ++r)
     for (int c = r + 1; c < n; ++c) {
       const double sym = 0.5 * (K[(size_t)r * n + c] + K[(size_t)c * n + r]);
       K[(size_t)r * n + c] = K[(size_t)c * n + r] = sym;
     }
   std::vector<double> Kp;
-  h->rank = sym_pinv(n, K, Kp, 1e-12);
+  bool done = false;
+  if (h->rank == n - 1) {
+    const size_t pbase = 3 * (size_t)lv.g.vstride;
+    int np = 0;
+    for (int r = 0; r < n; ++r) np += (size_t)h->unk_host[r] >= pbase;
+    std::vector<double> z(n, 0.0);
+    for (int r = 0; r < n; ++r)
+      if ((size_t)h->unk_host[r] >= pbase) z[r] = 1.0 / std::sqrt((double)np);
+    done = sym_pinv_null1(n, K, z, Kp);
+  }
+  if (!done) h->rank = sym_pinv(n, K, Kp, 1e-12);
   HHG_CHECK_HIP(hipMemcpy(h->Kp, Kp.data(), Kp.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
@@ -683,11 +699,19 @@ void build_coarse_device(hhg_hier h);
 // Coarse solve x <- x + A0^+ (b - A0 x) on the unknowns (float64 GEMV for
 // either storage precision), then zero pressure mean.  With an MLP attached
 // (float64 solves), the correction is ||r|| net([r / ||r||, log nu]) instead,
-// unless the fallback monitor has switched it off for this solve.
+// unless the fallback monitor has switched it off for this solve.  With
+// p->coarse_smooth > 0 the coarsest level is only relaxed (that many Uzawa
+// iterations), the comparison point without any coarse solve.  While the
+// recorder is on, every exact float64 solve also stores its training pair.
 template <typename T>
-void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true) {
-  HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "coarsest level has more than 2048 unknowns: no dense coarse solve");
+void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true, const hhg_solver_params* p = nullptr) {
   Level& lv = h->L(h->lmin);
+  if (p && p->coarse_smooth > 0) {
+    op_smooth<T>(h, h->lmin, x, b, p->coarse_smooth, p->gs, p->xi, 1.0 / p->omega_inv);
+    op_mean_zero<T>(h, h->lmin, x);
+    return;
+  }
+  HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "coarsest level has more than 2048 unknowns: no dense coarse solve");
   T* r = rbuf<T>(lv);
   op_apply<T>(h, h->lmin, full_mask(h), x, b, r, true, true, true);
   if constexpr (std::is_same<T, double>::value) {
@@ -704,6 +728,20 @@ void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true) {
     build_coarse_device(h);
     h->kp_stale = false;
   }
+  if constexpr (std::is_same<T, double>::value) {
+    if (h->rec_n < h->rec_cap) {
+      const size_t ni = (size_t)h->nunk + lv.g.nn;
+      launch_coarse_features(S(h), r, h->unk, h->nunk, lv.nu64, lv.g.nn, h->rec_f + h->rec_n * ni, h->norm);
+      launch_fill<double>(S(h), h->rc, lv.vec_words, 0.0);
+      launch_coarse<double>(S(h), h->Kp, h->unk, h->nunk, r, h->rc);
+      op_mean_zero<double>(h, h->lmin, h->rc);
+      launch_coarse_scatter(S(h), nullptr, h->unk, h->nunk, h->norm, h->rc, h->rec_t + h->rec_n * (size_t)h->nunk);
+      launch_axpy<double>(S(h), x, h->rc, lv.vec_words, 1.0);
+      op_mean_zero<double>(h, h->lmin, x);
+      ++h->rec_n;
+      return;
+    }
+  }
   launch_coarse<T>(S(h), h->Kp, h->unk, h->nunk, r, x);
   op_mean_zero<T>(h, h->lmin, x);
 }
@@ -712,7 +750,7 @@ void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true) {
 template <typename T>
 void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_params& p) {
   if (l == h->lmin) {
-    op_coarse<T>(h, x, b);
+    op_coarse<T>(h, x, b, true, &p);
     return;
   }
   Level& lv = h->L(l);
@@ -806,7 +844,7 @@ void fmg_body(hhg_hier h, double* x, BL bl, const hhg_solver_params& p) {
   Level& bot = h->L(h->lmin);
   launch_fill<double>(s, bot.xs, bot.vec_words, 0.0);
   launch_copy_boundary<double>(s, bot.g, bot.w, bot.xs);
-  op_coarse<double>(h, bot.xs, bl(h->lmin));
+  op_coarse<double>(h, bot.xs, bl(h->lmin), true, &p);
   for (int l = h->lmin + 1; l <= h->lmax; ++l) {
     Level& lv = h->L(l);
     double* X = l == h->lmax ? x : lv.xs;
@@ -1407,6 +1445,27 @@ hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* 
   });
 }
 
+hhg_status hhg_record_pairs(hhg_hier h, float* features, float* targets, int capacity) {
+  return guard([&] {
+    HHG_REQUIRE(h && capacity >= 0, HHG_ERR_ARG, "bad arguments");
+    HHG_REQUIRE(capacity == 0 || (features && targets), HHG_ERR_ARG, "null buffers");
+    HHG_REQUIRE(capacity == 0 || h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+    if (capacity > 0) ensure_coarse_buffers(h);
+    if (capacity > 0 && !h->rc) h->rc = h->arena.alloc<double>(h->L(h->lmin).vec_words);
+    h->rec_f = capacity ? features : nullptr;
+    h->rec_t = capacity ? targets : nullptr;
+    h->rec_cap = capacity;
+    h->rec_n = 0;
+  });
+}
+
+hhg_status hhg_recorded_pairs(hhg_hier h, int* count) {
+  return guard([&] {
+    HHG_REQUIRE(h && count, HHG_ERR_ARG, "null argument");
+    *count = h->rec_n;
+  });
+}
+
 hhg_status hhg_hier_set_mlp(hhg_hier h, hhg_mlp m, double rho_plain, double tau) {
   return guard([&] {
     HHG_REQUIRE(h, HHG_ERR_ARG, "null hierarchy");
@@ -1483,14 +1542,19 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, cons
     HHG_REQUIRE(prm->nu_pre >= 0 && prm->nu_post >= 0 && prm->nu_inc >= 0 && prm->extra_cycles >= 0, HHG_ERR_ARG,
                 "bad solver parameters");
     for (int l = h->lmin; l <= h->lmax; ++l) HHG_REQUIRE(b_levels[l - h->lmin], HHG_ERR_ARG, "null rhs");
-    HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+    HHG_REQUIRE(h->nunk > 0 || prm->coarse_smooth > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+    HHG_REQUIRE(prm->coarse_smooth >= 0, HHG_ERR_ARG, "bad solver parameters");
     const hhg_solver_params& p = *prm;
     double* x = (double*)xv;
     auto bl = [&](int l) { return (const double*)b_levels[l - h->lmin]; };
     // Fixed work (no stopping test, no statistics): the whole solve is one
     // replayed HIP graph, captured on the first call with these vectors and
     // parameters.  The event timer needs per-launch events, so it runs eagerly.
-    const bool fixed = stats == nullptr && p.rtol <= 0.0 && !timer_enabled();
+    const bool fixed = stats == nullptr && p.rtol <= 0.0 && !timer_enabled() && h->rec_cap == 0;
+    if (fixed && h->kp_stale && !h->mlp && p.coarse_smooth == 0) {  // no host work inside a capture
+      build_coarse_device(h);
+      h->kp_stale = false;
+    }
     if (fixed) {
       std::vector<unsigned char> key(sizeof(hhg_solver_params) + sizeof(void*) * (h->lmax - h->lmin + 2));
       std::memcpy(key.data(), &p, sizeof p);

@@ -41,5 +41,10 @@ Row row_stencil(const ElementSet& es, char kind, int g, int i, int j, int k, int
 // eigen-decomposition K = Q L Q^T, eigenvalues below rcond * max |L| dropped.
 // Returns the numerical rank.
 int sym_pinv(int n, const std::vector<double>& K, std::vector<double>& Kp, double rcond);
+// Pseudo-inverse of a symmetric K whose null space is exactly span{z} (|z| = 1):
+// K^+ = (K + z z^T)^{-1} - z z^T, the inverse by Gauss-Jordan elimination with
+// partial pivoting.  Returns false if a pivot vanishes (then K has a larger
+// null space and sym_pinv is needed).
+bool sym_pinv_null1(int n, const std::vector<double>& K, const std::vector<double>& z, std::vector<double>& Kp);
 
 }  // namespace hhg

@@ -296,4 +296,40 @@ int sym_pinv(int n, const std::vector<double>& Kin, std::vector<double>& Kp, dou
   return rank;
 }
 
+bool sym_pinv_null1(int n, const std::vector<double>& K, const std::vector<double>& z, std::vector<double>& Kp) {
+  // [M | I] -> [I | M^{-1}] with M = K + z z^T, row-major, n x 2n
+  const size_t w = 2 * (size_t)n;
+  std::vector<double> a((size_t)n * w, 0.0);
+  double scale = 0.0;
+  for (int r = 0; r < n; ++r) {
+    for (int c = 0; c < n; ++c) {
+      a[r * w + c] = K[(size_t)r * n + c] + z[r] * z[c];
+      scale = std::max(scale, std::fabs(a[r * w + c]));
+    }
+    a[r * w + n + r] = 1.0;
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r * w + c]) > std::fabs(a[piv * w + c])) piv = r;
+    if (!(std::fabs(a[piv * w + c]) > 1e-13 * scale)) return false;
+    if (piv != c)
+      for (size_t q = 0; q < w; ++q) std::swap(a[c * w + q], a[piv * w + q]);
+    const double inv = 1.0 / a[c * w + c];
+    for (size_t q = c; q < w; ++q) a[c * w + q] *= inv;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[r * w + c];
+      if (f == 0.0) continue;
+      double* ar = &a[r * w];
+      const double* ac = &a[c * w];
+      for (size_t q = c; q < w; ++q) ar[q] -= f * ac[q];
+    }
+  }
+  Kp.assign((size_t)n * n, 0.0);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) Kp[(size_t)r * n + c] = a[r * w + n + c] - z[r] * z[c];
+  return true;
+}
+
 }  // namespace hhg

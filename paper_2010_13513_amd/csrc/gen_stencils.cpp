@@ -7,6 +7,7 @@
 // are emitted as literals into fully unrolled device functions; kernels scale
 // the sums by h, h^2 or h^3.  Usage: gen_stencils <output file>.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -193,6 +194,81 @@ void emit_anu_diag(FILE* f, const char* name, const std::vector<ElemRow>& rows) 
   std::fprintf(f, "  return d;\n}\n\n");
 }
 
+// k-marching form of the constant-coefficient operator calA (A, B^T, B and
+// -C together) for one velocity component d and one loaded k-plane of the
+// input.  A wavefront owns 64 lattice columns (i, j) and walks k; every word
+// at (i + di, j + dj, kp) that component d's rows need is loaded once and
+// scattered into the rows of the lane's own column at k = kp - dk, kept in
+// three rotating accumulator planes (slot = relative plane index mod 3; Q =
+// relative index of the loaded plane mod 3).  Accumulator row g < G: velocity
+// row of component d, group g; row G: the part of the pressure row that
+// comes from u_d (and, for d = 0, from -C p).  Velocity words are scaled by
+// sa (A) and sb (B), pressure words by sb (B^T) and sc (C) before the literal
+// weights at h = 1.
+struct ZmUse {
+  int row, dk;
+  double w;
+};
+void emit_zm(FILE* f, const ElementSet& es, const char* D, int G) {
+  auto key = [](int di, int dj) { return (di + 1) + 3 * (dj + 1); };
+  auto slot = [](int Q, int dk) { return ((Q - dk) % 3 + 3) % 3; };
+  for (int d = 0; d < 3; ++d) {
+    // velocity column group c, (di, dj) -> uses
+    std::vector<std::vector<ZmUse>> vu(G * 9), pu(9);
+    for (int r = 0; r < G; ++r) {
+      for (auto& e : pruned(es, 'A', r, 1)) vu[e.g * 9 + key(e.di, e.dj)].push_back({r, e.dk, e.w[0]});
+      for (auto& e : pruned(es, 'T', r, 3))
+        if (e.w[d] != 0.0) pu[key(e.di, e.dj)].push_back({r, e.dk, e.w[d]});
+    }
+    for (auto& e : pruned(es, 'B', 0, 3))
+      if (e.w[d] != 0.0) vu[e.g * 9 + key(e.di, e.dj)].push_back({G, e.dk, e.w[d]});
+    if (G == 1 && d == 0)
+      for (auto& e : pruned(es, 'C', 0, 1)) pu[key(e.di, e.dj)].push_back({-1, e.dk, e.w[0]});
+    for (int Q = 0; Q < 3; ++Q) {
+      std::fprintf(f,
+                   "template <typename T>\n__device__ __forceinline__ void %s_zm%d_q%d(const T* __restrict__ x, int base, "
+                   "bool kin, unsigned ok, int s1, int nn, int vs, T sa, T sb, T sc, T (&acc)[3][%d]) {\n  (void)sc;\n",
+                   D, d, Q, G + 1);
+      int nload = 0;
+      for (int c = 0; c < G; ++c)
+        for (int kk = 0; kk < 9; ++kk) {
+          const auto& us = vu[c * 9 + kk];
+          if (us.empty()) continue;
+          ++nload;
+          std::fprintf(f, "  { const T v = (kin && ((ok >> %d) & 1u)) ? x[%d * vs + %d * nn + base + (%d) + (%d) * s1] : T(0);\n",
+                       kk, d, c, kk % 3 - 1, kk / 3 - 1);
+          bool a = false, b = false;
+          for (auto& u : us) (u.row < G ? a : b) = true;
+          if (a) std::fprintf(f, "    const T va = sa * v;\n");
+          if (b) std::fprintf(f, "    const T vb = sb * v;\n");
+          for (auto& u : us)
+            std::fprintf(f, "    acc[%d][%d] += T(%s) * %s;\n", slot(Q, u.dk), u.row, lit(u.w).c_str(),
+                         u.row < G ? "va" : "vb");
+          std::fprintf(f, "  }\n");
+        }
+      for (int kk = 0; kk < 9; ++kk) {
+        const auto& us = pu[kk];
+        if (us.empty()) continue;
+        ++nload;
+        std::fprintf(f, "  { const T v = (kin && ((ok >> %d) & 1u)) ? x[3 * vs + base + (%d) + (%d) * s1] : T(0);\n", kk,
+                     kk % 3 - 1, kk / 3 - 1);
+        bool b = false, c = false;
+        for (auto& u : us) (u.row >= 0 ? b : c) = true;
+        if (b) std::fprintf(f, "    const T vb = sb * v;\n");
+        if (c) std::fprintf(f, "    const T vc = sc * v;\n");
+        for (auto& u : us) {
+          if (u.row >= 0)
+            std::fprintf(f, "    acc[%d][%d] += T(%s) * vb;\n", slot(Q, u.dk), u.row, lit(u.w).c_str());
+          else
+            std::fprintf(f, "    acc[%d][%d] -= T(%s) * vc;\n", slot(Q, u.dk), G, lit(u.w).c_str());
+        }
+        std::fprintf(f, "  }\n");
+      }
+      std::fprintf(f, "}\n// %d loads per plane\n\n", nload);
+    }
+  }
+}
+
 double diag_of(const Row& r, int g) {
   for (auto& e : r)
     if (e.g == g && e.di == 0 && e.dj == 0 && e.dk == 0) return e.w[0];
@@ -239,6 +315,7 @@ int main(int argc, char** argv) {
       Row C = pruned(es, 'C', 0, 1);
       emit_pp(f, "p1_C", C);
     }
+    emit_zm(f, es, D, G);
   }
   std::fprintf(f, "}  // namespace gen\n}  // namespace hhg\n");
   std::fclose(f);

@@ -130,6 +130,7 @@ template <typename T>
 void launch_vsumsq(hipStream_t s, const Geom& g, const T* x, int nwords, double* partial, double* out);
 template <typename T>
 void launch_coarse(hipStream_t s, const double* Kp, const int* unk, int nunk, const T* r, T* x);
+void launch_unit_columns(hipStream_t s, double* E, size_t stride, const int* unk, int n);
 void launch_to_f32(hipStream_t s, const double* x, float* y, size_t n);
 void launch_coarse_features(hipStream_t s, const double* r, const int* unk, int nunk, const double* nu, int nn,
                             float* f, double* norm);

@@ -241,6 +241,132 @@ __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, cons
   }
 }
 
+// k-marching apply of the whole constant-coefficient operator (A, B^T, B and
+// -C; y = calA x or b - calA x).  A block is three wavefronts over the same
+// 64 lattice columns (i, j) of one chunk of k-planes [k0, k1); wavefront d
+// computes the velocity rows of component d.  Each wavefront loads every
+// input word its rows need at (i + di, j + dj, kp) once, for kp = k0 - 1 ..
+// k1, and scatters it into the rows of its lane's column at k = kp - dk, kept
+// in three rotating accumulator planes; the row plane kp - 1 is complete
+// after plane kp and is written.  The pressure row is the sum of the three
+// wavefronts' parts, added through LDS.  Per P2 site this issues 135 / 8
+// loads instead of one per stencil entry.
+constexpr int kZmCols = 64;
+
+template <typename T, int G, int D, int Q>
+__device__ __forceinline__ void zm_plane(const T* __restrict__ x, int base, bool kin, unsigned ok, int s1, int nn,
+                                         int vs, T sa, T sb, T sc, T (&acc)[3][G + 1]) {
+#define HHG_ZM(P) gen::P<T>(x, base, kin, ok, s1, nn, vs, sa, sb, sc, acc)
+  if constexpr (G == 1) {
+    if constexpr (D == 0 && Q == 0) HHG_ZM(p1_zm0_q0);
+    if constexpr (D == 0 && Q == 1) HHG_ZM(p1_zm0_q1);
+    if constexpr (D == 0 && Q == 2) HHG_ZM(p1_zm0_q2);
+    if constexpr (D == 1 && Q == 0) HHG_ZM(p1_zm1_q0);
+    if constexpr (D == 1 && Q == 1) HHG_ZM(p1_zm1_q1);
+    if constexpr (D == 1 && Q == 2) HHG_ZM(p1_zm1_q2);
+    if constexpr (D == 2 && Q == 0) HHG_ZM(p1_zm2_q0);
+    if constexpr (D == 2 && Q == 1) HHG_ZM(p1_zm2_q1);
+    if constexpr (D == 2 && Q == 2) HHG_ZM(p1_zm2_q2);
+  } else {
+    if constexpr (D == 0 && Q == 0) HHG_ZM(p2_zm0_q0);
+    if constexpr (D == 0 && Q == 1) HHG_ZM(p2_zm0_q1);
+    if constexpr (D == 0 && Q == 2) HHG_ZM(p2_zm0_q2);
+    if constexpr (D == 1 && Q == 0) HHG_ZM(p2_zm1_q0);
+    if constexpr (D == 1 && Q == 1) HHG_ZM(p2_zm1_q1);
+    if constexpr (D == 1 && Q == 2) HHG_ZM(p2_zm1_q2);
+    if constexpr (D == 2 && Q == 0) HHG_ZM(p2_zm2_q0);
+    if constexpr (D == 2 && Q == 1) HHG_ZM(p2_zm2_q1);
+    if constexpr (D == 2 && Q == 2) HHG_ZM(p2_zm2_q2);
+  }
+#undef HHG_ZM
+}
+
+struct ZmCol {
+  int col, i, j, k0, k1;
+  unsigned ok;
+  bool valid;
+};
+
+template <typename T, int G, int D, int Q>
+__device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                        const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol& c, int q,
+                                        T (&acc)[3][G + 1], T (*pshare)[3][kZmCols]) {
+  constexpr int S = (Q + 2) % 3;  // slot of the row plane completed by this step
+  const int N = g.N, s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn, vs = g.vstride;
+  const int kp = c.k0 - 1 + q;
+  zm_plane<T, G, D, Q>(x, c.col + kp * s2, c.valid && kp >= 0 && kp <= N, c.ok, s1, nn, vs, lc.a, lc.b, lc.c, acc);
+  const int kr = kp - 1;
+  const int lane = threadIdx.x & (kZmCols - 1);
+  if (kr >= c.k0 && kr < c.k1) {  // uniform over the block
+    const int at = c.col + kr * s2;
+    if (c.valid) {
+#pragma unroll
+      for (int gr = 0; gr < G; ++gr) {
+        const int pos = D * vs + gr * nn + at;
+        const T v = acc[S][gr];
+        y[pos] = vel_interior<G>(gr, c.i, c.j, kr, N) ? (has_b ? b[pos] - v : v) : T(0);
+      }
+    }
+    pshare[q & 1][D][lane] = acc[S][G];
+    __syncthreads();
+    if (D == 0 && c.valid && c.i >= 1 && c.j >= 1 && kr >= 1 && c.i <= N - 1 && c.j <= N - 1 && kr <= N - 1) {
+      const T v = pshare[q & 1][0][lane] + pshare[q & 1][1][lane] + pshare[q & 1][2][lane];
+      const int pp = 3 * vs + at;
+      y[pp] = has_b ? b[pp] - v : v;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r <= G; ++r) acc[S][r] = T(0);
+}
+
+template <typename T, int G, int D>
+__device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                       const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol& c,
+                                       T (*pshare)[3][kZmCols]) {
+  T acc[3][G + 1];
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int r = 0; r <= G; ++r) acc[s][r] = T(0);
+  const int nq = c.k1 - c.k0 + 2;
+  for (int q = 0; q < nq; q += 3) {
+    zm_step<T, G, D, 0>(g, lc, x, b, y, has_b, c, q, acc, pshare);
+    if (q + 1 < nq) zm_step<T, G, D, 1>(g, lc, x, b, y, has_b, c, q + 1, acc, pshare);
+    if (q + 2 < nq) zm_step<T, G, D, 2>(g, lc, x, b, y, has_b, c, q + 2, acc, pshare);
+  }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
+                                                          const T* __restrict__ b, T* __restrict__ y, int has_b, int kc,
+                                                          int ncb) {
+  __shared__ T pshare[2][3][kZmCols];
+  const int lin = xcd_block();
+  const int cb = lin % ncb, chunk = lin / ncb;
+  const int n1 = g.n1, N = g.N;
+  ZmCol c;
+  c.col = cb * kZmCols + (threadIdx.x & (kZmCols - 1));
+  c.k0 = chunk * kc;
+  if (c.k0 >= n1) return;  // whole block: grid padding
+  c.k1 = min(c.k0 + kc, n1);
+  c.valid = c.col < n1 * n1;
+  c.i = c.col % n1;
+  c.j = c.col / n1;
+  c.ok = 0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di)
+      if (c.i + di >= 0 && c.i + di <= N && c.j + dj >= 0 && c.j + dj <= N) c.ok |= 1u << ((di + 1) + 3 * (dj + 1));
+  const int wave = threadIdx.x / kZmCols;  // velocity component
+  if (wave == 0)
+    zm_run<T, G, 0>(g, lc, x, b, y, has_b, c, pshare);
+  else if (wave == 1)
+    zm_run<T, G, 1>(g, lc, x, b, y, has_b, c, pshare);
+  else
+    zm_run<T, G, 2>(g, lc, x, b, y, has_b, c, pshare);
+}
+
 // Pressure rows at boundary nodes (list), boundary-class stencils.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
@@ -768,6 +894,14 @@ __global__ void __launch_bounds__(kBlock) k_axpy(T* __restrict__ y, const T* __r
   if (t < n) y[t] += a * x[t];
 }
 
+// E[c stride + unk[c]] = 1 for c < n: the unit vectors of the coarse unknowns
+// (columns of the dense coarse operator), E zero-filled by the caller.
+__global__ void __launch_bounds__(kBlock) k_unit_columns(double* __restrict__ E, long stride,
+                                                         const int* __restrict__ unk, int n) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c < n) E[c * stride + unk[c]] = 1.0;
+}
+
 // Coarsest level: x[unk] += Kp r[unk] (one workgroup, unknowns staged in LDS,
 // float64 arithmetic whatever the storage type T).
 template <typename T>
@@ -859,7 +993,18 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     KScope ks(s, KF_APPLY, p_sites(g));
     const unsigned nb = nblocks8(g.nn);
     const int hb = has_b, vr = vel_rows, pr = p_rows;
-    if (g.G == 1) {
+    const int full = g.G == 1 ? 15 : 7;
+    if (!lc.nu && opmask == full && vel_rows && p_rows) {
+      // k-marching form: 64 columns per block, k in chunks of kc planes
+      const int kc = g.n1 <= 24 ? g.n1 : 16;
+      const int ncb = (g.n1 * g.n1 + kZmCols - 1) / kZmCols;
+      const int nch = (g.n1 + kc - 1) / kc;
+      const unsigned nbz = (unsigned)((ncb * nch + 7) & ~7);
+      if (g.G == 1)
+        hipLaunchKernelGGL((k_apply_zm<T, 1>), dim3(nbz), dim3(3 * kZmCols), 0, s, g, lc, x, b, y, hb, kc, ncb);
+      else
+        hipLaunchKernelGGL((k_apply_zm<T, 8>), dim3(nbz), dim3(3 * kZmCols), 0, s, g, lc, x, b, y, hb, kc, ncb);
+    } else if (g.G == 1) {
       if (lc.nu)
         HHG_LAUNCH((k_apply<T, 1, true>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
       else
@@ -1053,6 +1198,10 @@ template <typename T>
 void launch_coarse(hipStream_t s, const double* Kp, const int* unk, int nunk, const T* r, T* x) {
   KScope ks(s, KF_COARSE, nunk);
   HHG_LAUNCH((k_coarse<T>), 1, s, Kp, unk, nunk, r, x);
+}
+
+void launch_unit_columns(hipStream_t s, double* E, size_t stride, const int* unk, int n) {
+  if (n > 0) HHG_LAUNCH(k_unit_columns, nblocks(n), s, E, (long)stride, unk, n);
 }
 
 void launch_coarse_features(hipStream_t s, const double* r, const int* unk, int nunk, const double* nu, int nn,

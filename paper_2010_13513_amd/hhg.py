@@ -27,6 +27,7 @@ SYMBOLS = [
     "hhg_timer_start", "hhg_timer_read", "hhg_dc_solve", "hhg_set_viscosity",
     "hhg_mlp_create", "hhg_mlp_destroy", "hhg_mlp_num_params", "hhg_mlp_set_params", "hhg_mlp_get_params",
     "hhg_mlp_forward", "hhg_mlp_loss_grad", "hhg_mlp_train", "hhg_mlp_dims", "hhg_coarse_pair", "hhg_hier_set_mlp",
+    "hhg_record_pairs", "hhg_recorded_pairs",
 ]
 KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER, \
     KF_MLP = range(11)
@@ -42,7 +43,7 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("nu_inc", ctypes.c_int),
                 ("kappa", ctypes.c_int), ("gs", ctypes.c_int), ("xi", ctypes.c_int),
                 ("omega_inv", ctypes.c_double), ("extra_cycles", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("max_cycles", ctypes.c_int)]
+                ("max_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -102,6 +103,8 @@ def load():
         "hhg_mlp_dims": [P, P, P],
         "hhg_coarse_pair": [P, P, P, P],
         "hhg_hier_set_mlp": [P, P, D, D],
+        "hhg_record_pairs": [P, P, P, I],
+        "hhg_recorded_pairs": [P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -252,19 +255,24 @@ def hhg_timer_read(family):
     return ms.value, n.value, u.value
 
 
-def solver_params(nu_pre, nu_post, nu_inc, kappa, gs, xi, omega_inv, extra_cycles=0, rtol=0.0, max_cycles=100):
+def solver_params(nu_pre, nu_post, nu_inc, kappa, gs, xi, omega_inv, extra_cycles=0, rtol=0.0, max_cycles=100,
+                  coarse_smooth=0):
     return SolverParams(nu_pre, nu_post, nu_inc, kappa, gs, xi, float(omega_inv), extra_cycles, float(rtol),
-                        max_cycles)
+                        max_cycles, coarse_smooth)
 
 
 def hhg_vcycle(h, level, x, b, prm):
     _check(load().hhg_vcycle(h, level, _ptr(x), _ptr(b), ctypes.byref(prm)))
 
 
-def hhg_fmg_solve(h, x, b_levels, prm, want_stats=True):
+def hhg_fmg_solve(h, x, b_levels, prm, want_stats=True, check=True):
+    """Returns the stats; with check=False a tolerance miss (HHG_ERR_NOT_CONVERGED)
+    returns them too instead of raising."""
     arr = (ctypes.c_void_p * len(b_levels))(*[_ptr(b) for b in b_levels])
     st = Stats()
-    _check(load().hhg_fmg_solve(h, _ptr(x), arr, ctypes.byref(prm), ctypes.byref(st) if want_stats else None))
+    rc = load().hhg_fmg_solve(h, _ptr(x), arr, ctypes.byref(prm), ctypes.byref(st) if want_stats else None)
+    if rc != HHG_OK and (check or rc != HHG_ERR_NOT_CONVERGED):
+        _check(rc)
     return st
 
 
@@ -350,6 +358,17 @@ def hhg_mlp_dims(h):
 
 def hhg_coarse_pair(h, r, features, target):
     _check(load().hhg_coarse_pair(h, _ptr(r), _ptr(features), _ptr(target)))
+
+
+def hhg_record_pairs(h, features, targets, capacity):
+    _check(load().hhg_record_pairs(h, _ptr(features) if capacity else None, _ptr(targets) if capacity else None,
+                                   capacity))
+
+
+def hhg_recorded_pairs(h):
+    n = ctypes.c_int()
+    _check(load().hhg_recorded_pairs(h, ctypes.byref(n)))
+    return n.value
 
 
 def hhg_hier_set_mlp(h, m, rho_plain=1.0, tau=0.0):
