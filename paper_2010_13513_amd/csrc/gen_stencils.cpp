@@ -196,74 +196,77 @@ void emit_anu_diag(FILE* f, const char* name, const std::vector<ElemRow>& rows) 
 
 // k-marching form of the constant-coefficient operator calA (A, B^T, B and
 // -C together) for one velocity component d and one loaded k-plane of the
-// input.  A wavefront owns 64 lattice columns (i, j) and walks k; every word
-// at (i + di, j + dj, kp) that component d's rows need is loaded once and
-// scattered into the rows of the lane's own column at k = kp - dk, kept in
-// three rotating accumulator planes (slot = relative plane index mod 3; Q =
-// relative index of the loaded plane mod 3).  Accumulator row g < G: velocity
-// row of component d, group g; row G: the part of the pressure row that
-// comes from u_d (and, for d = 0, from -C p).  Velocity words are scaled by
-// sa (A) and sb (B), pressure words by sb (B^T) and sc (C) before the literal
-// weights at h = 1.
+// input.  A wavefront owns 64 consecutive lattice columns (i, j) and walks k;
+// for every (array, dj) that component d's rows need it loads the word of
+// column (i, j + dj) once -- the i -+ 1 neighbours come from the adjacent
+// lanes (from_prev / from_next, wavefront lane shifts) -- and scatters it
+// into the rows of the lane's own column at k = kp - dk, kept in three
+// rotating accumulator planes (slot = relative plane index mod 3; Q =
+// relative index of the loaded plane mod 3).  Loads are buffer loads: ru
+// addresses velocity component d (group c at byte offset c nnb), rp the
+// pressure; vo[dj + 1] is the byte offset of column (i, j + dj) in plane kp,
+// which the caller clamps into the lattice, and the caller discards the first
+// and last lane of the wavefront (their shifted neighbours are missing).  A clamped or wrapped
+// word only reaches rows that are not interior -- an interior row references
+// positions inside the cube only -- and those rows are written as zero.
+// Accumulator row g < G: velocity row of component d, group g; row G: the
+// part of the pressure row that comes from u_d (and, for d = 0, from -C p).
+// Velocity words are scaled by sa (A) and sb (B), pressure words by sb (B^T)
+// and sc (C) before the literal weights at h = 1.
 struct ZmUse {
   int row, dk;
   double w;
+  int kind;  // 0: sa, 1: sb, 2: sc (negated weight)
 };
 void emit_zm(FILE* f, const ElementSet& es, const char* D, int G) {
-  auto key = [](int di, int dj) { return (di + 1) + 3 * (dj + 1); };
   auto slot = [](int Q, int dk) { return ((Q - dk) % 3 + 3) % 3; };
+  const char* scal[3] = {"sa", "sb", "sc"};
   for (int d = 0; d < 3; ++d) {
-    // velocity column group c, (di, dj) -> uses
-    std::vector<std::vector<ZmUse>> vu(G * 9), pu(9);
+    // array a (velocity group c: a = c; pressure: a = G), dj + 1, di + 1 -> uses
+    std::vector<std::vector<ZmUse>> use((G + 1) * 9);
+    auto at = [&](int a, int di, int dj) -> std::vector<ZmUse>& { return use[a * 9 + (dj + 1) * 3 + (di + 1)]; };
     for (int r = 0; r < G; ++r) {
-      for (auto& e : pruned(es, 'A', r, 1)) vu[e.g * 9 + key(e.di, e.dj)].push_back({r, e.dk, e.w[0]});
+      for (auto& e : pruned(es, 'A', r, 1)) at(e.g, e.di, e.dj).push_back({r, e.dk, e.w[0], 0});
       for (auto& e : pruned(es, 'T', r, 3))
-        if (e.w[d] != 0.0) pu[key(e.di, e.dj)].push_back({r, e.dk, e.w[d]});
+        if (e.w[d] != 0.0) at(G, e.di, e.dj).push_back({r, e.dk, e.w[d], 1});
     }
     for (auto& e : pruned(es, 'B', 0, 3))
-      if (e.w[d] != 0.0) vu[e.g * 9 + key(e.di, e.dj)].push_back({G, e.dk, e.w[d]});
+      if (e.w[d] != 0.0) at(e.g, e.di, e.dj).push_back({G, e.dk, e.w[d], 1});
     if (G == 1 && d == 0)
-      for (auto& e : pruned(es, 'C', 0, 1)) pu[key(e.di, e.dj)].push_back({-1, e.dk, e.w[0]});
+      for (auto& e : pruned(es, 'C', 0, 1)) at(G, e.di, e.dj).push_back({G, e.dk, -e.w[0], 2});
     for (int Q = 0; Q < 3; ++Q) {
       std::fprintf(f,
-                   "template <typename T>\n__device__ __forceinline__ void %s_zm%d_q%d(const T* __restrict__ x, int base, "
-                   "bool kin, unsigned ok, int s1, int nn, int vs, T sa, T sb, T sc, T (&acc)[3][%d]) {\n  (void)sc;\n",
+                   "template <typename T>\n__device__ __forceinline__ void %s_zm%d_q%d(__amdgpu_buffer_rsrc_t ru, "
+                   "__amdgpu_buffer_rsrc_t rp, const int (&vo)[3], int nnb, T sa, T sb, T sc, T (&acc)[3][%d]) {\n"
+                   "  (void)sa; (void)sc; (void)nnb;\n",
                    D, d, Q, G + 1);
       int nload = 0;
-      for (int c = 0; c < G; ++c)
-        for (int kk = 0; kk < 9; ++kk) {
-          const auto& us = vu[c * 9 + kk];
-          if (us.empty()) continue;
+      for (int a = 0; a <= G; ++a)
+        for (int dj = -1; dj <= 1; ++dj) {
+          bool any = false;
+          for (int di = -1; di <= 1; ++di) any |= !at(a, di, dj).empty();
+          if (!any) continue;
           ++nload;
-          std::fprintf(f, "  { const T v = (kin && ((ok >> %d) & 1u)) ? x[%d * vs + %d * nn + base + (%d) + (%d) * s1] : T(0);\n",
-                       kk, d, c, kk % 3 - 1, kk / 3 - 1);
-          bool a = false, b = false;
-          for (auto& u : us) (u.row < G ? a : b) = true;
-          if (a) std::fprintf(f, "    const T va = sa * v;\n");
-          if (b) std::fprintf(f, "    const T vb = sb * v;\n");
-          for (auto& u : us)
-            std::fprintf(f, "    acc[%d][%d] += T(%s) * %s;\n", slot(Q, u.dk), u.row, lit(u.w).c_str(),
-                         u.row < G ? "va" : "vb");
+          if (a < G)
+            std::fprintf(f, "  { const T v0 = buffer_word<T>(ru, vo[%d], %d * nnb);\n", dj + 1, a);
+          else
+            std::fprintf(f, "  { const T v0 = buffer_word<T>(rp, vo[%d], 0);\n", dj + 1);
+          for (int di = -1; di <= 1; ++di) {
+            const auto& us = at(a, di, dj);
+            if (us.empty()) continue;
+            const char* src = di == -1 ? "from_prev(v0)" : (di == 1 ? "from_next(v0)" : "v0");
+            std::fprintf(f, "    { const T v = %s;\n", src);
+            bool kinds[3] = {false, false, false};
+            for (auto& u : us) kinds[u.kind] = true;
+            for (int k = 0; k < 3; ++k)
+              if (kinds[k]) std::fprintf(f, "      const T v%s = %s * v;\n", scal[k], scal[k]);
+            for (auto& u : us)
+              std::fprintf(f, "      acc[%d][%d] = fma(T(%s), v%s, acc[%d][%d]);\n", slot(Q, u.dk), u.row, lit(u.w).c_str(),
+                           scal[u.kind], slot(Q, u.dk), u.row);
+            std::fprintf(f, "    }\n");
+          }
           std::fprintf(f, "  }\n");
         }
-      for (int kk = 0; kk < 9; ++kk) {
-        const auto& us = pu[kk];
-        if (us.empty()) continue;
-        ++nload;
-        std::fprintf(f, "  { const T v = (kin && ((ok >> %d) & 1u)) ? x[3 * vs + base + (%d) + (%d) * s1] : T(0);\n", kk,
-                     kk % 3 - 1, kk / 3 - 1);
-        bool b = false, c = false;
-        for (auto& u : us) (u.row >= 0 ? b : c) = true;
-        if (b) std::fprintf(f, "    const T vb = sb * v;\n");
-        if (c) std::fprintf(f, "    const T vc = sc * v;\n");
-        for (auto& u : us) {
-          if (u.row >= 0)
-            std::fprintf(f, "    acc[%d][%d] += T(%s) * vb;\n", slot(Q, u.dk), u.row, lit(u.w).c_str());
-          else
-            std::fprintf(f, "    acc[%d][%d] -= T(%s) * vc;\n", slot(Q, u.dk), G, lit(u.w).c_str());
-        }
-        std::fprintf(f, "  }\n");
-      }
       std::fprintf(f, "}\n// %d loads per plane\n\n", nload);
     }
   }

@@ -9,6 +9,53 @@
 #include <vector>
 
 #include "kernels.h"
+
+namespace hhg {
+namespace gen {
+// Wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): the value held by lane
+// L - 1 (from_prev) or L + 1 (from_next); the end lanes receive 0.
+template <int CTRL>
+__device__ __forceinline__ int lane_shift(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __int_as_float(lane_shift<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = lane_shift<CTRL>((int)(unsigned)(b & 0xffffffffull));
+  const int hi = lane_shift<CTRL>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// One word of a buffer (raw buffer load, bounds-checked by the resource: an
+// offset outside it reads 0).
+template <typename T>
+__device__ __forceinline__ T buffer_word(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buffer_word<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buffer_word<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+// Buffer resource over n bytes from p (gfx9 word 3: 32-bit data format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T from_prev(T v) {
+  return lane_shift<0x138>(v);
+}
+template <typename T>
+__device__ __forceinline__ T from_next(T v) {
+  return lane_shift<0x130>(v);
+}
+}  // namespace gen
+}  // namespace hhg
+
 #include "generated/stencils.inc"
 
 namespace hhg {
@@ -243,20 +290,26 @@ __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, cons
 
 // k-marching apply of the whole constant-coefficient operator (A, B^T, B and
 // -C; y = calA x or b - calA x).  A block is three wavefronts over the same
-// 64 lattice columns (i, j) of one chunk of k-planes [k0, k1); wavefront d
-// computes the velocity rows of component d.  Each wavefront loads every
-// input word its rows need at (i + di, j + dj, kp) once, for kp = k0 - 1 ..
-// k1, and scatters it into the rows of its lane's column at k = kp - dk, kept
-// in three rotating accumulator planes; the row plane kp - 1 is complete
-// after plane kp and is written.  The pressure row is the sum of the three
-// wavefronts' parts, added through LDS.  Per P2 site this issues 135 / 8
-// loads instead of one per stencil entry.
+// 64 consecutive lattice columns (linear index i + n1 j) of one chunk of
+// k-planes [k0, k1); wavefront d computes the velocity rows of component d.
+// For kp = k0 - 1 .. k1 each wavefront loads the words of columns (i, j + dj)
+// its rows need, takes the i -+ 1 neighbours from the adjacent lanes, and
+// scatters them into the rows of its lane's column at k = kp - dk, kept in
+// three rotating accumulator planes; the row plane kp - 1 is complete after
+// plane kp and is written.  The first and last lane lack a shifted
+// neighbour, so windows overlap by two columns and only lanes 1..62 write.
+// The pressure row is the sum of the three wavefronts' parts, added through
+// LDS.  Per P2 site this issues 69 / 8 loads instead of one per stencil entry.
 constexpr int kZmCols = 64;
+#ifndef HHG_ZM_KC
+#define HHG_ZM_KC 16  // k-planes per chunk (the chunk re-reads 2 halo planes)
+#endif
+constexpr int kZmOut = kZmCols - 2;  // columns written per window
 
 template <typename T, int G, int D, int Q>
-__device__ __forceinline__ void zm_plane(const T* __restrict__ x, int base, bool kin, unsigned ok, int s1, int nn,
-                                         int vs, T sa, T sb, T sc, T (&acc)[3][G + 1]) {
-#define HHG_ZM(P) gen::P<T>(x, base, kin, ok, s1, nn, vs, sa, sb, sc, acc)
+__device__ __forceinline__ void zm_plane(__amdgpu_buffer_rsrc_t ru, __amdgpu_buffer_rsrc_t rp, const int (&vo)[3],
+                                         int nnb, T sa, T sb, T sc, T (&acc)[3][G + 1]) {
+#define HHG_ZM(P) gen::P<T>(ru, rp, vo, nnb, sa, sb, sc, acc)
   if constexpr (G == 1) {
     if constexpr (D == 0 && Q == 0) HHG_ZM(p1_zm0_q0);
     if constexpr (D == 0 && Q == 1) HHG_ZM(p1_zm0_q1);
@@ -281,9 +334,12 @@ __device__ __forceinline__ void zm_plane(const T* __restrict__ x, int base, bool
 #undef HHG_ZM
 }
 
+// Column of a lane: nb[dj + 1] = array index of column (i, j + dj) clamped
+// into the array, so every load stays in it; rows fed by a clamped (or
+// row-wrapped) word are never interior.  `valid`: the lane writes its column.
 struct ZmCol {
   int col, i, j, k0, k1;
-  unsigned ok;
+  int nb[3];
   bool valid;
 };
 
@@ -294,7 +350,13 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
   constexpr int S = (Q + 2) % 3;  // slot of the row plane completed by this step
   const int N = g.N, s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn, vs = g.vstride;
   const int kp = c.k0 - 1 + q;
-  zm_plane<T, G, D, Q>(x, c.col + kp * s2, c.valid && kp >= 0 && kp <= N, c.ok, s1, nn, vs, lc.a, lc.b, lc.c, acc);
+  const int kps = min(max(kp, 0), N) * s2;
+  const int vo[3] = {(c.nb[0] + kps) * (int)sizeof(T), (c.nb[1] + kps) * (int)sizeof(T),
+                     (c.nb[2] + kps) * (int)sizeof(T)};
+  const __amdgpu_buffer_rsrc_t ru = gen::make_rsrc(x + (size_t)D * vs, (unsigned)((size_t)vs * sizeof(T)));
+  const __amdgpu_buffer_rsrc_t rp = gen::make_rsrc(x + (size_t)3 * vs, (unsigned)((size_t)nn * sizeof(T)));
+  zm_plane<T, G, D, Q>(ru, rp, vo, nn * (int)sizeof(T), lc.a, lc.b, lc.c, acc);
+  (void)s1;
   const int kr = kp - 1;
   const int lane = threadIdx.x & (kZmCols - 1);
   if (kr >= c.k0 && kr < c.k1) {  // uniform over the block
@@ -345,19 +407,17 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
   const int cb = lin % ncb, chunk = lin / ncb;
   const int n1 = g.n1, N = g.N;
   ZmCol c;
-  c.col = cb * kZmCols + (threadIdx.x & (kZmCols - 1));
+  const int lane = threadIdx.x & (kZmCols - 1);
+  c.col = cb * kZmOut - 1 + lane;
   c.k0 = chunk * kc;
   if (c.k0 >= n1) return;  // whole block: grid padding
   c.k1 = min(c.k0 + kc, n1);
-  c.valid = c.col < n1 * n1;
+  const int ncol = n1 * n1;
+  c.valid = lane >= 1 && lane <= kZmOut && c.col < ncol;
   c.i = c.col % n1;
   c.j = c.col / n1;
-  c.ok = 0;
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-    for (int di = -1; di <= 1; ++di)
-      if (c.i + di >= 0 && c.i + di <= N && c.j + dj >= 0 && c.j + dj <= N) c.ok |= 1u << ((di + 1) + 3 * (dj + 1));
+  for (int dj = -1; dj <= 1; ++dj) c.nb[dj + 1] = min(max(c.col + dj * n1, 0), ncol - 1);
   const int wave = threadIdx.x / kZmCols;  // velocity component
   if (wave == 0)
     zm_run<T, G, 0>(g, lc, x, b, y, has_b, c, pshare);
@@ -996,8 +1056,8 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     const int full = g.G == 1 ? 15 : 7;
     if (!lc.nu && opmask == full && vel_rows && p_rows) {
       // k-marching form: 64 columns per block, k in chunks of kc planes
-      const int kc = g.n1 <= 24 ? g.n1 : 16;
-      const int ncb = (g.n1 * g.n1 + kZmCols - 1) / kZmCols;
+      const int kc = g.n1 <= HHG_ZM_KC + 8 ? g.n1 : HHG_ZM_KC;
+      const int ncb = (g.n1 * g.n1 + kZmOut - 1) / kZmOut;
       const int nch = (g.n1 + kc - 1) / kc;
       const unsigned nbz = (unsigned)((ncb * nch + 7) & ~7);
       if (g.G == 1)
