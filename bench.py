@@ -173,9 +173,9 @@ def main():
     fams = {hhg.KF_APPLY: "apply_residual", hhg.KF_PROW_BND: "boundary_pressure_rows",
             hhg.KF_GS_VERTEX: "gs_vertex_colour", hhg.KF_GS_EDGE: "gs_edge_colour", hhg.KF_PSTEP: "uzawa_pressure_step",
             hhg.KF_RESTRICT: "restrict", hhg.KF_PROLONG: "prolong", hhg.KF_COARSE: "coarse_gemv",
-            hhg.KF_REDUCE: "reductions", hhg.KF_OTHER: "other"}
+            hhg.KF_REDUCE: "reductions", hhg.KF_OTHER: "other", hhg.KF_SMALL: "small_level_vcycle"}
     rsteps = max(2, min(args.steps, 5))
-    hhg.hhg_timer_start((1 << len(fams)) - 1)
+    hhg.hhg_timer_start(sum(1 << f for f in fams))
     for _ in range(rsteps):
         step()
     torch.cuda.synchronize()

@@ -195,7 +195,8 @@ hhg_status hhg_dots(hhg_hier h, int level, const void* x, const void* y, double*
  * enables HIP events around every launch of the kernel families in the mask
  * (bit f = family f: 0 apply/residual, 1 boundary pressure rows, 2 vertex
  * Gauss-Seidel colour, 3 edge-group Gauss-Seidel colour, 4 Uzawa pressure
- * step, 5 restriction, 6 prolongation, 7 coarse solve, 8 reductions, 9 other)
+ * step, 5 restriction, 6 prolongation, 7 coarse solve, 8 reductions, 9 other,
+ * 10 MLP matrix products, 11 one-workgroup small-level V-cycle)
  * and clears earlier records; mask 0 disables it.  hhg_timer_read synchronises
  * and returns, for one family since the last read, the summed event time in
  * ms, the launches and the work units (sites processed: P2 sites or P1
@@ -283,6 +284,17 @@ hhg_status hhg_mlp_dims(hhg_hier h, int* n_in, int* n_out);
  * without viscosity)], target = (exact coarse correction)_unk / ||r_unk|| with
  * the pressure at zero mean.  Outputs device float32. */
 hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* target);
+/* Cycles on the small levels: a V-cycle whose top level has at most
+ * max_sites velocity sites per component ((N+1)^3 for P1-P1, (2N+1)^3 for
+ * P2-P1) runs from that level down to the coarse solve and back up in one
+ * single-workgroup kernel (phases separated by workgroup barriers instead of
+ * kernel launches; same arithmetic, sums in a different order), with the
+ * level vectors held in LDS when the levels up to the top fit in 128 KB.
+ * Applies to V-cycles with the exact coarse solve (not with a network
+ * attached, the recorder on or coarse_smooth > 0).  Default 800; 0 turns it
+ * off. */
+hhg_status hhg_hier_set_fused_sites(hhg_hier h, long max_sites);
+
 /* Training-pair recorder: while capacity > 0, every exact float64 coarse
  * solve (inside hhg_vcycle, hhg_fmg_solve, hhg_dc_solve with F64 inner
  * cycles) also writes the pair of its residual, as hhg_coarse_pair does, into

@@ -148,6 +148,14 @@ struct hhg_hier_s {
   int rec_cap = 0, rec_n = 0;
   double* rc = nullptr;      // coarse correction of a recorded solve
   double *ce = nullptr, *cy = nullptr;  // coarse-operator assembly scratch
+  // one-workgroup V-cycle over the small levels: level descriptors on the
+  // device (rebuilt when stale), levels with at most fused_sites velocity
+  // sites per component are cycled that way (0: never)
+  hhg::SmallLevel<double>* slv64 = nullptr;
+  hhg::SmallLevel<float>* slv32 = nullptr;
+  bool slv_stale = true;
+  long fused_sites = 800;
+  std::vector<int> lds_end64, lds_end32;  // LDS words of levels lmin..l (0: level not in LDS)
   // cached HIP graph of a fixed-work FMG solve (key: vectors + parameters)
   hipGraphExec_t fmg_exec = nullptr;
   std::vector<unsigned char> fmg_key;
@@ -692,6 +700,65 @@ float* cbbuf<float>(Level& lv) {
   return lv.cb32;
 }
 
+// Device descriptors of every level for the one-workgroup V-cycle (host
+// copies uploaded with a synchronous copy: called outside graph capture).
+template <typename T>
+void fill_small(hhg_hier h, std::vector<SmallLevel<T>>& out, std::vector<int>& lds_end) {
+  out.resize(h->levels.size());
+  lds_end.assign(h->levels.size(), 0);
+  size_t off = 0;
+  bool fits = true;
+  for (int l = h->lmin; l <= h->lmax; ++l) {
+    Level& lv = h->L(l);
+    SmallLevel<T>& s = out[l - h->lmin];
+    s.g = lv.g;
+    s.lc = lconst<T>(lv);
+    s.tb = tables<T>(lv);
+    s.tt = l > h->lmin ? ttables<T>(lv) : nullptr;
+    s.dinv = dinv<T>(lv);
+    s.bnd = lv.bnd;
+    s.nbnd = lv.nbnd;
+    s.r = rbuf<T>(lv);
+    s.cx = cxbuf<T>(lv);
+    s.cb = cbbuf<T>(lv);
+    // LDS copies of [x | b | r] for the lowest levels, as long as they fit
+    fits = fits && (off + 3 * lv.vec_words) * sizeof(T) <= (size_t)kSmallLdsBytes;
+    s.lds_off = fits ? (int)off : -1;
+    if (fits) {
+      off += 3 * lv.vec_words;
+      lds_end[l - h->lmin] = (int)off;
+    }
+  }
+}
+void refresh_small(hhg_hier h) {
+  if (!h->slv_stale) return;
+  if (!h->slv64) {
+    h->slv64 = h->arena.alloc<SmallLevel<double>>(h->levels.size());
+    h->slv32 = h->arena.alloc<SmallLevel<float>>(h->levels.size());
+  }
+  std::vector<SmallLevel<double>> a;
+  std::vector<SmallLevel<float>> b;
+  fill_small<double>(h, a, h->lds_end64);
+  fill_small<float>(h, b, h->lds_end32);
+  HHG_CHECK_HIP(hipMemcpy(h->slv64, a.data(), a.size() * sizeof(a[0]), hipMemcpyHostToDevice));
+  HHG_CHECK_HIP(hipMemcpy(h->slv32, b.data(), b.size() * sizeof(b[0]), hipMemcpyHostToDevice));
+  h->slv_stale = false;
+}
+template <typename T>
+const SmallLevel<T>* slv(hhg_hier h);
+template <>
+const SmallLevel<double>* slv<double>(hhg_hier h) {
+  return h->slv64;
+}
+template <>
+const SmallLevel<float>* slv<float>(hhg_hier h) {
+  return h->slv32;
+}
+long vel_sites(const Level& lv) {
+  const long m = lv.g.G == 1 ? lv.g.N + 1 : 2 * (long)lv.g.N + 1;
+  return m * m * m;
+}
+
 // Coarse solve x <- x + A0^+ (b - A0 x) on the unknowns (float64 GEMV for
 // either storage precision), then zero pressure mean.
 void build_coarse_device(hhg_hier h);
@@ -753,6 +820,31 @@ void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_para
     op_coarse<T>(h, x, b, true, &p);
     return;
   }
+  // the whole cycle from a small level down in one workgroup (plain exact
+  // coarse solve only: no network, recorder, relaxation-only mode or pending
+  // pseudo-inverse rebuild)
+  const bool mlp_on = std::is_same<T, double>::value && h->mlp && !h->mlp_off;
+  if (vel_sites(h->L(l)) <= h->fused_sites && !h->slv_stale && p.coarse_smooth == 0 && h->nunk > 0 && !mlp_on &&
+      h->rec_n >= h->rec_cap && !h->kp_stale && (std::is_same<T, double>::value || h->L(h->lmin).cx32)) {
+    SmallCycle<T> sc{};
+    sc.nlev = l - h->lmin + 1;
+    sc.G = h->G;
+    sc.pre0 = p.nu_pre + (lf - l) * p.nu_inc;
+    sc.post0 = p.nu_post + (lf - l) * p.nu_inc;
+    sc.inc = p.nu_inc;
+    sc.gs_sym = p.gs == HHG_GS_SYM;
+    sc.xi = p.xi;
+    sc.full_mask = full_mask(h);
+    sc.omega = (T)(1.0 / p.omega_inv);
+    sc.x = x;
+    sc.b = b;
+    sc.Kp = h->Kp;
+    sc.unk = h->unk;
+    sc.nunk = h->nunk;
+    sc.lds_words = (std::is_same<T, double>::value ? h->lds_end64 : h->lds_end32)[l - h->lmin];
+    launch_vcycle_small<T>(S(h), slv<T>(h), sc);
+    return;
+  }
   Level& lv = h->L(l);
   Level& lc = h->L(l - 1);
   const double om = 1.0 / p.omega_inv;
@@ -774,6 +866,7 @@ void ensure_f32_vectors(hhg_hier h) {
   for (int l = h->lmin; l < h->lmax; ++l) {
     Level& lv = h->L(l);
     if (!lv.cx32) {
+      h->slv_stale = true;
       lv.cx32 = h->arena.alloc<float>(lv.vec_words);
       lv.cb32 = h->arena.alloc<float>(lv.vec_words);
       launch_fill<float>(S(h), lv.cx32, lv.vec_words, 0.0f);
@@ -976,6 +1069,8 @@ hhg_status hhg_hier_create(hhg_ctx ctx, hhg_disc disc, int macro_refine, int lmi
     }
     for (int l = lmin + 1; l <= lmax; ++l) build_transfer(h.get(), h->L(l - 1), h->L(l));
     build_coarse(h.get());
+    small_kernel_attributes();
+    refresh_small(h.get());
     HHG_CHECK_HIP(hipStreamSynchronize(ctx->stream));
     *out = h.release();
   });
@@ -1247,6 +1342,7 @@ hhg_status hhg_set_viscosity(hhg_hier h, int level, const double* nu) {
     launch_nu_diag<float>(s, lv.g, lv.lc32, lv.ainvs32);
     launch_schur_diag<double>(s, lv.g, lv.tb64, lv.ainvs64, h->schur, lv.dinv64);
     launch_schur_diag<float>(s, lv.g, lv.tb32, lv.ainvs32, h->schur, lv.dinv32);
+    h->slv_stale = true;
     if (h->fmg_exec) {  // a captured solve holds the old operator
       HHG_CHECK_HIP(hipGraphExecDestroy(h->fmg_exec));
       h->fmg_exec = nullptr;
@@ -1277,6 +1373,7 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
     double* x = (double*)xv;
     const double* b = (const double*)bv;
     if (inner_prec == HHG_F32) ensure_f32_vectors(h);
+    refresh_small(h);
     double bu, bp, ru = 0, rp = 0;
     norms<double>(h, L, b, &bu, &bp);
     const double bn = std::sqrt(bu * bu + bp * bp);
@@ -1445,6 +1542,18 @@ hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* 
   });
 }
 
+hhg_status hhg_hier_set_fused_sites(hhg_hier h, long max_sites) {
+  return guard([&] {
+    HHG_REQUIRE(h && max_sites >= 0, HHG_ERR_ARG, "bad arguments");
+    h->fused_sites = max_sites;
+    if (h->fmg_exec) {  // a captured solve holds the old launch sequence
+      HHG_CHECK_HIP(hipGraphExecDestroy(h->fmg_exec));
+      h->fmg_exec = nullptr;
+      h->fmg_key.clear();
+    }
+  });
+}
+
 hhg_status hhg_record_pairs(hhg_hier h, float* features, float* targets, int capacity) {
   return guard([&] {
     HHG_REQUIRE(h && capacity >= 0, HHG_ERR_ARG, "bad arguments");
@@ -1529,6 +1638,7 @@ hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_s
   return guard([&] {
     check_level(h, level);
     HHG_REQUIRE(x && b && prm && prm->omega_inv > 0.0 && prm->xi >= 1, HHG_ERR_ARG, "bad arguments");
+    refresh_small(h);
     vcycle(h, level, level, (double*)x, (const double*)b, *prm);
     HHG_CHECK_HIP(hipGetLastError());
   });
@@ -1547,6 +1657,7 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, cons
     const hhg_solver_params& p = *prm;
     double* x = (double*)xv;
     auto bl = [&](int l) { return (const double*)b_levels[l - h->lmin]; };
+    refresh_small(h);
     // Fixed work (no stopping test, no statistics): the whole solve is one
     // replayed HIP graph, captured on the first call with these vectors and
     // parameters.  The event timer needs per-launch events, so it runs eagerly.

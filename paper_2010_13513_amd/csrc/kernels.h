@@ -54,7 +54,8 @@ enum KernelFamily {
   KF_REDUCE = 8,
   KF_OTHER = 9,
   KF_MLP = 10,      // MLP matrix products (work units: flops)
-  KF_COUNT = 11
+  KF_SMALL = 11,    // one-workgroup V-cycle over the small levels
+  KF_COUNT = 12
 };
 void timer_set_mask(unsigned mask);
 bool timer_enabled();
@@ -88,6 +89,45 @@ struct TransferTables {
   DStencil<T> rp;      // linear restriction of the P1 pressure (offsets into fine array)
   const int* rp_d;     // packed (di+2, dj+2, dk+2) of rp entries, for clipping
 };
+
+// A V-cycle over the small levels lmin..ltop run by one workgroup (one
+// launch; the phases are separated by workgroup barriers instead of kernel
+// boundaries).  lv (device array) describes the levels from lmin: lv[q] is
+// level lmin + q, its tt the transfer tables between levels lmin + q - 1 and
+// lmin + q; the work vectors r, cx, cb of the levels below ltop are used, and
+// x, b of the call replace cx, cb on ltop.
+template <typename T>
+struct SmallLevel {
+  Geom g;
+  LevelConst<T> lc;
+  const Tables<T>* tb;
+  const TransferTables<T>* tt;
+  const T* dinv;
+  const int* bnd;
+  int nbnd;
+  T *r, *cx, *cb;
+  int lds_off;  // LDS element offset of this level's [cx | cb | r] copy, -1: none
+};
+template <typename T>
+struct SmallCycle {
+  int nlev;                 // ltop - lmin + 1 (>= 2)
+  int G;
+  int pre0, post0, inc;     // smoothing on level lmin + q: pre0 + (nlev - 1 - q) inc (post likewise)
+  int gs_sym, xi, full_mask;
+  T omega;
+  T* x;                     // ltop vectors
+  const T* b;
+  const double* Kp;         // coarse pseudo-inverse (nunk x nunk, nunk <= 2048), unknown positions unk
+  const int* unk;
+  int nunk;
+  int lds_words;            // > 0: every level's vectors live in LDS (x, b copied in and x out)
+};
+// LDS available for the level vectors of the one-workgroup V-cycle (bytes).
+constexpr int kSmallLdsBytes = 128 * 1024;
+template <typename T>
+void launch_vcycle_small(hipStream_t s, const SmallLevel<T>* lv, const SmallCycle<T>& sc);
+// Allow kSmallLdsBytes of dynamic LDS for the one-workgroup V-cycle kernels.
+void small_kernel_attributes();
 
 // Launchers (kernels.hip).  All asynchronous on `s`.
 template <typename T>

@@ -264,11 +264,9 @@ __device__ __forceinline__ void apply_vrows(const Geom& g, const LevelConst<T>& 
 // pressure row (boundary pressure rows: k_prow_bnd).  opmask bits: 1 A, 2 B^T,
 // 4 B, 8 -C (block of calA), 16: +C instead.
 template <typename T, int G, bool VAR>
-__global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, const T* __restrict__ x,
-                                                  const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                                  int vel_rows, int p_rows) {
-  const int t = xcd_block() * kBlock + threadIdx.x;
-  if (t >= g.nn) return;
+__device__ __forceinline__ void apply_site(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                           const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                           int vel_rows, int p_rows, int t) {
   int i, j, k;
   decode(t, g.n1, i, j, k);
   const int N = g.N;
@@ -286,6 +284,14 @@ __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, cons
     const int pp = 3 * g.vstride + t;
     y[pp] = has_b ? b[pp] - acc : acc;
   }
+}
+template <typename T, int G, bool VAR>
+__global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, const T* __restrict__ x,
+                                                  const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                                  int vel_rows, int p_rows) {
+  const int t = xcd_block() * kBlock + threadIdx.x;
+  if (t >= g.nn) return;
+  apply_site<T, G, VAR>(g, lc, x, b, y, opmask, has_b, vel_rows, p_rows, t);
 }
 
 // k-marching apply of the whole constant-coefficient operator (A, B^T, B and
@@ -429,12 +435,9 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
 
 // Pressure rows at boundary nodes (list), boundary-class stencils.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
-                                                     const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                                     const int* __restrict__ bnd, int nb) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= nb) return;
-  const int node = bnd[t];
+__device__ __forceinline__ void prow_bnd_site(const Geom& g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
+                                              const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                              int node) {
   int i, j, k;
   decode(node, g.n1, i, j, k);
   const int cls = bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N);
@@ -458,6 +461,14 @@ __global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __
   }
   const int pp = 3 * g.vstride + node;
   y[pp] = has_b ? b[pp] - acc : acc;
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                                     const int* __restrict__ bnd, int nb) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nb) return;
+  prow_bnd_site<T>(g, tb, x, b, y, opmask, has_b, bnd[t]);
 }
 
 // ---------------------------------------------------------- Gauss-Seidel
@@ -489,33 +500,50 @@ __device__ __forceinline__ void gs_update(const Geom& g, const LevelConst<T>& lc
 
 // One colour of the vertex group: interior nodes with (i+j+k) mod 4 == c.
 // u_d += (f_d - (A u_d) - (B^T p)_d) / a_gg.
+__host__ __device__ __forceinline__ int gs_vertex_count(const Geom& g) {
+  const int nr = g.N - 1, ni = (nr + 3) >> 2;
+  return ni * nr * nr;
+}
 template <typename T, int G, bool VAR>
-__global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, LevelConst<T> lc, T* __restrict__ x,
-                                                      const T* __restrict__ b, int c) {
+__device__ __forceinline__ void gs_vertex_site(const Geom& g, const LevelConst<T>& lc, T* __restrict__ x,
+                                               const T* __restrict__ b, int c, int t, int d) {
   const int N = g.N, nr = N - 1, ni = (nr + 3) >> 2;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= ni * nr * nr) return;
   const int ip = t % ni, row = t / ni;
   const int j = 1 + row % nr, k = 1 + row / nr;
   const int i = 1 + ((((c - 1 - j - k) % 4) + 4) & 3) + 4 * ip;
   if (i > N - 1) return;
-  gs_update<T, G, VAR>(g, lc, x, b, 0, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
+  gs_update<T, G, VAR>(g, lc, x, b, 0, i + g.n1 * j + g.n1 * g.n1 * k, d);
+}
+template <typename T, int G, bool VAR>
+__global__ void __launch_bounds__(kBlock) k_gs_vertex(Geom g, LevelConst<T> lc, T* __restrict__ x,
+                                                      const T* __restrict__ b, int c) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gs_vertex_count(g)) return;
+  gs_vertex_site<T, G, VAR>(g, lc, x, b, c, t, blockIdx.y);
 }
 
 // One edge group (one colour) of the P2 velocity: all interior sites of group gr.
+__host__ __device__ __forceinline__ int gs_edge_count(const Geom& g, int gr) {
+  return (g.N - 1 + ((0xB2 >> gr) & 1)) * (g.N - 1 + ((0xD4 >> gr) & 1)) * (g.N - 1 + ((0xE8 >> gr) & 1));
+}
 template <typename T, bool VAR>
-__global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, LevelConst<T> lc, T* __restrict__ x,
-                                                    const T* __restrict__ b, int gr) {
+__device__ __forceinline__ void gs_edge_site(const Geom& g, const LevelConst<T>& lc, T* __restrict__ x,
+                                             const T* __restrict__ b, int gr, int t, int d) {
   const int N = g.N;
   const int dx = gdx(gr), dy = gdy(gr), dz = gdz(gr);
-  const int cx = N - 1 + dx, cy = N - 1 + dy, cz = N - 1 + dz;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= cx * cy * cz) return;
+  const int cx = N - 1 + dx, cy = N - 1 + dy;
   const int i = 1 - dx + t % cx;
   const int r = t / cx;
   const int j = 1 - dy + r % cy;
   const int k = 1 - dz + r / cy;
-  gs_update<T, 8, VAR>(g, lc, x, b, gr, i + g.n1 * j + g.n1 * g.n1 * k, blockIdx.y);
+  gs_update<T, 8, VAR>(g, lc, x, b, gr, i + g.n1 * j + g.n1 * g.n1 * k, d);
+}
+template <typename T, bool VAR>
+__global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, LevelConst<T> lc, T* __restrict__ x,
+                                                    const T* __restrict__ b, int gr) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gs_edge_count(g, gr)) return;
+  gs_edge_site<T, VAR>(g, lc, x, b, gr, t, blockIdx.y);
 }
 
 // p <- p - omega * dinv * rp (eq. uzawa-pressure with S_hat = omega^{-1} D).
@@ -663,10 +691,8 @@ __global__ void __launch_bounds__(kBlock) k_dot(const T* __restrict__ x, const T
 // ---------------------------------------------------------------- transfer
 // Restriction (transpose of the prolongation): coarse thread gathers fine values.
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const TransferTables<T>* __restrict__ tt,
-                                                     const T* __restrict__ rf, T* __restrict__ rc) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= gc.nn) return;
+__device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, const TransferTables<T>* __restrict__ tt,
+                                              const T* __restrict__ rf, T* __restrict__ rc, int t) {
   int i, j, k;
   decode(t, gc.n1, i, j, k);
   const int fbase = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
@@ -702,14 +728,19 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const Tra
   }
   rc[3 * gc.vstride + t] = acc;
 }
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const TransferTables<T>* __restrict__ tt,
+                                                     const T* __restrict__ rf, T* __restrict__ rc) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gc.nn) return;
+  restrict_site<T, G>(gf, gc, tt, rf, rc, t);
+}
 
 // Prolongation: fine thread evaluates the coarse function at its sites.
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
-                                                    const T* __restrict__ xc, T* __restrict__ xf, int add,
-                                                    int skip_boundary) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= gf.nn) return;
+__device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, const TransferTables<T>* __restrict__ tt,
+                                             const T* __restrict__ xc, T* __restrict__ xf, int add, int skip_boundary,
+                                             int t) {
   int i, j, k;
   decode(t, gf.n1, i, j, k);
   const int Nf = gf.N;
@@ -753,6 +784,14 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const Tran
   for (int e = 0; e < n; ++e) a += tt->pp_w[cls * 10 + e] * xc[3 * gc.vstride + base + tt->pp_off[cls * 10 + e]];
   const int pp = 3 * gf.vstride + t;
   xf[pp] = add ? xf[pp] + a : a;
+}
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
+                                                    const T* __restrict__ xc, T* __restrict__ xf, int add,
+                                                    int skip_boundary) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gf.nn) return;
+  prolong_site<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t);
 }
 
 // Boundary velocity values of the coarse level from the coincident fine nodes.
@@ -954,6 +993,178 @@ __global__ void __launch_bounds__(kBlock) k_axpy(T* __restrict__ y, const T* __r
   if (t < n) y[t] += a * x[t];
 }
 
+// ------------------------------------------------- small-level V-cycle
+// One workgroup runs the whole variable V-cycle of Alg. fmg below and at the
+// level lmin + nlev - 1: the same site bodies as the grid-wide kernels, each
+// phase a block-strided loop, phases separated by barriers.  On the small
+// levels a grid-wide launch is almost all launch latency; here a phase costs
+// a few hundred nanoseconds.
+#ifndef HHG_SMALL_BLOCK
+#define HHG_SMALL_BLOCK 256
+#endif
+constexpr int kSmallBlock = HHG_SMALL_BLOCK;
+
+template <typename T>
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kSmallBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+template <typename T, int G, bool VAR>
+__device__ void small_apply(const SmallLevel<T>& L, int opmask, const T* x, const T* b, T* y, int vel_rows) {
+  for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock)
+    apply_site<T, G, VAR>(L.g, L.lc, x, b, y, opmask, 1, vel_rows, 1, t);
+  for (int q = threadIdx.x; q < L.nbnd; q += kSmallBlock) prow_bnd_site<T>(L.g, L.tb, x, b, y, opmask, 1, L.bnd[q]);
+  __syncthreads();
+}
+
+template <typename T, int G, bool VAR>
+__device__ void small_colour(const SmallLevel<T>& L, T* x, const T* b, int c) {
+  if (c < 4) {
+    const int n = gs_vertex_count(L.g);
+    for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock) gs_vertex_site<T, G, VAR>(L.g, L.lc, x, b, c, w % n, w / n);
+  } else {
+    if constexpr (G == 8) {
+      const int gr = c - 3, n = gs_edge_count(L.g, gr);
+      for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock) gs_edge_site<T, VAR>(L.g, L.lc, x, b, gr, w % n, w / n);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int G, bool VAR>
+__device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters) {
+  if (L.g.N < 2) return;
+  const int ncol = G == 1 ? 4 : 11;
+  for (int it = 0; it < iters; ++it) {
+    for (int s = 0; s < sc.xi; ++s) {
+      for (int c = 0; c < ncol; ++c) small_colour<T, G, VAR>(L, x, b, c);
+      if (sc.gs_sym)
+        for (int c = ncol - 1; c >= 0; --c) small_colour<T, G, VAR>(L, x, b, c);
+    }
+    small_apply<T, G, VAR>(L, sc.full_mask & 12, x, b, r, 0);
+    const int vs = L.g.vstride;
+    for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) x[3 * vs + t] -= sc.omega * L.dinv[t] * r[3 * vs + t];
+    __syncthreads();
+  }
+}
+
+template <typename T, int G>
+__device__ void small_smooth_any(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters) {
+  if (L.lc.nu)
+    small_smooth<T, G, true>(sc, L, x, b, r, iters);
+  else
+    small_smooth<T, G, false>(sc, L, x, b, r, iters);
+}
+
+template <typename T, int G>
+__device__ void small_residual(const SmallCycle<T>& sc, const SmallLevel<T>& L, const T* x, const T* b, T* r) {
+  if (L.lc.nu)
+    small_apply<T, G, true>(L, sc.full_mask, x, b, r, 1);
+  else
+    small_apply<T, G, false>(L, sc.full_mask, x, b, r, 1);
+}
+
+// p -= sum_k w_k p_k / sum_k w_k with w_k = int psi_k (mode 0) or 1 (mode 1)
+template <typename T>
+__device__ void small_pshift(const SmallLevel<T>& L, T* p, int mode, double* red) {
+  double a = 0.0, m = 0.0;
+  for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) {
+    double w = 1.0;
+    if (mode == 0) {
+      int i, j, k;
+      decode(t, L.g.n1, i, j, k);
+      w = (double)L.tb->mclass[bcls3(i, L.g.N) + 3 * bcls3(j, L.g.N) + 9 * bcls3(k, L.g.N)];
+    }
+    a += w * (double)p[t];
+    m += w;
+  }
+  const double sa = block_sum<T>(a, red);
+  const double sm = block_sum<T>(m, red);
+  const double mean = sa / sm;
+  for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) p[t] = (T)((double)p[t] - mean);
+  __syncthreads();
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T>* __restrict__ lv, SmallCycle<T> sc) {
+  __shared__ double red[kSmallBlock];
+  __shared__ double rs[2048];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* const sm = reinterpret_cast<T*>(lds_raw);
+  const bool lds = sc.lds_words > 0;
+  const int top = sc.nlev - 1;
+  // the level vectors: LDS copies, or the work vectors (x, b of the call on top)
+  auto vw = [&](int q) { return 3 * lv[q].g.vstride + lv[q].g.nn; };
+  auto X = [&](int q) -> T* { return lds ? sm + lv[q].lds_off : (q == top ? sc.x : lv[q].cx); };
+  auto B = [&](int q) -> T* { return lds ? sm + lv[q].lds_off + vw(q) : (q == top ? const_cast<T*>(sc.b) : lv[q].cb); };
+  auto R = [&](int q) -> T* { return lds ? sm + lv[q].lds_off + 2 * vw(q) : lv[q].r; };
+  if (lds) {
+    T* xs = X(top);
+    T* bs = B(top);
+    for (int t = threadIdx.x; t < vw(top); t += kSmallBlock) {
+      xs[t] = sc.x[t];
+      bs[t] = sc.b[t];
+    }
+    __syncthreads();
+  }
+  // descend: smooth, residual, restrict (+ zero-sum pressure), zero correction
+  for (int q = top; q >= 1; --q) {
+    const SmallLevel<T>& L = lv[q];
+    const SmallLevel<T>& C = lv[q - 1];
+    T* x = X(q);
+    const T* b = B(q);
+    small_smooth_any<T, G>(sc, L, x, b, R(q), sc.pre0 + (top - q) * sc.inc);
+    small_residual<T, G>(sc, L, x, b, R(q));
+    T* cb = B(q - 1);
+    const T* r = R(q);
+    for (int t = threadIdx.x; t < C.g.nn; t += kSmallBlock) restrict_site<T, G>(L.g, C.g, L.tt, r, cb, t);
+    __syncthreads();
+    small_pshift<T>(C, cb + 3 * (size_t)C.g.vstride, 1, red);
+    T* cx = X(q - 1);
+    for (int t = threadIdx.x; t < vw(q - 1); t += kSmallBlock) cx[t] = T(0);
+    __syncthreads();
+  }
+  // coarsest level: x += K^+ (b - calA x) on the unknowns, zero pressure mean
+  {
+    const SmallLevel<T>& L = lv[0];
+    T* x = X(0);
+    const T* r = R(0);
+    small_residual<T, G>(sc, L, x, B(0), R(0));
+    for (int c = threadIdx.x; c < sc.nunk; c += kSmallBlock) rs[c] = (double)r[sc.unk[c]];
+    __syncthreads();
+    for (int row = threadIdx.x; row < sc.nunk; row += kSmallBlock) {
+      const double* kr = sc.Kp + (size_t)row * sc.nunk;
+      double acc = 0.0;
+      for (int c = 0; c < sc.nunk; ++c) acc += kr[c] * rs[c];
+      x[sc.unk[row]] = (T)((double)x[sc.unk[row]] + acc);
+    }
+    __syncthreads();
+    small_pshift<T>(L, x + 3 * (size_t)L.g.vstride, 0, red);
+  }
+  // ascend: prolongate and add, post-smooth
+  for (int q = 1; q <= top; ++q) {
+    const SmallLevel<T>& L = lv[q];
+    const SmallLevel<T>& C = lv[q - 1];
+    T* x = X(q);
+    const T* xc = X(q - 1);
+    for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) prolong_site<T, G>(C.g, L.g, L.tt, xc, x, 1, 1, t);
+    __syncthreads();
+    small_smooth_any<T, G>(sc, L, x, B(q), R(q), sc.post0 + (top - q) * sc.inc);
+  }
+  if (lds) {
+    const T* xs = X(top);
+    for (int t = threadIdx.x; t < vw(top); t += kSmallBlock) sc.x[t] = xs[t];
+  }
+}
+
 // E[c stride + unk[c]] = 1 for c < n: the unit vectors of the coarse unknowns
 // (columns of the dense coarse operator), E zero-filled by the caller.
 __global__ void __launch_bounds__(kBlock) k_unit_columns(double* __restrict__ E, long stride,
@@ -1110,7 +1321,7 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* 
     }
   } else {
     const int gr = colour - 3;
-    const size_t n = (size_t)(N - 1 + ((0xB2 >> gr) & 1)) * (N - 1 + ((0xD4 >> gr) & 1)) * (N - 1 + ((0xE8 >> gr) & 1));
+    const size_t n = (size_t)gs_edge_count(g, gr);
     KScope ks(s, KF_GS_EDGE, (double)n);
     if (lc.nu)
       hipLaunchKernelGGL((k_gs_edge<T, true>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, lc, x, b, gr);
@@ -1260,6 +1471,24 @@ void launch_coarse(hipStream_t s, const double* Kp, const int* unk, int nunk, co
   HHG_LAUNCH((k_coarse<T>), 1, s, Kp, unk, nunk, r, x);
 }
 
+template <typename T>
+void launch_vcycle_small(hipStream_t s, const SmallLevel<T>* lv, const SmallCycle<T>& sc) {
+  KScope ks(s, KF_SMALL, sc.nlev);
+  const size_t lds = (size_t)sc.lds_words * sizeof(T);
+  if (sc.G == 1)
+    hipLaunchKernelGGL((k_vcycle_small<T, 1>), dim3(1), dim3(kSmallBlock), lds, s, lv, sc);
+  else
+    hipLaunchKernelGGL((k_vcycle_small<T, 8>), dim3(1), dim3(kSmallBlock), lds, s, lv, sc);
+}
+
+void small_kernel_attributes() {
+  const int bytes = kSmallLdsBytes;
+  (void)hipFuncSetAttribute((const void*)k_vcycle_small<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute((const void*)k_vcycle_small<double, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute((const void*)k_vcycle_small<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute((const void*)k_vcycle_small<float, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 void launch_unit_columns(hipStream_t s, double* E, size_t stride, const int* unk, int n) {
   if (n > 0) HHG_LAUNCH(k_unit_columns, nblocks(n), s, E, (long)stride, unk, n);
 }
@@ -1332,7 +1561,8 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
   template void launch_fill<T>(hipStream_t, T*, size_t, T);                                                         \
   template void launch_coarse<T>(hipStream_t, const double*, const int*, int, const T*, T*);                        \
   template void launch_scaled_copy<T>(hipStream_t, T*, const T*, const T*, size_t, T);                              \
-  template void launch_axpy<T>(hipStream_t, T*, const T*, size_t, T);
+  template void launch_axpy<T>(hipStream_t, T*, const T*, size_t, T);                                              \
+  template void launch_vcycle_small<T>(hipStream_t, const SmallLevel<T>*, const SmallCycle<T>&);
 
 HHG_INSTANTIATE(double)
 HHG_INSTANTIATE(float)

@@ -27,10 +27,10 @@ SYMBOLS = [
     "hhg_timer_start", "hhg_timer_read", "hhg_dc_solve", "hhg_set_viscosity",
     "hhg_mlp_create", "hhg_mlp_destroy", "hhg_mlp_num_params", "hhg_mlp_set_params", "hhg_mlp_get_params",
     "hhg_mlp_forward", "hhg_mlp_loss_grad", "hhg_mlp_train", "hhg_mlp_dims", "hhg_coarse_pair", "hhg_hier_set_mlp",
-    "hhg_record_pairs", "hhg_recorded_pairs",
+    "hhg_record_pairs", "hhg_recorded_pairs", "hhg_hier_set_fused_sites",
 ]
 KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER, \
-    KF_MLP = range(11)
+    KF_MLP, KF_SMALL = range(12)
 
 
 class HHGError(RuntimeError):
@@ -105,6 +105,7 @@ def load():
         "hhg_hier_set_mlp": [P, P, D, D],
         "hhg_record_pairs": [P, P, P, I],
         "hhg_recorded_pairs": [P, P],
+        "hhg_hier_set_fused_sites": [P, ctypes.c_long],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -358,6 +359,10 @@ def hhg_mlp_dims(h):
 
 def hhg_coarse_pair(h, r, features, target):
     _check(load().hhg_coarse_pair(h, _ptr(r), _ptr(features), _ptr(target)))
+
+
+def hhg_hier_set_fused_sites(h, max_sites):
+    _check(load().hhg_hier_set_fused_sites(h, int(max_sites)))
 
 
 def hhg_record_pairs(h, features, targets, capacity):
