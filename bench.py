@@ -47,7 +47,7 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-apply-roofline", action="store_true")
-    ap.add_argument("--mode", choices=["fmg", "apply", "learned"], default="fmg",
+    ap.add_argument("--mode", choices=["fmg", "apply", "learned", "dc"], default="fmg",
                     help="apply: only the operator-apply roofline (for counter runs); learned: the "
                          "learned coarse-solve workload (pairs, GPU training, held-out evaluation)")
     ap.add_argument("--pairs", type=int, default=20000)
@@ -72,6 +72,11 @@ def main():
     prob = W.paper_cube()
 
     ctx = hhg.hhg_ctx_create(0, stream.cuda_stream)
+    if args.mode == "dc":
+        res = bench_dc(torch, hhg, ctx, level=args.level if args.level != 5 else 7)
+        print(json.dumps(res), flush=True)
+        hhg.hhg_ctx_destroy(ctx)
+        return
     if args.mode == "learned":
         res = bench_learned(torch, hhg, ctx, args)
         print(json.dumps(res), flush=True)
@@ -374,6 +379,64 @@ def bench_learned(torch, hhg, ctx, args, L=6, lmin=2):
         if m is not None:
             hhg.hhg_hier_set_mlp(P.h, None)
             hhg.hhg_mlp_destroy(m)
+        P.close()
+    return out
+
+
+def bench_dc(torch, hhg, ctx, level=7, lmin=1):
+    """Mixed precision: P2-P1 Taylor-Hood, 6 macro-tets, the given level,
+    Gaussian-bump viscosity 1:100, Fourier forcing, u = 0 on the boundary.
+    Defect correction in float64 to ||r|| <= 1e-12 ||b|| around one V(3,3)
+    cycle per correction, inner cycles in float32 and in float64; reports
+    times, cycles and ||x32 - x64||_M / ||x64||_M."""
+    from paper_2010_13513_amd import workloads as W
+    from paper_2010_13513_amd.problem import Problem
+    P = Problem(torch, ctx, hhg.HHG_P2P1, lmin, level)
+    N = P.N(level)
+    out = {"mode": "dc", "workload": f"P2-P1 Taylor-Hood, 6 Kuhn macro-tets, level {level} ({P.dofs(level)} DoFs), "
+                                     f"Gaussian-bump viscosity 1:100, Fourier forcing, V(3,3) inner cycles (A_f, xi=3)"}
+    try:
+        t0 = time.perf_counter()
+        P.set_viscosity(W.gaussian_bump_viscosity(W.SEED_BASE + 4000, N_ref=N))
+        prob = W.fourier_forcing(W.SEED_BASE + 4001)
+        b = P.rhs(prob)[-1]
+        x0 = P.boundary(prob)
+        v0 = torch.from_numpy(W.normal_vector(W.SEED_BASE + 4002, (N + 1) ** 3)).to(P.dev)
+        om = hhg.hhg_estimate_omega(P.h, level, v0, 100)
+        torch.cuda.synchronize()
+        out["setup_s"] = round(time.perf_counter() - t0, 2)
+        out["omega_inv"] = om
+        log(f"[dc] level {level}: {P.dofs(level)} DoFs, omega_inv {om:.4f}, setup {out['setup_s']} s")
+        # V(3,3) with A_f and xi = 3 Gauss-Seidel sweeps per Uzawa step: every
+        # P2-P1 tuple of Tab. fmg-table with A_f uses xi = 3 (xi = 1 diverges here)
+        prm = hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 3, om)
+        xs = {}
+        for name, prec in (("f64", hhg.HHG_F64), ("f32", hhg.HHG_F32)):
+            x = x0.clone()                                  # warm-up solve (allocations, code paths)
+            hhg.hhg_dc_solve(P.h, x, b, prm, prec, 1, 1e-12, 200, check=False)
+            x = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = hhg.hhg_dc_solve(P.h, x, b, prm, prec, 1, 1e-12, 200, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            xs[name] = x
+            out[name] = {"seconds": round(dt, 4), "cycles": st.cycles, "rel_res": st.rel_res,
+                         "ms_per_cycle": round(1e3 * dt / max(st.cycles, 1), 3),
+                         "dofs_per_s": P.dofs(level) / dt}
+            log(f"[dc] inner {name}: {st.cycles} cycles, rel res {st.rel_res:.2e}, {dt:.3f} s")
+        e = xs["f32"] - xs["f64"]
+        hhg.hhg_project_mean_zero(P.h, level, e)
+        me, mx = torch.empty_like(e), torch.empty_like(e)
+        hhg.hhg_apply(P.h, level, hhg.HHG_OP_MASS, e, me)
+        hhg.hhg_apply(P.h, level, hhg.HHG_OP_MASS, xs["f64"], mx)
+        eu, ep = hhg.hhg_dots(P.h, level, e, me)
+        xu, xp = hhg.hhg_dots(P.h, level, xs["f64"], mx)
+        out["rel_diff_M"] = {"u": float(np.sqrt(eu / xu)), "p": float(np.sqrt(ep / xp))}
+        out["speedup_f32_vs_f64"] = round(out["f64"]["seconds"] / out["f32"]["seconds"], 3)
+        log(f"[dc] ||x32 - x64||_M / ||x64||_M: u {out['rel_diff_M']['u']:.2e}, p {out['rel_diff_M']['p']:.2e}; "
+            f"speed-up {out['speedup_f32_vs_f64']}")
+    finally:
         P.close()
     return out
 

@@ -27,12 +27,6 @@ namespace {
 const int kGroupDir[8][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1},
                              {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
 
-int group_of_parity(int px, int py, int pz) {
-  for (int g = 0; g < 8; ++g)
-    if (kGroupDir[g][0] == px && kGroupDir[g][1] == py && kGroupDir[g][2] == pz) return g;
-  return -1;
-}
-
 // Device memory arena owned by a hierarchy.
 struct Arena {
   std::vector<void*> ptrs;
@@ -343,56 +337,6 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
   HHG_CHECK_HIP(hipGetLastError());
 }
 
-// Kuhn point location inside the unit cube at t (in [0,1]^3): vertices (P1
-// offsets from the cube origin) and barycentric coordinates.
-void kuhn_locate(const double t[3], int V[4][3], double lam[4]) {
-  int ord[3] = {0, 1, 2};
-  std::stable_sort(ord, ord + 3, [&](int a, int b) { return t[a] > t[b]; });
-  lam[0] = 1.0 - t[ord[0]];
-  lam[1] = t[ord[0]] - t[ord[1]];
-  lam[2] = t[ord[1]] - t[ord[2]];
-  lam[3] = t[ord[2]];
-  for (int d = 0; d < 3; ++d) V[0][d] = 0;
-  for (int s = 0; s < 3; ++s) {
-    for (int d = 0; d < 3; ++d) V[s + 1][d] = V[s][d];
-    V[s + 1][ord[s]] += 1;
-  }
-}
-
-// Interpolation weights of a coarse element function at a point of a fine class.
-// order 1: P1 (coarse DoFs on the P1 lattice, group 0); order 2: P2 (groups).
-// Returns entries (coarse group, offset from cube origin in coarse index units, weight).
-std::vector<std::tuple<int, int, int, int, double>> interp_weights(int order, const double t[3]) {
-  int V[4][3];
-  double lam[4];
-  kuhn_locate(t, V, lam);
-  std::map<std::tuple<int, int, int, int>, double> acc;
-  if (order == 1) {
-    for (int a = 0; a < 4; ++a)
-      if (lam[a] != 0.0) acc[std::make_tuple(0, V[a][0], V[a][1], V[a][2])] += lam[a];
-  } else {
-    const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
-    for (int a = 0; a < 4; ++a) {
-      const double v = lam[a] * (2.0 * lam[a] - 1.0);
-      if (v != 0.0) acc[std::make_tuple(0, V[a][0], V[a][1], V[a][2])] += v;
-    }
-    for (int e = 0; e < 6; ++e) {
-      const int p = E[e][0], q = E[e][1];
-      const double v = 4.0 * lam[p] * lam[q];
-      if (v == 0.0) continue;
-      int S[3];
-      for (int d = 0; d < 3; ++d) S[d] = V[p][d] + V[q][d];  // doubled coarse position rel. to 2*cube
-      const int gr = group_of_parity(S[0] & 1, S[1] & 1, S[2] & 1);
-      acc[std::make_tuple(gr, S[0] >> 1, S[1] >> 1, S[2] >> 1)] += v;
-    }
-  }
-  std::vector<std::tuple<int, int, int, int, double>> out;
-  for (auto& kv : acc)
-    if (std::fabs(kv.second) > 1e-15)
-      out.emplace_back(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
-                       kv.second);
-  return out;
-}
 
 void build_transfer(hhg_hier h, Level& lc, Level& lf) {
   Arena& a = h->arena;

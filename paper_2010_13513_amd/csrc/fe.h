@@ -1,6 +1,7 @@
 // Host-side finite-element setup shared by the library and the build-time
 // stencil generator (plain C++, no HIP).
 #pragma once
+#include <tuple>
 #include <vector>
 
 namespace hhg {
@@ -36,6 +37,24 @@ void build_elements(int vorder, ElementSet* es);
 // 3 weights), 'B' (pressure row -> velocity cols, 3 weights), 'C' pressure
 // stiffness, 'P' pressure mass.  Row position: group g and index (i, j, k).
 Row row_stencil(const ElementSet& es, char kind, int g, int i, int j, int k, int Nbox);
+
+// Velocity group (0: vertex, 1..7: edge directions) of a doubled-lattice parity.
+int group_of_parity(int px, int py, int pz);
+// Point location in the Kuhn cube: t in [0,1]^3 -> vertices V (offsets from
+// the cube origin) and barycentric coordinates lam of the containing tet.
+void kuhn_locate(const double t[3], int V[4][3], double lam[4]);
+// Interpolation weights of a coarse element function at a point of a fine
+// class: entries (coarse group, offset from cube origin in coarse index
+// units, weight); order 1: P1 (group 0), order 2: P2 (groups).
+std::vector<std::tuple<int, int, int, int, double>> interp_weights(int order, const double t[3]);
+// Restriction (transpose of the interpolation): per coarse velocity group the
+// (fine group, fine offset from 2 (i,j,k), weight) entries; the linear P1
+// pressure restriction (offsets from 2 (i,j,k)).
+struct RestrictEntry {
+  int g, di, dj, dk;
+  double w;
+};
+void restriction_entries(int vorder, std::vector<std::vector<RestrictEntry>>& vel, std::vector<RestrictEntry>& pres);
 
 // Dense symmetric pseudo-inverse by cyclic Jacobi rotations (host, float64):
 // eigen-decomposition K = Q L Q^T, eigenvalues below rcond * max |L| dropped.

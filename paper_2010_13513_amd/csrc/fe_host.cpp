@@ -332,4 +332,107 @@ bool sym_pinv_null1(int n, const std::vector<double>& K, const std::vector<doubl
   return true;
 }
 
+int group_of_parity(int px, int py, int pz) {
+  for (int g = 0; g < 8; ++g)
+    if (kGroupDir[g][0] == px && kGroupDir[g][1] == py && kGroupDir[g][2] == pz) return g;
+  return -1;
+}
+
+// Kuhn point location inside the unit cube at t (in [0,1]^3): vertices (P1
+// offsets from the cube origin) and barycentric coordinates.
+void kuhn_locate(const double t[3], int V[4][3], double lam[4]) {
+  int ord[3] = {0, 1, 2};
+  std::stable_sort(ord, ord + 3, [&](int a, int b) { return t[a] > t[b]; });
+  lam[0] = 1.0 - t[ord[0]];
+  lam[1] = t[ord[0]] - t[ord[1]];
+  lam[2] = t[ord[1]] - t[ord[2]];
+  lam[3] = t[ord[2]];
+  for (int d = 0; d < 3; ++d) V[0][d] = 0;
+  for (int s = 0; s < 3; ++s) {
+    for (int d = 0; d < 3; ++d) V[s + 1][d] = V[s][d];
+    V[s + 1][ord[s]] += 1;
+  }
+}
+
+// Interpolation weights of a coarse element function at a point of a fine class.
+// order 1: P1 (coarse DoFs on the P1 lattice, group 0); order 2: P2 (groups).
+// Returns entries (coarse group, offset from cube origin in coarse index units, weight).
+std::vector<std::tuple<int, int, int, int, double>> interp_weights(int order, const double t[3]) {
+  int V[4][3];
+  double lam[4];
+  kuhn_locate(t, V, lam);
+  std::map<std::tuple<int, int, int, int>, double> acc;
+  if (order == 1) {
+    for (int a = 0; a < 4; ++a)
+      if (lam[a] != 0.0) acc[std::make_tuple(0, V[a][0], V[a][1], V[a][2])] += lam[a];
+  } else {
+    const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int a = 0; a < 4; ++a) {
+      const double v = lam[a] * (2.0 * lam[a] - 1.0);
+      if (v != 0.0) acc[std::make_tuple(0, V[a][0], V[a][1], V[a][2])] += v;
+    }
+    for (int e = 0; e < 6; ++e) {
+      const int p = E[e][0], q = E[e][1];
+      const double v = 4.0 * lam[p] * lam[q];
+      if (v == 0.0) continue;
+      int S[3];
+      for (int d = 0; d < 3; ++d) S[d] = V[p][d] + V[q][d];  // doubled coarse position rel. to 2*cube
+      const int gr = group_of_parity(S[0] & 1, S[1] & 1, S[2] & 1);
+      acc[std::make_tuple(gr, S[0] >> 1, S[1] >> 1, S[2] >> 1)] += v;
+    }
+  }
+  std::vector<std::tuple<int, int, int, int, double>> out;
+  for (auto& kv : acc)
+    if (std::fabs(kv.second) > 1e-15)
+      out.emplace_back(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                       kv.second);
+  return out;
+}
+
+void restriction_entries(int vorder, std::vector<std::vector<RestrictEntry>>& vel, std::vector<RestrictEntry>& pres) {
+  const int G = vorder == 1 ? 1 : 8;
+  const int vq = vorder == 1 ? 2 : 4;  // fine positions per coarse cube edge
+  std::vector<std::map<std::tuple<int, int, int, int>, double>> racc(G);
+  for (int cz = 0; cz < vq; ++cz)
+    for (int cy = 0; cy < vq; ++cy)
+      for (int cx = 0; cx < vq; ++cx) {
+        const double t[3] = {(double)cx / vq, (double)cy / vq, (double)cz / vq};
+        for (auto& w : interp_weights(vorder, t)) {
+          const int gc = std::get<0>(w);
+          const int c[3] = {cx, cy, cz};
+          const int o[3] = {std::get<1>(w), std::get<2>(w), std::get<3>(w)};
+          int fofs[3], fpar[3];
+          for (int d = 0; d < 3; ++d) {
+            if (vorder == 2) {
+              const int delta = c[d] - 4 * o[d] - 2 * kGroupDir[gc][d];  // fine doubled, rel. to 2 S_c
+              fpar[d] = delta & 1;
+              fofs[d] = kGroupDir[gc][d] + (delta >> 1);  // fine index rel. to 2 (i,j,k)
+            } else {
+              fpar[d] = 0;
+              fofs[d] = c[d] - 2 * o[d];
+            }
+          }
+          const int fg = vorder == 2 ? group_of_parity(fpar[0], fpar[1], fpar[2]) : 0;
+          racc[gc][std::make_tuple(fg, fofs[0], fofs[1], fofs[2])] += std::get<4>(w);
+        }
+      }
+  vel.assign(G, {});
+  for (int gc = 0; gc < G; ++gc)
+    for (auto& kv : racc[gc])
+      vel[gc].push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                         kv.second});
+  std::map<std::tuple<int, int, int>, double> pracc;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const double t[3] = {cx / 2.0, cy / 2.0, cz / 2.0};
+        for (auto& w : interp_weights(1, t))
+          pracc[std::make_tuple(cx - 2 * std::get<1>(w), cy - 2 * std::get<2>(w), cz - 2 * std::get<3>(w))] +=
+              std::get<4>(w);
+      }
+  pres.clear();
+  for (auto& kv : pracc)
+    pres.push_back({0, std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second});
+}
+
 }  // namespace hhg

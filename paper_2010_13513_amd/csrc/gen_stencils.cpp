@@ -272,6 +272,71 @@ void emit_zm(FILE* f, const ElementSet& es, const char* D, int G) {
   }
 }
 
+// Pressure rows at boundary nodes, one function per boundary class (cls =
+// c_i + 3 c_j + 9 c_k, c = 0 low face, 1 inside, 2 high face; 13 is the
+// interior): the row summed over the lattice elements inside the cube only,
+// taken at a representative node of the class in a box of 4 intervals.
+Row pruned_at(const ElementSet& es, char kind, int ci, int cj, int ck, int nw) {
+  Row r = row_stencil(es, kind, 0, ci, cj, ck, 4);
+  double mx = 0.0;
+  for (auto& e : r)
+    for (int d = 0; d < nw; ++d) mx = std::max(mx, std::fabs(e.w[d]));
+  Row out;
+  for (auto& e : r) {
+    bool keep = false;
+    for (int d = 0; d < nw; ++d) keep |= std::fabs(e.w[d]) > 1e-13 * mx;
+    if (keep) out.push_back(e);
+  }
+  return out;
+}
+void emit_boundary_rows(FILE* f, const ElementSet& es, const char* D, int G) {
+  const int rep[3] = {0, 2, 4};
+  for (int cls = 0; cls < 27; ++cls) {
+    if (cls == 13) continue;
+    const int ci = rep[cls % 3], cj = rep[(cls / 3) % 3], ck = rep[cls / 9];
+    char name[64];
+    std::snprintf(name, sizeof name, "%s_Bc%d", D, cls);
+    emit_pv(f, name, pruned_at(es, 'B', ci, cj, ck, 3));
+    if (G == 1) {
+      std::snprintf(name, sizeof name, "%s_Cc%d", D, cls);
+      emit_pp(f, name, pruned_at(es, 'C', ci, cj, ck, 1));
+    }
+  }
+}
+
+// Restriction (transpose of the interpolation) gathered at coarse index
+// (i, j, k): per coarse velocity group the three components from the fine
+// residual around fine index fb = 2 (i, j, k) (fine strides s1, s2, group
+// stride nn, component stride vs); and the P1 pressure with every entry
+// clipped to the fine lattice [0, Nf]^3.
+void emit_restriction(FILE* f, const char* D, int vorder) {
+  std::vector<std::vector<RestrictEntry>> vel;
+  std::vector<RestrictEntry> pres;
+  restriction_entries(vorder, vel, pres);
+  for (size_t gc = 0; gc < vel.size(); ++gc) {
+    std::fprintf(f,
+                 "template <typename T>\n__device__ __forceinline__ void %s_R_g%zu(const T* __restrict__ rf, int fb, int "
+                 "s1, int s2, int nn, int vs, T& a0, T& a1, T& a2) {\n",
+                 D, gc);
+    for (auto& e : vel[gc])
+      std::fprintf(f,
+                   "  { const int o = fb + (%d) * nn + (%d) + (%d) * s1 + (%d) * s2; const T w = T(%s); a0 += w * rf[o]; "
+                   "a1 += w * rf[vs + o]; a2 += w * rf[2 * vs + o]; }\n",
+                   e.g, e.di, e.dj, e.dk, lit(e.w).c_str());
+    std::fprintf(f, "}\n// %zu entries\n\n", vel[gc].size());
+  }
+  std::fprintf(f,
+               "template <typename T>\n__device__ __forceinline__ T %s_RP(const T* __restrict__ p, int fb, int fi, int fj, "
+               "int fk, int Nf, int s1, int s2) {\n  T a = 0;\n",
+               D);
+  for (auto& e : pres)
+    std::fprintf(f,
+                 "  if (fi + (%d) >= 0 && fi + (%d) <= Nf && fj + (%d) >= 0 && fj + (%d) <= Nf && fk + (%d) >= 0 && fk + (%d) "
+                 "<= Nf) a += T(%s) * p[fb + (%d) + (%d) * s1 + (%d) * s2];\n",
+                 e.di, e.di, e.dj, e.dj, e.dk, e.dk, lit(e.w).c_str(), e.di, e.dj, e.dk);
+  std::fprintf(f, "  return a;\n}\n// %zu entries\n\n", pres.size());
+}
+
 double diag_of(const Row& r, int g) {
   for (auto& e : r)
     if (e.g == g && e.di == 0 && e.dj == 0 && e.dk == 0) return e.w[0];
@@ -319,6 +384,8 @@ int main(int argc, char** argv) {
       emit_pp(f, "p1_C", C);
     }
     emit_zm(f, es, D, G);
+    emit_boundary_rows(f, es, D, G);
+    emit_restriction(f, D, vorder);
   }
   std::fprintf(f, "}  // namespace gen\n}  // namespace hhg\n");
   std::fclose(f);

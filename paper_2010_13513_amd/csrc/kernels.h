@@ -44,7 +44,7 @@ struct Tables {
 // Kernel families for the event timer (hhg_timer_*).
 enum KernelFamily {
   KF_APPLY = 0,     // stencil apply / residual (interior pressure and all velocity rows)
-  KF_PROW_BND = 1,  // boundary pressure rows
+  KF_PROW_BND = 1,  // boundary pressure rows (now extra blocks of the apply launches: no launches of their own)
   KF_GS_VERTEX = 2, // Gauss-Seidel colour of the vertex group
   KF_GS_EDGE = 3,   // Gauss-Seidel colour of one P2 edge group
   KF_PSTEP = 4,     // Uzawa pressure step

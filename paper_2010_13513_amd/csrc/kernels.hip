@@ -215,6 +215,65 @@ __device__ __forceinline__ int xcd_block() {
   return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 unsigned nblocks8(size_t n) { return (unsigned)(((n + kBlock - 1) / kBlock + 7) & ~(size_t)7); }
+// The same remap over the first nmain blocks of a grid (nmain a multiple of 8).
+__device__ __forceinline__ int xcd_block_of(int nmain) {
+  const int per = nmain >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// Pressure rows of the boundary nodes, run by the extra blocks appended to an
+// apply launch (blocks nmain.. of the grid, block size bs): they overlap the
+// interior rows instead of taking a launch of their own.
+template <typename T, int G>
+__device__ __forceinline__ void prow_bnd_block(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                               const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                               const int* __restrict__ bnd, int nbnd, int nmain, int bs);
+
+// Pressure row value at any node t = (i, j, k): interior rows from the
+// generated interior stencils, boundary rows from the generated per-class
+// stencils (cls = c_i + 3 c_j + 9 c_k, c = 0 low face, 1 inside, 2 high
+// face): B u (opmask 4) and -C p (8) or +C p (8 | 16) for PSPG, summed over
+// the elements inside the cube.
+#define HHG_BCLS_CASES(D, X)                                                                              \
+  switch (cls) {                                                                                          \
+    case 0: X(D, 0); break;   case 1: X(D, 1); break;   case 2: X(D, 2); break;   case 3: X(D, 3); break;   \
+    case 4: X(D, 4); break;   case 5: X(D, 5); break;   case 6: X(D, 6); break;   case 7: X(D, 7); break;   \
+    case 8: X(D, 8); break;   case 9: X(D, 9); break;   case 10: X(D, 10); break; case 11: X(D, 11); break; \
+    case 12: X(D, 12); break; case 14: X(D, 14); break; case 15: X(D, 15); break; case 16: X(D, 16); break; \
+    case 17: X(D, 17); break; case 18: X(D, 18); break; case 19: X(D, 19); break; case 20: X(D, 20); break; \
+    case 21: X(D, 21); break; case 22: X(D, 22); break; case 23: X(D, 23); break; case 24: X(D, 24); break; \
+    case 25: X(D, 25); break; default: X(D, 26); break;                                                   \
+  }
+#define HHG_BROW(D, C) gen::D##_Bc##C<T>(u0, u1, u2, t, s1, s2, nn, ab)
+#define HHG_CROW(D, C) gen::D##_Cc##C<T>(p, t, s1, s2, ac)
+template <typename T, int G>
+__device__ __forceinline__ T prow_value(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x, int opmask,
+                                        int t, int i, int j, int k) {
+  const int N = g.N, s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
+  const T* __restrict__ u0 = x;
+  const T* __restrict__ u1 = x + g.vstride;
+  const T* __restrict__ u2 = x + 2 * g.vstride;
+  const T* __restrict__ p = x + 3 * g.vstride;
+  T ab = 0, ac = 0;
+  if (i >= 1 && j >= 1 && k >= 1 && i <= N - 1 && j <= N - 1 && k <= N - 1) {
+    if (opmask & 4) Rows<T, G>::B(u0, u1, u2, t, s1, s2, nn, ab);
+    if (opmask & 24) Rows<T, G>::C(p, t, s1, s2, ac);
+  } else {
+    const int cls = bcls3(i, N) + 3 * bcls3(j, N) + 9 * bcls3(k, N);
+    if (opmask & 4) {
+      if constexpr (G == 1) {
+        HHG_BCLS_CASES(p1, HHG_BROW)
+      } else {
+        HHG_BCLS_CASES(p2, HHG_BROW)
+      }
+    }
+    if constexpr (G == 1)
+      if (opmask & 24) HHG_BCLS_CASES(p1, HHG_CROW)
+  }
+  return lc.b * ab + ((opmask & 16) ? lc.c * ac : -lc.c * ac);
+}
+#undef HHG_BROW
+#undef HHG_CROW
 
 // One velocity row type (group GR) of the apply at array index t.
 template <typename T, int G, int GR, bool VAR>
@@ -261,7 +320,7 @@ __device__ __forceinline__ void apply_vrows(const Geom& g, const LevelConst<T>& 
 
 // y = [b -] op x on every row type at array index t: the G velocity groups
 // (zero rows where the site is not an interior velocity DoF) and the interior
-// pressure row (boundary pressure rows: k_prow_bnd).  opmask bits: 1 A, 2 B^T,
+// pressure row (boundary pressure rows: extra blocks, prow_bnd_block).  opmask bits: 1 A, 2 B^T,
 // 4 B, 8 -C (block of calA), 16: +C instead.
 template <typename T, int G, bool VAR>
 __device__ __forceinline__ void apply_site(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
@@ -271,16 +330,8 @@ __device__ __forceinline__ void apply_site(const Geom& g, const LevelConst<T>& l
   decode(t, g.n1, i, j, k);
   const int N = g.N;
   if (vel_rows) apply_vrows<T, G, 0, VAR>(g, lc, x, b, y, opmask, has_b, t, i, j, k);
-  if (p_rows && i >= 1 && j >= 1 && k >= 1 && i <= N - 1 && j <= N - 1 && k <= N - 1) {
-    const int s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
-    const T* __restrict__ u0 = x;
-    const T* __restrict__ u1 = x + g.vstride;
-    const T* __restrict__ u2 = x + 2 * g.vstride;
-    const T* __restrict__ p = x + 3 * g.vstride;
-    T ab = 0, ac = 0;
-    if (opmask & 4) Rows<T, G>::B(u0, u1, u2, t, s1, s2, nn, ab);
-    if (opmask & 24) Rows<T, G>::C(p, t, s1, s2, ac);
-    const T acc = lc.b * ab + ((opmask & 16) ? lc.c * ac : -lc.c * ac);
+  if (p_rows && i >= 1 && j >= 1 && k >= 1 && i <= N - 1 && j <= N - 1 && k <= N - 1) {  // boundary: prow_bnd_block
+    const T acc = prow_value<T, G>(g, lc, x, opmask, t, i, j, k);
     const int pp = 3 * g.vstride + t;
     y[pp] = has_b ? b[pp] - acc : acc;
   }
@@ -288,8 +339,13 @@ __device__ __forceinline__ void apply_site(const Geom& g, const LevelConst<T>& l
 template <typename T, int G, bool VAR>
 __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, const T* __restrict__ x,
                                                   const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                                  int vel_rows, int p_rows) {
-  const int t = xcd_block() * kBlock + threadIdx.x;
+                                                  int vel_rows, int p_rows, const int* __restrict__ bnd, int nbnd,
+                                                  int nmain) {
+  if ((int)blockIdx.x >= nmain) {
+    prow_bnd_block<T, G>(g, lc, x, b, y, opmask, has_b, bnd, nbnd, nmain, kBlock);
+    return;
+  }
+  const int t = xcd_block_of(nmain) * kBlock + threadIdx.x;
   if (t >= g.nn) return;
   apply_site<T, G, VAR>(g, lc, x, b, y, opmask, has_b, vel_rows, p_rows, t);
 }
@@ -407,9 +463,13 @@ __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, c
 template <typename T, int G>
 __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
                                                           const T* __restrict__ b, T* __restrict__ y, int has_b, int kc,
-                                                          int ncb) {
+                                                          int ncb, const int* __restrict__ bnd, int nbnd, int nmain) {
   __shared__ T pshare[2][3][kZmCols];
-  const int lin = xcd_block();
+  if ((int)blockIdx.x >= nmain) {
+    prow_bnd_block<T, G>(g, lc, x, b, y, G == 1 ? 15 : 7, has_b, bnd, nbnd, nmain, 3 * kZmCols);
+    return;
+  }
+  const int lin = xcd_block_of(nmain);
   const int cb = lin % ncb, chunk = lin / ncb;
   const int n1 = g.n1, N = g.N;
   ZmCol c;
@@ -434,42 +494,21 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
 }
 
 // Pressure rows at boundary nodes (list), boundary-class stencils.
-template <typename T>
-__device__ __forceinline__ void prow_bnd_site(const Geom& g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
-                                              const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                              int node) {
+template <typename T, int G>
+__device__ __forceinline__ void prow_bnd_block(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                               const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
+                                               const int* __restrict__ bnd, int nbnd, int nmain, int bs) {
+  const int q = ((int)blockIdx.x - nmain) * bs + (int)threadIdx.x;
+  if (q >= nbnd) return;
+  const int t = bnd[q];
   int i, j, k;
-  decode(node, g.n1, i, j, k);
-  const int cls = bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N);
-  const T* u0 = x;
-  const T* u1 = x + g.vstride;
-  const T* u2 = x + 2 * g.vstride;
-  const T* p = x + 3 * g.vstride;
-  T acc = 0;
-  if (opmask & 4) {
-    const DStencil<T> s = tb->B[cls];
-    for (int e = 0; e < s.n; ++e) {
-      const int o = node + s.off[e];
-      acc += s.w[3 * e] * u0[o] + s.w[3 * e + 1] * u1[o] + s.w[3 * e + 2] * u2[o];
-    }
-  }
-  if (opmask & 8) {
-    const DStencil<T> s = tb->C[cls];
-    T c = 0;
-    for (int e = 0; e < s.n; ++e) c += s.w[e] * p[node + s.off[e]];
-    acc += (opmask & 16) ? c : -c;
-  }
-  const int pp = 3 * g.vstride + node;
+  decode(t, g.n1, i, j, k);
+  const T acc = prow_value<T, G>(g, lc, x, opmask, t, i, j, k);
+  const int pp = 3 * g.vstride + t;
   y[pp] = has_b ? b[pp] - acc : acc;
 }
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prow_bnd(Geom g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
-                                                     const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                                     const int* __restrict__ bnd, int nb) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= nb) return;
-  prow_bnd_site<T>(g, tb, x, b, y, opmask, has_b, bnd[t]);
-}
+
+
 
 // ---------------------------------------------------------- Gauss-Seidel
 // The generated row functions accumulate three components at once; the
@@ -690,50 +729,42 @@ __global__ void __launch_bounds__(kBlock) k_dot(const T* __restrict__ x, const T
 
 // ---------------------------------------------------------------- transfer
 // Restriction (transpose of the prolongation): coarse thread gathers fine values.
+// Restriction (transpose of the prolongation, generated gathers): one coarse
+// node t and one group gr per call -- velocity group gr < G (three
+// components), or the P1 pressure for gr = G (entries clipped at the domain
+// boundary).  Coarse boundary velocity rows are zero.
 template <typename T, int G>
-__device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, const TransferTables<T>* __restrict__ tt,
-                                              const T* __restrict__ rf, T* __restrict__ rc, int t) {
+__device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, const T* __restrict__ rf,
+                                              T* __restrict__ rc, int t, int gr) {
   int i, j, k;
   decode(t, gc.n1, i, j, k);
-  const int fbase = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
-#pragma unroll
-  for (int gr = 0; gr < G; ++gr) {
-    const bool in = vel_interior<G>(gr, i, j, k, gc.N);
-    T a0 = 0, a1 = 0, a2 = 0;
-    if (in) {
-      const int n = tt->r[gr].n;
-      const int* __restrict__ off = tt->r[gr].off;
-      const T* __restrict__ w = tt->r[gr].w;
-      for (int e = 0; e < n; ++e) {
-        const int o = fbase + off[e];
-        a0 += w[e] * rf[o];
-        a1 += w[e] * rf[gf.vstride + o];
-        a2 += w[e] * rf[2 * gf.vstride + o];
-      }
+  const int fb = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
+  const int s1 = gf.n1, s2 = gf.n1 * gf.n1, nn = gf.nn, vs = gf.vstride;
+  if (gr == G) {
+    const T* pf = rf + 3 * (size_t)vs;
+    rc[3 * gc.vstride + t] = G == 1 ? gen::p1_RP<T>(pf, fb, 2 * i, 2 * j, 2 * k, gf.N, s1, s2)
+                                    : gen::p2_RP<T>(pf, fb, 2 * i, 2 * j, 2 * k, gf.N, s1, s2);
+    return;
+  }
+  T a0 = 0, a1 = 0, a2 = 0;
+  if (vel_interior<G>(gr, i, j, k, gc.N)) {
+    if constexpr (G == 1) {
+      gen::p1_R_g0<T>(rf, fb, s1, s2, nn, vs, a0, a1, a2);
+    } else {
+      const int g = gr;
+      HHG_P2_CASES(p2_R, rf, fb, s1, s2, nn, vs, a0, a1, a2)
     }
-    const int pos = gr * gc.nn + t;
-    rc[pos] = a0;
-    rc[gc.vstride + pos] = a1;
-    rc[2 * gc.vstride + pos] = a2;
   }
-  // pressure: linear restriction, clipped at the domain boundary
-  T acc = 0;
-  const int Nf = gf.N;
-  const int n = tt->rp.n;
-  for (int e = 0; e < n; ++e) {
-    const int cd = tt->rp_d[e];
-    const int fi = 2 * i + (cd & 15) - 2, fj = 2 * j + ((cd >> 4) & 15) - 2, fk = 2 * k + ((cd >> 8) & 15) - 2;
-    if (fi < 0 || fj < 0 || fk < 0 || fi > Nf || fj > Nf || fk > Nf) continue;
-    acc += tt->rp.w[e] * rf[3 * gf.vstride + fbase + tt->rp.off[e]];
-  }
-  rc[3 * gc.vstride + t] = acc;
+  const int pos = gr * gc.nn + t;
+  rc[pos] = a0;
+  rc[gc.vstride + pos] = a1;
+  rc[2 * gc.vstride + pos] = a2;
 }
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const TransferTables<T>* __restrict__ tt,
-                                                     const T* __restrict__ rf, T* __restrict__ rc) {
+__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const T* __restrict__ rf, T* __restrict__ rc) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= gc.nn) return;
-  restrict_site<T, G>(gf, gc, tt, rf, rc, t);
+  restrict_site<T, G>(gf, gc, rf, rc, t, blockIdx.y);
 }
 
 // Prolongation: fine thread evaluates the coarse function at its sites.
@@ -1021,7 +1052,13 @@ template <typename T, int G, bool VAR>
 __device__ void small_apply(const SmallLevel<T>& L, int opmask, const T* x, const T* b, T* y, int vel_rows) {
   for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock)
     apply_site<T, G, VAR>(L.g, L.lc, x, b, y, opmask, 1, vel_rows, 1, t);
-  for (int q = threadIdx.x; q < L.nbnd; q += kSmallBlock) prow_bnd_site<T>(L.g, L.tb, x, b, y, opmask, 1, L.bnd[q]);
+  for (int q = threadIdx.x; q < L.nbnd; q += kSmallBlock) {
+    const int t = L.bnd[q];
+    int i, j, k;
+    decode(t, L.g.n1, i, j, k);
+    const int pp = 3 * L.g.vstride + t;
+    y[pp] = b[pp] - prow_value<T, G>(L.g, L.lc, x, opmask, t, i, j, k);
+  }
   __syncthreads();
 }
 
@@ -1049,8 +1086,8 @@ __device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, T*
       if (sc.gs_sym)
         for (int c = ncol - 1; c >= 0; --c) small_colour<T, G, VAR>(L, x, b, c);
     }
-    small_apply<T, G, VAR>(L, sc.full_mask & 12, x, b, r, 0);
     const int vs = L.g.vstride;
+    small_apply<T, G, VAR>(L, sc.full_mask & 12, x, b, r, 0);
     for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) x[3 * vs + t] -= sc.omega * L.dinv[t] * r[3 * vs + t];
     __syncthreads();
   }
@@ -1125,7 +1162,8 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
     small_residual<T, G>(sc, L, x, b, R(q));
     T* cb = B(q - 1);
     const T* r = R(q);
-    for (int t = threadIdx.x; t < C.g.nn; t += kSmallBlock) restrict_site<T, G>(L.g, C.g, L.tt, r, cb, t);
+    for (int w = threadIdx.x; w < (G + 1) * C.g.nn; w += kSmallBlock)
+      restrict_site<T, G>(L.g, C.g, r, cb, w % C.g.nn, w / C.g.nn);
     __syncthreads();
     small_pshift<T>(C, cb + 3 * (size_t)C.g.vstride, 1, red);
     T* cx = X(q - 1);
@@ -1260,37 +1298,40 @@ static double p_sites(const Geom& g) {
 template <typename T>
 void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const Tables<T>* tb, const T* x, const T* b,
                   T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd) {
-  if (vel_rows || p_rows) {
-    KScope ks(s, KF_APPLY, p_sites(g));
-    const unsigned nb = nblocks8(g.nn);
-    const int hb = has_b, vr = vel_rows, pr = p_rows;
-    const int full = g.G == 1 ? 15 : 7;
-    if (!lc.nu && opmask == full && vel_rows && p_rows) {
-      // k-marching form: 64 columns per block, k in chunks of kc planes
-      const int kc = g.n1 <= HHG_ZM_KC + 8 ? g.n1 : HHG_ZM_KC;
-      const int ncb = (g.n1 * g.n1 + kZmOut - 1) / kZmOut;
-      const int nch = (g.n1 + kc - 1) / kc;
-      const unsigned nbz = (unsigned)((ncb * nch + 7) & ~7);
-      if (g.G == 1)
-        hipLaunchKernelGGL((k_apply_zm<T, 1>), dim3(nbz), dim3(3 * kZmCols), 0, s, g, lc, x, b, y, hb, kc, ncb);
-      else
-        hipLaunchKernelGGL((k_apply_zm<T, 8>), dim3(nbz), dim3(3 * kZmCols), 0, s, g, lc, x, b, y, hb, kc, ncb);
-    } else if (g.G == 1) {
+  if (!(vel_rows || p_rows)) return;
+  KScope ks(s, KF_APPLY, p_sites(g));
+  const int hb = has_b, vr = vel_rows, pr = p_rows;
+  const int full = g.G == 1 ? 15 : 7;
+  const int nb_bnd = p_rows ? nbnd : 0;
+  if (!lc.nu && opmask == full && vel_rows && p_rows) {
+    // k-marching form: 62 output columns per block, k in chunks of kc planes;
+    // the boundary pressure rows in extra blocks of 192 threads
+    const int kc = g.n1 <= HHG_ZM_KC + 8 ? g.n1 : HHG_ZM_KC;
+    const int ncb = (g.n1 * g.n1 + kZmOut - 1) / kZmOut;
+    const int nch = (g.n1 + kc - 1) / kc;
+    const int nmain = (ncb * nch + 7) & ~7;
+    const int nextra = (nb_bnd + 3 * kZmCols - 1) / (3 * kZmCols);
+    const dim3 grid(nmain + nextra), block(3 * kZmCols);
+    if (g.G == 1)
+      hipLaunchKernelGGL((k_apply_zm<T, 1>), grid, block, 0, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
+    else
+      hipLaunchKernelGGL((k_apply_zm<T, 8>), grid, block, 0, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
+  } else {
+    const int nmain = (int)nblocks8(g.nn);
+    const unsigned nb = (unsigned)(nmain + (nb_bnd + kBlock - 1) / kBlock);
+    if (g.G == 1) {
       if (lc.nu)
-        HHG_LAUNCH((k_apply<T, 1, true>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+        HHG_LAUNCH((k_apply<T, 1, true>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr, bnd, nb_bnd, nmain);
       else
-        HHG_LAUNCH((k_apply<T, 1, false>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+        HHG_LAUNCH((k_apply<T, 1, false>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr, bnd, nb_bnd, nmain);
     } else {
       if (lc.nu)
-        HHG_LAUNCH((k_apply<T, 8, true>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+        HHG_LAUNCH((k_apply<T, 8, true>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr, bnd, nb_bnd, nmain);
       else
-        HHG_LAUNCH((k_apply<T, 8, false>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr);
+        HHG_LAUNCH((k_apply<T, 8, false>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr, bnd, nb_bnd, nmain);
     }
   }
-  if (p_rows && nbnd > 0) {
-    KScope ks(s, KF_PROW_BND, nbnd);
-    HHG_LAUNCH((k_prow_bnd<T>), nblocks(nbnd), s, g, tb, x, b, y, opmask, (int)has_b, bnd, nbnd);
-  }
+  (void)tb;
 }
 
 template <typename T>
@@ -1381,10 +1422,11 @@ void launch_dot(hipStream_t s, const T* x, const T* y, size_t n, double* partial
 template <typename T>
 void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc) {
   KScope ks(s, KF_RESTRICT, p_sites(gf));
+  (void)tt;
   if (gc.G == 1)
-    HHG_LAUNCH((k_restrict<T, 1>), nblocks(gc.nn), s, gf, gc, tt, rf, rc);
+    hipLaunchKernelGGL((k_restrict<T, 1>), dim3(nblocks(gc.nn), 2), dim3(kBlock), 0, s, gf, gc, rf, rc);
   else
-    HHG_LAUNCH((k_restrict<T, 8>), nblocks(gc.nn), s, gf, gc, tt, rf, rc);
+    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 9), dim3(kBlock), 0, s, gf, gc, rf, rc);
 }
 
 template <typename T>
