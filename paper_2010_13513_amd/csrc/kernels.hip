@@ -1025,6 +1025,74 @@ __global__ void __launch_bounds__(kBlock) k_axpy(T* __restrict__ y, const T* __r
 }
 
 // ------------------------------------------------- small-level V-cycle
+// Table-driven forms of the boundary pressure rows and of the restriction:
+// the generated unrolled forms are fastest in grid-wide launches, but in the
+// one-workgroup cycle these compact loops measured faster (its many phases
+// run a lot of distinct code; the Gauss-Seidel and interior rows stay
+// generated, where independent unrolled loads win over table loops).
+template <typename T>
+__device__ __forceinline__ T prow_bnd_table(const Geom& g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
+                                            int opmask, int node) {
+  int i, j, k;
+  decode(node, g.n1, i, j, k);
+  const int cls = bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N);
+  const T* u0 = x;
+  const T* u1 = x + g.vstride;
+  const T* u2 = x + 2 * g.vstride;
+  const T* p = x + 3 * g.vstride;
+  T acc = 0;
+  if (opmask & 4) {
+    const DStencil<T> s = tb->B[cls];
+    for (int e = 0; e < s.n; ++e) {
+      const int o = node + s.off[e];
+      acc += s.w[3 * e] * u0[o] + s.w[3 * e + 1] * u1[o] + s.w[3 * e + 2] * u2[o];
+    }
+  }
+  if (opmask & 8) {
+    const DStencil<T> s = tb->C[cls];
+    T c = 0;
+    for (int e = 0; e < s.n; ++e) c += s.w[e] * p[node + s.off[e]];
+    acc += (opmask & 16) ? c : -c;
+  }
+  return acc;
+}
+
+template <typename T, int G>
+__device__ __forceinline__ void restrict_table(const Geom& gf, const Geom& gc, const TransferTables<T>* __restrict__ tt,
+                                               const T* __restrict__ rf, T* __restrict__ rc, int t, int gr) {
+  int i, j, k;
+  decode(t, gc.n1, i, j, k);
+  const int fbase = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
+  if (gr == G) {
+    T acc = 0;
+    const int Nf = gf.N, n = tt->rp.n;
+    for (int e = 0; e < n; ++e) {
+      const int cd = tt->rp_d[e];
+      const int fi = 2 * i + (cd & 15) - 2, fj = 2 * j + ((cd >> 4) & 15) - 2, fk = 2 * k + ((cd >> 8) & 15) - 2;
+      if (fi < 0 || fj < 0 || fk < 0 || fi > Nf || fj > Nf || fk > Nf) continue;
+      acc += tt->rp.w[e] * rf[3 * gf.vstride + fbase + tt->rp.off[e]];
+    }
+    rc[3 * gc.vstride + t] = acc;
+    return;
+  }
+  T a0 = 0, a1 = 0, a2 = 0;
+  if (vel_interior<G>(gr, i, j, k, gc.N)) {
+    const int n = tt->r[gr].n;
+    const int* __restrict__ off = tt->r[gr].off;
+    const T* __restrict__ w = tt->r[gr].w;
+    for (int e = 0; e < n; ++e) {
+      const int o = fbase + off[e];
+      a0 += w[e] * rf[o];
+      a1 += w[e] * rf[gf.vstride + o];
+      a2 += w[e] * rf[2 * gf.vstride + o];
+    }
+  }
+  const int pos = gr * gc.nn + t;
+  rc[pos] = a0;
+  rc[gc.vstride + pos] = a1;
+  rc[2 * gc.vstride + pos] = a2;
+}
+
 // One workgroup runs the whole variable V-cycle of Alg. fmg below and at the
 // level lmin + nlev - 1: the same site bodies as the grid-wide kernels, each
 // phase a block-strided loop, phases separated by barriers.  On the small
@@ -1054,10 +1122,8 @@ __device__ void small_apply(const SmallLevel<T>& L, int opmask, const T* x, cons
     apply_site<T, G, VAR>(L.g, L.lc, x, b, y, opmask, 1, vel_rows, 1, t);
   for (int q = threadIdx.x; q < L.nbnd; q += kSmallBlock) {
     const int t = L.bnd[q];
-    int i, j, k;
-    decode(t, L.g.n1, i, j, k);
     const int pp = 3 * L.g.vstride + t;
-    y[pp] = b[pp] - prow_value<T, G>(L.g, L.lc, x, opmask, t, i, j, k);
+    y[pp] = b[pp] - prow_bnd_table<T>(L.g, L.tb, x, opmask, t);
   }
   __syncthreads();
 }
@@ -1163,7 +1229,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
     T* cb = B(q - 1);
     const T* r = R(q);
     for (int w = threadIdx.x; w < (G + 1) * C.g.nn; w += kSmallBlock)
-      restrict_site<T, G>(L.g, C.g, r, cb, w % C.g.nn, w / C.g.nn);
+      restrict_table<T, G>(L.g, C.g, L.tt, r, cb, w % C.g.nn, w / C.g.nn);
     __syncthreads();
     small_pshift<T>(C, cb + 3 * (size_t)C.g.vstride, 1, red);
     T* cx = X(q - 1);
