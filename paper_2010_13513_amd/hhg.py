@@ -61,6 +61,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() first")
+    # The library must share the HIP runtime that torch brings (its device
+    # memory and streams are what the library is handed): load torch first, so
+    # that the runtime is already in the process when libhhg's dependency is
+    # resolved, whichever of the two a caller touches first.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     sig = {
