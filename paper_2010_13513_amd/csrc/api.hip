@@ -1434,22 +1434,38 @@ hhg_status hhg_mlp_train(hhg_mlp m, const float* x, const float* y, int n_sample
     HHG_REQUIRE(n_samples >= 1 && epochs >= 1 && lr > 0.f && batch >= 1 && batch <= m->net.max_batch, HHG_ERR_ARG,
                 "bad training parameters");
     hipStream_t s = m->ctx->stream;
-    double tot = 0.0;
-    int nb = 0;
-    for (int e = 0; e < epochs; ++e) {
-      tot = 0.0, nb = 0;
-      for (int b0 = 0; b0 + batch <= n_samples; b0 += batch) {
-        const int* ord = order + (size_t)e * n_samples + b0;
-        for (int q = 0; q < batch; ++q)
-          HHG_REQUIRE(ord[q] >= 0 && ord[q] < n_samples, HHG_ERR_ARG, "sample index out of range");
-        HHG_CHECK_HIP(hipMemcpyAsync(m->idx, ord, sizeof(int) * batch, hipMemcpyHostToDevice, s));
-        launch_gather_rows(s, x, m->idx, batch, m->net.n_in, m->bx);
-        launch_gather_rows(s, y, m->idx, batch, m->net.n_out, m->by);
-        tot += m->net.train_step(s, m->bx, m->by, batch, lr);
-        ++nb;
-      }
+    const int nb = n_samples / batch;  // full minibatches per epoch
+    HHG_REQUIRE(nb >= 1, HHG_ERR_ARG, "batch larger than the data set");
+    const size_t nord = (size_t)epochs * n_samples;
+    for (size_t q = 0; q < nord; ++q)
+      HHG_REQUIRE(order[q] >= 0 && order[q] < n_samples, HHG_ERR_ARG, "sample index out of range");
+    // the whole order and one loss accumulator per epoch on the device: the
+    // steps are enqueued without host round trips
+    int* dord = nullptr;
+    double* dloss = nullptr;
+    HHG_CHECK_HIP(hipMalloc(&dord, nord * sizeof(int)));
+    hipError_t e0 = hipMalloc(&dloss, (size_t)epochs * sizeof(double));
+    if (e0 != hipSuccess) {
+      (void)hipFree(dord);
+      HHG_CHECK_HIP(e0);
     }
-    if (last_loss) *last_loss = nb ? tot / nb : 0.0;
+    std::vector<double> hloss(epochs, 0.0);
+    hipError_t err = hipMemcpyAsync(dord, order, nord * sizeof(int), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(dloss, hloss.data(), epochs * sizeof(double), hipMemcpyHostToDevice, s);
+    for (int e = 0; e < epochs && err == hipSuccess; ++e)
+      for (int q = 0; q < nb; ++q) {
+        const int* idx = dord + (size_t)e * n_samples + (size_t)q * batch;
+        launch_gather_rows(s, x, idx, batch, m->net.n_in, m->bx);
+        launch_gather_rows(s, y, idx, batch, m->net.n_out, m->by);
+        m->net.train_step_dev(s, m->bx, m->by, batch, lr, dloss + e);
+      }
+    if (err == hipSuccess) err = hipMemcpyAsync(hloss.data(), dloss, epochs * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    (void)hipFree(dord);
+    (void)hipFree(dloss);
+    HHG_CHECK_HIP(err);
+    HHG_CHECK_HIP(hipGetLastError());
+    if (last_loss) *last_loss = hloss[epochs - 1] / nb;
   });
 }
 

@@ -19,6 +19,7 @@ struct Mlp {
   unsigned short* G[4] = {nullptr, nullptr, nullptr, nullptr};    // bf16 gradients wrt pre-activations
   float* dA = nullptr;
   double* partial = nullptr;
+  double* loss_acc = nullptr;          // device loss accumulator (2 doubles)
   long step = 0;
   std::vector<void*> allocs;
 
@@ -29,8 +30,10 @@ struct Mlp {
   void unpack(const float* dev_vec, float* host) const;
   void forward_dev(hipStream_t s, const float* x, int B);          // output in Z[3]
   void forward(hipStream_t s, const float* x, int B, float* y);
-  double loss_grad(hipStream_t s, const float* x, const float* y, int B);  // grads in Gr
-  double train_step(hipStream_t s, const float* x, const float* y, int B, float lr);
+  // grads in Gr; *_dev add the batch's mean loss to loss_acc[0] on the device (no host sync)
+  void loss_grad_dev(hipStream_t s, const float* x, const float* y, int B, double* loss_acc);
+  double loss_grad(hipStream_t s, const float* x, const float* y, int B);
+  void train_step_dev(hipStream_t s, const float* x, const float* y, int B, float lr, double* loss_acc);
 };
 
 }  // namespace hhg

@@ -31,9 +31,21 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 // B[p*sbp + n*sbn], bf16 inputs, float32 output with leading dimension ldc.
 // One wavefront per 16 x 16 tile of C; operand lanes: row/column = lane % 16,
 // k = 4 (lane / 16) + q; result lanes: row 4 (lane / 16) + q, column lane % 16.
+// Epilogue (Ep): bias != null: C = acc + bias[n]; act != null: act[m][n] =
+// bf16(relu(C)) (relu != 0) or bf16(C) (ldc-strided, the next layer's input);
+// mask != null: no C; gout[m][n] = bf16(acc * (bf16 mask[m][n] > 0)) (the
+// ReLU backward of the previous layer).
+struct GemmEpilogue {
+  const float* bias = nullptr;
+  unsigned short* act = nullptr;
+  int relu = 0;
+  const unsigned short* mask = nullptr;
+  unsigned short* gout = nullptr;
+};
 __global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const unsigned short* __restrict__ A,
                                                   long sam, long sap, const unsigned short* __restrict__ B, long sbp,
-                                                  long sbn, float* __restrict__ C, long ldc, int accumulate) {
+                                                  long sbn, float* __restrict__ C, long ldc, int accumulate,
+                                                  GemmEpilogue ep) {
   const int lane = threadIdx.x;
   const int tm = blockIdx.x * 16, tn = blockIdx.y * 16;
   const int r = lane & 15, kg = lane >> 4;
@@ -53,26 +65,17 @@ __global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uns
   for (int q = 0; q < 4; ++q) {
     const int mm = tm + 4 * kg + q;
     if (mm < M && n < N) {
-      float* c = C + mm * ldc + n;
-      *c = accumulate ? *c + acc[q] : acc[q];
+      const long o = mm * ldc + n;
+      if (ep.gout) {
+        ep.gout[o] = f2bf(bf2f(ep.mask[o]) > 0.f ? acc[q] : 0.f);
+        continue;
+      }
+      float v = accumulate ? C[o] + acc[q] : acc[q];
+      if (ep.bias) v += ep.bias[n];
+      C[o] = v;
+      if (ep.act) ep.act[o] = f2bf(ep.relu ? fmaxf(v, 0.f) : v);
     }
   }
-}
-
-// Z[b][n] += bias[n]; A[b][n] = bf16(relu(Z)) (relu != 0) for n < N, 0 in padding.
-__global__ void k_bias_act(int B, int N, int Npad, float* __restrict__ Z, const float* __restrict__ bias,
-                           unsigned short* __restrict__ Aout, int relu) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= B * Npad) return;
-  const int n = t % Npad;
-  float z = 0.f;
-  if (n < N) {
-    z = Z[t] + bias[n];
-    Z[t] = z;
-  } else {
-    Z[t] = 0.f;
-  }
-  if (Aout) Aout[t] = f2bf(relu ? fmaxf(z, 0.f) : z);
 }
 
 // Input features (float32, B x n_in) -> bf16, padded to Kpad columns.
@@ -116,12 +119,19 @@ __global__ void __launch_bounds__(256) k_mse(int B, int n_out, int Npad, const f
   if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
 }
 
-// dZ = bf16(dA * (A > 0))
-__global__ void k_relu_bwd(int n, const float* __restrict__ dA, const unsigned short* __restrict__ A,
-                           unsigned short* __restrict__ G) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  G[t] = f2bf(bf2f(A[t]) > 0.f ? dA[t] : 0.f);
+// acc[0] += sum of the block partials / (B n_out) (one workgroup, fixed order).
+__global__ void __launch_bounds__(256) k_loss_accum(const double* __restrict__ partial, int nblk, double scale,
+                                                    double* __restrict__ acc) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += 256) a += partial[q];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += s[0] * scale;
 }
 
 // db[n] = sum_b G[b][n] for n < N (bf16 inputs, float32 sum)
@@ -147,6 +157,10 @@ __global__ void k_adam(long n, float* __restrict__ p, const float* __restrict__ 
   const float w = p[t] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
   p[t] = w;
   if (pb) pb[t] = f2bf(w);
+}
+
+__global__ void k_fill_f64(double* __restrict__ x, int n) {
+  if ((int)threadIdx.x < n) x[threadIdx.x] = 0.0;
 }
 
 __global__ void k_to_bf16(long n, const float* __restrict__ p, unsigned short* __restrict__ pb) {
@@ -199,6 +213,7 @@ void Mlp::init(int in, int H, int out, int max_b) {
   }
   dA = (float*)al((size_t)bpad * H * 4);
   partial = (double*)al(sizeof(double) * ((size_t)bpad * kout / 256 + 2));
+  loss_acc = (double*)al(sizeof(double) * 2);
   step = 0;
 }
 
@@ -239,10 +254,14 @@ void Mlp::unpack(const float* dev_vec, float* host) const {
 }
 
 static void gemm(hipStream_t s, int M, int N, int K, const unsigned short* A, long sam, long sap,
-                 const unsigned short* B, long sbp, long sbn, float* C, long ldc, int acc) {
+                 const unsigned short* B, long sbp, long sbn, float* C, long ldc, int acc,
+                 const GemmEpilogue& ep = GemmEpilogue()) {
   KScope ks(s, KF_MLP, 2.0 * M * N * K);
+  // one wavefront per 16 x 16 tile: these products (batch <= 256, widths <= 512)
+  // are small, and the finest tiling spreads them over the most CUs (a
+  // 64 x 64 LDS-tiled form measured 3x slower here)
   hipLaunchKernelGGL(k_gemm_bf16, dim3((M + 15) / 16, (N + 15) / 16), dim3(64), 0, s, M, N, K, A, sam, sap, B, sbp,
-                     sbn, C, ldc, acc);
+                     sbn, C, ldc, acc, ep);
 }
 
 void Mlp::forward_dev(hipStream_t s, const float* x, int B) {
@@ -250,11 +269,13 @@ void Mlp::forward_dev(hipStream_t s, const float* x, int B) {
   const unsigned short* a = A0;
   int ka = kin;
   for (int l = 0; l < 4; ++l) {
-    // Z[b][n] = sum_k a[b][k] W[n][k]
-    gemm(s, B, rows[l], ka, a, ka, 1, Pb + woff[l], 1, cols[l], Z[l], rows[l], 0);
-    const int N = l == 3 ? n_out : rows[l];
-    hipLaunchKernelGGL(k_bias_act, dim3(nb((long)B * rows[l])), dim3(256), 0, s, B, N, rows[l], Z[l], P + boff[l],
-                       l < 3 ? Ab[l] : nullptr, 1);
+    // Z[b][n] = sum_k a[b][k] W[n][k] + bias[n]; hidden layers: Ab = bf16(relu(Z))
+    // (padded output columns: zero weights and bias, so Z = 0 there)
+    GemmEpilogue ep;
+    ep.bias = P + boff[l];
+    ep.act = l < 3 ? Ab[l] : nullptr;
+    ep.relu = 1;
+    gemm(s, B, rows[l], ka, a, ka, 1, Pb + woff[l], 1, cols[l], Z[l], rows[l], 0, ep);
     if (l < 3) {
       a = Ab[l];
       ka = rows[l];
@@ -267,11 +288,13 @@ void Mlp::forward(hipStream_t s, const float* x, int B, float* y) {
   hipLaunchKernelGGL(k_unpack_output, dim3(nb((long)B * n_out)), dim3(256), 0, s, B, n_out, kout, Z[3], y);
 }
 
-double Mlp::loss_grad(hipStream_t s, const float* x, const float* y, int B) {
+void Mlp::loss_grad_dev(hipStream_t s, const float* x, const float* y, int B, double* loss_acc) {
   forward_dev(s, x, B);
   const long nG = (long)B * kout;
   const unsigned nblk = nb(nG);
   hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, s, B, n_out, kout, Z[3], y, G[3], partial);
+  hipLaunchKernelGGL(k_loss_accum, dim3(1), dim3(256), 0, s, partial, (int)nblk, 1.0 / ((double)B * n_out),
+                     loss_acc);
   for (int l = 3; l >= 0; --l) {
     const unsigned short* a = l > 0 ? Ab[l - 1] : A0;
     const int ka = l > 0 ? rows[l - 1] : kin;
@@ -279,27 +302,31 @@ double Mlp::loss_grad(hipStream_t s, const float* x, const float* y, int B) {
     gemm(s, rows[l], ka, B, G[l], 1, rows[l], a, ka, 1, Gr + woff[l], cols[l], 0);
     hipLaunchKernelGGL(k_colsum, dim3(nb(rows[l])), dim3(256), 0, s, B, rows[l], rows[l], G[l], Gr + boff[l]);
     if (l > 0) {
-      // dA[b][k] = sum_n G[b][n] W[n][k]
-      gemm(s, B, ka, rows[l], G[l], rows[l], 1, Pb + woff[l], cols[l], 1, dA, ka, 0);
-      hipLaunchKernelGGL(k_relu_bwd, dim3(nb((long)B * ka)), dim3(256), 0, s, B * ka, dA, Ab[l - 1], G[l - 1]);
+      // dA[b][k] = sum_n G[b][n] W[n][k], then G[l-1] = bf16(dA * (A[l-1] > 0)) in the epilogue
+      GemmEpilogue ep;
+      ep.mask = Ab[l - 1];
+      ep.gout = G[l - 1];
+      gemm(s, B, ka, rows[l], G[l], rows[l], 1, Pb + woff[l], cols[l], 1, dA, ka, 0, ep);
     }
   }
-  std::vector<double> part(nblk);
-  HHG_CHECK_HIP(hipMemcpyAsync(part.data(), partial, nblk * sizeof(double), hipMemcpyDeviceToHost, s));
-  HHG_CHECK_HIP(hipStreamSynchronize(s));
-  double l = 0.0;
-  for (double v : part) l += v;
-  return l / ((double)B * n_out);
 }
 
-double Mlp::train_step(hipStream_t s, const float* x, const float* y, int B, float lr) {
-  const double loss = loss_grad(s, x, y, B);
+double Mlp::loss_grad(hipStream_t s, const float* x, const float* y, int B) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, loss_acc, 2);
+  loss_grad_dev(s, x, y, B, loss_acc);
+  double l = 0.0;
+  HHG_CHECK_HIP(hipMemcpyAsync(&l, loss_acc, sizeof(double), hipMemcpyDeviceToHost, s));
+  HHG_CHECK_HIP(hipStreamSynchronize(s));
+  return l;
+}
+
+void Mlp::train_step_dev(hipStream_t s, const float* x, const float* y, int B, float lr, double* loss_acc) {
+  loss_grad_dev(s, x, y, B, loss_acc);
   ++step;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(nb(nparams_dev)), dim3(256), 0, s, nparams_dev, P, Gr, Mo, Vo, Pb, lr, b1, b2,
                      1e-8f, c1, c2);
-  return loss;
 }
 
 }  // namespace hhg
