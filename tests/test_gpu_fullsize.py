@@ -1,0 +1,144 @@
+"""Operator apply at the benchmark's full size (48 macro-tets, level 7,
+N = 256: 1.35e8 P2 sites for P2-P1, 1.7e7 nodes for P1-P1), in the launch
+configuration the benchmark times, checked row by row on sampled outputs.
+
+The oracle cannot assemble the operator at this size; a row of the
+discrete operator depends only on the row type (velocity parity class and
+the boundary class of its position) and scales with a power of h.  So each
+sampled row's expected value is the oracle's assembled row at a
+representative node of the same type on the N = 8 lattice, rescaled
+(A: h, B and B^T: h^2, PSPG C: h^3) and applied to the same input words.
+Samples: interior velocity rows of every parity class and component,
+boundary velocity rows (zero), pressure rows of all 27 boundary classes.
+The row construction itself is checked on the CPU against the oracle's
+assembled operator at N = 16."""
+import numpy as np
+import pytest
+
+from oracle import fe
+from oracle.stokes import Stokes
+from paper_2010_13513_amd import hhg
+from tests.gpu_util import Lib
+
+NS = 8          # oracle lattice of the representative rows
+PARITIES = [(a, b, c) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+
+
+def sampled_rows(vo, N, rng, per_class=6):
+    """Rows of calA on the N lattice, as (lattice index of the output,
+    [(lattice index of an input word, weight)]), plus lattice indices of
+    boundary velocity rows (whose output is zero).  Plain lattice order:
+    [u1 | u2 | u3 | p], velocity on the (vo N + 1)^3 lattice."""
+    lev = fe.Level(NS, vo)
+    A = lev.A.tocsr()
+    BT = [b.tocsc() for b in lev.B]
+    Bc = [b.tocsr() for b in lev.B]
+    C = lev.C.tocsr()
+    vc, pc = lev.vcoords, lev.pcoords
+    ms = vo * NS + 1
+    n1, M = N + 1, vo * N
+    m1 = M + 1
+    f = NS / float(N)
+    fA, fB, fC = f, f * f, f ** 3
+
+    def vlat(d, X, Y, Z):
+        return int(d * m1 ** 3 + X + m1 * (Y + m1 * Z))
+
+    def plat(i, j, k):
+        return int(3 * m1 ** 3 + i + n1 * (j + n1 * k))
+
+    rows = []
+    for par in PARITIES:
+        n = 0
+        while n < per_class:
+            S = np.array([rng.integers(1, M) for _ in range(3)])
+            S = S - (S & 1) + np.array(par)
+            if S.min() < 1 or S.max() > M - 1:
+                continue
+            n += 1
+            d = int(rng.integers(0, 3))
+            rep = np.array([vo * NS // 2 + (s & 1) for s in S])
+            r = int(rep[0] + ms * (rep[1] + ms * rep[2]))
+            terms = []
+            row = A.getrow(r)
+            for c, w in zip(row.indices, row.data):
+                terms.append((vlat(d, *(S + vc[c] - rep)), fA * w))
+            col = BT[d][:, r]
+            for kk, w in zip(col.indices, col.data):
+                terms.append((plat(*((S + vo * pc[kk] - rep) // vo)), fB * w))
+            rows.append((vlat(d, *S), terms))
+    bnd = []
+    for _ in range(16):
+        S = [int(rng.integers(0, M + 1)) for _ in range(3)]
+        S[int(rng.integers(0, 3))] = int(rng.choice([0, M]))
+        bnd.append(vlat(int(rng.integers(0, 3)), *S))
+    for cls in range(27):
+        cc = [cls % 3, (cls // 3) % 3, cls // 9]
+        for _ in range(2):
+            P = np.array([0 if c == 0 else (N if c == 2 else int(rng.integers(1, N))) for c in cc])
+            rep = np.array([0 if c == 0 else (NS if c == 2 else NS // 2) for c in cc])
+            k = int(rep[0] + (NS + 1) * (rep[1] + (NS + 1) * rep[2]))
+            terms = []
+            for d in range(3):
+                row = Bc[d].getrow(k)
+                for c, w in zip(row.indices, row.data):
+                    terms.append((vlat(d, *(vo * P + vc[c] - vo * rep)), fB * w))
+            row = C.getrow(k)
+            for c, w in zip(row.indices, row.data):
+                terms.append((plat(*(P + pc[c] - rep)), -fC * w))
+            rows.append((plat(*P), terms))
+    return rows, bnd
+
+
+def check_rows(rows, bnd, xval, got, rtol=1e-12):
+    """Compare gathered outputs with the rows; xval maps input index -> value."""
+    for (yl, terms), g in zip(rows, got[:len(rows)]):
+        want = sum(w * xval[i] for i, w in terms)
+        scale = sum(abs(w * xval[i]) for i, w in terms)
+        assert abs(g - want) <= rtol * scale, (yl, g, want)
+    assert np.all(got[len(rows):] == 0.0)
+
+
+@pytest.mark.parametrize("vo", [2, 1])
+def test_sampled_rows_reproduce_assembled_operator(vo):
+    """CPU: the representative-row construction at N = 16 against the
+    oracle's operator assembled at N = 16."""
+    N = 16
+    rows, bnd = sampled_rows(vo, N, np.random.default_rng(11), per_class=3)
+    S = Stokes(fe.Level(N, vo))
+    x = np.random.default_rng(12).standard_normal(S.n)
+    y = S.apply(x)
+    got = y[[r[0] for r in rows] + bnd]
+    check_rows(rows, bnd, x, got)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("disc", [hhg.HHG_P2P1, hhg.HHG_P1P1])
+def test_apply_full_size_sampled_rows(disc):
+    lib = Lib(disc, 6, 7, macro_refine=1)
+    torch = lib.torch
+    try:
+        vo = 2 if disc == hhg.HHG_P2P1 else 1
+        N, nn, vw, lw = lib.layout(7)
+        assert N == 256
+        print(f"apply full size: disc {disc}, N {N}, {vw} words", flush=True)
+        gen = torch.Generator(device=lib.dev).manual_seed(13513 + 3000)
+        lat = torch.randn(lw, generator=gen, dtype=torch.float64, device=lib.dev)
+        x = torch.zeros(vw, dtype=torch.float64, device=lib.dev)
+        hhg.hhg_vec_from_lattice(lib.h, 7, lat, x)
+        y = torch.empty_like(x)
+        hhg.hhg_apply(lib.h, 7, hhg.HHG_OP_FULL, x, y)
+        del x
+        ylat = torch.empty_like(lat)
+        hhg.hhg_vec_to_lattice(lib.h, 7, y, ylat)
+        del y
+        torch.cuda.synchronize()
+
+        rows, bnd = sampled_rows(vo, N, np.random.default_rng(7))
+        assert len(rows) > 100
+        got = ylat.index_select(0, torch.tensor([r[0] for r in rows] + bnd, device=lib.dev)).cpu().numpy()
+        xi = sorted({t[0] for r in rows for t in r[1]})
+        xv = dict(zip(xi, lat.index_select(0, torch.tensor(xi, device=lib.dev)).cpu().numpy()))
+        check_rows(rows, bnd, xv, got)
+    finally:
+        lib.close()
