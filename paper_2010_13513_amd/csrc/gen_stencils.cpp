@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -211,16 +212,50 @@ void emit_anu_diag(FILE* f, const char* name, const std::vector<ElemRow>& rows) 
 // positions inside the cube only -- and those rows are written as zero.
 // Accumulator row g < G: velocity row of component d, group g; row G: the
 // part of the pressure row that comes from u_d (and, for d = 0, from -C p).
-// Velocity words are scaled by sa (A) and sb (B), pressure words by sb (B^T)
-// and sc (C) before the literal weights at h = 1.
+// Every weight at h = 1 is a rational k / den with a small integer k and one
+// denominator per block (A, B^T, B, C; {D}_zm_den), so the code multiplies by
+// the integer k -- an f64 literal with a zero low word, which needs no scalar
+// register -- and the denominators and the h scales sa, sb, sc are applied
+// once: velocity rows are in units of sa / den_A and pressure rows in units
+// of sb / den_B (the caller scales them when it writes), and each loaded
+// pressure word is pre-scaled once, by rt = sb den_A / (sa den_T) for the
+// B^T entries, by rc = sc den_B / (sb den_C) for the C entries.
 struct ZmUse {
   int row, dk;
   double w;
-  int kind;  // 0: sa, 1: sb, 2: sc (negated weight)
+  int kind;  // 0: A, 1: B^T or B (by the array), 2: C (negated weight)
 };
+// Smallest denominator (<= 10^4) that makes every weight an integer to
+// rounding; generation fails if there is none.
+int common_den(const std::vector<double>& ws) {
+  for (int den = 1; den <= 10000; ++den) {
+    bool ok = true;
+    for (double w : ws) ok = ok && std::fabs(w * den - std::nearbyint(w * den)) <= 1e-9 * std::max(1.0, std::fabs(w * den));
+    if (ok) return den;
+  }
+  std::fprintf(stderr, "gen_stencils: zm weights are not small rationals\n");
+  std::exit(1);
+}
 void emit_zm(FILE* f, const ElementSet& es, const char* D, int G) {
   auto slot = [](int Q, int dk) { return ((Q - dk) % 3 + 3) % 3; };
-  const char* scal[3] = {"sa", "sb", "sc"};
+  // denominators per block, over all components
+  std::vector<double> wa, wt, wb, wc;
+  for (int r = 0; r < G; ++r) {
+    for (auto& e : pruned(es, 'A', r, 1)) wa.push_back(e.w[0]);
+    for (auto& e : pruned(es, 'T', r, 3))
+      for (int d = 0; d < 3; ++d) wt.push_back(e.w[d]);
+  }
+  for (auto& e : pruned(es, 'B', 0, 3))
+    for (int d = 0; d < 3; ++d) wb.push_back(e.w[d]);
+  if (G == 1)
+    for (auto& e : pruned(es, 'C', 0, 1)) wc.push_back(e.w[0]);
+  const int den[4] = {common_den(wa), common_den(wt), common_den(wb), wc.empty() ? 1 : common_den(wc)};
+  std::fprintf(f, "// denominators of the k-marching weights: A, B^T, B, C\nconstexpr int %s_zm_den[4] = {%d, %d, %d, %d};\n\n",
+               D, den[0], den[1], den[2], den[3]);
+  auto kw = [&](const ZmUse& u, int a) {
+    const int dn = u.kind == 0 ? den[0] : (u.kind == 2 ? den[3] : (a == G ? den[1] : den[2]));
+    return lit(std::nearbyint(u.w * dn));
+  };
   for (int d = 0; d < 3; ++d) {
     // array a (velocity group c: a = c; pressure: a = G), dj + 1, di + 1 -> uses
     std::vector<std::vector<ZmUse>> use((G + 1) * 9);
@@ -237,8 +272,8 @@ void emit_zm(FILE* f, const ElementSet& es, const char* D, int G) {
     for (int Q = 0; Q < 3; ++Q) {
       std::fprintf(f,
                    "template <typename T>\n__device__ __forceinline__ void %s_zm%d_q%d(__amdgpu_buffer_rsrc_t ru, "
-                   "__amdgpu_buffer_rsrc_t rp, const int (&vo)[3], int nnb, T sa, T sb, T sc, T (&acc)[3][%d]) {\n"
-                   "  (void)sa; (void)sc; (void)nnb;\n",
+                   "__amdgpu_buffer_rsrc_t rp, const int (&vo)[3], int nnb, T rt, T rc, T (&acc)[3][%d]) {\n"
+                   "  (void)rc; (void)nnb;\n",
                    D, d, Q, G + 1);
       int nload = 0;
       for (int a = 0; a <= G; ++a)
@@ -247,22 +282,27 @@ void emit_zm(FILE* f, const ElementSet& es, const char* D, int G) {
           for (int di = -1; di <= 1; ++di) any |= !at(a, di, dj).empty();
           if (!any) continue;
           ++nload;
-          if (a < G)
+          // pressure words: one scaled copy per kind that uses them
+          bool kinds[3] = {false, false, false};
+          for (int di = -1; di <= 1; ++di)
+            for (auto& u : at(a, di, dj)) kinds[u.kind] = true;
+          if (a < G) {
             std::fprintf(f, "  { const T v0 = buffer_word<T>(ru, vo[%d], %d * nnb);\n", dj + 1, a);
-          else
-            std::fprintf(f, "  { const T v0 = buffer_word<T>(rp, vo[%d], 0);\n", dj + 1);
+          } else {
+            std::fprintf(f, "  { const T w0 = buffer_word<T>(rp, vo[%d], 0);\n", dj + 1);
+            if (kinds[1]) std::fprintf(f, "    const T v0 = rt * w0;\n");
+            if (kinds[2]) std::fprintf(f, "    const T c0 = rc * w0;\n");
+          }
           for (int di = -1; di <= 1; ++di) {
             const auto& us = at(a, di, dj);
             if (us.empty()) continue;
-            const char* src = di == -1 ? "from_prev(v0)" : (di == 1 ? "from_next(v0)" : "v0");
-            std::fprintf(f, "    { const T v = %s;\n", src);
-            bool kinds[3] = {false, false, false};
-            for (auto& u : us) kinds[u.kind] = true;
-            for (int k = 0; k < 3; ++k)
-              if (kinds[k]) std::fprintf(f, "      const T v%s = %s * v;\n", scal[k], scal[k]);
+            const char* sh = di == -1 ? "from_prev" : (di == 1 ? "from_next" : "");
+            std::fprintf(f, "    {\n");
+            if (a < G || kinds[1]) std::fprintf(f, "      const T v = %s(v0);\n", sh);
+            if (a == G && kinds[2]) std::fprintf(f, "      const T c = %s(c0);\n", sh);
             for (auto& u : us)
-              std::fprintf(f, "      acc[%d][%d] = fma(T(%s), v%s, acc[%d][%d]);\n", slot(Q, u.dk), u.row, lit(u.w).c_str(),
-                           scal[u.kind], slot(Q, u.dk), u.row);
+              std::fprintf(f, "      acc[%d][%d] = fma(T(%s), %s, acc[%d][%d]);\n", slot(Q, u.dk), u.row, kw(u, a).c_str(),
+                           u.kind == 2 ? "c" : "v", slot(Q, u.dk), u.row);
             std::fprintf(f, "    }\n");
           }
           std::fprintf(f, "  }\n");

@@ -16,7 +16,7 @@ namespace gen {
 // L - 1 (from_prev) or L + 1 (from_next); the end lanes receive 0.
 template <int CTRL>
 __device__ __forceinline__ int lane_shift(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ float lane_shift(float v) {
@@ -370,8 +370,8 @@ constexpr int kZmOut = kZmCols - 2;  // columns written per window
 
 template <typename T, int G, int D, int Q>
 __device__ __forceinline__ void zm_plane(__amdgpu_buffer_rsrc_t ru, __amdgpu_buffer_rsrc_t rp, const int (&vo)[3],
-                                         int nnb, T sa, T sb, T sc, T (&acc)[3][G + 1]) {
-#define HHG_ZM(P) gen::P<T>(ru, rp, vo, nnb, sa, sb, sc, acc)
+                                         int nnb, T rt, T rc, T (&acc)[3][G + 1]) {
+#define HHG_ZM(P) gen::P<T>(ru, rp, vo, nnb, rt, rc, acc)
   if constexpr (G == 1) {
     if constexpr (D == 0 && Q == 0) HHG_ZM(p1_zm0_q0);
     if constexpr (D == 0 && Q == 1) HHG_ZM(p1_zm0_q1);
@@ -399,15 +399,18 @@ __device__ __forceinline__ void zm_plane(__amdgpu_buffer_rsrc_t ru, __amdgpu_buf
 // Column of a lane: nb[dj + 1] = array index of column (i, j + dj) clamped
 // into the array, so every load stays in it; rows fed by a clamped (or
 // row-wrapped) word are never interior.  `valid`: the lane writes its column.
+template <typename T>
 struct ZmCol {
   int col, i, j, k0, k1;
   int nb[3];
   bool valid;
+  T rt, rc;  // pressure-word scales of the B^T and C entries
+  T sv, sp;  // units of the accumulated velocity and pressure rows
 };
 
 template <typename T, int G, int D, int Q>
 __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
-                                        const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol& c, int q,
+                                        const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol<T>& c, int q,
                                         T (&acc)[3][G + 1], T (*pshare)[3][kZmCols]) {
   constexpr int S = (Q + 2) % 3;  // slot of the row plane completed by this step
   const int N = g.N, s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn, vs = g.vstride;
@@ -417,7 +420,7 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
                      (c.nb[2] + kps) * (int)sizeof(T)};
   const __amdgpu_buffer_rsrc_t ru = gen::make_rsrc(x + (size_t)D * vs, (unsigned)((size_t)vs * sizeof(T)));
   const __amdgpu_buffer_rsrc_t rp = gen::make_rsrc(x + (size_t)3 * vs, (unsigned)((size_t)nn * sizeof(T)));
-  zm_plane<T, G, D, Q>(ru, rp, vo, nn * (int)sizeof(T), lc.a, lc.b, lc.c, acc);
+  zm_plane<T, G, D, Q>(ru, rp, vo, nn * (int)sizeof(T), c.rt, c.rc, acc);
   (void)s1;
   const int kr = kp - 1;
   const int lane = threadIdx.x & (kZmCols - 1);
@@ -427,14 +430,14 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
 #pragma unroll
       for (int gr = 0; gr < G; ++gr) {
         const int pos = D * vs + gr * nn + at;
-        const T v = acc[S][gr];
+        const T v = c.sv * acc[S][gr];
         y[pos] = vel_interior<G>(gr, c.i, c.j, kr, N) ? (has_b ? b[pos] - v : v) : T(0);
       }
     }
     pshare[q & 1][D][lane] = acc[S][G];
     __syncthreads();
     if (D == 0 && c.valid && c.i >= 1 && c.j >= 1 && kr >= 1 && c.i <= N - 1 && c.j <= N - 1 && kr <= N - 1) {
-      const T v = pshare[q & 1][0][lane] + pshare[q & 1][1][lane] + pshare[q & 1][2][lane];
+      const T v = c.sp * (pshare[q & 1][0][lane] + pshare[q & 1][1][lane] + pshare[q & 1][2][lane]);
       const int pp = 3 * vs + at;
       y[pp] = has_b ? b[pp] - v : v;
     }
@@ -445,7 +448,7 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
 
 template <typename T, int G, int D>
 __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
-                                       const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol& c,
+                                       const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol<T>& c,
                                        T (*pshare)[3][kZmCols]) {
   T acc[3][G + 1];
 #pragma unroll
@@ -472,7 +475,14 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
   const int lin = xcd_block_of(nmain);
   const int cb = lin % ncb, chunk = lin / ncb;
   const int n1 = g.n1, N = g.N;
-  ZmCol c;
+  ZmCol<T> c;
+  {
+    const int* den = G == 1 ? gen::p1_zm_den : gen::p2_zm_den;  // A, B^T, B, C
+    c.rt = (lc.b * T(den[0])) / (lc.a * T(den[1]));
+    c.rc = (lc.c * T(den[2])) / (lc.b * T(den[3]));
+    c.sv = lc.a / T(den[0]);
+    c.sp = lc.b / T(den[2]);
+  }
   const int lane = threadIdx.x & (kZmCols - 1);
   c.col = cb * kZmOut - 1 + lane;
   c.k0 = chunk * kc;
