@@ -227,8 +227,10 @@ hhg_status hhg_query_interpolation(int order, int tx, int ty, int tz, int q, int
 
 /* ----------------------------------------------------------------- cycles */
 /* One variable V-cycle of Alg. fmg on x (finest level `level`,
- * l_fine = level).  F64. */
-hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_solver_params* prm);
+ * l_fine = level), storage and arithmetic in `prec` (the coarsest-level
+ * pseudo-inverse is applied in float64 either way; the learned coarse solve
+ * and the training-pair recorder act on float64 cycles only). */
+hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_solver_params* prm, hhg_prec prec);
 /* Alg. fmg on lmin..lmax.  b_levels[l - lmin]: right-hand sides of every level
  * (hhg_rhs); x: finest-level vector whose boundary velocity DoFs hold the
  * boundary data (interpolated to coarser levels by injection), overwritten by
@@ -294,6 +296,18 @@ hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* 
  * attached, the recorder on or coarse_smooth > 0).  Default 800; 0 turns it
  * off. */
 hhg_status hhg_hier_set_fused_sites(hhg_hier h, long max_sites);
+/* Not in the paper: bfloat16 storage on the coarse levels of float32
+ * cycles.  The n coarsest levels (lmin .. lmin + n - 1, 0 <= n <= number of
+ * levels; default 0) hold bfloat16 values: every float32 operation that
+ * writes a vector of such a level -- apply, residual, rhs, mass, lattice
+ * conversion, smoother (per colour and pressure step), restriction,
+ * prolongation, coarse solve, mean-zero projection, and the inner cycles of
+ * hhg_dc_solve -- rounds the words it writes to the nearest bfloat16 (ties
+ * to even).  The values stay in the float32 vectors (layout unchanged):
+ * bfloat16 to float32 is exact, so the arithmetic is that of bfloat16 storage
+ * with float32 computation.  hhg_copy_boundary moves words unchanged; float64
+ * operations are not affected. */
+hhg_status hhg_hier_set_bf16_levels(hhg_hier h, int n);
 
 /* Training-pair recorder: while capacity > 0, every exact float64 coarse
  * solve (inside hhg_vcycle, hhg_fmg_solve, hhg_dc_solve with F64 inner

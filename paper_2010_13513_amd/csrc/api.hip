@@ -150,6 +150,9 @@ struct hhg_hier_s {
   bool slv_stale = true;
   long fused_sites = 800;
   std::vector<int> lds_end64, lds_end32;  // LDS words of levels lmin..l (0: level not in LDS)
+  // levels lmin .. lmin + bf16_levels - 1 hold bfloat16 values in their
+  // float32 vectors (hhg_hier_set_bf16_levels)
+  int bf16_levels = 0;
   // cached HIP graph of a fixed-work FMG solve (key: vectors + parameters)
   hipGraphExec_t fmg_exec = nullptr;
   std::vector<unsigned char> fmg_key;
@@ -562,10 +565,25 @@ void build_coarse_device(hhg_hier h) {
 }
 
 // ---------------------------------------------------------------- ops
+// Levels that hold bfloat16 values: a float32 operation writing a vector of
+// such a level rounds the words it wrote, v[s stride + off + t] for s < nseg,
+// t < n, to the nearest bfloat16 right after the kernel that wrote them --
+// within one kernel no site reads another site's output, so this gives the
+// values of bfloat16 storage with float32 arithmetic.
+template <typename T>
+void round_out(hhg_hier h, int l, T* v, size_t stride, size_t off, size_t n, int nseg) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (l - h->lmin < h->bf16_levels) launch_round_bf16(S(h), v, stride, off, n, nseg);
+  } else {
+    (void)h, (void)l, (void)v, (void)stride, (void)off, (void)n, (void)nseg;
+  }
+}
+
 template <typename T>
 void op_apply(hhg_hier h, int l, int opmask, const T* x, const T* b, T* y, bool has_b, bool vel, bool prs) {
   Level& lv = h->L(l);
   launch_apply<T>(S(h), lv.g, lconst<T>(lv), tables<T>(lv), x, b, y, opmask, has_b, vel, prs, lv.bnd, lv.nbnd);
+  round_out<T>(h, l, y, 0, 0, lv.vec_words, 1);
 }
 
 int full_mask(hhg_hier h) { return h->disc == HHG_P1P1 ? 15 : 7; }
@@ -586,15 +604,20 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
   Level& lv = h->L(l);
   const int ncol = h->G == 1 ? 4 : 11;
   T* r = rbuf<T>(lv);
+  auto colour = [&](int c) {  // colour c < 4 writes the vertex group, c >= 4 the edge group c - 3
+    launch_gs_colour<T>(S(h), lv.g, lconst<T>(lv), x, b, c);
+    round_out<T>(h, l, x, lv.g.vstride, c < 4 ? 0 : (size_t)(c - 3) * lv.g.nn, lv.g.nn, 3);
+  };
   for (int it = 0; it < iters; ++it) {
     for (int s = 0; s < xi; ++s) {
-      for (int c = 0; c < ncol; ++c) launch_gs_colour<T>(S(h), lv.g, lconst<T>(lv), x, b, c);
+      for (int c = 0; c < ncol; ++c) colour(c);
       if (gs == HHG_GS_SYM)
-        for (int c = ncol - 1; c >= 0; --c) launch_gs_colour<T>(S(h), lv.g, lconst<T>(lv), x, b, c);
+        for (int c = ncol - 1; c >= 0; --c) colour(c);
     }
     // r_p = g - B u + C p, then p -= omega D^{-1} r_p
     op_apply<T>(h, l, full_mask(h) & 12, x, b, r, true, false, true);
     launch_pressure_step<T>(S(h), lv.g, dinv<T>(lv), x, r, (T)omega);
+    round_out<T>(h, l, x, 0, 3 * (size_t)lv.g.vstride, lv.g.nn, 1);
   }
 }
 
@@ -604,6 +627,7 @@ void op_mean_zero(hhg_hier h, int l, T* x) {
   T* p = x + 3 * (size_t)lv.g.vstride;
   launch_psum<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
   launch_pshift<T>(S(h), lv.g, p, h->sums, 0);
+  round_out<T>(h, l, p, 0, 0, lv.g.nn, 1);
 }
 
 template <typename T>
@@ -611,9 +635,11 @@ void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
   Level& f = h->L(lf);
   Level& c = h->L(lf - 1);
   launch_restrict<T>(S(h), f.g, c.g, ttables<T>(f), rf, rc);
+  round_out<T>(h, lf - 1, rc, 0, 0, c.vec_words, 1);
   T* p = rc + 3 * (size_t)c.g.vstride;
   launch_psum<T>(S(h), c.g, tables<T>(c), p, h->partial, h->sums, 1);
   launch_pshift<T>(S(h), c.g, p, h->sums, 1);
+  round_out<T>(h, lf - 1, p, 0, 0, c.g.nn, 1);
 }
 
 template <typename T>
@@ -621,6 +647,7 @@ void op_prolong(hhg_hier h, int lc, const T* xc, T* xf, bool add, bool skip_bnd)
   Level& c = h->L(lc);
   Level& f = h->L(lc + 1);
   launch_prolong<T>(S(h), c.g, f.g, ttables<T>(f), xc, xf, add, skip_bnd);
+  round_out<T>(h, lc + 1, xf, 0, 0, f.vec_words, 1);
 }
 
 template <typename T>
@@ -754,6 +781,7 @@ void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true, const hhg_so
     }
   }
   launch_coarse<T>(S(h), h->Kp, h->unk, h->nunk, r, x);
+  round_out<T>(h, h->lmin, x, 0, 0, lv.vec_words, 1);
   op_mean_zero<T>(h, h->lmin, x);
 }
 
@@ -786,6 +814,7 @@ void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_para
     sc.unk = h->unk;
     sc.nunk = h->nunk;
     sc.lds_words = (std::is_same<T, double>::value ? h->lds_end64 : h->lds_end32)[l - h->lmin];
+    sc.q16 = std::is_same<T, float>::value ? h->bf16_levels : 0;
     launch_vcycle_small<T>(S(h), slv<T>(h), sc);
     return;
   }
@@ -1063,6 +1092,7 @@ hhg_status hhg_vec_from_lattice(hhg_hier h, int level, const double* src, void* 
     HHG_DISPATCH(prec, {
       launch_fill<T>(S(h), (T*)dst, lv.vec_words, T(0));
       launch_from_lattice<T>(S(h), lv.g, src, (T*)dst);
+      round_out<T>(h, level, (T*)dst, 0, 0, lv.vec_words, 1);
     });
     HHG_CHECK_HIP(hipGetLastError());
   });
@@ -1094,7 +1124,10 @@ hhg_status hhg_apply(hhg_hier h, int level, hhg_op op, const void* x, void* y, h
       default: throw Error{HHG_ERR_ARG, "operator not supported"};
     }
     if (mask < 0) {
-      HHG_DISPATCH(prec, launch_mass<T>(S(h), lv.g, tables<T>(lv), (const T*)x, (T*)y));
+      HHG_DISPATCH(prec, {
+        launch_mass<T>(S(h), lv.g, tables<T>(lv), (const T*)x, (T*)y);
+        round_out<T>(h, level, (T*)y, 0, 0, lv.vec_words, 1);
+      });
       HHG_CHECK_HIP(hipGetLastError());
       return;
     }
@@ -1121,7 +1154,10 @@ hhg_status hhg_rhs(hhg_hier h, int level, const void* f, void* b, hhg_prec prec)
     check_level(h, level);
     HHG_REQUIRE(f && b && f != b, HHG_ERR_ARG, "bad vectors");
     Level& lv = h->L(level);
-    HHG_DISPATCH(prec, launch_rhs<T>(S(h), lv.g, lconst<T>(lv), (const T*)f, (T*)b));
+    HHG_DISPATCH(prec, {
+      launch_rhs<T>(S(h), lv.g, lconst<T>(lv), (const T*)f, (T*)b);
+      round_out<T>(h, level, (T*)b, 0, 0, lv.vec_words, 1);
+    });
     HHG_CHECK_HIP(hipGetLastError());
   });
 }
@@ -1332,6 +1368,7 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
       if (std::sqrt(ru * ru + rp * rp) <= rtol * bn || outer >= max_outer) break;
       if (inner_prec == HHG_F32) {
         launch_to_f32(s, top.r, top.cb32, top.vec_words);                     // RNE
+        round_out<float>(h, L, top.cb32, 0, 0, top.vec_words, 1);
         launch_fill<float>(s, top.cx32, top.vec_words, 0.0f);
         for (int c = 0; c < inner_cycles; ++c) vcycle_t<float>(h, L, L, top.cx32, top.cb32, *prm);
         launch_add_f32_to_f64(s, x, top.cx32, top.vec_words);
@@ -1502,6 +1539,13 @@ hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* 
   });
 }
 
+hhg_status hhg_hier_set_bf16_levels(hhg_hier h, int n) {
+  return guard([&] {
+    HHG_REQUIRE(h && n >= 0 && n <= h->lmax - h->lmin + 1, HHG_ERR_ARG, "bad number of levels");
+    h->bf16_levels = n;
+  });
+}
+
 hhg_status hhg_hier_set_fused_sites(hhg_hier h, long max_sites) {
   return guard([&] {
     HHG_REQUIRE(h && max_sites >= 0, HHG_ERR_ARG, "bad arguments");
@@ -1594,12 +1638,20 @@ hhg_status hhg_query_interpolation(int order, int tx, int ty, int tz, int q, int
   });
 }
 
-hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_solver_params* prm) {
+hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_solver_params* prm, hhg_prec prec) {
   return guard([&] {
     check_level(h, level);
     HHG_REQUIRE(x && b && prm && prm->omega_inv > 0.0 && prm->xi >= 1, HHG_ERR_ARG, "bad arguments");
-    refresh_small(h);
-    vcycle(h, level, level, (double*)x, (const double*)b, *prm);
+    HHG_REQUIRE(prec == HHG_F64 || prec == HHG_F32, HHG_ERR_PREC, "bad precision");
+    if (prec == HHG_F32) {
+      HHG_REQUIRE(h->nunk > 0 || prm->coarse_smooth > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
+      ensure_f32_vectors(h);
+      refresh_small(h);
+      vcycle_t<float>(h, level, level, (float*)x, (const float*)b, *prm);
+    } else {
+      refresh_small(h);
+      vcycle(h, level, level, (double*)x, (const double*)b, *prm);
+    }
     HHG_CHECK_HIP(hipGetLastError());
   });
 }

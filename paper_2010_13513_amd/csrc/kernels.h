@@ -121,6 +121,7 @@ struct SmallCycle {
   const int* unk;
   int nunk;
   int lds_words;            // > 0: every level's vectors live in LDS (x, b copied in and x out)
+  int q16;                  // levels lmin + q, q < q16, hold bfloat16 values (float32 only)
 };
 // LDS available for the level vectors of the one-workgroup V-cycle (bytes).
 constexpr int kSmallLdsBytes = 128 * 1024;
@@ -178,6 +179,9 @@ void launch_coarse_scatter(hipStream_t s, const float* y, const int* unk, int nu
                            float* out);
 void launch_gather_rows(hipStream_t s, const float* src, const int* idx, int B, int w, float* dst);
 void launch_add_f32_to_f64(hipStream_t s, double* y, const float* e, size_t n);
+// Round to bfloat16 (nearest, ties to even) in place, stored as float32:
+// x[s stride + off + t] for s < nseg, t < n.
+void launch_round_bf16(hipStream_t s, float* x, size_t stride, size_t off, size_t n, int nseg);
 template <typename T>
 void launch_scale(hipStream_t s, T* x, size_t n, const double* sums, int slot);
 template <typename T>

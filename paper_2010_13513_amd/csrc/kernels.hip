@@ -1103,6 +1103,15 @@ __device__ __forceinline__ void restrict_table(const Geom& gf, const Geom& gc, c
   rc[2 * gc.vstride + pos] = a2;
 }
 
+// Round a float32 value to the nearest bfloat16 (ties to even), kept as a
+// float32 whose low 16 bits are zero; NaN stays NaN.
+__device__ __forceinline__ float round_bf16(float v) {
+  unsigned u = __float_as_uint(v);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return __uint_as_float((u | 0x400000u) & 0xffff0000u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
 // One workgroup runs the whole variable V-cycle of Alg. fmg below and at the
 // level lmin + nlev - 1: the same site bodies as the grid-wide kernels, each
 // phase a block-strided loop, phases separated by barriers.  On the small
@@ -1126,6 +1135,23 @@ __device__ double block_sum(double v, double* red) {
   return out;
 }
 
+// Levels stored as bfloat16 (float32 only): round what a phase wrote,
+// v[s stride + off + t] for s < nseg, t < n, then a barrier.
+template <typename T>
+__device__ void small_round(bool on, T* v, int stride, int off, int n, int nseg) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (!on) return;
+    for (int t = threadIdx.x; t < n * nseg; t += kSmallBlock) {
+      const int sg = t / n;
+      T* p = v + sg * stride + off + (t - sg * n);
+      *p = round_bf16(*p);
+    }
+    __syncthreads();
+  } else {
+    (void)on, (void)v, (void)stride, (void)off, (void)n, (void)nseg;
+  }
+}
+
 template <typename T, int G, bool VAR>
 __device__ void small_apply(const SmallLevel<T>& L, int opmask, const T* x, const T* b, T* y, int vel_rows) {
   for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock)
@@ -1139,7 +1165,7 @@ __device__ void small_apply(const SmallLevel<T>& L, int opmask, const T* x, cons
 }
 
 template <typename T, int G, bool VAR>
-__device__ void small_colour(const SmallLevel<T>& L, T* x, const T* b, int c) {
+__device__ void small_colour(const SmallLevel<T>& L, T* x, const T* b, int c, bool q16) {
   if (c < 4) {
     const int n = gs_vertex_count(L.g);
     for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock) gs_vertex_site<T, G, VAR>(L.g, L.lc, x, b, c, w % n, w / n);
@@ -1150,31 +1176,36 @@ __device__ void small_colour(const SmallLevel<T>& L, T* x, const T* b, int c) {
     }
   }
   __syncthreads();
+  small_round<T>(q16, x, L.g.vstride, c < 4 ? 0 : (c - 3) * L.g.nn, L.g.nn, 3);  // the group the colour wrote
 }
 
 template <typename T, int G, bool VAR>
-__device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters) {
+__device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters,
+                             bool q16) {
   if (L.g.N < 2) return;
   const int ncol = G == 1 ? 4 : 11;
   for (int it = 0; it < iters; ++it) {
     for (int s = 0; s < sc.xi; ++s) {
-      for (int c = 0; c < ncol; ++c) small_colour<T, G, VAR>(L, x, b, c);
+      for (int c = 0; c < ncol; ++c) small_colour<T, G, VAR>(L, x, b, c, q16);
       if (sc.gs_sym)
-        for (int c = ncol - 1; c >= 0; --c) small_colour<T, G, VAR>(L, x, b, c);
+        for (int c = ncol - 1; c >= 0; --c) small_colour<T, G, VAR>(L, x, b, c, q16);
     }
     const int vs = L.g.vstride;
     small_apply<T, G, VAR>(L, sc.full_mask & 12, x, b, r, 0);
+    small_round<T>(q16, r, 0, 3 * vs, L.g.nn, 1);
     for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) x[3 * vs + t] -= sc.omega * L.dinv[t] * r[3 * vs + t];
     __syncthreads();
+    small_round<T>(q16, x, 0, 3 * vs, L.g.nn, 1);
   }
 }
 
 template <typename T, int G>
-__device__ void small_smooth_any(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters) {
+__device__ void small_smooth_any(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters,
+                                 bool q16) {
   if (L.lc.nu)
-    small_smooth<T, G, true>(sc, L, x, b, r, iters);
+    small_smooth<T, G, true>(sc, L, x, b, r, iters, q16);
   else
-    small_smooth<T, G, false>(sc, L, x, b, r, iters);
+    small_smooth<T, G, false>(sc, L, x, b, r, iters, q16);
 }
 
 template <typename T, int G>
@@ -1234,14 +1265,17 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
     const SmallLevel<T>& C = lv[q - 1];
     T* x = X(q);
     const T* b = B(q);
-    small_smooth_any<T, G>(sc, L, x, b, R(q), sc.pre0 + (top - q) * sc.inc);
+    small_smooth_any<T, G>(sc, L, x, b, R(q), sc.pre0 + (top - q) * sc.inc, q < sc.q16);
     small_residual<T, G>(sc, L, x, b, R(q));
+    small_round<T>(q < sc.q16, R(q), 0, 0, vw(q), 1);
     T* cb = B(q - 1);
     const T* r = R(q);
     for (int w = threadIdx.x; w < (G + 1) * C.g.nn; w += kSmallBlock)
       restrict_table<T, G>(L.g, C.g, L.tt, r, cb, w % C.g.nn, w / C.g.nn);
     __syncthreads();
+    small_round<T>(q - 1 < sc.q16, cb, 0, 0, vw(q - 1), 1);
     small_pshift<T>(C, cb + 3 * (size_t)C.g.vstride, 1, red);
+    small_round<T>(q - 1 < sc.q16, cb, 0, 3 * C.g.vstride, C.g.nn, 1);
     T* cx = X(q - 1);
     for (int t = threadIdx.x; t < vw(q - 1); t += kSmallBlock) cx[t] = T(0);
     __syncthreads();
@@ -1252,6 +1286,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
     T* x = X(0);
     const T* r = R(0);
     small_residual<T, G>(sc, L, x, B(0), R(0));
+    small_round<T>(0 < sc.q16, R(0), 0, 0, vw(0), 1);
     for (int c = threadIdx.x; c < sc.nunk; c += kSmallBlock) rs[c] = (double)r[sc.unk[c]];
     __syncthreads();
     for (int row = threadIdx.x; row < sc.nunk; row += kSmallBlock) {
@@ -1261,7 +1296,9 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
       x[sc.unk[row]] = (T)((double)x[sc.unk[row]] + acc);
     }
     __syncthreads();
+    small_round<T>(0 < sc.q16, x, 0, 0, vw(0), 1);
     small_pshift<T>(L, x + 3 * (size_t)L.g.vstride, 0, red);
+    small_round<T>(0 < sc.q16, x, 0, 3 * L.g.vstride, L.g.nn, 1);
   }
   // ascend: prolongate and add, post-smooth
   for (int q = 1; q <= top; ++q) {
@@ -1271,7 +1308,8 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
     const T* xc = X(q - 1);
     for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) prolong_site<T, G>(C.g, L.g, L.tt, xc, x, 1, 1, t);
     __syncthreads();
-    small_smooth_any<T, G>(sc, L, x, B(q), R(q), sc.post0 + (top - q) * sc.inc);
+    small_round<T>(q < sc.q16, x, 0, 0, vw(q), 1);
+    small_smooth_any<T, G>(sc, L, x, B(q), R(q), sc.post0 + (top - q) * sc.inc, q < sc.q16);
   }
   if (lds) {
     const T* xs = X(top);
@@ -1352,6 +1390,16 @@ template <typename X, typename Y>
 __global__ void __launch_bounds__(kBlock) k_convert(const X* __restrict__ x, Y* __restrict__ y, long n) {
   const long t = (long)blockIdx.x * kBlock + threadIdx.x;
   if (t < n) y[t] = (Y)x[t];
+}
+
+// x[s * stride + off + t] = round_bf16(...) for s < nseg, t < n.
+__global__ void __launch_bounds__(kBlock) k_round_bf16(float* __restrict__ x, long stride, long off, long n,
+                                                       int nseg) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n * nseg) return;
+  const long seg = t / n, i = t - seg * n;
+  float* p = x + seg * stride + off + i;
+  *p = round_bf16(*p);
 }
 
 // y += (double) e
@@ -1629,6 +1677,10 @@ void launch_gather_rows(hipStream_t s, const float* src, const int* idx, int B, 
 
 void launch_to_f32(hipStream_t s, const double* x, float* y, size_t n) {
   if (n) HHG_LAUNCH((k_convert<double, float>), nblocks(n), s, x, y, (long)n);
+}
+
+void launch_round_bf16(hipStream_t s, float* x, size_t stride, size_t off, size_t n, int nseg) {
+  if (n && nseg) HHG_LAUNCH(k_round_bf16, nblocks(n * (size_t)nseg), s, x, (long)stride, (long)off, (long)n, nseg);
 }
 
 void launch_add_f32_to_f64(hipStream_t s, double* y, const float* e, size_t n) {

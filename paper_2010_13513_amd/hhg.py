@@ -27,7 +27,7 @@ SYMBOLS = [
     "hhg_timer_start", "hhg_timer_read", "hhg_dc_solve", "hhg_set_viscosity",
     "hhg_mlp_create", "hhg_mlp_destroy", "hhg_mlp_num_params", "hhg_mlp_set_params", "hhg_mlp_get_params",
     "hhg_mlp_forward", "hhg_mlp_loss_grad", "hhg_mlp_train", "hhg_mlp_dims", "hhg_coarse_pair", "hhg_hier_set_mlp",
-    "hhg_record_pairs", "hhg_recorded_pairs", "hhg_hier_set_fused_sites",
+    "hhg_record_pairs", "hhg_recorded_pairs", "hhg_hier_set_fused_sites", "hhg_hier_set_bf16_levels",
 ]
 KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER, \
     KF_MLP, KF_SMALL = range(12)
@@ -88,7 +88,7 @@ def load():
         "hhg_copy_boundary": [P, I, P, P, I],
         "hhg_estimate_omega": [P, I, P, I, P],
         "hhg_norms": [P, I, P, P, P, I],
-        "hhg_vcycle": [P, I, P, P, P],
+        "hhg_vcycle": [P, I, P, P, P, I],
         "hhg_fmg_solve": [P, P, P, P, P],
         "hhg_query_stencil": [I, ctypes.c_char, I, I, I, I, I, I, P, P, P],
         "hhg_query_interpolation": [I, I, I, I, I, P, P, P],
@@ -111,6 +111,7 @@ def load():
         "hhg_record_pairs": [P, P, P, I],
         "hhg_recorded_pairs": [P, P],
         "hhg_hier_set_fused_sites": [P, ctypes.c_long],
+        "hhg_hier_set_bf16_levels": [P, I],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -267,8 +268,8 @@ def solver_params(nu_pre, nu_post, nu_inc, kappa, gs, xi, omega_inv, extra_cycle
                         max_cycles, coarse_smooth)
 
 
-def hhg_vcycle(h, level, x, b, prm):
-    _check(load().hhg_vcycle(h, level, _ptr(x), _ptr(b), ctypes.byref(prm)))
+def hhg_vcycle(h, level, x, b, prm, prec=HHG_F64):
+    _check(load().hhg_vcycle(h, level, _ptr(x), _ptr(b), ctypes.byref(prm), prec))
 
 
 def hhg_fmg_solve(h, x, b_levels, prm, want_stats=True, check=True):
@@ -368,6 +369,10 @@ def hhg_coarse_pair(h, r, features, target):
 
 def hhg_hier_set_fused_sites(h, max_sites):
     _check(load().hhg_hier_set_fused_sites(h, int(max_sites)))
+
+
+def hhg_hier_set_bf16_levels(h, n):
+    _check(load().hhg_hier_set_bf16_levels(h, n))
 
 
 def hhg_record_pairs(h, features, targets, capacity):

@@ -1,0 +1,166 @@
+"""bfloat16 storage on the coarse levels of float32 cycles
+(hhg_hier_set_bf16_levels).
+
+(i) An operation on a bf16 level returns exactly the float32 result rounded
+to bfloat16 (torch's round-to-nearest-even conversion is the reference), and
+levels above the bf16 range are untouched.  (ii) Every word the smoother,
+the transfers and whole V-cycles (one-workgroup small-level kernel and the
+launch-per-phase form) leave in a bf16 level is a bfloat16 value.  (iii) The
+float64 defect correction with float32 inner cycles and bf16 coarse levels
+reaches the same float64 solution as the all-float64 solve."""
+import numpy as np
+import pytest
+
+from oracle import multigrid as mg
+from paper_2010_13513_amd import hhg, workloads as W
+from tests.gpu_util import Lib, rel_err
+
+pytestmark = pytest.mark.gpu
+
+P1, P2 = hhg.HHG_P1P1, hhg.HHG_P2P1
+F32 = hhg.HHG_F32
+
+
+def _bf16(t):
+    import torch
+    return t.to(torch.bfloat16).to(torch.float32)
+
+
+def _is_bf16(t):
+    import torch
+    return bool(((t.view(torch.int32) & 0xFFFF) == 0).all())
+
+
+def _f32_vec(lib, level, seed):
+    """A float32 vector of bf16 values, seeded N(0, 1) on every word."""
+    torch = lib.torch
+    _, _, _, lw = lib.layout(level)
+    g = np.random.default_rng(seed)
+    x = lib.from_lattice(level, g.standard_normal(lw), F32)
+    return _bf16(x)
+
+
+@pytest.mark.parametrize("disc,lmin,L", [(P1, 1, 3), (P2, 1, 3)])
+def test_operator_outputs_are_rounded_float32_results(disc, lmin, L):
+    lib = Lib(disc, lmin, L)
+    torch = lib.torch
+    try:
+        for level in range(lmin, L + 1):
+            x = _f32_vec(lib, level, 100 + level)
+            b = _f32_vec(lib, level, 200 + level)
+            outs = {}
+            for n in (0, L - lmin):              # levels lmin .. L-1 in bf16, L not
+                hhg.hhg_hier_set_bf16_levels(lib.h, n)
+                y = torch.empty_like(x)
+                r = torch.empty_like(x)
+                m = torch.empty_like(x)
+                hhg.hhg_apply(lib.h, level, hhg.HHG_OP_FULL, x, y, F32)
+                hhg.hhg_residual(lib.h, level, x, b, r, F32)
+                hhg.hhg_apply(lib.h, level, hhg.HHG_OP_MASS, x, m, F32)
+                torch.cuda.synchronize()
+                outs[n] = (y, r, m)
+            for plain, rounded in zip(outs[0], outs[L - lmin]):
+                if level < L:
+                    assert torch.equal(rounded, _bf16(plain)), level
+                    assert not torch.equal(rounded, plain)
+                else:
+                    assert torch.equal(rounded, plain)
+    finally:
+        lib.close()
+
+
+@pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 3), (P2, 1, 3)])
+def test_smoother_transfers_and_cycles_leave_bf16_values(disc, lmin, L):
+    lib = Lib(disc, lmin, L)
+    torch = lib.torch
+    try:
+        hhg.hhg_hier_set_bf16_levels(lib.h, L - lmin + 1)
+        H = mg.Hierarchy(1 if disc == P1 else 2, lmin, L, schur="sd")
+        prob = W.fourier_forcing(W.SEED_BASE + 2100)
+        for level in (L - 1, L):
+            b = lib.from_lattice(level, H.rhs(level, prob), F32)
+            x = lib.from_lattice(level, H.initial(level, prob), F32)
+            assert _is_bf16(b) and _is_bf16(x)
+            hhg.hhg_smooth(lib.h, level, x, b, 2, hhg.HHG_GS_FWD, 2, 2.3, F32)
+            torch.cuda.synchronize()
+            assert _is_bf16(x)
+            rc = lib.empty(level - 1, torch.float32)
+            hhg.hhg_restrict(lib.h, level, b, rc, F32)
+            xf = x.clone()
+            hhg.hhg_prolong_add(lib.h, level - 1, rc, xf, F32)
+            hhg.hhg_project_mean_zero(lib.h, level, xf, F32)
+            torch.cuda.synchronize()
+            assert _is_bf16(rc) and _is_bf16(xf)
+        # V-cycles: level L - 1 runs in the one-workgroup kernel, level L
+        # launches per phase above it; both also with that kernel switched off
+        prm = hhg.solver_params(2, 2, 1, 1, hhg.HHG_GS_FWD, 2, 2.3)
+        res = {}
+        for fused in (800 if disc == P2 else 5000, 0):
+            hhg.hhg_hier_set_fused_sites(lib.h, fused)
+            for level in (L - 1, L):
+                b = lib.from_lattice(level, H.rhs(level, prob), F32)
+                x = lib.from_lattice(level, H.initial(level, prob), F32)
+                r0 = lib.empty(level, torch.float32)
+                hhg.hhg_residual(lib.h, level, x, b, r0, F32)
+                for _ in range(2):
+                    hhg.hhg_vcycle(lib.h, level, x, b, prm, F32)
+                r = lib.empty(level, torch.float32)
+                hhg.hhg_residual(lib.h, level, x, b, r, F32)
+                torch.cuda.synchronize()
+                assert _is_bf16(x), (fused, level)
+                red = float(r.double().norm() / r0.double().norm())
+                res[(fused, level)] = red
+        print({k: round(v, 4) for k, v in res.items()})
+        # bf16 storage everywhere still reduces the residual
+        assert max(res.values()) < 0.5
+    finally:
+        lib.close()
+
+
+@pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 4), (P2, 1, 4)])
+def test_defect_correction_with_bf16_coarse_levels(disc, lmin, L):
+    lib = Lib(disc, lmin, L)
+    torch = lib.torch
+    try:
+        H = mg.Hierarchy(1 if disc == P1 else 2, lmin, L, schur="sd")
+        prob = W.fourier_forcing(W.SEED_BASE + 2200)
+        b = lib.from_lattice(L, H.rhs(L, prob))
+        x0 = lib.from_lattice(L, H.initial(L, prob))
+        prm = hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 3 if disc == P2 else 1, 2.3)
+        out = {}
+        for name, prec, nbf in (("f64", hhg.HHG_F64, 0), ("f32", F32, 0), ("bf16", F32, 3)):
+            hhg.hhg_hier_set_bf16_levels(lib.h, nbf)
+            x = x0.clone()
+            st = hhg.hhg_dc_solve(lib.h, x, b, prm, prec, 1, 1e-12, 200)
+            out[name] = (lib.to_lattice(L, x), st.cycles, st.rel_res)
+        hhg.hhg_hier_set_bf16_levels(lib.h, 0)
+        print({k: (v[1], v[2]) for k, v in out.items()})
+        for k in ("f32", "bf16"):
+            assert out[k][2] <= 1e-12
+            assert rel_err(out[k][0], out["f64"][0]) < 1e-9
+        assert out["bf16"][1] <= 2 * out["f32"][1] + 2
+    finally:
+        lib.close()
+
+
+@pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 4), (P2, 1, 4)])
+def test_float32_vcycle_tracks_float64(disc, lmin, L):
+    """hhg_vcycle in float32 (no bf16 levels) against the float64 cycle from
+    the same start: agreement to float32 rounding."""
+    lib = Lib(disc, lmin, L)
+    torch = lib.torch
+    try:
+        H = mg.Hierarchy(1 if disc == P1 else 2, lmin, L, schur="sd")
+        prob = W.fourier_forcing(W.SEED_BASE + 2300)
+        bl, xl = H.rhs(L, prob), H.initial(L, prob)
+        prm = hhg.solver_params(2, 2, 1, 1, hhg.HHG_GS_FWD, 2, 2.3)
+        x64, b64 = lib.from_lattice(L, xl), lib.from_lattice(L, bl)
+        x32, b32 = lib.from_lattice(L, xl, F32), lib.from_lattice(L, bl, F32)
+        for _ in range(2):
+            hhg.hhg_vcycle(lib.h, L, x64, b64, prm)
+            hhg.hhg_vcycle(lib.h, L, x32, b32, prm, F32)
+        e = rel_err(lib.to_lattice(L, x32, F32), lib.to_lattice(L, x64))
+        print(f"float32 vs float64 V-cycles: {e:.2e}")
+        assert e < 1e-4
+    finally:
+        lib.close()

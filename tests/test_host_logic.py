@@ -16,7 +16,7 @@ P1, P2 = hhg.HHG_P1P1, hhg.HHG_P2P1
 
 def _declared_symbols():
     txt = open(os.path.join(ROOT, "include", "hhg.h")).read()
-    return sorted(set(re.findall(r"\b(hhg_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(hhg_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
