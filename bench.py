@@ -387,8 +387,9 @@ def bench_dc(torch, hhg, ctx, level=7, lmin=1):
     """Mixed precision: P2-P1 Taylor-Hood, 6 macro-tets, the given level,
     Gaussian-bump viscosity 1:100, Fourier forcing, u = 0 on the boundary.
     Defect correction in float64 to ||r|| <= 1e-12 ||b|| around one V(3,3)
-    cycle per correction, inner cycles in float32 and in float64; reports
-    times, cycles and ||x32 - x64||_M / ||x64||_M."""
+    cycle per correction, inner cycles in float64, in float32, and in float32
+    with bfloat16 storage on the levels <= 3; reports times, cycles and
+    ||x - x64||_M / ||x64||_M."""
     from paper_2010_13513_amd import workloads as W
     from paper_2010_13513_amd.problem import Problem
     P = Problem(torch, ctx, hhg.HHG_P2P1, lmin, level)
@@ -410,8 +411,11 @@ def bench_dc(torch, hhg, ctx, level=7, lmin=1):
         # V(3,3) with A_f and xi = 3 Gauss-Seidel sweeps per Uzawa step: every
         # P2-P1 tuple of Tab. fmg-table with A_f uses xi = 3 (xi = 1 diverges here)
         prm = hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 3, om)
+        nbf = max(0, min(3, level) - lmin + 1)             # bfloat16 storage on levels <= 3
+        out["bf16_levels"] = f"{lmin}..{lmin + nbf - 1}"
         xs = {}
-        for name, prec in (("f64", hhg.HHG_F64), ("f32", hhg.HHG_F32)):
+        for name, prec, nb in (("f64", hhg.HHG_F64, 0), ("f32", hhg.HHG_F32, 0), ("f32_bf16", hhg.HHG_F32, nbf)):
+            hhg.hhg_hier_set_bf16_levels(P.h, nb)
             x = x0.clone()                                  # warm-up solve (allocations, code paths)
             hhg.hhg_dc_solve(P.h, x, b, prm, prec, 1, 1e-12, 200, check=False)
             x = x0.clone()
@@ -425,17 +429,21 @@ def bench_dc(torch, hhg, ctx, level=7, lmin=1):
                          "ms_per_cycle": round(1e3 * dt / max(st.cycles, 1), 3),
                          "dofs_per_s": P.dofs(level) / dt}
             log(f"[dc] inner {name}: {st.cycles} cycles, rel res {st.rel_res:.2e}, {dt:.3f} s")
-        e = xs["f32"] - xs["f64"]
-        hhg.hhg_project_mean_zero(P.h, level, e)
-        me, mx = torch.empty_like(e), torch.empty_like(e)
-        hhg.hhg_apply(P.h, level, hhg.HHG_OP_MASS, e, me)
+        hhg.hhg_hier_set_bf16_levels(P.h, 0)
+        mx = torch.empty_like(xs["f64"])
         hhg.hhg_apply(P.h, level, hhg.HHG_OP_MASS, xs["f64"], mx)
-        eu, ep = hhg.hhg_dots(P.h, level, e, me)
         xu, xp = hhg.hhg_dots(P.h, level, xs["f64"], mx)
-        out["rel_diff_M"] = {"u": float(np.sqrt(eu / xu)), "p": float(np.sqrt(ep / xp))}
-        out["speedup_f32_vs_f64"] = round(out["f64"]["seconds"] / out["f32"]["seconds"], 3)
-        log(f"[dc] ||x32 - x64||_M / ||x64||_M: u {out['rel_diff_M']['u']:.2e}, p {out['rel_diff_M']['p']:.2e}; "
-            f"speed-up {out['speedup_f32_vs_f64']}")
+        for name in ("f32", "f32_bf16"):
+            e = xs[name] - xs["f64"]
+            hhg.hhg_project_mean_zero(P.h, level, e)
+            me = torch.empty_like(e)
+            hhg.hhg_apply(P.h, level, hhg.HHG_OP_MASS, e, me)
+            eu, ep = hhg.hhg_dots(P.h, level, e, me)
+            out[name]["rel_diff_M"] = {"u": float(np.sqrt(eu / xu)), "p": float(np.sqrt(ep / xp))}
+            out[name]["speedup_vs_f64"] = round(out["f64"]["seconds"] / out[name]["seconds"], 3)
+            log(f"[dc] {name}: ||x - x64||_M / ||x64||_M u {out[name]['rel_diff_M']['u']:.2e}, "
+                f"p {out[name]['rel_diff_M']['p']:.2e}; speed-up {out[name]['speedup_vs_f64']}")
+        out["speedup_f32_vs_f64"] = out["f32"]["speedup_vs_f64"]
     finally:
         P.close()
     return out
