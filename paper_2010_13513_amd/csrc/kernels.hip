@@ -1135,16 +1135,28 @@ __device__ double block_sum(double v, double* red) {
   return out;
 }
 
+// Pointer type of the level vectors in the one-workgroup V-cycle: LDS
+// pointers when every level lives in LDS.  The helpers below are real calls
+// (too large to inline at every use); with an LDS-typed parameter their
+// stencil loads compile to LDS reads instead of generic (flat) loads.
+template <typename T, bool LDS>
+struct SmallVec {
+  using type = T*;
+};
+template <typename T>
+struct SmallVec<T, true> {
+  typedef __attribute__((address_space(3))) T* type;
+};
+
 // Levels stored as bfloat16 (float32 only): round what a phase wrote,
 // v[s stride + off + t] for s < nseg, t < n, then a barrier.
-template <typename T>
-__device__ void small_round(bool on, T* v, int stride, int off, int n, int nseg) {
+template <typename T, typename V>
+__device__ void small_round(bool on, V v, int stride, int off, int n, int nseg) {
   if constexpr (std::is_same<T, float>::value) {
     if (!on) return;
     for (int t = threadIdx.x; t < n * nseg; t += kSmallBlock) {
-      const int sg = t / n;
-      T* p = v + sg * stride + off + (t - sg * n);
-      *p = round_bf16(*p);
+      const int sg = t / n, at = sg * stride + off + (t - sg * n);
+      v[at] = round_bf16(v[at]);
     }
     __syncthreads();
   } else {
@@ -1152,36 +1164,37 @@ __device__ void small_round(bool on, T* v, int stride, int off, int n, int nseg)
   }
 }
 
-template <typename T, int G, bool VAR>
-__device__ void small_apply(const SmallLevel<T>& L, int opmask, const T* x, const T* b, T* y, int vel_rows) {
+template <typename T, int G, bool VAR, typename V>
+__device__ void small_apply(const SmallLevel<T>& L, int opmask, V x, V b, V y, int vel_rows) {
   for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock)
-    apply_site<T, G, VAR>(L.g, L.lc, x, b, y, opmask, 1, vel_rows, 1, t);
+    apply_site<T, G, VAR>(L.g, L.lc, (const T*)x, (const T*)b, (T*)y, opmask, 1, vel_rows, 1, t);
   for (int q = threadIdx.x; q < L.nbnd; q += kSmallBlock) {
     const int t = L.bnd[q];
     const int pp = 3 * L.g.vstride + t;
-    y[pp] = b[pp] - prow_bnd_table<T>(L.g, L.tb, x, opmask, t);
+    y[pp] = b[pp] - prow_bnd_table<T>(L.g, L.tb, (const T*)x, opmask, t);
   }
   __syncthreads();
 }
 
-template <typename T, int G, bool VAR>
-__device__ void small_colour(const SmallLevel<T>& L, T* x, const T* b, int c, bool q16) {
+template <typename T, int G, bool VAR, typename V>
+__device__ void small_colour(const SmallLevel<T>& L, V x, V b, int c, bool q16) {
   if (c < 4) {
     const int n = gs_vertex_count(L.g);
-    for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock) gs_vertex_site<T, G, VAR>(L.g, L.lc, x, b, c, w % n, w / n);
+    for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock)
+      gs_vertex_site<T, G, VAR>(L.g, L.lc, (T*)x, (const T*)b, c, w % n, w / n);
   } else {
     if constexpr (G == 8) {
       const int gr = c - 3, n = gs_edge_count(L.g, gr);
-      for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock) gs_edge_site<T, VAR>(L.g, L.lc, x, b, gr, w % n, w / n);
+      for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock)
+        gs_edge_site<T, VAR>(L.g, L.lc, (T*)x, (const T*)b, gr, w % n, w / n);
     }
   }
   __syncthreads();
   small_round<T>(q16, x, L.g.vstride, c < 4 ? 0 : (c - 3) * L.g.nn, L.g.nn, 3);  // the group the colour wrote
 }
 
-template <typename T, int G, bool VAR>
-__device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters,
-                             bool q16) {
+template <typename T, int G, bool VAR, typename V>
+__device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, V x, V b, V r, int iters, bool q16) {
   if (L.g.N < 2) return;
   const int ncol = G == 1 ? 4 : 11;
   for (int it = 0; it < iters; ++it) {
@@ -1199,17 +1212,16 @@ __device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, T*
   }
 }
 
-template <typename T, int G>
-__device__ void small_smooth_any(const SmallCycle<T>& sc, const SmallLevel<T>& L, T* x, const T* b, T* r, int iters,
-                                 bool q16) {
+template <typename T, int G, typename V>
+__device__ void small_smooth_any(const SmallCycle<T>& sc, const SmallLevel<T>& L, V x, V b, V r, int iters, bool q16) {
   if (L.lc.nu)
     small_smooth<T, G, true>(sc, L, x, b, r, iters, q16);
   else
     small_smooth<T, G, false>(sc, L, x, b, r, iters, q16);
 }
 
-template <typename T, int G>
-__device__ void small_residual(const SmallCycle<T>& sc, const SmallLevel<T>& L, const T* x, const T* b, T* r) {
+template <typename T, int G, typename V>
+__device__ void small_residual(const SmallCycle<T>& sc, const SmallLevel<T>& L, V x, V b, V r) {
   if (L.lc.nu)
     small_apply<T, G, true>(L, sc.full_mask, x, b, r, 1);
   else
@@ -1217,8 +1229,8 @@ __device__ void small_residual(const SmallCycle<T>& sc, const SmallLevel<T>& L, 
 }
 
 // p -= sum_k w_k p_k / sum_k w_k with w_k = int psi_k (mode 0) or 1 (mode 1)
-template <typename T>
-__device__ void small_pshift(const SmallLevel<T>& L, T* p, int mode, double* red) {
+template <typename T, typename V>
+__device__ void small_pshift(const SmallLevel<T>& L, V p, int mode, double* red) {
   double a = 0.0, m = 0.0;
   for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) {
     double w = 1.0;
@@ -1237,22 +1249,35 @@ __device__ void small_pshift(const SmallLevel<T>& L, T* p, int mode, double* red
   __syncthreads();
 }
 
-template <typename T, int G>
+// LDS: every level's vectors live in LDS (sc.lds_words > 0).  A separate
+// instantiation, so that every level pointer derives from the LDS array and
+// the stencil loads compile to LDS reads rather than generic (flat) loads.
+template <typename T, int G, bool LDS>
 __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T>* __restrict__ lv, SmallCycle<T> sc) {
   __shared__ double red[kSmallBlock];
   __shared__ double rs[2048];
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* const sm = reinterpret_cast<T*>(lds_raw);
-  const bool lds = sc.lds_words > 0;
+  constexpr bool lds = LDS;
+  using V = typename SmallVec<T, LDS>::type;
   const int top = sc.nlev - 1;
   // the level vectors: LDS copies, or the work vectors (x, b of the call on top)
   auto vw = [&](int q) { return 3 * lv[q].g.vstride + lv[q].g.nn; };
-  auto X = [&](int q) -> T* { return lds ? sm + lv[q].lds_off : (q == top ? sc.x : lv[q].cx); };
-  auto B = [&](int q) -> T* { return lds ? sm + lv[q].lds_off + vw(q) : (q == top ? const_cast<T*>(sc.b) : lv[q].cb); };
-  auto R = [&](int q) -> T* { return lds ? sm + lv[q].lds_off + 2 * vw(q) : lv[q].r; };
+  auto X = [&](int q) -> V {
+    if constexpr (LDS) return (V)(sm + lv[q].lds_off);
+    else return q == top ? sc.x : lv[q].cx;
+  };
+  auto B = [&](int q) -> V {
+    if constexpr (LDS) return (V)(sm + lv[q].lds_off + vw(q));
+    else return q == top ? const_cast<T*>(sc.b) : lv[q].cb;
+  };
+  auto R = [&](int q) -> V {
+    if constexpr (LDS) return (V)(sm + lv[q].lds_off + 2 * vw(q));
+    else return lv[q].r;
+  };
   if (lds) {
-    T* xs = X(top);
-    T* bs = B(top);
+    V xs = X(top);
+    V bs = B(top);
     for (int t = threadIdx.x; t < vw(top); t += kSmallBlock) {
       xs[t] = sc.x[t];
       bs[t] = sc.b[t];
@@ -1263,28 +1288,28 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
   for (int q = top; q >= 1; --q) {
     const SmallLevel<T>& L = lv[q];
     const SmallLevel<T>& C = lv[q - 1];
-    T* x = X(q);
-    const T* b = B(q);
+    V x = X(q);
+    V b = B(q);
     small_smooth_any<T, G>(sc, L, x, b, R(q), sc.pre0 + (top - q) * sc.inc, q < sc.q16);
     small_residual<T, G>(sc, L, x, b, R(q));
     small_round<T>(q < sc.q16, R(q), 0, 0, vw(q), 1);
-    T* cb = B(q - 1);
-    const T* r = R(q);
+    V cb = B(q - 1);
+    V r = R(q);
     for (int w = threadIdx.x; w < (G + 1) * C.g.nn; w += kSmallBlock)
-      restrict_table<T, G>(L.g, C.g, L.tt, r, cb, w % C.g.nn, w / C.g.nn);
+      restrict_table<T, G>(L.g, C.g, L.tt, (const T*)r, (T*)cb, w % C.g.nn, w / C.g.nn);
     __syncthreads();
     small_round<T>(q - 1 < sc.q16, cb, 0, 0, vw(q - 1), 1);
     small_pshift<T>(C, cb + 3 * (size_t)C.g.vstride, 1, red);
     small_round<T>(q - 1 < sc.q16, cb, 0, 3 * C.g.vstride, C.g.nn, 1);
-    T* cx = X(q - 1);
+    V cx = X(q - 1);
     for (int t = threadIdx.x; t < vw(q - 1); t += kSmallBlock) cx[t] = T(0);
     __syncthreads();
   }
   // coarsest level: x += K^+ (b - calA x) on the unknowns, zero pressure mean
   {
     const SmallLevel<T>& L = lv[0];
-    T* x = X(0);
-    const T* r = R(0);
+    V x = X(0);
+    V r = R(0);
     small_residual<T, G>(sc, L, x, B(0), R(0));
     small_round<T>(0 < sc.q16, R(0), 0, 0, vw(0), 1);
     for (int c = threadIdx.x; c < sc.nunk; c += kSmallBlock) rs[c] = (double)r[sc.unk[c]];
@@ -1304,15 +1329,16 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
   for (int q = 1; q <= top; ++q) {
     const SmallLevel<T>& L = lv[q];
     const SmallLevel<T>& C = lv[q - 1];
-    T* x = X(q);
-    const T* xc = X(q - 1);
-    for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock) prolong_site<T, G>(C.g, L.g, L.tt, xc, x, 1, 1, t);
+    V x = X(q);
+    V xc = X(q - 1);
+    for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock)
+      prolong_site<T, G>(C.g, L.g, L.tt, (const T*)xc, (T*)x, 1, 1, t);
     __syncthreads();
     small_round<T>(q < sc.q16, x, 0, 0, vw(q), 1);
     small_smooth_any<T, G>(sc, L, x, B(q), R(q), sc.post0 + (top - q) * sc.inc, q < sc.q16);
   }
   if (lds) {
-    const T* xs = X(top);
+    V xs = X(top);
     for (int t = threadIdx.x; t < vw(top); t += kSmallBlock) sc.x[t] = xs[t];
   }
 }
@@ -1641,18 +1667,29 @@ template <typename T>
 void launch_vcycle_small(hipStream_t s, const SmallLevel<T>* lv, const SmallCycle<T>& sc) {
   KScope ks(s, KF_SMALL, sc.nlev);
   const size_t lds = (size_t)sc.lds_words * sizeof(T);
-  if (sc.G == 1)
-    hipLaunchKernelGGL((k_vcycle_small<T, 1>), dim3(1), dim3(kSmallBlock), lds, s, lv, sc);
-  else
-    hipLaunchKernelGGL((k_vcycle_small<T, 8>), dim3(1), dim3(kSmallBlock), lds, s, lv, sc);
+  const dim3 grid(1), block(kSmallBlock);
+  if (sc.G == 1) {
+    if (lds)
+      hipLaunchKernelGGL((k_vcycle_small<T, 1, true>), grid, block, lds, s, lv, sc);
+    else
+      hipLaunchKernelGGL((k_vcycle_small<T, 1, false>), grid, block, 0, s, lv, sc);
+  } else {
+    if (lds)
+      hipLaunchKernelGGL((k_vcycle_small<T, 8, true>), grid, block, lds, s, lv, sc);
+    else
+      hipLaunchKernelGGL((k_vcycle_small<T, 8, false>), grid, block, 0, s, lv, sc);
+  }
 }
 
+template <typename T, int G>
+void small_attributes_of(int bytes) {
+  (void)hipFuncSetAttribute((const void*)k_vcycle_small<T, G, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
 void small_kernel_attributes() {
-  const int bytes = kSmallLdsBytes;
-  (void)hipFuncSetAttribute((const void*)k_vcycle_small<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute((const void*)k_vcycle_small<double, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute((const void*)k_vcycle_small<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute((const void*)k_vcycle_small<float, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  small_attributes_of<double, 1>(kSmallLdsBytes);
+  small_attributes_of<double, 8>(kSmallLdsBytes);
+  small_attributes_of<float, 1>(kSmallLdsBytes);
+  small_attributes_of<float, 8>(kSmallLdsBytes);
 }
 
 void launch_unit_columns(hipStream_t s, double* E, size_t stride, const int* unk, int n) {
