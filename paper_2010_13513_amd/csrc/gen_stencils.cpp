@@ -275,24 +275,40 @@ void emit_zm(FILE* f, const ElementSet& es, const char* D, int G) {
                    "__amdgpu_buffer_rsrc_t rp, const int (&vo)[3], int nnb, T rt, T rc, T (&acc)[3][%d]) {\n"
                    "  (void)rc; (void)nnb;\n",
                    D, d, Q, G + 1);
+      // all loads of the plane first, then the words one by one in a fixed
+      // order (zm_order / zm_word): a word's lane-shifted copies die before
+      // the next word's are made
       int nload = 0;
       for (int a = 0; a <= G; ++a)
         for (int dj = -1; dj <= 1; ++dj) {
           bool any = false;
           for (int di = -1; di <= 1; ++di) any |= !at(a, di, dj).empty();
           if (!any) continue;
+          if (a < G)
+            std::fprintf(f, "  const T l%d = buffer_word<T>(ru, vo[%d], %d * nnb);\n", nload, dj + 1, a);
+          else
+            std::fprintf(f, "  const T l%d = buffer_word<T>(rp, vo[%d], 0);\n", nload, dj + 1);
           ++nload;
+        }
+      int iw = 0;
+      for (int a = 0; a <= G; ++a)
+        for (int dj = -1; dj <= 1; ++dj) {
+          bool any = false;
+          for (int di = -1; di <= 1; ++di) any |= !at(a, di, dj).empty();
+          if (!any) continue;
           // pressure words: one scaled copy per kind that uses them
           bool kinds[3] = {false, false, false};
           for (int di = -1; di <= 1; ++di)
             for (auto& u : at(a, di, dj)) kinds[u.kind] = true;
+          std::fprintf(f, "  zm_order(acc);\n");
           if (a < G) {
-            std::fprintf(f, "  { const T v0 = buffer_word<T>(ru, vo[%d], %d * nnb);\n", dj + 1, a);
+            std::fprintf(f, "  { const T v0 = zm_word(l%d);\n", iw);
           } else {
-            std::fprintf(f, "  { const T w0 = buffer_word<T>(rp, vo[%d], 0);\n", dj + 1);
+            std::fprintf(f, "  { const T w0 = zm_word(l%d);\n", iw);
             if (kinds[1]) std::fprintf(f, "    const T v0 = rt * w0;\n");
             if (kinds[2]) std::fprintf(f, "    const T c0 = rc * w0;\n");
           }
+          ++iw;
           for (int di = -1; di <= 1; ++di) {
             const auto& us = at(a, di, dj);
             if (us.empty()) continue;
