@@ -10,25 +10,32 @@ representative node of the same type on the N = 8 lattice, rescaled
 (A: h, B and B^T: h^2, PSPG C: h^3) and applied to the same input words.
 Samples: interior velocity rows of every parity class and component,
 boundary velocity rows (zero), pressure rows of all 27 boundary classes.
-The row construction itself is checked on the CPU against the oracle's
-assembled operator at N = 16."""
+The same check runs on the mixed-precision workload's variable-viscosity
+operator (6 macro-tets, level 7, N = 128).  The row construction itself is
+checked on the CPU against the oracle's assembled operator at N = 16."""
 import numpy as np
 import pytest
 
 from oracle import fe
 from oracle.stokes import Stokes
-from paper_2010_13513_amd import hhg
+from paper_2010_13513_amd import hhg, workloads as W
 from tests.gpu_util import Lib
 
 NS = 8          # oracle lattice of the representative rows
 PARITIES = [(a, b, c) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
 
 
-def sampled_rows(vo, N, rng, per_class=6):
+def sampled_rows(vo, N, rng, per_class=6, nu=None):
     """Rows of calA on the N lattice, as (lattice index of the output,
     [(lattice index of an input word, weight)]), plus lattice indices of
     boundary velocity rows (whose output is zero).  Plain lattice order:
-    [u1 | u2 | u3 | p], velocity on the (vo N + 1)^3 lattice."""
+    [u1 | u2 | u3 | p], velocity on the (vo N + 1)^3 lattice.
+
+    nu: viscosity at the P1 nodes of the N lattice ((N+1)^3, lattice order)
+    for the variable-viscosity A.  A velocity row then comes from an N = 8
+    oracle level whose vertex viscosities are those of the same window of the
+    big lattice (shifted by the P1 offset between the sampled site and its
+    representative); only the vertices of the row's own elements enter it."""
     lev = fe.Level(NS, vo)
     A = lev.A.tocsr()
     BT = [b.tocsc() for b in lev.B]
@@ -60,6 +67,13 @@ def sampled_rows(vo, N, rng, per_class=6):
             rep = np.array([vo * NS // 2 + (s & 1) for s in S])
             r = int(rep[0] + ms * (rep[1] + ms * rep[2]))
             terms = []
+            if nu is not None:
+                delta = (S - rep) // vo
+                q = np.arange(NS + 1)
+                I, J, K = np.meshgrid(q, q, q, indexing="ij")
+                idx = [np.clip(a + o, 0, N) for a, o in zip((I, J, K), delta)]
+                nu_s = nu.reshape(N + 1, N + 1, N + 1)[idx[2], idx[1], idx[0]]
+                A = fe.Level(NS, vo, np.transpose(nu_s, (2, 1, 0)).ravel()).A.tocsr()
             row = A.getrow(r)
             for c, w in zip(row.indices, row.data):
                 terms.append((vlat(d, *(S + vc[c] - rep)), fA * w))
@@ -99,13 +113,23 @@ def check_rows(rows, bnd, xval, got, rtol=1e-12):
     assert np.all(got[len(rows):] == 0.0)
 
 
+def _nu_nodes(N):
+    """The variable-viscosity workload's field at the P1 nodes of the N
+    lattice (lattice order)."""
+    from oracle import mesh
+    c = mesh.p1_coords(N) / float(N)
+    return W.gaussian_bump_viscosity(W.SEED_BASE + 4000, N_ref=N)(c[:, 0], c[:, 1], c[:, 2])
+
+
 @pytest.mark.parametrize("vo", [2, 1])
-def test_sampled_rows_reproduce_assembled_operator(vo):
+@pytest.mark.parametrize("varnu", [False, True])
+def test_sampled_rows_reproduce_assembled_operator(vo, varnu):
     """CPU: the representative-row construction at N = 16 against the
-    oracle's operator assembled at N = 16."""
+    oracle's operator assembled at N = 16 (constant and variable viscosity)."""
     N = 16
-    rows, bnd = sampled_rows(vo, N, np.random.default_rng(11), per_class=3)
-    S = Stokes(fe.Level(N, vo))
+    nu = _nu_nodes(N) if varnu else None
+    rows, bnd = sampled_rows(vo, N, np.random.default_rng(11), per_class=3, nu=nu)
+    S = Stokes(fe.Level(N, vo, nu))
     x = np.random.default_rng(12).standard_normal(S.n)
     y = S.apply(x)
     got = y[[r[0] for r in rows] + bnd]
@@ -136,6 +160,40 @@ def test_apply_full_size_sampled_rows(disc):
 
         rows, bnd = sampled_rows(vo, N, np.random.default_rng(7))
         assert len(rows) > 100
+        got = ylat.index_select(0, torch.tensor([r[0] for r in rows] + bnd, device=lib.dev)).cpu().numpy()
+        xi = sorted({t[0] for r in rows for t in r[1]})
+        xv = dict(zip(xi, lat.index_select(0, torch.tensor(xi, device=lib.dev)).cpu().numpy()))
+        check_rows(rows, bnd, xv, got)
+    finally:
+        lib.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("disc", [hhg.HHG_P2P1, hhg.HHG_P1P1])
+def test_variable_viscosity_apply_full_size_sampled_rows(disc):
+    """The mixed-precision workload's operator: 6 macro-tets, level 7
+    (N = 128), Gaussian-bump viscosity 1:100, float64, sampled rows against
+    oracle rows assembled with the same vertex viscosities."""
+    lib = Lib(disc, 6, 7)
+    torch = lib.torch
+    try:
+        vo = 2 if disc == hhg.HHG_P2P1 else 1
+        N, nn, vw, lw = lib.layout(7)
+        assert N == 128
+        nu = _nu_nodes(N)
+        hhg.hhg_set_viscosity(lib.h, 7, torch.from_numpy(nu).to(lib.dev))
+        print(f"variable-viscosity apply full size: disc {disc}, N {N}, {vw} words", flush=True)
+        gen = torch.Generator(device=lib.dev).manual_seed(13513 + 3001)
+        lat = torch.randn(lw, generator=gen, dtype=torch.float64, device=lib.dev)
+        x = torch.zeros(vw, dtype=torch.float64, device=lib.dev)
+        hhg.hhg_vec_from_lattice(lib.h, 7, lat, x)
+        y = torch.empty_like(x)
+        hhg.hhg_apply(lib.h, 7, hhg.HHG_OP_FULL, x, y)
+        ylat = torch.empty_like(lat)
+        hhg.hhg_vec_to_lattice(lib.h, 7, y, ylat)
+        torch.cuda.synchronize()
+
+        rows, bnd = sampled_rows(vo, N, np.random.default_rng(8), per_class=4, nu=nu)
         got = ylat.index_select(0, torch.tensor([r[0] for r in rows] + bnd, device=lib.dev)).cpu().numpy()
         xi = sorted({t[0] for r in rows for t in r[1]})
         xv = dict(zip(xi, lat.index_select(0, torch.tensor(xi, device=lib.dev)).cpu().numpy()))
