@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, cons
 // LDS.  Per P2 site this issues 69 / 8 loads instead of one per stencil entry.
 constexpr int kZmCols = 64;
 #ifndef HHG_ZM_KC
-#define HHG_ZM_KC 16  // k-planes per chunk (the chunk re-reads 2 halo planes)
+#define HHG_ZM_KC 20  // k-planes per chunk (the chunk re-reads 2 halo planes); 20 measured best of 8..48
 #endif
 constexpr int kZmOut = kZmCols - 2;  // columns written per window
 
