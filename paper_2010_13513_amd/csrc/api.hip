@@ -614,8 +614,14 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
       if (gs == HHG_GS_SYM)
         for (int c = ncol - 1; c >= 0; --c) colour(c);
     }
-    // r_p = g - B u + C p, then p -= omega D^{-1} r_p
-    op_apply<T>(h, l, full_mask(h) & 12, x, b, r, true, false, true);
+    // r_p = g - B u + C p, then p -= omega D^{-1} r_p.  With constant
+    // coefficients the k-marching form of the whole operator is cheaper than
+    // the pressure rows alone (a few loads per lattice point against a load
+    // per stencil entry); its velocity rows land in the scratch residual.
+    if (!lv.nu64)
+      op_apply<T>(h, l, full_mask(h), x, b, r, true, true, true);
+    else
+      op_apply<T>(h, l, full_mask(h) & 12, x, b, r, true, false, true);
     launch_pressure_step<T>(S(h), lv.g, dinv<T>(lv), x, r, (T)omega);
     round_out<T>(h, l, x, 0, 3 * (size_t)lv.g.vstride, lv.g.nn, 1);
   }

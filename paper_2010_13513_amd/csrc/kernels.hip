@@ -1489,8 +1489,13 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
   if (!lc.nu && opmask == full && vel_rows && p_rows) {
     // k-marching form: 62 output columns per block, k in chunks of kc planes;
     // the boundary pressure rows in extra blocks of 192 threads
-    const int kc = g.n1 <= HHG_ZM_KC + 8 ? g.n1 : HHG_ZM_KC;
+    // chunk length: HHG_ZM_KC planes, halved (down to 2) while the grid has
+    // fewer than ~1000 blocks -- on the small levels a chunk is a chain of
+    // dependent plane steps, so short chunks (more blocks) win over the
+    // re-read halo planes
     const int ncb = (g.n1 * g.n1 + kZmOut - 1) / kZmOut;
+    int kc = std::min(HHG_ZM_KC, g.n1);
+    while (kc > 2 && ncb * ((g.n1 + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
     const int nch = (g.n1 + kc - 1) / kc;
     const int nmain = (ncb * nch + 7) & ~7;
     const int nextra = (nb_bnd + 3 * kZmCols - 1) / (3 * kZmCols);
