@@ -771,37 +771,38 @@ __global__ void __launch_bounds__(kBlock) k_dot(const T* __restrict__ x, const T
 }
 
 // ---------------------------------------------------------------- transfer
-// Restriction (transpose of the prolongation): coarse thread gathers fine values.
 // Restriction (transpose of the prolongation, generated gathers): one coarse
-// node t and one group gr per call -- velocity group gr < G (three
-// components), or the P1 pressure for gr = G (entries clipped at the domain
-// boundary).  Coarse boundary velocity rows are zero.
+// node t and one slice sl per thread -- velocity group sl / 3 < G, component
+// sl % 3, or the P1 pressure for sl = 3 G (entries clipped at the domain
+// boundary).  One component per thread: the small levels are latency-bound,
+// and a vertex-group gather of all three components is ~375 dependent-ish
+// loads.  Coarse boundary velocity rows are zero.
 template <typename T, int G>
 __device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, const T* __restrict__ rf,
-                                              T* __restrict__ rc, int t, int gr) {
+                                              T* __restrict__ rc, int t, int sl) {
   int i, j, k;
   decode(t, gc.n1, i, j, k);
   const int fb = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
   const int s1 = gf.n1, s2 = gf.n1 * gf.n1, nn = gf.nn, vs = gf.vstride;
-  if (gr == G) {
+  if (sl == 3 * G) {
     const T* pf = rf + 3 * (size_t)vs;
     rc[3 * gc.vstride + t] = G == 1 ? gen::p1_RP<T>(pf, fb, 2 * i, 2 * j, 2 * k, gf.N, s1, s2)
                                     : gen::p2_RP<T>(pf, fb, 2 * i, 2 * j, 2 * k, gf.N, s1, s2);
     return;
   }
+  const int gr = sl / 3, d = sl - 3 * gr;
+  const T* rd = rf + (size_t)d * vs;  // component d; the other two outputs of the gather are unused
   T a0 = 0, a1 = 0, a2 = 0;
   if (vel_interior<G>(gr, i, j, k, gc.N)) {
     if constexpr (G == 1) {
-      gen::p1_R_g0<T>(rf, fb, s1, s2, nn, vs, a0, a1, a2);
+      gen::p1_R_g0<T>(rd, fb, s1, s2, nn, 0, a0, a1, a2);
     } else {
       const int g = gr;
-      HHG_P2_CASES(p2_R, rf, fb, s1, s2, nn, vs, a0, a1, a2)
+      HHG_P2_CASES(p2_R, rd, fb, s1, s2, nn, 0, a0, a1, a2)
     }
   }
-  const int pos = gr * gc.nn + t;
-  rc[pos] = a0;
-  rc[gc.vstride + pos] = a1;
-  rc[2 * gc.vstride + pos] = a2;
+  (void)a1, (void)a2;
+  rc[(size_t)d * gc.vstride + gr * gc.nn + t] = a0;
 }
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const T* __restrict__ rf, T* __restrict__ rc) {
@@ -810,7 +811,46 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const T* 
   restrict_site<T, G>(gf, gc, rf, rc, t, blockIdx.y);
 }
 
-// Prolongation: fine thread evaluates the coarse function at its sites.
+// Prolongation: a fine thread evaluates the coarse function at its site of
+// one slice sl -- velocity group sl / 3 < G, component sl % 3, or the
+// pressure for sl = 3 G (or every slice for sl < 0, the one-workgroup
+// V-cycle's form).
+template <typename T, int G>
+__device__ __forceinline__ void prolong_slice(const Geom& gc, const Geom& gf, const TransferTables<T>* __restrict__ tt,
+                                              const T* __restrict__ xc, T* __restrict__ xf, int add,
+                                              int skip_boundary, int t, int i, int j, int k, int sl) {
+  if (sl == 3 * G) {
+    const int cls = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    const int base = (i >> 1) + gc.n1 * ((j >> 1) + gc.n1 * (k >> 1));
+    T a = 0;
+    const int n = tt->pp_n[cls];
+    for (int e = 0; e < n; ++e) a += tt->pp_w[cls * 10 + e] * xc[3 * gc.vstride + base + tt->pp_off[cls * 10 + e]];
+    const int pp = 3 * gf.vstride + t;
+    xf[pp] = add ? xf[pp] + a : a;
+    return;
+  }
+  const int gr = sl / 3, d = sl - 3 * gr;
+  const int Nf = gf.N;
+  if (!vel_exists<G>(gr, i, j, k, Nf)) return;
+  if (skip_boundary && !vel_interior<G>(gr, i, j, k, Nf)) return;
+  int cls, base;
+  if (G == 1) {
+    cls = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    base = (i >> 1) + gc.n1 * ((j >> 1) + gc.n1 * (k >> 1));
+  } else {
+    const int X = 2 * i + gdx(gr), Y = 2 * j + gdy(gr), Z = 2 * k + gdz(gr);
+    cls = (X & 3) + 4 * (Y & 3) + 16 * (Z & 3);
+    base = (X >> 2) + gc.n1 * ((Y >> 2) + gc.n1 * (Z >> 2));
+  }
+  const int n = tt->vp_n[cls];
+  const T* xd = xc + (size_t)d * gc.vstride;
+  T a = 0;
+  for (int e = 0; e < n; ++e) a += tt->vp_w[cls * 10 + e] * xd[base + tt->vp_off[cls * 10 + e]];
+  const int pos = d * gf.vstride + gr * gf.nn + t;
+  xf[pos] = add ? xf[pos] + a : a;
+}
+// Every slice of one fine site, the three components of a group together
+// (the one-workgroup V-cycle's form: same sums as prolong_slice).
 template <typename T, int G>
 __device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, const TransferTables<T>* __restrict__ tt,
                                              const T* __restrict__ xc, T* __restrict__ xf, int add, int skip_boundary,
@@ -841,23 +881,11 @@ __device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, con
       a2 += w * xc[2 * gc.vstride + o];
     }
     const int pos = gr * gf.nn + t;
-    if (add) {
-      xf[pos] += a0;
-      xf[gf.vstride + pos] += a1;
-      xf[2 * gf.vstride + pos] += a2;
-    } else {
-      xf[pos] = a0;
-      xf[gf.vstride + pos] = a1;
-      xf[2 * gf.vstride + pos] = a2;
-    }
+    xf[pos] = add ? xf[pos] + a0 : a0;
+    xf[gf.vstride + pos] = add ? xf[gf.vstride + pos] + a1 : a1;
+    xf[2 * gf.vstride + pos] = add ? xf[2 * gf.vstride + pos] + a2 : a2;
   }
-  const int cls = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
-  const int base = (i >> 1) + gc.n1 * ((j >> 1) + gc.n1 * (k >> 1));
-  T a = 0;
-  const int n = tt->pp_n[cls];
-  for (int e = 0; e < n; ++e) a += tt->pp_w[cls * 10 + e] * xc[3 * gc.vstride + base + tt->pp_off[cls * 10 + e]];
-  const int pp = 3 * gf.vstride + t;
-  xf[pp] = add ? xf[pp] + a : a;
+  prolong_slice<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, 3 * G);
 }
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
@@ -865,7 +893,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const Tran
                                                     int skip_boundary) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= gf.nn) return;
-  prolong_site<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t);
+  int i, j, k;
+  decode(t, gf.n1, i, j, k);
+  prolong_slice<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, blockIdx.y);
 }
 
 // Boundary velocity values of the coarse level from the coincident fine nodes.
@@ -1611,20 +1641,25 @@ template <typename T>
 void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc) {
   KScope ks(s, KF_RESTRICT, p_sites(gf));
   (void)tt;
+  // grid.y: (velocity group, component) slices and the pressure
   if (gc.G == 1)
-    hipLaunchKernelGGL((k_restrict<T, 1>), dim3(nblocks(gc.nn), 2), dim3(kBlock), 0, s, gf, gc, rf, rc);
+    hipLaunchKernelGGL((k_restrict<T, 1>), dim3(nblocks(gc.nn), 4), dim3(kBlock), 0, s, gf, gc, rf, rc);
   else
-    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 9), dim3(kBlock), 0, s, gf, gc, rf, rc);
+    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 25), dim3(kBlock), 0, s, gf, gc, rf, rc);
 }
 
 template <typename T>
 void launch_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, const T* xc, T* xf,
                     bool add, bool skip_boundary) {
   KScope ks(s, KF_PROLONG, p_sites(gf));
+  // grid.y: (velocity group, component) slices and the pressure
+  const dim3 block(kBlock);
   if (gf.G == 1)
-    HHG_LAUNCH((k_prolong<T, 1>), nblocks(gf.nn), s, gc, gf, tt, xc, xf, (int)add, (int)skip_boundary);
+    hipLaunchKernelGGL((k_prolong<T, 1>), dim3(nblocks(gf.nn), 4), block, 0, s, gc, gf, tt, xc, xf, (int)add,
+                       (int)skip_boundary);
   else
-    HHG_LAUNCH((k_prolong<T, 8>), nblocks(gf.nn), s, gc, gf, tt, xc, xf, (int)add, (int)skip_boundary);
+    hipLaunchKernelGGL((k_prolong<T, 8>), dim3(nblocks(gf.nn), 25), block, 0, s, gc, gf, tt, xc, xf, (int)add,
+                       (int)skip_boundary);
 }
 
 template <typename T>
