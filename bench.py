@@ -200,7 +200,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": int(bytes_launch),
-                "launches_per_step": n_d, "share_of_step": round(ms_d / ms_step, 3)}
+                "launches_per_step": n_d, "share_of_step": round(ms_d / ms_step, 3),
+                "timing": ("HIP events stamped by each launch's dispatch packet (kernel start to end)"
+                           if dom.startswith("gs_") else "HIP events recorded around each launch")}
 
     # ---- operator-apply HBM roofline at the throughput size (48 tets, level 7)
     apply_roofline = None

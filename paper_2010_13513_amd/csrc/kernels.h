@@ -64,7 +64,14 @@ bool timer_enabled();
 struct KScope {
   hipStream_t s_;
   hipEvent_t b_ = nullptr;
-  KScope(hipStream_t s, int fam, double units);
+  // packet = true: the events are left to the launch (launch_timed), which
+  // has the dispatch packet stamp the kernel's own start and end -- the
+  // kernel's execution time without the event and queue overhead around a
+  // launch (for kernels of a few microseconds that overhead is most of a
+  // bracketed measurement).  Not while the stream is being captured.
+  hipEvent_t a_ = nullptr;
+  bool packet_ = false;
+  KScope(hipStream_t s, int fam, double units, bool packet = false);
   ~KScope();
 };
 // Sum of event-measured durations (ms), launches and work units of one family

@@ -8,6 +8,8 @@
 // small device tables with wavefront-uniform addresses (scalar loads).
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace hhg {
@@ -134,17 +136,22 @@ Timer& timer() {
 }
 }  // namespace
 
-KScope::KScope(hipStream_t s, int fam, double units) : s_(s) {
+KScope::KScope(hipStream_t s, int fam, double units, bool packet) : s_(s) {
   Timer& t = timer();
   if (!((t.mask >> fam) & 1u)) return;
   TimerRec r{fam, nullptr, nullptr, units};
   if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
-  (void)hipEventRecord(r.a, s);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  packet_ = packet && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+  if (packet_)
+    a_ = r.a;
+  else
+    (void)hipEventRecord(r.a, s);
   b_ = r.b;
   t.recs.push_back(r);
 }
 KScope::~KScope() {
-  if (b_) (void)hipEventRecord(b_, s_);
+  if (b_ && !packet_) (void)hipEventRecord(b_, s_);
 }
 
 namespace {
@@ -1552,6 +1559,15 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
   (void)tb;
 }
 
+// Launch, with the packet-stamped events of a KScope opened with packet = true.
+template <typename K, typename... Args>
+void launch_timed(const KScope& ks, K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (ks.packet_)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ks.a_, ks.b_, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 template <typename T>
 void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* x, const T* b, int colour) {
   const int N = g.N;
@@ -1565,27 +1581,28 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* 
           const int i0 = 1 + (((colour - 1 - j - k) % 4) + 4) % 4;
           if (i0 <= nr) cnt += (nr - i0) / 4 + 1;
         }
-    KScope ks(s, KF_GS_VERTEX, cnt);
-    const dim3 grid(nblocks((size_t)ni * nr * nr), 3);
+    KScope ks(s, KF_GS_VERTEX, cnt, true);
+    const dim3 grid(nblocks((size_t)ni * nr * nr), 3), block(kBlock);
     if (g.G == 1) {
       if (lc.nu)
-        hipLaunchKernelGGL((k_gs_vertex<T, 1, true>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+        launch_timed(ks, k_gs_vertex<T, 1, true>, grid, block, s, g, lc, x, b, colour);
       else
-        hipLaunchKernelGGL((k_gs_vertex<T, 1, false>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+        launch_timed(ks, k_gs_vertex<T, 1, false>, grid, block, s, g, lc, x, b, colour);
     } else {
       if (lc.nu)
-        hipLaunchKernelGGL((k_gs_vertex<T, 8, true>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+        launch_timed(ks, k_gs_vertex<T, 8, true>, grid, block, s, g, lc, x, b, colour);
       else
-        hipLaunchKernelGGL((k_gs_vertex<T, 8, false>), grid, dim3(kBlock), 0, s, g, lc, x, b, colour);
+        launch_timed(ks, k_gs_vertex<T, 8, false>, grid, block, s, g, lc, x, b, colour);
     }
   } else {
     const int gr = colour - 3;
     const size_t n = (size_t)gs_edge_count(g, gr);
-    KScope ks(s, KF_GS_EDGE, (double)n);
+    KScope ks(s, KF_GS_EDGE, (double)n, true);
+    const dim3 grid(nblocks(n), 3), block(kBlock);
     if (lc.nu)
-      hipLaunchKernelGGL((k_gs_edge<T, true>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, lc, x, b, gr);
+      launch_timed(ks, k_gs_edge<T, true>, grid, block, s, g, lc, x, b, gr);
     else
-      hipLaunchKernelGGL((k_gs_edge<T, false>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, lc, x, b, gr);
+      launch_timed(ks, k_gs_edge<T, false>, grid, block, s, g, lc, x, b, gr);
   }
 }
 
