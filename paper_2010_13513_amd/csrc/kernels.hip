@@ -68,20 +68,14 @@ namespace gen {
 // it emits no instruction and touches no memory.
 template <typename T, int R>
 __device__ __forceinline__ void zm_order(T (&acc)[3][R]) {
-#ifndef HHG_ZM_FREE_ORDER
 #pragma unroll
   for (int s = 0; s < 3; ++s)
 #pragma unroll
     for (int r = 0; r < R; ++r) asm volatile("" : "+v"(acc[s][r]));
-#else
-  (void)acc;
-#endif
 }
 template <typename T>
 __device__ __forceinline__ T zm_word(T v) {
-#ifndef HHG_ZM_FREE_ORDER
   asm volatile("" : "+v"(v));
-#endif
   return v;
 }
 }  // namespace gen
@@ -500,11 +494,7 @@ __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, c
 }
 
 template <typename T, int G>
-__global__ void __launch_bounds__(3 * kZmCols)
-#ifdef HHG_ZM_WAVES
-__attribute__((amdgpu_waves_per_eu(HHG_ZM_WAVES)))
-#endif
-k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
+__global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
                                                           const T* __restrict__ b, T* __restrict__ y, int has_b, int kc,
                                                           int ncb, const int* __restrict__ bnd, int nbnd, int nmain) {
   __shared__ T pshare[2][3][kZmCols];
