@@ -631,8 +631,7 @@ template <typename T>
 void op_mean_zero(hhg_hier h, int l, T* x) {
   Level& lv = h->L(l);
   T* p = x + 3 * (size_t)lv.g.vstride;
-  launch_psum<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
-  launch_pshift<T>(S(h), lv.g, p, h->sums, 0);
+  launch_mean_zero<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
   round_out<T>(h, l, p, 0, 0, lv.g.nn, 1);
 }
 
@@ -643,8 +642,7 @@ void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
   launch_restrict<T>(S(h), f.g, c.g, ttables<T>(f), rf, rc);
   round_out<T>(h, lf - 1, rc, 0, 0, c.vec_words, 1);
   T* p = rc + 3 * (size_t)c.g.vstride;
-  launch_psum<T>(S(h), c.g, tables<T>(c), p, h->partial, h->sums, 1);
-  launch_pshift<T>(S(h), c.g, p, h->sums, 1);
+  launch_mean_zero<T>(S(h), c.g, tables<T>(c), p, h->partial, h->sums, 1);
   round_out<T>(h, lf - 1, p, 0, 0, c.g.nn, 1);
 }
 

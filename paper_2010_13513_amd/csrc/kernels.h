@@ -174,6 +174,12 @@ void launch_psum(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* p, 
                  int mode);
 template <typename T>
 void launch_pshift(hipStream_t s, const Geom& g, T* p, const double* sums, int mode);
+// p -= (weighted, mode 0, or plain, mode 1) mean of p: launch_psum + launch_pshift,
+// or one workgroup for levels with at most kMeanOneBlock pressure nodes.
+constexpr int kMeanOneBlock = 65536;
+template <typename T>
+void launch_mean_zero(hipStream_t s, const Geom& g, const Tables<T>* tb, T* p, double* partial, double* sums,
+                      int mode);
 template <typename T>
 void launch_vsumsq(hipStream_t s, const Geom& g, const T* x, int nwords, double* partial, double* out);
 template <typename T>

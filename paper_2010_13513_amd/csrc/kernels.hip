@@ -1064,6 +1064,45 @@ __global__ void __launch_bounds__(kBlock) k_pshift(int nn, T* __restrict__ p, co
   p[t] = (T)((double)p[t] - mean);
 }
 
+// The whole mean-zero shift of a small level in one workgroup: the sums of
+// k_psum (mode 0 or 1), a tree reduction, then p -= mean; sums[0], sums[1]
+// as k_final_sum leaves them.  Three launches become one.
+constexpr int kMeanBlock = 1024;
+template <typename T>
+__global__ void __launch_bounds__(kMeanBlock) k_mean_zero_1b(Geom g, const Tables<T>* __restrict__ tb,
+                                                             T* __restrict__ p, double* __restrict__ sums, int mode) {
+  __shared__ double sa[kMeanBlock], sb[kMeanBlock];
+  double a = 0.0, bsum = 0.0;
+  for (int t = threadIdx.x; t < g.nn; t += kMeanBlock) {
+    const double v = (double)p[t];
+    if (mode == 0) {
+      int i, j, k;
+      decode(t, g.n1, i, j, k);
+      const double m = (double)tb->mclass[bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N)];
+      a += m * v;
+      bsum += m;
+    } else {
+      a += v;
+    }
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = bsum;
+  __syncthreads();
+  for (int s = kMeanBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  const double mean = mode == 0 ? sa[0] / sb[0] : sa[0] / (double)g.nn;
+  for (int t = threadIdx.x; t < g.nn; t += kMeanBlock) p[t] = (T)((double)p[t] - mean);
+  if (threadIdx.x == 0) {
+    sums[0] = sa[0];
+    sums[1] = sb[0];
+  }
+}
+
 // x *= 1 / sqrt(sums[slot])
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_scale(T* __restrict__ x, long n, const double* __restrict__ sums,
@@ -1724,6 +1763,18 @@ void launch_psum(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* p, 
 }
 
 template <typename T>
+void launch_mean_zero(hipStream_t s, const Geom& g, const Tables<T>* tb, T* p, double* partial, double* sums,
+                      int mode) {
+  if (g.nn <= kMeanOneBlock) {
+    KScope ks(s, KF_REDUCE, g.nn);
+    hipLaunchKernelGGL((k_mean_zero_1b<T>), dim3(1), dim3(kMeanBlock), 0, s, g, tb, p, sums, mode);
+  } else {
+    launch_psum<T>(s, g, tb, p, partial, sums, mode);
+    launch_pshift<T>(s, g, p, sums, mode);
+  }
+}
+
+template <typename T>
 void launch_pshift(hipStream_t s, const Geom& g, T* p, const double* sums, int mode) {
   KScope ks(s, KF_REDUCE, g.nn);
   HHG_LAUNCH((k_pshift<T>), nblocks(g.nn), s, g.nn, p, sums, mode);
@@ -1843,6 +1894,7 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
   template void launch_to_lattice<T>(hipStream_t, const Geom&, const T*, double*);                                  \
   template void launch_psum<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, double*, double*, int);        \
   template void launch_pshift<T>(hipStream_t, const Geom&, T*, const double*, int);                                 \
+  template void launch_mean_zero<T>(hipStream_t, const Geom&, const Tables<T>*, T*, double*, double*, int);         \
   template void launch_vsumsq<T>(hipStream_t, const Geom&, const T*, int, double*, double*);                        \
   template void launch_scale<T>(hipStream_t, T*, size_t, const double*, int);                                       \
   template void launch_fill<T>(hipStream_t, T*, size_t, T);                                                         \
