@@ -397,6 +397,7 @@ constexpr int kZmCols = 64;
 #define HHG_ZM_KC 20  // k-planes per chunk (the chunk re-reads 2 halo planes); 20 measured best of 8..48
 #endif
 constexpr int kZmOut = kZmCols - 2;  // columns written per window
+constexpr unsigned kZmF32Lds = 50000;  // dynamic LDS of the float32 launch: 3 workgroups per CU
 
 template <typename T, int G, int D, int Q>
 __device__ __forceinline__ void zm_plane(__amdgpu_buffer_rsrc_t ru, __amdgpu_buffer_rsrc_t rp, const int (&vo)[3],
@@ -1566,10 +1567,18 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     const int nmain = (ncb * nch + 7) & ~7;
     const int nextra = (nb_bnd + 3 * kZmCols - 1) / (3 * kZmCols);
     const dim3 grid(nmain + nextra), block(3 * kZmCols);
+    // float32: the kernel's registers allow 8 resident workgroups per CU, but
+    // the columns of more than 3 workgroups in flight evict each other's
+    // j-neighbour rows from L2 before they are re-read (measured on the
+    // 48-tet level-7 lattice: 8 -> 1.23 ms, 4 -> 1.16 ms, 3 -> 1.14 ms,
+    // 2 -> 1.36 ms).  Unused dynamic LDS caps residency at 3 of the CU's
+    // 160 KiB; float64 is already held to 4 by its registers and does not
+    // gain from fewer.
+    const unsigned dyn = sizeof(T) == 4 ? kZmF32Lds : 0;
     if (g.G == 1)
-      hipLaunchKernelGGL((k_apply_zm<T, 1>), grid, block, 0, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
+      hipLaunchKernelGGL((k_apply_zm<T, 1>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
     else
-      hipLaunchKernelGGL((k_apply_zm<T, 8>), grid, block, 0, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
+      hipLaunchKernelGGL((k_apply_zm<T, 8>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
   } else {
     const int nmain = (int)nblocks8(g.nn);
     const unsigned nb = (unsigned)(nmain + (nb_bnd + kBlock - 1) / kBlock);
