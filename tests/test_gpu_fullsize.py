@@ -137,24 +137,34 @@ def test_sampled_rows_reproduce_assembled_operator(vo, varnu):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("disc", [hhg.HHG_P2P1, hhg.HHG_P1P1])
-def test_apply_full_size_sampled_rows(disc):
+@pytest.mark.parametrize("disc,prec", [(hhg.HHG_P2P1, hhg.HHG_F64), (hhg.HHG_P1P1, hhg.HHG_F64),
+                                       (hhg.HHG_P2P1, hhg.HHG_F32)])
+def test_apply_full_size_sampled_rows(disc, prec):
+    """float32: the input is the float32 rounding of the float64 lattice
+    vector, which the expected rows use as well; arithmetic in float32.
+    Tolerance 3e-5 of the sum of |weight x input| of the row: a float32 sum
+    of n terms errs by at most about n u of that sum (u = 6e-8), and the
+    longest row (a P2-P1 pressure row) has ~200 terms plus a few rounded
+    scalings, so 500 u bounds every row."""
     lib = Lib(disc, 6, 7, macro_refine=1)
     torch = lib.torch
     try:
         vo = 2 if disc == hhg.HHG_P2P1 else 1
+        dt = torch.float64 if prec == hhg.HHG_F64 else torch.float32
         N, nn, vw, lw = lib.layout(7)
         assert N == 256
-        print(f"apply full size: disc {disc}, N {N}, {vw} words", flush=True)
+        print(f"apply full size: disc {disc}, prec {prec}, N {N}, {vw} words", flush=True)
         gen = torch.Generator(device=lib.dev).manual_seed(13513 + 3000)
         lat = torch.randn(lw, generator=gen, dtype=torch.float64, device=lib.dev)
-        x = torch.zeros(vw, dtype=torch.float64, device=lib.dev)
-        hhg.hhg_vec_from_lattice(lib.h, 7, lat, x)
+        if prec == hhg.HHG_F32:
+            lat = lat.float().double()
+        x = torch.zeros(vw, dtype=dt, device=lib.dev)
+        hhg.hhg_vec_from_lattice(lib.h, 7, lat, x, prec)
         y = torch.empty_like(x)
-        hhg.hhg_apply(lib.h, 7, hhg.HHG_OP_FULL, x, y)
+        hhg.hhg_apply(lib.h, 7, hhg.HHG_OP_FULL, x, y, prec)
         del x
         ylat = torch.empty_like(lat)
-        hhg.hhg_vec_to_lattice(lib.h, 7, y, ylat)
+        hhg.hhg_vec_to_lattice(lib.h, 7, y, ylat, prec)
         del y
         torch.cuda.synchronize()
 
@@ -163,7 +173,7 @@ def test_apply_full_size_sampled_rows(disc):
         got = ylat.index_select(0, torch.tensor([r[0] for r in rows] + bnd, device=lib.dev)).cpu().numpy()
         xi = sorted({t[0] for r in rows for t in r[1]})
         xv = dict(zip(xi, lat.index_select(0, torch.tensor(xi, device=lib.dev)).cpu().numpy()))
-        check_rows(rows, bnd, xv, got)
+        check_rows(rows, bnd, xv, got, rtol=1e-12 if prec == hhg.HHG_F64 else 3e-5)
     finally:
         lib.close()
 
