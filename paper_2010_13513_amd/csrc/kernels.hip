@@ -618,12 +618,15 @@ __device__ __forceinline__ void gs_edge_site(const Geom& g, const LevelConst<T>&
   const int k = 1 - dz + r / cy;
   gs_update<T, 8, VAR>(g, lc, x, b, gr, i + g.n1 * j + g.n1 * g.n1 * k, d);
 }
-template <typename T, bool VAR>
+// One instantiation per edge group: with the group a compile-time constant
+// the A-row and B^T-row loads form one straight-line batch (one memory round
+// trip); behind a runtime switch on the group they were two.
+template <typename T, bool VAR, int GR>
 __global__ void __launch_bounds__(kBlock) k_gs_edge(Geom g, LevelConst<T> lc, T* __restrict__ x,
-                                                    const T* __restrict__ b, int gr) {
+                                                    const T* __restrict__ b) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= gs_edge_count(g, gr)) return;
-  gs_edge_site<T, VAR>(g, lc, x, b, gr, t, blockIdx.y);
+  if (t >= gs_edge_count(g, GR)) return;
+  gs_edge_site<T, VAR>(g, lc, x, b, GR, t, blockIdx.y);
 }
 
 // p <- p - omega * dinv * rp (eq. uzawa-pressure with S_hat = omega^{-1} D).
@@ -1637,10 +1640,19 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* 
     const size_t n = (size_t)gs_edge_count(g, gr);
     KScope ks(s, KF_GS_EDGE, (double)n, true);
     const dim3 grid(nblocks(n), 3), block(kBlock);
-    if (lc.nu)
-      launch_timed(ks, k_gs_edge<T, true>, grid, block, s, g, lc, x, b, gr);
-    else
-      launch_timed(ks, k_gs_edge<T, false>, grid, block, s, g, lc, x, b, gr);
+#define HHG_GS_EDGE(GR)                                                               \
+  case GR:                                                                            \
+    if (lc.nu)                                                                        \
+      launch_timed(ks, k_gs_edge<T, true, GR>, grid, block, s, g, lc, x, b);          \
+    else                                                                              \
+      launch_timed(ks, k_gs_edge<T, false, GR>, grid, block, s, g, lc, x, b);         \
+    break
+    switch (gr) {
+      HHG_GS_EDGE(1); HHG_GS_EDGE(2); HHG_GS_EDGE(3); HHG_GS_EDGE(4);
+      HHG_GS_EDGE(5); HHG_GS_EDGE(6); HHG_GS_EDGE(7);
+      default: break;
+    }
+#undef HHG_GS_EDGE
   }
 }
 
