@@ -385,11 +385,17 @@ void emit_restriction(FILE* f, const char* D, int vorder) {
                "template <typename T>\n__device__ __forceinline__ T %s_RP(const T* __restrict__ p, int fb, int fi, int fj, "
                "int fk, int Nf, int s1, int s2) {\n  T a = 0;\n",
                D);
+  // Entries outside the fine lattice drop out.  Each word is read at its
+  // position clamped into the lattice (always a valid address) and the entry's
+  // weight is zeroed when the position was outside: the loads carry no branch,
+  // so they issue as one batch instead of one round trip each.
   for (auto& e : pres)
     std::fprintf(f,
-                 "  if (fi + (%d) >= 0 && fi + (%d) <= Nf && fj + (%d) >= 0 && fj + (%d) <= Nf && fk + (%d) >= 0 && fk + (%d) "
-                 "<= Nf) a += T(%s) * p[fb + (%d) + (%d) * s1 + (%d) * s2];\n",
-                 e.di, e.di, e.dj, e.dj, e.dk, e.dk, lit(e.w).c_str(), e.di, e.dj, e.dk);
+                 "  { const int ci = min(max(fi + (%d), 0), Nf), cj = min(max(fj + (%d), 0), Nf), "
+                 "ck = min(max(fk + (%d), 0), Nf);\n"
+                 "    const T v = p[fb + (ci - fi) + (cj - fj) * s1 + (ck - fk) * s2];\n"
+                 "    a += (ci == fi + (%d) && cj == fj + (%d) && ck == fk + (%d) ? T(%s) : T(0)) * v; }\n",
+                 e.di, e.dj, e.dk, e.di, e.dj, e.dk, lit(e.w).c_str());
   std::fprintf(f, "  return a;\n}\n// %zu entries\n\n", pres.size());
 }
 

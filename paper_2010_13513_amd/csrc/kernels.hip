@@ -824,8 +824,12 @@ __device__ __forceinline__ void prolong_slice(const Geom& gc, const Geom& gf, co
     const int cls = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
     const int base = (i >> 1) + gc.n1 * ((j >> 1) + gc.n1 * (k >> 1));
     T a = 0;
-    const int n = tt->pp_n[cls];
-    for (int e = 0; e < n; ++e) a += tt->pp_w[cls * 10 + e] * xc[3 * gc.vstride + base + tt->pp_off[cls * 10 + e]];
+    // all 10 table slots: the slots past a class's count hold weight 0 and
+    // offset 0 (the class's own coarse node, a valid index), so every load is
+    // unconditional and the table and value loads go out as two batches
+    // instead of two round trips per entry; the sum is unchanged
+#pragma unroll
+    for (int e = 0; e < 10; ++e) a += tt->pp_w[cls * 10 + e] * xc[3 * gc.vstride + base + tt->pp_off[cls * 10 + e]];
     const int pp = 3 * gf.vstride + t;
     xf[pp] = add ? xf[pp] + a : a;
     return;
@@ -843,10 +847,10 @@ __device__ __forceinline__ void prolong_slice(const Geom& gc, const Geom& gf, co
     cls = (X & 3) + 4 * (Y & 3) + 16 * (Z & 3);
     base = (X >> 2) + gc.n1 * ((Y >> 2) + gc.n1 * (Z >> 2));
   }
-  const int n = tt->vp_n[cls];
   const T* xd = xc + (size_t)d * gc.vstride;
   T a = 0;
-  for (int e = 0; e < n; ++e) a += tt->vp_w[cls * 10 + e] * xd[base + tt->vp_off[cls * 10 + e]];
+#pragma unroll
+  for (int e = 0; e < 10; ++e) a += tt->vp_w[cls * 10 + e] * xd[base + tt->vp_off[cls * 10 + e]];  // as above
   const int pos = d * gf.vstride + gr * gf.nn + t;
   xf[pos] = add ? xf[pos] + a : a;
 }
@@ -872,9 +876,9 @@ __device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, con
       cls = (X & 3) + 4 * (Y & 3) + 16 * (Z & 3);
       base = (X >> 2) + gc.n1 * ((Y >> 2) + gc.n1 * (Z >> 2));
     }
-    const int n = tt->vp_n[cls];
     T a0 = 0, a1 = 0, a2 = 0;
-    for (int e = 0; e < n; ++e) {
+#pragma unroll
+    for (int e = 0; e < 10; ++e) {  // all slots, as in prolong_slice
       const int o = base + tt->vp_off[cls * 10 + e];
       const T w = tt->vp_w[cls * 10 + e];
       a0 += w * xc[o];
