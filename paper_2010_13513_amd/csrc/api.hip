@@ -344,15 +344,13 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
 void build_transfer(hhg_hier h, Level& lc, Level& lf) {
   Arena& a = h->arena;
   const int G = lf.g.G;
-  const int n1c = lc.g.n1, nnc = lc.g.nn, n1f = lf.g.n1, nnf = lf.g.nn;
+  const int n1c = lc.g.n1, nnc = lc.g.nn;
   // velocity prolongation classes
   const int vorder = G == 1 ? 1 : 2;
   const int vq = vorder == 1 ? 2 : 4;  // fine positions per coarse cube edge
   const int ncls = vq * vq * vq;
-  std::vector<int> vp_off(ncls * 10, 0), vp_n(ncls, 0);
+  std::vector<int> vp_off(ncls * 10, 0);
   std::vector<double> vp_w(ncls * 10, 0.0);
-  // restriction accumulators per coarse group: (fine group, fine index offset) -> w
-  std::vector<std::map<std::tuple<int, int, int, int>, double>> racc(G);
   for (int cz = 0; cz < vq; ++cz)
     for (int cy = 0; cy < vq; ++cy)
       for (int cx = 0; cx < vq; ++cx) {
@@ -366,30 +364,11 @@ void build_transfer(hhg_hier h, Level& lc, Level& lf) {
           vp_off[cls * 10 + e] = gc * nnc + lin(oi, oj, ok, n1c);
           vp_w[cls * 10 + e] = std::get<4>(w);
           ++e;
-          // transpose: fine site relative to the coarse site
-          const int c[3] = {cx, cy, cz};
-          const int o[3] = {oi, oj, ok};
-          int fofs[3];
-          int fpar[3];
-          for (int d = 0; d < 3; ++d) {
-            if (vorder == 2) {
-              const int delta = c[d] - 4 * o[d] - 2 * kGroupDir[gc][d];  // fine doubled, rel. to 2 S_c
-              fpar[d] = delta & 1;
-              fofs[d] = kGroupDir[gc][d] + (delta >> 1);  // fine index rel. to 2 (i,j,k)
-            } else {
-              fpar[d] = 0;
-              fofs[d] = c[d] - 2 * o[d];
-            }
-          }
-          const int fg = vorder == 2 ? group_of_parity(fpar[0], fpar[1], fpar[2]) : 0;
-          racc[gc][std::make_tuple(fg, fofs[0], fofs[1], fofs[2])] += std::get<4>(w);
         }
-        vp_n[cls] = e;
       }
-  // pressure (linear) prolongation classes and restriction
-  std::vector<int> pp_off(80, 0), pp_n(8, 0);
+  // pressure (linear) prolongation classes
+  std::vector<int> pp_off(80, 0);
   std::vector<double> pp_w(80, 0.0);
-  std::map<std::tuple<int, int, int>, double> pracc;
   for (int cz = 0; cz < 2; ++cz)
     for (int cy = 0; cy < 2; ++cy)
       for (int cx = 0; cx < 2; ++cx) {
@@ -402,38 +381,15 @@ void build_transfer(hhg_hier h, Level& lc, Level& lf) {
           pp_off[cls * 10 + e] = lin(oi, oj, ok, n1c);
           pp_w[cls * 10 + e] = std::get<4>(w);
           ++e;
-          pracc[std::make_tuple(cx - 2 * oi, cy - 2 * oj, cz - 2 * ok)] += std::get<4>(w);
         }
-        pp_n[cls] = e;
       }
   auto mk = [&](auto& tt, auto tag) {
     using T = decltype(tag);
     std::vector<T> vw(vp_w.begin(), vp_w.end()), pw(pp_w.begin(), pp_w.end());
     tt.vp_off = a.upload(vp_off);
     tt.vp_w = a.upload(vw);
-    tt.vp_n = a.upload(vp_n);
     tt.pp_off = a.upload(pp_off);
     tt.pp_w = a.upload(pw);
-    tt.pp_n = a.upload(pp_n);
-    for (int gc = 0; gc < G; ++gc) {
-      HostStencil r;
-      for (auto& kv : racc[gc]) {
-        const int fg = std::get<0>(kv.first);
-        r.off.push_back(fg * nnf + lin(std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), n1f));
-        r.w.push_back(kv.second);
-      }
-      tt.r[gc] = upload_stencil<T>(a, r);
-    }
-    HostStencil rp;
-    std::vector<int> rpd;
-    for (auto& kv : pracc) {
-      const int di = std::get<0>(kv.first), dj = std::get<1>(kv.first), dk = std::get<2>(kv.first);
-      rp.off.push_back(lin(di, dj, dk, n1f));
-      rp.w.push_back(kv.second);
-      rpd.push_back((di + 2) | ((dj + 2) << 4) | ((dk + 2) << 8));
-    }
-    tt.rp = upload_stencil<T>(a, rp);
-    tt.rp_d = a.upload(rpd);
   };
   TransferTables<double> t64{};
   TransferTables<float> t32{};

@@ -78,23 +78,17 @@ struct KScope {
 // since the last read; synchronises the recorded events.
 void timer_read(int family, double* total_ms, int* launches, double* units);
 
-// Transfer tables between level l-1 (coarse) and l (fine) for one field kind.
-// Prolongation: fine class (S & 3 per coordinate, 64 classes for quadratic,
-// 8 for linear on the P1 lattice) -> up to 10 (coarse offset, weight) pairs,
-// offsets relative to the coarse cube (S >> 2 or S >> 1) position in group 0.
-// Restriction: coarse group -> (fine offset, weight) relative to the fine index
-// 2 (i, j, k) in group 0.
+// Prolongation tables between level l-1 (coarse) and l (fine): fine class
+// (S & 3 per coordinate, 64 classes for quadratic, 8 for linear on the P1
+// lattice) -> 10 (coarse offset, weight) slots, offsets relative to the coarse
+// cube (S >> 2 or S >> 1) position in group 0; slots past the class's weights
+// hold offset 0 and weight 0.  (The restriction is generated code.)
 template <typename T>
 struct TransferTables {
   const int* vp_off;   // velocity prolongation [ncls][10], ncls = 64 (P2) or 8 (P1)
   const T* vp_w;
-  const int* vp_n;
   const int* pp_off;   // P1 pressure prolongation [8][10]
   const T* pp_w;
-  const int* pp_n;
-  DStencil<T> r[8];    // restriction per coarse velocity group (interior rows)
-  DStencil<T> rp;      // linear restriction of the P1 pressure (offsets into fine array)
-  const int* rp_d;     // packed (di+2, dj+2, dk+2) of rp entries, for clipping
 };
 
 // A V-cycle over the small levels lmin..ltop run by one workgroup (one

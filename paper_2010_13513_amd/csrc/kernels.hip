@@ -1174,41 +1174,6 @@ __device__ __forceinline__ T prow_bnd_table(const Geom& g, const Tables<T>* __re
   return acc;
 }
 
-template <typename T, int G>
-__device__ __forceinline__ void restrict_table(const Geom& gf, const Geom& gc, const TransferTables<T>* __restrict__ tt,
-                                               const T* __restrict__ rf, T* __restrict__ rc, int t, int gr) {
-  int i, j, k;
-  decode(t, gc.n1, i, j, k);
-  const int fbase = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
-  if (gr == G) {
-    T acc = 0;
-    const int Nf = gf.N, n = tt->rp.n;
-    for (int e = 0; e < n; ++e) {
-      const int cd = tt->rp_d[e];
-      const int fi = 2 * i + (cd & 15) - 2, fj = 2 * j + ((cd >> 4) & 15) - 2, fk = 2 * k + ((cd >> 8) & 15) - 2;
-      if (fi < 0 || fj < 0 || fk < 0 || fi > Nf || fj > Nf || fk > Nf) continue;
-      acc += tt->rp.w[e] * rf[3 * gf.vstride + fbase + tt->rp.off[e]];
-    }
-    rc[3 * gc.vstride + t] = acc;
-    return;
-  }
-  T a0 = 0, a1 = 0, a2 = 0;
-  if (vel_interior<G>(gr, i, j, k, gc.N)) {
-    const int n = tt->r[gr].n;
-    const int* __restrict__ off = tt->r[gr].off;
-    const T* __restrict__ w = tt->r[gr].w;
-    for (int e = 0; e < n; ++e) {
-      const int o = fbase + off[e];
-      a0 += w[e] * rf[o];
-      a1 += w[e] * rf[gf.vstride + o];
-      a2 += w[e] * rf[2 * gf.vstride + o];
-    }
-  }
-  const int pos = gr * gc.nn + t;
-  rc[pos] = a0;
-  rc[gc.vstride + pos] = a1;
-  rc[2 * gc.vstride + pos] = a2;
-}
 
 // Round a float32 value to the nearest bfloat16 (ties to even), kept as a
 // float32 whose low 16 bits are zero; NaN stays NaN.
@@ -1402,8 +1367,8 @@ __global__ void __launch_bounds__(kSmallBlock) k_vcycle_small(const SmallLevel<T
     small_round<T>(q < sc.q16, R(q), 0, 0, vw(q), 1);
     V cb = B(q - 1);
     V r = R(q);
-    for (int w = threadIdx.x; w < (G + 1) * C.g.nn; w += kSmallBlock)
-      restrict_table<T, G>(L.g, C.g, L.tt, (const T*)r, (T*)cb, w % C.g.nn, w / C.g.nn);
+    for (int w = threadIdx.x; w < (3 * G + 1) * C.g.nn; w += kSmallBlock)
+      restrict_site<T, G>(L.g, C.g, (const T*)r, (T*)cb, w % C.g.nn, w / C.g.nn);
     __syncthreads();
     small_round<T>(q - 1 < sc.q16, cb, 0, 0, vw(q - 1), 1);
     small_pshift<T>(C, cb + 3 * (size_t)C.g.vstride, 1, red);
