@@ -1142,11 +1142,11 @@ __global__ void __launch_bounds__(kBlock) k_axpy(T* __restrict__ y, const T* __r
 }
 
 // ------------------------------------------------- small-level V-cycle
-// Table-driven forms of the boundary pressure rows and of the restriction:
-// the generated unrolled forms are fastest in grid-wide launches, but in the
-// one-workgroup cycle these compact loops measured faster (its many phases
-// run a lot of distinct code; the Gauss-Seidel and interior rows stay
-// generated, where independent unrolled loads win over table loops).
+// Table-driven form of the boundary pressure rows: the generated per-class
+// rows are fastest in grid-wide launches, but in the one-workgroup cycle
+// this compact loop measured faster (its many phases run a lot of distinct
+// code).  The restriction, the Gauss-Seidel and the interior rows there are
+// the generated forms, whose independent unrolled loads win over table loops.
 template <typename T>
 __device__ __forceinline__ T prow_bnd_table(const Geom& g, const Tables<T>* __restrict__ tb, const T* __restrict__ x,
                                             int opmask, int node) {
