@@ -138,3 +138,77 @@ def test_local_p2_stiffness_reference_values():
     vol = 1.0 / 6.0
     assert np.allclose(load[:4], -vol / 20.0, atol=1e-16)
     assert np.allclose(load[4:], vol / 5.0, atol=1e-16)
+
+
+# ------------------------------------------------------ variable viscosity
+# Reading of the paper's operator with a viscosity field (not in the paper's
+# experiments): a_ij = sum_T nu_T int_T grad phi_i . grad phi_j per velocity
+# component, nu_T the mean of the four vertex values of nu.  For a linear nu
+# that mean is the exact element mean, which gives closed forms.
+def _nu_linear(x, y, z):
+    return 1.0 + 2.0 * x + 3.0 * y + 5.0 * z          # grad nu = (2, 3, 5), int_cube nu = 6
+
+
+def _nu_level(N, vorder, fn):
+    cp = mesh.p1_coords(N) / float(N)
+    return fe.Level(N, vorder, fn(cp[:, 0], cp[:, 1], cp[:, 2]))
+
+
+def test_variable_viscosity_p1_rows_linear_nu():
+    """P1, linear nu, linear q: int nu grad phi_i . grad q = -(grad nu . grad q)
+    int phi_i on interior rows (integration by parts, no boundary term), and
+    int phi_i is the lumped mass."""
+    N = 4
+    lev = _nu_level(N, 1, _nu_linear)
+    c = lev.vpos()
+    q = lambda x, y, z: 2 * x - y + 3 * z + 0.25              # grad nu . grad q = 4 - 3 + 15 = 16
+    got = (lev.A @ _poly_vals(c, q))[lev.vint]
+    want = -16.0 * lev.ML[lev.vint]
+    assert np.allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("vorder", [1, 2])
+def test_variable_viscosity_bilinear_form_linear_nu(vorder):
+    """I(r)^T A(nu) I(q) = (grad r . grad q) int_cube nu for linear r, q (both
+    in the element space) and linear nu: 6 * (2 - 2 - 1) = -6."""
+    N = 3
+    lev = _nu_level(N, vorder, _nu_linear)
+    c = lev.vpos()
+    r = lambda x, y, z: x - 2 * y + z
+    q = lambda x, y, z: 2 * x + y - z + 1.0                    # grad r . grad q = 2 - 2 - 1 = -1
+    val = _poly_vals(c, r) @ (lev.A @ _poly_vals(c, q))
+    assert abs(val - (-6.0)) < 1e-12
+
+
+def test_variable_viscosity_p2_vertex_rows_vanish():
+    """P2, any element-wise constant nu, linear q: the integral of the gradient
+    of a quadratic vertex basis function over each element is zero
+    (int (4 lam - 1) = 0), so A(nu) I(q) vanishes on the vertex rows; the
+    edge rows do not (they carry nu_T |T| grad q . (grad lam_a + grad lam_b))."""
+    N = 4
+    g = np.random.default_rng(5)
+    nu_nodes = np.exp(g.standard_normal((N + 1) ** 3))
+    lev = fe.Level(N, 2, nu_nodes)
+    c = lev.vpos()
+    q = lambda x, y, z: 3 * x - 2 * y + 0.5 * z
+    Aq = lev.A @ _poly_vals(c, q)
+    vert = np.all(lev.vcoords % 2 == 0, axis=1) & lev.vint
+    edge = ~np.all(lev.vcoords % 2 == 0, axis=1) & lev.vint
+    assert np.abs(Aq[vert]).max() < 1e-13
+    assert np.abs(Aq[edge]).max() > 1e-3
+
+
+@pytest.mark.parametrize("vorder", [1, 2])
+def test_variable_viscosity_scaling_symmetry_row_sums(vorder):
+    """A(c 1) = c A(1); A(nu) symmetric with zero row sums for a random
+    positive nu; A(nu) with nu = 1 equals the constant-coefficient matrix."""
+    N = 3
+    n1 = (N + 1) ** 3
+    A1 = fe.Level(N, vorder).A
+    Ac = fe.Level(N, vorder, np.full(n1, 3.7)).A
+    assert abs(Ac - 3.7 * A1).max() < 1e-13 * abs(Ac).max()
+    assert abs(fe.Level(N, vorder, np.ones(n1)).A - A1).max() < 1e-15 * abs(A1).max()
+    nu = np.exp(np.random.default_rng(7).standard_normal(n1))
+    A = fe.Level(N, vorder, nu).A
+    assert abs(A - A.T).max() < 1e-14 * abs(A).max()
+    assert np.abs(A @ np.ones(A.shape[0])).max() < 1e-12 * abs(A).max()

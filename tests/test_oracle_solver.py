@@ -277,3 +277,24 @@ def test_fmg_reaches_discretisation_accuracy():
         x = Hf.fmg(prob, mg.Params(*s, omega_inv=om))
         eu, ep = mg.l2_errors(H.S[L + 1], H.T[L + 1], x, prob)
         assert eu / eud < gmax, s
+
+
+# ------------------------------------------------------------- metrics
+@pytest.mark.parametrize("vorder", [1, 2])
+def test_relative_error_closed_forms(vorder):
+    """eq. relative-error in the consistent-mass norm: for fields inside the
+    element spaces the norms are exact integrals.  Reference u = (x, y, z)
+    (sum of int x^2 = 1), p = x (int = 1/3); perturbation e_u = (q, 0, 0) with
+    q = y z (P2, int = 1/9) or q = y (P1, int = 1/3), e_p = y - 1/2 (int =
+    1/12): delta_u = 1/3 or sqrt(1/3), delta_p = 1/2; and delta(2 x, x) = 1."""
+    S = Stokes(fe.Level(3, vorder))
+    ref = S.interpolate(lambda x, y, z: np.stack([x, y, z]), lambda x, y, z: x)
+    if vorder == 2:
+        eu, want_u = (lambda x, y, z: np.stack([y * z, 0 * x, 0 * x])), 1.0 / 3.0
+    else:
+        eu, want_u = (lambda x, y, z: np.stack([y, 0 * x, 0 * x])), np.sqrt(1.0 / 3.0)
+    e = S.interpolate(eu, lambda x, y, z: y - 0.5)
+    du, dp = mg.relative_error(S, ref + e, ref)
+    assert abs(du - want_u) < 1e-13
+    assert abs(dp - 0.5) < 1e-13
+    assert np.allclose(mg.relative_error(S, 2 * ref, ref), (1.0, 1.0), rtol=0, atol=1e-14)
