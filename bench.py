@@ -95,8 +95,10 @@ def main():
         print(json.dumps({"apply_roofline": res}), flush=True)
         hhg.hhg_ctx_destroy(ctx)
         return
-    H = hhg.hhg_hier_create(ctx, hhg.HHG_P2P1, 0, lmin, L, hhg.HHG_SCHUR_SD)
-    Ev = hhg.hhg_hier_create(ctx, hhg.HHG_P2P1, 0, L, L + 1, hhg.HHG_SCHUR_SD)   # error evaluation only
+    mesh = hhg.hhg_mesh_cube(ctx, 0)
+    H = hhg.hhg_hier_create(mesh, hhg.HHG_P2P1, lmin, L, hhg.HHG_SCHUR_SD)
+    Ev = hhg.hhg_hier_create(mesh, hhg.HHG_P2P1, L, L + 1, hhg.HHG_SCHUR_SD)   # error evaluation only
+    hhg.hhg_mesh_destroy(mesh)
 
     def lattice_fields(level, fn_u, fn_p=None):
         N = 2 ** level
@@ -235,7 +237,9 @@ def bench_apply(torch, hhg, dev, stream, ctx, level=7, reps=20):
     """y = calA x, P2-P1 on the 48-tet cube at the given macro level
     (N = 2^(level+1) intervals), float64 and float32, N(0,1) input."""
     res = {}
-    H = hhg.hhg_hier_create(ctx, hhg.HHG_P2P1, 1, level - 1, level, hhg.HHG_SCHUR_SD)
+    mesh = hhg.hhg_mesh_cube(ctx, 1)
+    H = hhg.hhg_hier_create(mesh, hhg.HHG_P2P1, level - 1, level, hhg.HHG_SCHUR_SD)
+    hhg.hhg_mesh_destroy(mesh)
     try:
         N, nn, vw, lw = hhg.hhg_vec_layout(H, level)
         sites = (2 * N + 1) ** 3

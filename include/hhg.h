@@ -8,11 +8,12 @@
  * stabilisation eq. pspg (P1-P1) or C = 0 (P2-P1 Taylor-Hood).  Smoother:
  * Sec. 3.2, eq. uzawa-iteration.  Transfer: Sec. 3.3.  Cycles: Alg. fmg.
  *
- * Domain and hierarchy.  The macro mesh is the unit cube split into the six
- * Kuhn tetrahedra (macro_refine = 0) or the 48 tetrahedra of one Bey step of it
- * (macro_refine = 1).  Bey refinement keeps Kuhn simplices, so level l is the
- * Freudenthal lattice with N = 2^(l + macro_refine) intervals per cube edge and
- * every macro-primitive's refined DoFs are sub-lattices of it.  Velocity is
+ * Domain and hierarchy.  The macro mesh (hhg_mesh) is the unit cube split into
+ * the six Kuhn tetrahedra (macro_refine = 0) or the 48 tetrahedra of one Bey
+ * step of it (macro_refine = 1).  Bey refinement keeps Kuhn simplices, so
+ * level l is the Freudenthal lattice with N = 2^(l + macro_refine) intervals
+ * per cube edge and every macro-primitive's refined DoFs are sub-lattices of
+ * it.  Velocity is
  * Dirichlet on the whole boundary; the pressure is fixed by int p = 0.
  *
  * Vectors.  All vectors are caller-owned device buffers holding every DoF of a
@@ -61,11 +62,14 @@ enum {
 };
 
 typedef struct hhg_ctx_s* hhg_ctx;
+typedef struct hhg_mesh_s* hhg_mesh;
 typedef struct hhg_hier_s* hhg_hier;
 typedef struct hhg_mlp_s* hhg_mlp;
 
 typedef enum { HHG_P1P1 = 0, HHG_P2P1 = 1 } hhg_disc;
-typedef enum { HHG_F64 = 0, HHG_F32 = 1 } hhg_prec;
+/* Storage precision of a vector.  HHG_BF16 (bfloat16 words) is accepted only
+ * where a call says so; elsewhere it is refused with HHG_ERR_PREC. */
+typedef enum { HHG_F64 = 0, HHG_F32 = 1, HHG_BF16 = 2 } hhg_prec;
 /* Operator blocks of eq. stokes-discrete; MASS = consistent velocity mass and
  * P1 pressure mass (used for right-hand sides and error norms). */
 typedef enum { HHG_OP_FULL = 0, HHG_OP_A = 1, HHG_OP_BT = 2, HHG_OP_B = 3, HHG_OP_C = 4, HHG_OP_MASS = 5 } hhg_op;
@@ -97,6 +101,8 @@ typedef struct {
   double res_u, res_p;    /* Euclidean norms of the final residual blocks    */
   double rel_res;         /* ||r|| / ||b||                                   */
   double work_units;      /* Sec. 4 model, in W(calA_L)                      */
+  double seconds;         /* device time of the call on the context stream
+                             (HIP events around its work)                   */
   int fallbacks;          /* learned coarse solve switched off (hhg_hier_set_mlp) */
 } hhg_stats;
 
@@ -108,6 +114,32 @@ hhg_status hhg_ctx_set_stream(hhg_ctx ctx, void* stream);
 hhg_status hhg_ctx_destroy(hhg_ctx ctx);
 const char* hhg_last_error(void);
 
+/* ------------------------------------------------------------ macro mesh */
+/* The macro mesh T_0 of Sec. 2 (host data; no device memory).
+ *
+ * hhg_mesh_cube: the unit cube split into the six Kuhn tetrahedra sharing the
+ * diagonal (0,0,0)-(1,1,1) (macro_refine = 0), or the 48 tetrahedra of one
+ * Bey refinement step of them (macro_refine = 1, the six Kuhn tetrahedra of
+ * each of the eight half-size sub-cubes).
+ *
+ * hhg_mesh_create: an explicit T_0.  xyz: host, nv x 3 doubles (vertex
+ * coordinates); tet: host, nt x 4 vertex indices (any vertex order within a
+ * tetrahedron, any order of the tetrahedra).  Copied.  The lattice layout of
+ * this library needs a T_0 whose uniform refinement is one Freudenthal
+ * lattice: the call accepts a partition of the unit cube into the Kuhn
+ * tetrahedra of its N^3 sub-cubes, N = 1 or 2 (6 or 48 tetrahedra; every
+ * vertex on the lattice within 1e-9, no duplicate or unused vertex, every
+ * tetrahedron a Kuhn simplex, no tetrahedron twice), and returns
+ * HHG_ERR_ARG with a message naming the first violation for any other mesh.
+ *
+ * A hierarchy copies what it needs: the mesh may be destroyed after
+ * hhg_hier_create.  hhg_mesh_info: vertex and tetrahedron counts and the
+ * macro refinement (N = 2^macro_refine sub-cubes per edge). */
+hhg_status hhg_mesh_cube(hhg_ctx ctx, int macro_refine, hhg_mesh* out);
+hhg_status hhg_mesh_create(hhg_ctx ctx, const double* xyz, int nv, const int* tet, int nt, hhg_mesh* out);
+hhg_status hhg_mesh_info(hhg_mesh mesh, int* nv, int* nt, int* macro_refine);
+hhg_status hhg_mesh_destroy(hhg_mesh mesh);
+
 /* ------------------------------------------------------------- hierarchy */
 /* Build levels lmin..lmax (lmin is the coarsest, solved directly when it has
  * at most 2048 unknowns; otherwise hhg_coarse_solve, hhg_vcycle and
@@ -118,12 +150,12 @@ const char* hhg_last_error(void);
  * macro-primitive), the dense pseudo-inverse of the coarsest operator, and
  * library work vectors (one residual per level plus the V-cycle and FMG
  * vectors of the coarser levels), all in the given working precision.
- * Limits: 0 <= lmin < lmax, N(lmax) <= 512 (P1-P1) or 256 (P2-P1), macro_refine
- * in {0, 1};
- * Taylor-Hood needs N(lmin) >= 2 (a level-0 Taylor-Hood system on six
- * tetrahedra has spurious pressure modes).  Ownership: the hierarchy. */
-hhg_status hhg_hier_create(hhg_ctx ctx, hhg_disc disc, int macro_refine, int lmin, int lmax,
-                           hhg_schur schur, hhg_hier* out);
+ * Level l of a mesh with macro refinement r has N = 2^(l + r) intervals per
+ * cube edge.  Limits: 0 <= lmin < lmax, N(lmax) <= 512 (P1-P1) or 256
+ * (P2-P1); Taylor-Hood needs N(lmin) >= 2 (a level-0 Taylor-Hood system on
+ * six tetrahedra has spurious pressure modes).  The hierarchy runs on the
+ * mesh's context.  Ownership: the hierarchy. */
+hhg_status hhg_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg_schur schur, hhg_hier* out);
 hhg_status hhg_hier_destroy(hhg_hier h);
 
 /* Sizes of one level: N, words per lattice array (nn = (N+1)^3), words of a

@@ -116,6 +116,15 @@ struct hhg_ctx_s {
   hipStream_t capture = nullptr;  // private stream for HIP-graph capture
 };
 
+// Macro mesh T_0 (host data): vertex coordinates, tetrahedra, and the number
+// of Bey steps between the six-tetrahedron Kuhn cube and it.
+struct hhg_mesh_s {
+  hhg_ctx ctx = nullptr;
+  int mr = 0;
+  std::vector<double> xyz;
+  std::vector<int> tet;
+};
+
 struct hhg_hier_s {
   hhg_ctx ctx = nullptr;
   int disc = 0, mr = 0, lmin = 0, lmax = 0, schur = 0;
@@ -156,6 +165,8 @@ struct hhg_hier_s {
   // cached HIP graph of a fixed-work FMG solve (key: vectors + parameters)
   hipGraphExec_t fmg_exec = nullptr;
   std::vector<unsigned char> fmg_key;
+  // events bracketing a call that reports statistics (hhg_stats.seconds)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hhg::Level& L(int l) { return levels[l - lmin]; }
 };
 
@@ -888,6 +899,123 @@ void fmg_body(hhg_hier h, double* x, BL bl, const hhg_solver_params& p) {
     }
 }
 
+// The six Kuhn simplices of the cube [0,1]^3: vertices 0, e_a, e_a + e_b,
+// (1,1,1) for the permutations (a, b, c) of the axes.
+const int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+// Kuhn partition of the unit cube into N^3 sub-cubes of 6 tetrahedra each.
+void kuhn_cube_mesh(int N, std::vector<double>& xyz, std::vector<int>& tet) {
+  const int n1 = N + 1;
+  xyz.clear();
+  tet.clear();
+  for (int k = 0; k <= N; ++k)
+    for (int j = 0; j <= N; ++j)
+      for (int i = 0; i <= N; ++i) {
+        xyz.push_back((double)i / N);
+        xyz.push_back((double)j / N);
+        xyz.push_back((double)k / N);
+      }
+  for (int k = 0; k < N; ++k)
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i)
+        for (const auto& pm : kPerm) {
+          int c[3] = {i, j, k};
+          tet.push_back(c[0] + n1 * (c[1] + n1 * c[2]));
+          for (int s = 0; s < 3; ++s) {
+            ++c[pm[s]];
+            tet.push_back(c[0] + n1 * (c[1] + n1 * c[2]));
+          }
+        }
+}
+
+// N if (xyz, tet) is the Kuhn partition of the unit cube into N^3 sub-cubes
+// (N = 1 or 2) in any vertex and tetrahedron order; otherwise throws
+// HHG_ERR_ARG naming the first violation.
+int kuhn_cube_refinement(const double* xyz, int nv, const int* tet, int nt) {
+  HHG_REQUIRE(nt == 6 || nt == 48, HHG_ERR_ARG,
+              "mesh: only the Kuhn partitions of the unit cube (6 or 48 tetrahedra) are supported, got " +
+                  std::to_string(nt) + " tetrahedra");
+  const int N = nt == 6 ? 1 : 2, n1 = N + 1;
+  HHG_REQUIRE(nv == n1 * n1 * n1, HHG_ERR_ARG,
+              "mesh: expected " + std::to_string(n1 * n1 * n1) + " vertices, got " + std::to_string(nv));
+  std::vector<int> lat(nv);
+  std::vector<int> seen(nv, 0);
+  for (int v = 0; v < nv; ++v) {
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+      const double t = xyz[3 * v + d] * N;
+      c[d] = (int)std::lround(t);
+      HHG_REQUIRE(std::isfinite(t) && std::fabs(t - c[d]) <= 1e-9 && c[d] >= 0 && c[d] <= N, HHG_ERR_ARG,
+                  "mesh: vertex " + std::to_string(v) + " is not a point of the unit-cube lattice");
+    }
+    lat[v] = c[0] + n1 * (c[1] + n1 * c[2]);
+    HHG_REQUIRE(!seen[lat[v]], HHG_ERR_ARG, "mesh: vertex " + std::to_string(v) + " duplicates another vertex");
+    seen[lat[v]] = 1;
+  }
+  std::vector<int> used(nv, 0), cell_perm(6 * N * N * N, 0);
+  for (int t = 0; t < nt; ++t) {
+    int p[4][3];
+    for (int q = 0; q < 4; ++q) {
+      const int v = tet[4 * t + q];
+      HHG_REQUIRE(v >= 0 && v < nv, HHG_ERR_ARG, "mesh: tetrahedron " + std::to_string(t) + " has a bad vertex index");
+      used[v] = 1;
+      const int L = lat[v];
+      p[q][0] = L % n1, p[q][1] = (L / n1) % n1, p[q][2] = L / (n1 * n1);
+    }
+    // sort the corners by coordinate sum: a Kuhn simplex has one corner at
+    // each sum b, b+1, b+2, b+3, each a unit step from the one before
+    int ord[4] = {0, 1, 2, 3};
+    std::sort(ord, ord + 4, [&](int a, int b) {
+      return p[a][0] + p[a][1] + p[a][2] < p[b][0] + p[b][1] + p[b][2];
+    });
+    int axis[3];
+    bool ok = true;
+    for (int s = 0; s < 3 && ok; ++s) {
+      int nd = 0, ax = -1;
+      for (int d = 0; d < 3; ++d) {
+        const int df = p[ord[s + 1]][d] - p[ord[s]][d];
+        if (df == 1) ++nd, ax = d;
+        else if (df != 0) ok = false;
+      }
+      ok = ok && nd == 1;
+      axis[s] = ax;
+    }
+    ok = ok && axis[0] != axis[1] && axis[1] != axis[2] && axis[0] != axis[2];
+    HHG_REQUIRE(ok, HHG_ERR_ARG, "mesh: tetrahedron " + std::to_string(t) + " is not a Kuhn simplex of a sub-cube");
+    int perm = -1;
+    for (int q = 0; q < 6; ++q)
+      if (kPerm[q][0] == axis[0] && kPerm[q][1] == axis[1]) perm = q;
+    const int* b = p[ord[0]];
+    const int cell = b[0] + N * (b[1] + N * b[2]);
+    HHG_REQUIRE(!cell_perm[6 * cell + perm], HHG_ERR_ARG,
+                "mesh: tetrahedron " + std::to_string(t) + " appears twice");
+    cell_perm[6 * cell + perm] = 1;
+  }
+  for (int v = 0; v < nv; ++v)
+    HHG_REQUIRE(used[v], HHG_ERR_ARG, "mesh: vertex " + std::to_string(v) + " belongs to no tetrahedron");
+  return N;
+}
+
+// Device time of a call: start() records an event on the context stream,
+// seconds() records the end event and waits for it.
+struct CallClock {
+  hhg_hier h;
+  explicit CallClock(hhg_hier hh) : h(hh) {
+    if (!h->ev0) {
+      HHG_CHECK_HIP(hipEventCreate(&h->ev0));
+      HHG_CHECK_HIP(hipEventCreate(&h->ev1));
+    }
+    HHG_CHECK_HIP(hipEventRecord(h->ev0, h->ctx->stream));
+  }
+  double seconds() {
+    HHG_CHECK_HIP(hipEventRecord(h->ev1, h->ctx->stream));
+    HHG_CHECK_HIP(hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    HHG_CHECK_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    return 1e-3 * ms;
+  }
+};
+
 hhg_hier check_level(hhg_hier h, int l) {
   HHG_REQUIRE(h != nullptr, HHG_ERR_ARG, "null hierarchy");
   HHG_REQUIRE(l >= h->lmin && l <= h->lmax, HHG_ERR_ARG, "level out of range");
@@ -948,12 +1076,50 @@ hhg_status hhg_ctx_destroy(hhg_ctx ctx) {
   });
 }
 
-hhg_status hhg_hier_create(hhg_ctx ctx, hhg_disc disc, int macro_refine, int lmin, int lmax, hhg_schur schur,
-                           hhg_hier* out) {
+hhg_status hhg_mesh_cube(hhg_ctx ctx, int macro_refine, hhg_mesh* out) {
   return guard([&] {
     HHG_REQUIRE(ctx && out, HHG_ERR_ARG, "null argument");
-    HHG_REQUIRE(disc == HHG_P1P1 || disc == HHG_P2P1, HHG_ERR_ARG, "unknown discretisation");
     HHG_REQUIRE(macro_refine == 0 || macro_refine == 1, HHG_ERR_ARG, "macro_refine must be 0 or 1");
+    std::unique_ptr<hhg_mesh_s> m(new hhg_mesh_s);
+    m->ctx = ctx;
+    m->mr = macro_refine;
+    kuhn_cube_mesh(1 << macro_refine, m->xyz, m->tet);
+    *out = m.release();
+  });
+}
+
+hhg_status hhg_mesh_create(hhg_ctx ctx, const double* xyz, int nv, const int* tet, int nt, hhg_mesh* out) {
+  return guard([&] {
+    HHG_REQUIRE(ctx && out && xyz && tet && nv > 0 && nt > 0, HHG_ERR_ARG, "null or empty argument");
+    const int N = kuhn_cube_refinement(xyz, nv, tet, nt);
+    std::unique_ptr<hhg_mesh_s> m(new hhg_mesh_s);
+    m->ctx = ctx;
+    m->mr = N == 1 ? 0 : 1;
+    m->xyz.assign(xyz, xyz + 3 * (size_t)nv);
+    m->tet.assign(tet, tet + 4 * (size_t)nt);
+    *out = m.release();
+  });
+}
+
+hhg_status hhg_mesh_info(hhg_mesh mesh, int* nv, int* nt, int* macro_refine) {
+  return guard([&] {
+    HHG_REQUIRE(mesh, HHG_ERR_ARG, "null mesh");
+    if (nv) *nv = (int)(mesh->xyz.size() / 3);
+    if (nt) *nt = (int)(mesh->tet.size() / 4);
+    if (macro_refine) *macro_refine = mesh->mr;
+  });
+}
+
+hhg_status hhg_mesh_destroy(hhg_mesh mesh) {
+  return guard([&] { delete mesh; });
+}
+
+hhg_status hhg_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg_schur schur, hhg_hier* out) {
+  return guard([&] {
+    HHG_REQUIRE(mesh && out, HHG_ERR_ARG, "null argument");
+    hhg_ctx ctx = mesh->ctx;
+    const int macro_refine = mesh->mr;
+    HHG_REQUIRE(disc == HHG_P1P1 || disc == HHG_P2P1, HHG_ERR_ARG, "unknown discretisation");
     HHG_REQUIRE(lmin >= 0 && lmin < lmax, HHG_ERR_ARG, "need 0 <= lmin < lmax");
     HHG_REQUIRE((1 << (lmax + macro_refine)) <= (disc == HHG_P1P1 ? 512 : 256), HHG_ERR_ARG,
                 "finest level too large (N <= 512 for P1-P1, N <= 256 for P2-P1)");
@@ -1014,6 +1180,8 @@ hhg_status hhg_hier_destroy(hhg_hier h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->ctx->stream);
     if (h->fmg_exec) (void)hipGraphExecDestroy(h->fmg_exec);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->hsums) (void)hipHostFree(h->hsums);
     delete h;
   });
@@ -1314,6 +1482,7 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
     const double* b = (const double*)bv;
     if (inner_prec == HHG_F32) ensure_f32_vectors(h);
     refresh_small(h);
+    CallClock clock(h);
     double bu, bp, ru = 0, rp = 0;
     norms<double>(h, L, b, &bu, &bp);
     const double bn = std::sqrt(bu * bu + bp * bp);
@@ -1349,6 +1518,7 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
       stats->res_p = rp;
       stats->rel_res = bn > 0 ? std::sqrt(ru * ru + rp * rp) / bn : 0.0;
       stats->work_units = cycles * vcycle_work_units(h, *prm);
+      stats->seconds = clock.seconds();
       stats->fallbacks = 0;
     }
     if (std::sqrt(ru * ru + rp * rp) > rtol * bn)
@@ -1673,6 +1843,7 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, cons
       HHG_CHECK_HIP(hipGraphLaunch(h->fmg_exec, S(h)));
       return;
     }
+    CallClock clock(h);
     fmg_body(h, x, bl, p);
     Level& top = h->L(h->lmax);
     int cycles = p.kappa + (p.rtol > 0.0 ? 0 : p.extra_cycles);
@@ -1718,6 +1889,7 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, cons
       stats->res_p = rp;
       stats->rel_res = bn > 0 ? std::sqrt(ru * ru + rp * rp) / bn : 0.0;
       stats->work_units = fmg_work_units(h, p) + (cycles - p.kappa) * vcycle_work_units(h, p);
+      stats->seconds = clock.seconds();
       stats->fallbacks = fallbacks;
     }
     if (p.rtol > 0.0 && std::sqrt(ru * ru + rp * rp) > p.rtol * bn)

@@ -13,13 +13,14 @@ LIB_PATH = os.path.join(HERE, "libhhg.so")
 
 HHG_OK, HHG_ERR_ARG, HHG_ERR_PREC, HHG_ERR_HIP, HHG_ERR_OOM, HHG_ERR_NOT_CONVERGED, HHG_ERR_STATE = range(7)
 HHG_P1P1, HHG_P2P1 = 0, 1
-HHG_F64, HHG_F32 = 0, 1
+HHG_F64, HHG_F32, HHG_BF16 = 0, 1, 2
 HHG_OP_FULL, HHG_OP_A, HHG_OP_BT, HHG_OP_B, HHG_OP_C, HHG_OP_MASS = range(6)
 HHG_GS_FWD, HHG_GS_SYM = 0, 1
 HHG_SCHUR_SD, HHG_SCHUR_ML = 0, 1
 
 SYMBOLS = [
     "hhg_ctx_create", "hhg_ctx_set_stream", "hhg_ctx_destroy", "hhg_last_error",
+    "hhg_mesh_cube", "hhg_mesh_create", "hhg_mesh_info", "hhg_mesh_destroy",
     "hhg_hier_create", "hhg_hier_destroy", "hhg_vec_layout", "hhg_vec_from_lattice", "hhg_vec_to_lattice",
     "hhg_apply", "hhg_residual", "hhg_rhs", "hhg_smooth", "hhg_restrict", "hhg_prolong_add",
     "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
@@ -48,7 +49,8 @@ class SolverParams(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("res_u", ctypes.c_double), ("res_p", ctypes.c_double),
-                ("rel_res", ctypes.c_double), ("work_units", ctypes.c_double), ("fallbacks", ctypes.c_int)]
+                ("rel_res", ctypes.c_double), ("work_units", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("fallbacks", ctypes.c_int)]
 
 
 _lib = None
@@ -72,7 +74,11 @@ def load():
         "hhg_ctx_create": [I, P, P],
         "hhg_ctx_set_stream": [P, P],
         "hhg_ctx_destroy": [P],
-        "hhg_hier_create": [P, I, I, I, I, I, P],
+        "hhg_mesh_cube": [P, I, P],
+        "hhg_mesh_create": [P, P, I, P, I, P],
+        "hhg_mesh_info": [P, P, P, P],
+        "hhg_mesh_destroy": [P],
+        "hhg_hier_create": [P, I, I, I, I, P],
         "hhg_hier_destroy": [P],
         "hhg_vec_layout": [P, I, P, P, P, P],
         "hhg_vec_from_lattice": [P, I, P, P, I],
@@ -158,9 +164,35 @@ def hhg_ctx_destroy(ctx):
     _check(load().hhg_ctx_destroy(ctx))
 
 
-def hhg_hier_create(ctx, disc, macro_refine, lmin, lmax, schur=HHG_SCHUR_SD):
+def hhg_mesh_cube(ctx, macro_refine=0):
     out = ctypes.c_void_p()
-    _check(load().hhg_hier_create(ctx, disc, macro_refine, lmin, lmax, schur, ctypes.byref(out)))
+    _check(load().hhg_mesh_cube(ctx, macro_refine, ctypes.byref(out)))
+    return out
+
+
+def hhg_mesh_create(ctx, xyz, tet):
+    """xyz: (nv, 3) host array of vertex coordinates; tet: (nt, 4) vertex indices."""
+    import numpy as np
+    x = np.ascontiguousarray(xyz, dtype=np.float64)
+    t = np.ascontiguousarray(tet, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(load().hhg_mesh_create(ctx, x.ctypes.data, x.shape[0], t.ctypes.data, t.shape[0], ctypes.byref(out)))
+    return out
+
+
+def hhg_mesh_info(mesh):
+    nv, nt, mr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().hhg_mesh_info(mesh, ctypes.byref(nv), ctypes.byref(nt), ctypes.byref(mr)))
+    return nv.value, nt.value, mr.value
+
+
+def hhg_mesh_destroy(mesh):
+    _check(load().hhg_mesh_destroy(mesh))
+
+
+def hhg_hier_create(mesh, disc, lmin, lmax, schur=HHG_SCHUR_SD):
+    out = ctypes.c_void_p()
+    _check(load().hhg_hier_create(mesh, disc, lmin, lmax, schur, ctypes.byref(out)))
     return out
 
 

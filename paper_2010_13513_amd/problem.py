@@ -20,7 +20,11 @@ class Problem:
         self.disc = disc
         self.lmin, self.lmax, self.mr = lmin, lmax, macro_refine
         self.dev = torch.device(device)
-        self.h = hhg.hhg_hier_create(ctx, disc, macro_refine, lmin, lmax, schur)
+        mesh = hhg.hhg_mesh_cube(ctx, macro_refine)
+        try:
+            self.h = hhg.hhg_hier_create(mesh, disc, lmin, lmax, schur)
+        finally:
+            hhg.hhg_mesh_destroy(mesh)
         self.has_nu = False
 
     def close(self):

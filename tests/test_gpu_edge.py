@@ -37,14 +37,21 @@ def test_hierarchy_limits():
             (P1, 2, 0, 3),        # macro_refine outside {0, 1}
             (7, 0, 0, 3),         # unknown discretisation
         ]
+        meshes = {0: hhg.hhg_mesh_cube(ctx, 0), 1: hhg.hhg_mesh_cube(ctx, 1)}
         for disc, mr, lmin, lmax in bad:
-            assert _status(hhg.hhg_hier_create, ctx, disc, mr, lmin, lmax) == hhg.HHG_ERR_ARG, (disc, mr, lmin, lmax)
-        assert _status(hhg.hhg_hier_create, ctx, P1, 0, 0, 3, 9) == hhg.HHG_ERR_ARG      # unknown Schur option
+            if mr not in meshes:
+                assert _status(hhg.hhg_mesh_cube, ctx, mr) == hhg.HHG_ERR_ARG
+                continue
+            assert _status(hhg.hhg_hier_create, meshes[mr], disc, lmin, lmax) == hhg.HHG_ERR_ARG, (disc, mr, lmin, lmax)
+        assert _status(hhg.hhg_hier_create, meshes[0], P1, 0, 3, 9) == hhg.HHG_ERR_ARG      # unknown Schur option
+        assert _status(hhg.hhg_hier_create, None, P1, 0, 3) == hhg.HHG_ERR_ARG              # no mesh
         # the smallest valid hierarchies
         for disc, lmin in ((P1, 0), (P2, 1)):
-            h = hhg.hhg_hier_create(ctx, disc, 0, lmin, lmin + 1)
+            h = hhg.hhg_hier_create(meshes[0], disc, lmin, lmin + 1)
             assert hhg.hhg_vec_layout(h, lmin)[0] == 2 ** lmin
             hhg.hhg_hier_destroy(h)
+        for m in meshes.values():
+            hhg.hhg_mesh_destroy(m)
     finally:
         torch.cuda.synchronize()
         hhg.hhg_ctx_destroy(ctx)
@@ -124,3 +131,83 @@ def test_apply_largest_p1_hierarchy_sampled_rows():
         check_rows(rows, bnd, xv, got)
     finally:
         lib.close()
+
+
+def _kuhn_mesh(N, rng=None):
+    """The Kuhn partition of the unit cube into N^3 sub-cubes (6 N^3
+    tetrahedra), optionally with shuffled vertex numbering, tetrahedron order
+    and vertex order inside each tetrahedron."""
+    n1 = N + 1
+    pts = np.array([(i, j, k) for k in range(n1) for j in range(n1) for i in range(n1)], float) / N
+    idx = lambda c: int(c[0] + n1 * (c[1] + n1 * c[2]))
+    tets = []
+    for k in range(N):
+        for j in range(N):
+            for i in range(N):
+                for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+                    c = [i, j, k]
+                    t = [idx(c)]
+                    for a in perm:
+                        c[a] += 1
+                        t.append(idx(c))
+                    tets.append(t)
+    tets = np.array(tets)
+    if rng is not None:
+        relabel = rng.permutation(len(pts))
+        inv = np.argsort(relabel)
+        pts = pts[inv]                  # new vertex v is old vertex inv[v]
+        tets = relabel[tets]
+        tets = tets[rng.permutation(len(tets))]
+        tets = np.array([rng.permutation(t) for t in tets])
+    return pts, tets
+
+
+def test_mesh_handle():
+    """hhg_mesh_cube and hhg_mesh_create: the Kuhn cube meshes in any vertex
+    and tetrahedron order give the hierarchy of hhg_mesh_cube (the same
+    operator on the same lattice); anything else is refused with HHG_ERR_ARG
+    (no hierarchy is built from it)."""
+    torch = torch_cuda()
+    ctx = hhg.hhg_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+    rng = np.random.default_rng(2024)
+    try:
+        for N, mr in ((1, 0), (2, 1)):
+            ref = hhg.hhg_mesh_cube(ctx, mr)
+            assert hhg.hhg_mesh_info(ref) == ((N + 1) ** 3, 6 * N ** 3, mr)
+            xyz, tet = _kuhn_mesh(N, rng)
+            m = hhg.hhg_mesh_create(ctx, xyz, tet)
+            assert hhg.hhg_mesh_info(m) == ((N + 1) ** 3, 6 * N ** 3, mr)
+            outs = []
+            for mesh in (ref, m):
+                h = hhg.hhg_hier_create(mesh, P2, 1, 2)
+                hhg.hhg_mesh_destroy(mesh)          # the hierarchy keeps what it needs
+                _, _, vw, lw = hhg.hhg_vec_layout(h, 2)
+                src = torch.from_numpy(np.random.default_rng(5).standard_normal(lw)).cuda()
+                x = torch.zeros(vw, dtype=torch.float64, device="cuda")
+                y = torch.zeros_like(x)
+                hhg.hhg_vec_from_lattice(h, 2, src, x)
+                hhg.hhg_apply(h, 2, hhg.HHG_OP_FULL, x, y)
+                torch.cuda.synchronize()
+                outs.append(y.cpu())
+                hhg.hhg_hier_destroy(h)
+            assert torch.equal(outs[0], outs[1])
+        E = hhg.HHG_ERR_ARG
+        xyz, tet = _kuhn_mesh(2)
+        bad = {
+            "not 6 or 48 tetrahedra": (xyz, tet[:47]),
+            "vertex off the lattice": (xyz + np.array([[0.0, 0.0, 0.1]] * len(xyz)) * (np.arange(len(xyz)) == 4)[:, None], tet),
+            "duplicate vertex": (np.vstack([xyz[:-1], xyz[:1]]), tet),
+            "non-Kuhn tetrahedron": (xyz, np.vstack([tet[:-1], [[0, 1, 4, 26]]])),
+            "tetrahedron twice": (xyz, np.vstack([tet[:-1], tet[:1]])),
+            "vertex index out of range": (xyz, np.vstack([tet[:-1], [[0, 1, 4, 27]]])),
+            "unused vertex": (np.vstack([xyz, [[0.5, 0.5, 0.5]]]), tet),
+            "outside the unit cube": (xyz * 2.0, tet),
+        }
+        for why, (x_, t_) in bad.items():
+            assert _status(hhg.hhg_mesh_create, ctx, x_, t_) == E, why
+            print(f"[mesh] refused ({why}): {hhg.hhg_last_error()}")
+        assert _status(hhg.hhg_mesh_cube, ctx, 2) == E
+        assert _status(hhg.hhg_mesh_info, None) == E
+    finally:
+        torch.cuda.synchronize()
+        hhg.hhg_ctx_destroy(ctx)

@@ -2,12 +2,19 @@
 MLP oracle (same bf16 storage points), training, training pairs against the
 oracle's exact coarse correction, and the fallback monitor.
 
-Tolerances: weights and layer inputs are bf16 on both sides, so the products
-agree up to float32-vs-float64 accumulation; where that difference crosses a
-bf16 rounding boundary of a hidden activation the two sides round one entry
-differently (one bf16 ulp, 2^-8 relative), which moves the outputs by about
-1e-3 relative.  Outputs and gradients are therefore compared in norm at 1e-2
-and the bulk of entries at 2e-3.
+Tolerances.  (i) Exact-arithmetic networks: small-integer inputs, sparse
++-1 weights and integer biases keep every pre-activation a small integer, and
+a batch of B x n_out a power of two makes the loss gradient's scale 2 / (B
+n_out) exact, so every product, bf16 rounding and float32 sum is exact on
+both sides and outputs and gradients must agree entry by entry, bit for bit
+-- at ragged sizes (n_in = 331, tails of every 16-wide tile) and the hidden
+width of the learned coarse solve (512), so a dropped or misplaced tile
+cannot hide.  (ii) Random real-valued networks: weights and layer inputs are
+bf16 on both sides, so the products agree up to float32-vs-float64
+accumulation; where that difference crosses a bf16 rounding boundary of a
+hidden activation the two sides round one entry differently (one bf16 ulp),
+which moves the outputs by about 1e-3 relative, so these are compared in
+norm at 1e-2 and the bulk of entries at 2e-3.
 """
 import numpy as np
 import pytest
@@ -72,6 +79,52 @@ def test_forward_and_gradients_match_oracle(ctx, n_in, H, n_out, B):
         shapes = [p.shape for p in ps]
         for k, (a, b) in enumerate(zip(_split(g.astype(np.float64), shapes), wg)):
             assert np.linalg.norm(a - b) < 2e-2 * np.linalg.norm(b) + 1e-12, k
+    finally:
+        hhg.hhg_mlp_destroy(m)
+
+
+def _exact_net(rng, n_in, H, n_out, per_row=4):
+    """Sparse +-1 weights (per_row nonzeros per row), biases in {-1, 0, 1}."""
+    dims = [n_in, H, H, H, n_out]
+    ps = []
+    for l in range(4):
+        W = np.zeros((dims[l + 1], dims[l]))
+        for r in range(dims[l + 1]):
+            cols = rng.choice(dims[l], size=min(per_row, dims[l]), replace=False)
+            W[r, cols] = rng.choice([-1.0, 1.0], size=cols.size)
+        ps += [W, rng.integers(-1, 2, size=dims[l + 1]).astype(np.float64)]
+    return ps
+
+
+@pytest.mark.parametrize("n_in,H,n_out,B", [(331, 512, 64, 32), (37, 48, 16, 16), (331, 64, 206, 64)])
+def test_exact_arithmetic_network_matches_oracle_entrywise(ctx, n_in, H, n_out, B):
+    torch, c = ctx
+    rng = np.random.default_rng(1000 + n_in + H)
+    ps = _exact_net(rng, n_in, H, n_out)
+    X = rng.integers(-2, 3, size=(B, n_in)).astype(np.float64)
+    Y = rng.integers(-3, 4, size=(B, n_out)).astype(np.float64)
+    net = omlp.MLP(ps, quantize=True)
+    want, cache = net.forward(X)
+    assert max(np.abs(z).max() for _, z in cache) < 128        # every value exact in bf16
+    assert np.all(want == np.round(want))
+    m = hhg.hhg_mlp_create(c, n_in, H, n_out, B)
+    try:
+        hhg.hhg_mlp_set_params(m, _flat(ps))
+        dx = torch.from_numpy(X.astype(np.float32)).cuda()
+        dy = torch.from_numpy(Y.astype(np.float32)).cuda()
+        out = torch.empty(B, n_out, dtype=torch.float32, device="cuda")
+        hhg.hhg_mlp_forward(m, dx, B, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, want), np.argwhere(got != want)[:5]
+        scale = 2.0 / (B * n_out)
+        if scale != 2.0 ** round(np.log2(scale)):
+            return             # loss-gradient scale not exact (n_out = 206): forward only
+        loss, g = hhg.hhg_mlp_loss_grad(m, dx, dy, B)
+        wl, wg = net.loss_and_grads(X, Y)
+        assert abs(loss - wl) <= 1e-12 * abs(wl)
+        for k, (a, b) in enumerate(zip(_split(g.astype(np.float64), [p.shape for p in ps]), wg)):
+            assert np.array_equal(a, b), (k, np.argwhere(a != b)[:5])
     finally:
         hhg.hhg_mlp_destroy(m)
 

@@ -6,7 +6,7 @@ import pytest
 from oracle import fe, mesh, multigrid as mg, smoother as osm
 from oracle.stokes import Stokes
 from paper_2010_13513_amd import hhg, workloads as W
-from tests.gpu_util import Lib, rel_err
+from tests.gpu_util import Lib, assert_blocks, block_errors, coarse_tolerance, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_apply_variable_viscosity(libs, disc, lmin, L, op):
     dy = lib.empty(L)
     hhg.hhg_apply(lib.h, L, hhg.HHG_OP_FULL if op == "FULL" else hhg.HHG_OP_A, lib.from_lattice(L, x), dy)
     want = S.apply(x) if op == "FULL" else S.apply_block(x, "A")
-    assert rel_err(lib.to_lattice(L, dy), want) < 1e-12
+    assert_blocks(lib, L, lib.to_lattice(L, dy), want, 1e-12, f"variable nu apply {op}")
 
 
 @pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 3), (P2, 1, 3)])
@@ -68,7 +68,7 @@ def test_smooth_variable_viscosity(libs, disc, lmin, L):
         want = U.iterate(want, b, "f", 2, 0.5)
     dx = lib.from_lattice(L, x)
     hhg.hhg_smooth(lib.h, L, dx, lib.from_lattice(L, b), 2, hhg.HHG_GS_FWD, 2, 2.0)
-    assert rel_err(lib.to_lattice(L, dx), want) < 1e-10
+    assert_blocks(lib, L, lib.to_lattice(L, dx), want, 1e-12, "variable nu smooth")
 
 
 @pytest.mark.parametrize("disc,lmin,L", [(P1, 0, 3), (P2, 1, 3)])
@@ -85,7 +85,8 @@ def test_fmg_variable_viscosity(libs, disc, lmin, L):
     bs = [lib.from_lattice(l, H.rhs(l, prob)) for l in range(lmin, L + 1)]
     dx = lib.from_lattice(L, H.initial(L, prob))
     hhg.hhg_fmg_solve(lib.h, dx, bs, hhg.solver_params(1, 2, 1, 1, hhg.HHG_GS_FWD, 2, om, extra_cycles=1))
-    assert rel_err(lib.to_lattice(L, dx), want) < 1e-9
+    tol, kappa = coarse_tolerance(vo, 2 ** lmin, _nu_nodes(2 ** lmin))
+    assert_blocks(lib, L, lib.to_lattice(L, dx), want, tol, f"variable nu FMG (coarse kappa {kappa:.1e})")
 
 
 @pytest.mark.parametrize("disc,lmin,L,varnu", [(P1, 0, 3, False), (P2, 1, 3, True)])
@@ -101,11 +102,19 @@ def test_defect_correction_float32(libs, disc, lmin, L, varnu):
     xd = H.exact_discrete(L, prob)
     db = lib.from_lattice(L, b)
     prm = hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 1 if disc == P1 else 3, 2.3)
-    out = {}
-    for prec in (hhg.HHG_F32, hhg.HHG_F64):
+    out, err = {}, {}
+    for prec in (hhg.HHG_F64, hhg.HHG_F32):
         dx = lib.from_lattice(L, H.initial(L, prob))
         st = hhg.hhg_dc_solve(lib.h, dx, db, prm, prec, 1, 1e-12, 200)
         assert st.rel_res <= 1e-12
         out[prec] = lib.to_lattice(L, dx)
-        assert rel_err(out[prec], xd) < 1e-7
-    assert rel_err(out[hhg.HHG_F32], out[hhg.HHG_F64]) < 1e-9
+        err[prec] = block_errors(lib, L, out[prec], xd)
+        print(f"[parity] defect correction inner {'f64' if prec == hhg.HHG_F64 else 'f32'} vs oracle "
+              f"sparse direct: velocity {err[prec][0]:.2e}, pressure {err[prec][1]:.2e} "
+              f"({st.cycles} cycles)", flush=True)
+    # both stop at ||r|| <= 1e-12 ||b||, so each is as close to the exact
+    # discrete solution as that residual allows; the float32 inner cycles
+    # may end at a different residual below the tolerance, hence the factor
+    for k in (0, 1):
+        assert err[hhg.HHG_F64][k] < 1e-8
+        assert err[hhg.HHG_F32][k] < 10 * err[hhg.HHG_F64][k] + 1e-10
