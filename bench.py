@@ -47,7 +47,7 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-apply-roofline", action="store_true")
-    ap.add_argument("--mode", choices=["fmg", "apply", "learned", "dc"], default="fmg",
+    ap.add_argument("--mode", choices=["fmg", "apply", "learned", "dc", "sweep"], default="fmg",
                     help="apply: only the operator-apply roofline (for counter runs); learned: the "
                          "learned coarse-solve workload (pairs, GPU training, held-out evaluation)")
     ap.add_argument("--pairs", type=int, default=20000)
@@ -55,6 +55,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--test-seeds", type=int, default=1000)
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--sweep-out", default=None, help="sweep: write every row of the study to this JSON file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
@@ -74,6 +75,11 @@ def main():
     ctx = hhg.hhg_ctx_create(0, stream.cuda_stream)
     if args.mode == "dc":
         res = bench_dc(torch, hhg, ctx, level=args.level if args.level != 5 else 7)
+        print(json.dumps(res), flush=True)
+        hhg.hhg_ctx_destroy(ctx)
+        return
+    if args.mode == "sweep":
+        res = bench_sweep(torch, hhg, ctx, args)
         print(json.dumps(res), flush=True)
         hhg.hhg_ctx_destroy(ctx)
         return
@@ -452,6 +458,46 @@ def bench_dc(torch, hhg, ctx, level=7, lmin=1):
         out["speedup_f32_vs_f64"] = out["f32"]["speedup_vs_f64"]
     finally:
         P.close()
+    return out
+
+
+def bench_sweep(torch, hhg, ctx, args):
+    """The paper's parameter study (Sec. 5.1): all 768 tuples of the search
+    space S with GPU FMG on the 6-tet cube, paper cube solution, P1-P1 level 6
+    (coarsest 0) and P2-P1 level 5 (coarsest 1); gamma of eq. gamma against
+    the discrete solution; the synthetic Tab. fmg-table and the least-error-
+    for-work envelopes."""
+    from paper_2010_13513_amd import study, workloads as W
+    from paper_2010_13513_amd.problem import Problem
+    prob = W.paper_cube()
+    out = {"mode": "sweep", "problem": "paper cube solution (Sec. 5.1.1), 6 Kuhn macro-tets, Dirichlet",
+           "schur": "SD", "ordering": "multicolour"}
+    allrows = {}
+    for disc, name, lmin, L in ((hhg.HHG_P1P1, "P1-P1", 0, 6), (hhg.HHG_P2P1, "P2-P1", 1, 5)):
+        P = Problem(torch, ctx, disc, lmin, L)
+        try:
+            v0 = torch.from_numpy(W.normal_vector(W.SEED_BASE + 1000, (2 ** L + 1) ** 3)).to(P.dev)
+            om = hhg.hhg_estimate_omega(P.h, L, v0, 100)
+            log(f"[sweep] {name} level {L} ({P.dofs(L)} DoFs): omega_inv {om:.6f}")
+            t0 = time.perf_counter()
+            rows, ed = study.run(torch, P, prob, om, study.search_space(), log=log)
+            el = time.perf_counter() - t0
+            tab = study.best_under_bounds(rows)
+            env_u = study.min_error_for_work(rows, "gamma_u")
+            env_p = study.min_error_for_work(rows, "gamma_p")
+            for t in tab:
+                b = t["best"]
+                log(f"[sweep] {name} bounds {t['bounds']}: " +
+                    (f"{b['name']} WU {b['wu']:.2f} gamma ({b['gamma_u']:.3f}, {b['gamma_p']:.3f})" if b else "none"))
+            out[name] = {"level": L, "dofs": P.dofs(L), "omega_inv": om, "disc_errors": ed, "seconds": round(el, 2),
+                         "tuples": len(rows), "table": tab, "envelope_gamma_u": env_u, "envelope_gamma_p": env_p,
+                         "solve_ms_median": round(1e3 * float(np.median([r["seconds"] for r in rows])), 3)}
+            allrows[name] = rows
+        finally:
+            P.close()
+    if args.sweep_out:
+        with open(args.sweep_out, "w") as f:
+            json.dump(allrows, f)
     return out
 
 

@@ -143,6 +143,7 @@ struct hhg_hier_s {
   double rho_plain = 0.0, tau = 0.0;
   bool mlp_off = false;      // fallback taken in the current solve
   bool kp_stale = false;     // coarse pseudo-inverse not rebuilt for the current viscosity
+  bool kp_ready = false;     // coarse pseudo-inverse computed (lazily, ensure_coarse)
   float *feat = nullptr, *mlp_out = nullptr;
   double* norm = nullptr;
   double* bk = nullptr;      // copy of x before a monitored V-cycle
@@ -414,8 +415,11 @@ void build_transfer(hhg_hier h, Level& lc, Level& lf) {
 
 int full_mask(hhg_hier h);
 
-// Dense coarse operator on the unknowns (interior velocity DoFs, all pressure
-// DoFs) from the host stencil tables, and its pseudo-inverse.
+// Coarse unknowns (interior velocity DoFs, all pressure DoFs) of the
+// coarsest level and the device buffer of the pseudo-inverse; the
+// pseudo-inverse itself is computed on first use (ensure_coarse), so a
+// hierarchy that never solves on its coarsest level (an error-evaluation
+// pair of levels, say) does not pay for the host decomposition.
 void build_coarse(hhg_hier h) {
   Level& lv = h->L(h->lmin);
   const Geom& g = lv.g;
@@ -448,6 +452,23 @@ void build_coarse(hhg_hier h) {
     h->nunk = 0;
     return;
   }
+  h->nunk = n;
+  h->Kp = h->arena.alloc<double>((size_t)n * n);
+  h->unk = h->arena.upload(unk);
+  h->unk_host = unk;
+  h->kp_ready = false;
+}
+
+// Dense coarse operator on the unknowns from the host stencil tables
+// (constant coefficients), and its pseudo-inverse into h->Kp.
+void build_coarse_pinv(hhg_hier h) {
+  Level& lv = h->L(h->lmin);
+  const Geom& g = lv.g;
+  const int N = g.N, n1 = g.n1, nn = g.nn;
+  const int n = h->nunk;
+  const std::vector<int>& unk = h->unk_host;
+  std::unordered_map<int, int> pos2u;
+  for (int r = 0; r < n; ++r) pos2u[unk[r]] = r;
   std::vector<double> K((size_t)n * n, 0.0);
   auto add = [&](int r, int pos, double w) {
     auto it = pos2u.find(pos);
@@ -479,10 +500,23 @@ void build_coarse(hhg_hier h) {
     }
   std::vector<double> Kp;
   h->rank = sym_pinv(n, K, Kp, 1e-12);
-  h->nunk = n;
-  h->Kp = h->arena.upload(Kp);
-  h->unk = h->arena.upload(unk);
-  h->unk_host = unk;
+  HHG_CHECK_HIP(hipMemcpy(h->Kp, Kp.data(), Kp.size() * sizeof(double), hipMemcpyHostToDevice));
+  h->kp_ready = true;
+}
+
+void build_coarse_device(hhg_hier h);
+
+// The coarse pseudo-inverse of the current operator, computed now if it has
+// not been (host work: call outside graph capture).
+void ensure_coarse(hhg_hier h) {
+  if (h->nunk == 0) return;
+  if (!h->kp_ready) {
+    HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
+    if (h->L(h->lmin).nu64)
+      build_coarse_device(h);
+    else
+      build_coarse_pinv(h);
+  }
 }
 
 // Dense coarse operator from the device operator itself (columns = calA e_c
@@ -518,7 +552,7 @@ void build_coarse_device(hhg_hier h) {
     }
   std::vector<double> Kp;
   bool done = false;
-  if (h->rank == n - 1) {
+  if (h->kp_ready && h->rank == n - 1) {
     const size_t pbase = 3 * (size_t)lv.g.vstride;
     int np = 0;
     for (int r = 0; r < n; ++r) np += (size_t)h->unk_host[r] >= pbase;
@@ -529,6 +563,7 @@ void build_coarse_device(hhg_hier h) {
   }
   if (!done) h->rank = sym_pinv(n, K, Kp, 1e-12);
   HHG_CHECK_HIP(hipMemcpy(h->Kp, Kp.data(), Kp.size() * sizeof(double), hipMemcpyHostToDevice));
+  h->kp_ready = true;
 }
 
 // ---------------------------------------------------------------- ops
@@ -737,6 +772,7 @@ void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true, const hhg_so
     build_coarse_device(h);
     h->kp_stale = false;
   }
+  ensure_coarse(h);
   if constexpr (std::is_same<T, double>::value) {
     if (h->rec_n < h->rec_cap) {
       const size_t ni = (size_t)h->nunk + lv.g.nn;
@@ -768,7 +804,8 @@ void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_para
   // pseudo-inverse rebuild)
   const bool mlp_on = std::is_same<T, double>::value && h->mlp && !h->mlp_off;
   if (vel_sites(h->L(l)) <= h->fused_sites && !h->slv_stale && p.coarse_smooth == 0 && h->nunk > 0 && !mlp_on &&
-      h->rec_n >= h->rec_cap && !h->kp_stale && (std::is_same<T, double>::value || h->L(h->lmin).cx32)) {
+      h->rec_n >= h->rec_cap && !h->kp_stale && h->kp_ready &&
+      (std::is_same<T, double>::value || h->L(h->lmin).cx32)) {
     SmallCycle<T> sc{};
     sc.nlev = l - h->lmin + 1;
     sc.G = h->G;
@@ -1326,6 +1363,7 @@ hhg_status hhg_coarse_solve(hhg_hier h, void* x, const void* b, hhg_prec prec) {
   return guard([&] {
     HHG_REQUIRE(h && x && b && x != b, HHG_ERR_ARG, "bad arguments");
     HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "coarse solve is float64");
+    ensure_coarse(h);
     op_coarse<double>(h, (double*)x, (const double*)b);
     HHG_CHECK_HIP(hipGetLastError());
   });
@@ -1481,6 +1519,7 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
     double* x = (double*)xv;
     const double* b = (const double*)bv;
     if (inner_prec == HHG_F32) ensure_f32_vectors(h);
+    ensure_coarse(h);
     refresh_small(h);
     CallClock clock(h);
     double bu, bp, ru = 0, rp = 0;
@@ -1693,7 +1732,10 @@ hhg_status hhg_record_pairs(hhg_hier h, float* features, float* targets, int cap
     HHG_REQUIRE(h && capacity >= 0, HHG_ERR_ARG, "bad arguments");
     HHG_REQUIRE(capacity == 0 || (features && targets), HHG_ERR_ARG, "null buffers");
     HHG_REQUIRE(capacity == 0 || h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
-    if (capacity > 0) ensure_coarse_buffers(h);
+    if (capacity > 0) {
+      ensure_coarse_buffers(h);
+      ensure_coarse(h);
+    }
     if (capacity > 0 && !h->rc) h->rc = h->arena.alloc<double>(h->L(h->lmin).vec_words);
     h->rec_f = capacity ? features : nullptr;
     h->rec_t = capacity ? targets : nullptr;
@@ -1773,6 +1815,7 @@ hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_s
     check_level(h, level);
     HHG_REQUIRE(x && b && prm && prm->omega_inv > 0.0 && prm->xi >= 1, HHG_ERR_ARG, "bad arguments");
     HHG_REQUIRE(prec == HHG_F64 || prec == HHG_F32, HHG_ERR_PREC, "bad precision");
+    ensure_coarse(h);
     if (prec == HHG_F32) {
       HHG_REQUIRE(h->nunk > 0 || prm->coarse_smooth > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
       ensure_f32_vectors(h);
@@ -1799,6 +1842,7 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* xv, const void* const* b_levels, cons
     const hhg_solver_params& p = *prm;
     double* x = (double*)xv;
     auto bl = [&](int l) { return (const double*)b_levels[l - h->lmin]; };
+    if (!(h->mlp && h->kp_stale)) ensure_coarse(h);
     refresh_small(h);
     // Fixed work (no stopping test, no statistics): the whole solve is one
     // replayed HIP graph, captured on the first call with these vectors and

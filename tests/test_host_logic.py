@@ -156,3 +156,12 @@ def test_query_rejects_bad_arguments():
         hhg.hhg_query_interpolation(3, 0, 0, 0, 2)
     with pytest.raises(hhg.HHGError):
         hhg.hhg_query_stencil(P2, "A", 0, 3, 3, 3, 64, max_entries=4)
+
+
+def test_parameter_search_space_has_768_tuples():
+    """Sec. 5.1: 0 <= nu_pre, nu_post, nu_inc <= 3, kappa in {1, 2}, six
+    (A_hat, xi) pairs: 4 * 4 * 4 * 2 * 6 = 768 distinct tuples."""
+    from paper_2010_13513_amd import study
+    s = study.search_space()
+    assert len(s) == 768 and len(set(s)) == 768
+    assert {t[5] for t in s if t[4] == 0} == {1, 2, 3, 4} and {t[5] for t in s if t[4] == 1} == {1, 2}
