@@ -8,6 +8,12 @@ Basis functions are polynomials in the four barycentric coordinates
 (dict exponent-tuple -> coefficient).  Integrals use the exact formula
 int_T lam^alpha dx = 6|T| alpha! / (|alpha| + 3)!.
 
+Boundary (Sec. 2): Dirichlet on the faces of the cube not listed in
+`neumann`, natural Neumann outflow (du/dn = n p) on the listed ones.  The
+outflow condition is natural: the weak form has no boundary term, so the
+velocity DoFs on a Neumann face (not on its Dirichlet edges) are unknowns with
+the assembled rows of A and B^T, and the pressure has no null space.
+
 Variable viscosity (not in the paper's experiments): the A block becomes
 sum_T nu_T int_T grad phi_i . grad phi_j with nu_T the mean of nu at the four
 vertices of T (per velocity component, so A stays block diagonal).
@@ -155,9 +161,10 @@ class Level:
 
     vorder = 1 (P1-P1 PSPG) or 2 (P2-P1 Taylor-Hood).  nu_vertex: optional
     viscosity at the P1 nodes (lattice order) for the variable-viscosity A.
+    neumann: faces (mesh.on_dirichlet numbering) with the outflow condition.
     """
 
-    def __init__(self, N, vorder, nu_vertex=None):
+    def __init__(self, N, vorder, nu_vertex=None, neumann=()):
         self.N = N
         self.vorder = vorder
         self.h = 1.0 / N
@@ -211,8 +218,9 @@ class Level:
         vc = mesh.p1_coords(N) if vorder == 1 else mesh.p2_coords(N)
         self.vcoords = vc                    # integer coords, units h / vorder
         self.pcoords = mesh.p1_coords(N)
-        self.vbnd = mesh.on_boundary(vc, N * vorder)
-        self.vint = ~self.vbnd
+        self.neumann = tuple(sorted(set(neumann)))
+        self.vbnd = mesh.on_dirichlet(vc, N * vorder, self.neumann)   # Dirichlet velocity nodes
+        self.vint = ~self.vbnd                                         # velocity unknowns
         self.Adiag = self.A.diagonal()
 
     # positions in [0,1]^3

@@ -121,6 +121,21 @@ def on_boundary(coords, M):
     return np.any((c == 0) | (c == M), axis=-1)
 
 
+# Faces of the unit cube: 0: x = 0, 1: x = 1, 2: y = 0, 3: y = 1, 4: z = 0, 5: z = 1.
+def on_dirichlet(coords, M, neumann=()):
+    """True where a node lies on a face that is not in `neumann` (the Dirichlet
+    part of the boundary is closed: a node on an edge or corner shared with a
+    Dirichlet face is a Dirichlet node)."""
+    c = np.asarray(coords)
+    out = np.zeros(c.shape[:-1], dtype=bool)
+    for f in range(6):
+        if f in neumann:
+            continue
+        d, hi = f // 2, f % 2
+        out |= c[..., d] == (M if hi else 0)
+    return out
+
+
 def p2_group(X, Y, Z):
     """DoF group of a doubled-lattice node: -1 vertex, else index into EDGE_DIRS."""
     par = (X % 2, Y % 2, Z % 2)

@@ -50,11 +50,12 @@ class Problem:
 
 
 class Hierarchy:
-    def __init__(self, vorder, Lmin, Lmax, macro_refine=0, nu_fn=None, schur="ml"):
+    def __init__(self, vorder, Lmin, Lmax, macro_refine=0, nu_fn=None, schur="ml", neumann=()):
         self.vorder = vorder
         self.Lmin, self.Lmax = Lmin, Lmax
         self.mr = macro_refine
         self.nu_fn = nu_fn
+        self.neumann = tuple(neumann)
         self.S, self.U, self.T = {}, {}, {}
         for l in range(Lmin, Lmax + 1):
             self.S[l] = Stokes(self.make_level(l))
@@ -73,7 +74,7 @@ class Hierarchy:
             from . import mesh
             c = mesh.p1_coords(N) / float(N)
             nu = self.nu_fn(c[:, 0], c[:, 1], c[:, 2])
-        return fe.Level(N, self.vorder, nu)
+        return fe.Level(N, self.vorder, nu, self.neumann)
 
     # ------------------------------------------------------------ cycles
     def smooth(self, l, x, b, its, prm):
@@ -130,12 +131,15 @@ class Hierarchy:
 
         The all-Dirichlet system is singular only along (0, 1_p); fixing the
         last pressure unknown to zero removes that direction, and the result
-        is then shifted to zero pressure mean (int p = 0, Sec. 2)."""
+        is then shifted to zero pressure mean (int p = 0, Sec. 2).  With an
+        outflow face the system is regular and solved on all unknowns."""
         from .coarse import unknown_index
         S = self.S[l]
         b = self.rhs(l, prob) if b is None else b
         x0 = self.initial(l, prob)
-        idx = unknown_index(S)[:-1]
+        idx = unknown_index(S)
+        if not S.lev.neumann:
+            idx = idx[:-1]
         K = self.sparse_system(l)[idx][:, idx].tocsc()
         r = S.residual(x0, b)[idx]
         sol = spla.spsolve(K, r)
@@ -161,8 +165,9 @@ def l2_errors(H_fine_stokes, T_up, x_l, prob):
     us, p = Sf.split(xf)
     ws, ps = Sf.split(xs)
     m = Sf.lev.ML
-    p = p - (m @ p) / m.sum()
-    ps = ps - (m @ ps) / m.sum()
+    if not Sf.lev.neumann:          # pressure fixed only up to a constant
+        p = p - (m @ p) / m.sum()
+        ps = ps - (m @ ps) / m.sum()
     eu = np.sqrt(sum((w - u) @ (Sf.lev.M @ (w - u)) for u, w in zip(us, ws)))
     ep = np.sqrt((ps - p) @ (Sf.lev.Mp @ (ps - p)))
     return float(eu), float(ep)

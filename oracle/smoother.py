@@ -128,7 +128,7 @@ class Uzawa:
         lev = self.S.lev
         m = lev.ML
         D = self.D
-        v = v0 - (m @ v0) / m.sum()
+        v = v0 - (m @ v0) / m.sum() if not lev.neumann else np.array(v0, dtype=float)
         v = v / np.linalg.norm(v)
         lam = 0.0
         for _ in range(iters):

@@ -110,7 +110,11 @@ class Stokes:
         return self.join([np.where(vi, u, 0.0) for u in us], p)
 
     def mean_zero(self, x):
-        """p <- p - (m^T p / m^T 1) 1 with m_k = int psi_k (Sec. 2, int p = 0)."""
+        """p <- p - (m^T p / m^T 1) 1 with m_k = int psi_k (Sec. 2, int p = 0).
+        With an outflow boundary the pressure is determined and x is returned
+        unchanged."""
+        if self.lev.neumann:
+            return x
         us, p = self.split(x)
         m = self.lev.ML
         return self.join(us, p - (m @ p) / m.sum())

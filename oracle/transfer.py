@@ -88,5 +88,7 @@ class Transfer:
         us, p = self.Sf.split(self.Sf.zero_boundary(rf))
         rc = self.Sc.join([self.Rv @ u for u in us], self.Rp @ p)
         rc = self.Sc.zero_boundary(rc)
+        if self.Sc.lev.neumann:          # no null vector: nothing to be compatible with
+            return rc
         uc, pc = self.Sc.split(rc)
         return self.Sc.join(uc, pc - pc.mean())

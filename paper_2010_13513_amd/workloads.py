@@ -96,6 +96,65 @@ def linear_exact():
     return Fields(u, p, f, "linear_exact")
 
 
+# Outflow (natural Neumann) boundary on the face x = 1 (Sec. 2: du/dn = n p on
+# the Neumann part), Dirichlet on the other five faces.
+OUTFLOW_FACES = (1,)
+
+
+def outflow_cube():
+    """Smooth solution satisfying the outflow condition on x = 1:
+    u = (a q, a' chi_y, a' chi_z), p = a' q with a = x^3 - 3 x^2,
+    chi = sin(pi y) sin(pi z), q = 2 pi^2 chi (= -lap_yz chi), so div u = 0,
+    du/dx = (a' q, a'' chi_y, a'' chi_z) = (p, 0, 0) at x = 1 (a''(1) = 0);
+    f = -lap u + grad p = (2 pi^2 a q, (4 pi^2 a' - 6) chi_y, (4 pi^2 a' - 6) chi_z)."""
+    def parts(x, y, z):
+        a = x ** 3 - 3 * x ** 2
+        da = 3 * x ** 2 - 6 * x
+        sy, cy, sz, cz = np.sin(PI * y), np.cos(PI * y), np.sin(PI * z), np.cos(PI * z)
+        chi = sy * sz
+        return a, da, chi, PI * cy * sz, PI * sy * cz
+
+    def u(x, y, z):
+        a, da, chi, chy, chz = parts(x, y, z)
+        return np.stack([a * 2 * PI ** 2 * chi, da * chy, da * chz])
+
+    def p(x, y, z):
+        a, da, chi, _, _ = parts(x, y, z)
+        return da * 2 * PI ** 2 * chi
+
+    def f(x, y, z):
+        a, da, chi, chy, chz = parts(x, y, z)
+        g = 4 * PI ** 2 * da - 6.0
+        return np.stack([2 * PI ** 2 * a * 2 * PI ** 2 * chi, g * chy, g * chz])
+    return Fields(u, p, f, "outflow_cube")
+
+
+def outflow_polynomial(vorder):
+    """Fields inside the element spaces that satisfy the outflow condition on
+    x = 1, so the discrete solution reproduces them: P2-P1 u = (y^2 - z^2,
+    x^2 - 2 x, 3), p = 1 - x, f = (-1, -2, 0); P1-P1 u = (x, -y, 0), p = 1,
+    f = 0."""
+    if vorder == 2:
+        def u(x, y, z):
+            return np.stack([y * y - z * z, x * x - 2 * x, 3.0 + _z(x)])
+
+        def p(x, y, z):
+            return 1.0 - x
+
+        def f(x, y, z):
+            return np.stack([-1.0 + _z(x), -2.0 + _z(x), _z(x)])
+    else:
+        def u(x, y, z):
+            return np.stack([np.asarray(x, float) + _z(x), -np.asarray(y, float) + _z(x), _z(x)])
+
+        def p(x, y, z):
+            return 1.0 + _z(x)
+
+        def f(x, y, z):
+            return np.stack([_z(x)] * 3)
+    return Fields(u, p, f, f"outflow_polynomial_p{vorder}")
+
+
 def fourier_forcing(seed, modes=8, kmax=4):
     """f = sum_m a_m sin(2 pi k_m . x + phi_m); k_m uniform in {-kmax..kmax}^3 \\ 0,
     a_m ~ N(0,1)^3 / |k_m|^2, phi_m ~ U[0, 2 pi); u = 0 on the boundary, p unknown."""
