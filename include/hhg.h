@@ -138,6 +138,20 @@ const char* hhg_last_error(void);
 hhg_status hhg_mesh_cube(hhg_ctx ctx, int macro_refine, hhg_mesh* out);
 hhg_status hhg_mesh_create(hhg_ctx ctx, const double* xyz, int nv, const int* tet, int nt, hhg_mesh* out);
 hhg_status hhg_mesh_info(hhg_mesh mesh, int* nv, int* nt, int* macro_refine);
+/* Natural outflow boundary (Sec. 2: du/dn = n p on the Neumann part of the
+ * boundary, u = w on the Dirichlet part).  faces: bit f marks face f of the
+ * unit cube as outflow (0: x = 0, 1: x = 1, 2: y = 0, 3: y = 1, 4: z = 0,
+ * 5: z = 1); the others stay Dirichlet, and the Dirichlet part is closed (a
+ * site on an edge or corner of a Dirichlet face is Dirichlet).  Default 0 (all
+ * Dirichlet); 63 is refused (HHG_ERR_ARG: the velocity would have a null
+ * space).  Applies to hierarchies created afterwards.  On such a hierarchy the
+ * outflow sites are unknowns of every operator, smoother, transfer and solve;
+ * the pressure is determined, so the solvers do no mean-zero projection
+ * (hhg_project_mean_zero still projects when called); the vectors keep their
+ * layout (the outflow sites hold values, not boundary data:
+ * hhg_copy_boundary skips them); variable viscosity is refused
+ * (HHG_ERR_STATE) and the one-workgroup small-level V-cycle is not used. */
+hhg_status hhg_mesh_set_outflow(hhg_mesh mesh, unsigned faces);
 hhg_status hhg_mesh_destroy(hhg_mesh mesh);
 
 /* ------------------------------------------------------------- hierarchy */
@@ -228,7 +242,8 @@ hhg_status hhg_dots(hhg_hier h, int level, const void* x, const void* y, double*
  * (bit f = family f: 0 apply/residual, 1 boundary pressure rows, 2 vertex
  * Gauss-Seidel colour, 3 edge-group Gauss-Seidel colour, 4 Uzawa pressure
  * step, 5 restriction, 6 prolongation, 7 coarse solve, 8 reductions, 9 other,
- * 10 MLP matrix products, 11 one-workgroup small-level V-cycle)
+ * 10 MLP matrix products, 11 one-workgroup small-level V-cycle, 12
+ * outflow-face rows, Gauss-Seidel sites and transfers)
  * and clears earlier records; mask 0 disables it.  hhg_timer_read synchronises
  * and returns, for one family since the last read, the summed event time in
  * ms, the launches and the work units (sites processed: P2 sites or P1

@@ -99,6 +99,14 @@ struct Level {
   // host copies of the double tables (coarse assembly)
   std::vector<HostStencil> hA, hBT, hB, hC;
   double adiag[8] = {0};
+  // outflow-face sites (ordered by colour; neu_coff[c] .. neu_coff[c + 1] is
+  // colour c) and their row / restriction tables
+  int neu_n = 0;
+  int *neu_pos = nullptr, *neu_slot = nullptr;
+  std::vector<int> neu_coff;
+  NeuTables<double>* neu64 = nullptr;
+  NeuTables<float>* neu32 = nullptr;
+  NeuList neu() const { return NeuList{neu_pos, neu_slot}; }
 };
 
 }  // namespace hhg
@@ -121,6 +129,7 @@ struct hhg_ctx_s {
 struct hhg_mesh_s {
   hhg_ctx ctx = nullptr;
   int mr = 0;
+  unsigned nf = 0;   // outflow faces (hhg_mesh_set_outflow)
   std::vector<double> xyz;
   std::vector<int> tet;
 };
@@ -128,6 +137,7 @@ struct hhg_mesh_s {
 struct hhg_hier_s {
   hhg_ctx ctx = nullptr;
   int disc = 0, mr = 0, lmin = 0, lmax = 0, schur = 0;
+  int nf = 0;        // outflow faces of the domain (Geom::nf)
   int G = 1;
   hhg::Arena arena;
   std::vector<hhg::Level> levels;
@@ -205,6 +215,16 @@ const LevelConst<double>& lconst<double>(Level& lv) {
 template <>
 const LevelConst<float>& lconst<float>(Level& lv) {
   return lv.lc32;
+}
+template <typename T>
+const NeuTables<T>* neutab(Level& lv);
+template <>
+const NeuTables<double>* neutab<double>(Level& lv) {
+  return lv.neu64;
+}
+template <>
+const NeuTables<float>* neutab<float>(Level& lv) {
+  return lv.neu32;
 }
 template <typename T>
 const T* dinv(Level& lv);
@@ -346,10 +366,112 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
         if (i == 0 || j == 0 || k == 0 || i == g.N || j == g.N || k == g.N) bnd.push_back(lin(i, j, k, n1));
   lv.nbnd = (int)bnd.size();
   lv.bnd = a.upload(bnd);
-  // Schur diagonal per node
-  launch_schur_diag<double>(S(h), g, lv.tb64, nullptr, h->schur, lv.dinv64);
-  launch_schur_diag<float>(S(h), g, lv.tb32, nullptr, h->schur, lv.dinv32);
-  HHG_CHECK_HIP(hipGetLastError());
+}
+
+// Outflow faces: the site lists of every level (sites on Neumann faces off the
+// closed Dirichlet part, ordered by Gauss-Seidel colour), their boundary-class
+// A and B^T rows, and for every coarse level the restriction rows of its
+// sites (the interior restriction row -- transpose of the interpolation --
+// without the fine sites outside the cube).
+void build_neumann(hhg_hier h, const ElementSet& es) {
+  const int G = h->G;
+  const int rep[3] = {0, 2, 4};
+  std::vector<std::vector<RestrictEntry>> rvel;
+  std::vector<RestrictEntry> rpres;
+  restriction_entries(G == 1 ? 1 : 2, rvel, rpres);
+  for (int l = h->lmin; l <= h->lmax; ++l) {
+    Level& lv = h->L(l);
+    const Geom& g = lv.g;
+    const int N = g.N, n1 = g.n1, nn = g.nn;
+    const int M = G == 1 ? N : 2 * N;
+    const int ncol = G == 1 ? 4 : 11;
+    std::vector<std::vector<std::pair<int, int>>> bycol(ncol);  // (pos, slot)
+    std::vector<char> used(kNeuSlots, 0);
+    for (int gr = 0; gr < G; ++gr)
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            const int dir[3] = {G == 1 ? 0 : kGroupDir[gr][0], G == 1 ? 0 : kGroupDir[gr][1],
+                                G == 1 ? 0 : kGroupDir[gr][2]};
+            const int c[3] = {i, j, k};
+            int X[3], faces = 0, cls = 0, mul = 1;
+            bool exists = true;
+            for (int d = 0; d < 3; ++d) {
+              X[d] = G == 1 ? c[d] : 2 * c[d] + dir[d];
+              exists = exists && X[d] <= M;
+              faces |= (X[d] == 0 ? 1 : 0) << (2 * d);
+              faces |= (X[d] == M ? 1 : 0) << (2 * d + 1);
+              cls += mul * (X[d] == 0 ? 0 : (X[d] == M ? 2 : 1));
+              mul *= 3;
+            }
+            if (!exists || faces == 0 || (faces & ~h->nf)) continue;
+            const int colour = gr == 0 ? (i + j + k) % 4 : 3 + gr;
+            bycol[colour].push_back({gr * nn + lin(i, j, k, n1), gr * 27 + cls});
+            used[gr * 27 + cls] = 1;
+          }
+    std::vector<int> pos, slot;
+    lv.neu_coff.assign(1, 0);
+    for (int c = 0; c < ncol; ++c) {
+      for (auto& ps : bycol[c]) pos.push_back(ps.first), slot.push_back(ps.second);
+      lv.neu_coff.push_back((int)pos.size());
+    }
+    lv.neu_n = (int)pos.size();
+    lv.neu_pos = h->arena.upload(pos);
+    lv.neu_slot = h->arena.upload(slot);
+    const double sA = lv.h, sB = lv.h * lv.h;
+    NeuTables<double> t64{};
+    NeuTables<float> t32{};
+    for (int sl = 0; sl < kNeuSlots; ++sl) {
+      if (!used[sl]) continue;
+      const int gr = sl / 27, cls = sl % 27;
+      const int ci = rep[cls % 3], cj = rep[(cls / 3) % 3], ck = rep[cls / 9];
+      HostStencil A, BT;
+      double diag = 0.0;
+      for (auto& e : row_stencil(es, 'A', gr, ci, cj, ck, 4)) {
+        if (e.w[0] == 0.0) continue;
+        A.off.push_back((e.g - gr) * nn + lin(e.di, e.dj, e.dk, n1));
+        A.w.push_back(e.w[0] * sA);
+        if (e.g == gr && e.di == 0 && e.dj == 0 && e.dk == 0) diag = e.w[0] * sA;
+      }
+      for (auto& e : row_stencil(es, 'T', gr, ci, cj, ck, 4)) {
+        if (e.w[0] == 0.0 && e.w[1] == 0.0 && e.w[2] == 0.0) continue;
+        BT.off.push_back(lin(e.di, e.dj, e.dk, n1));
+        for (int d = 0; d < 3; ++d) BT.w.push_back(e.w[d] * sB);
+      }
+      HHG_REQUIRE(diag > 0.0, HHG_ERR_STATE, "outflow setup: missing diagonal");
+      t64.A[sl] = upload_stencil<double>(h->arena, A);
+      t32.A[sl] = upload_stencil<float>(h->arena, A);
+      t64.BT[sl] = upload_stencil<double>(h->arena, BT);
+      t32.BT[sl] = upload_stencil<float>(h->arena, BT);
+      t64.adiag_inv[sl] = 1.0 / diag;
+      t32.adiag_inv[sl] = (float)(1.0 / diag);
+      if (l < h->lmax) {  // restriction rows from level l + 1 to these sites
+        const Level& fl = h->L(l + 1);
+        const int n1f = fl.g.n1, nnf = fl.g.nn;
+        const int cc[3] = {cls % 3, (cls / 3) % 3, cls / 9};
+        HostStencil R;
+        for (const auto& e : rvel[gr]) {
+          const int fo[3] = {e.di, e.dj, e.dk};
+          bool inside = true;
+          for (int d = 0; d < 3; ++d) {
+            // fine position relative to the coarse site, in fine site units
+            const int delta = G == 1 ? fo[d] : 2 * fo[d] + kGroupDir[e.g][d] - 2 * kGroupDir[gr][d];
+            if (cc[d] == 0 && delta < 0) inside = false;
+            if (cc[d] == 2 && delta > 0) inside = false;
+          }
+          if (!inside || e.w == 0.0) continue;
+          R.off.push_back(e.g * nnf + lin(e.di, e.dj, e.dk, n1f));
+          R.w.push_back(e.w);
+        }
+        t64.R[sl] = upload_stencil<double>(h->arena, R);
+        t32.R[sl] = upload_stencil<float>(h->arena, R);
+      }
+    }
+    lv.neu64 = h->arena.alloc<NeuTables<double>>(1);
+    lv.neu32 = h->arena.alloc<NeuTables<float>>(1);
+    HHG_CHECK_HIP(hipMemcpy(lv.neu64, &t64, sizeof(t64), hipMemcpyHostToDevice));
+    HHG_CHECK_HIP(hipMemcpy(lv.neu32, &t32, sizeof(t32), hipMemcpyHostToDevice));
+  }
 }
 
 
@@ -426,9 +548,18 @@ void build_coarse(hhg_hier h) {
   const int N = g.N, n1 = g.n1, nn = g.nn, G = g.G;
   std::vector<int> unk;
   std::unordered_map<int, int> pos2u;
+  // velocity unknowns: sites that exist and lie on no Dirichlet face
   auto vint = [&](int gr, int i, int j, int k) {
-    const int dx = G == 1 ? 0 : kGroupDir[gr][0], dy = G == 1 ? 0 : kGroupDir[gr][1], dz = G == 1 ? 0 : kGroupDir[gr][2];
-    return i >= 1 - dx && j >= 1 - dy && k >= 1 - dz && i <= N - 1 && j <= N - 1 && k <= N - 1;
+    const int dir[3] = {G == 1 ? 0 : kGroupDir[gr][0], G == 1 ? 0 : kGroupDir[gr][1], G == 1 ? 0 : kGroupDir[gr][2]};
+    const int c[3] = {i, j, k}, M = G == 1 ? N : 2 * N;
+    int faces = 0;
+    for (int d = 0; d < 3; ++d) {
+      const int X = G == 1 ? c[d] : 2 * c[d] + dir[d];
+      if (X > M) return false;
+      faces |= (X == 0 ? 1 : 0) << (2 * d);
+      faces |= (X == M ? 1 : 0) << (2 * d + 1);
+    }
+    return (faces & ~h->nf) == 0;
   };
   for (int d = 0; d < 3; ++d)
     for (int gr = 0; gr < G; ++gr)
@@ -512,12 +643,15 @@ void ensure_coarse(hhg_hier h) {
   if (h->nunk == 0) return;
   if (!h->kp_ready) {
     HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
-    if (h->L(h->lmin).nu64)
+    if (h->L(h->lmin).nu64 || h->nf)  // rows the host tables do not hold: from the device operator
       build_coarse_device(h);
     else
       build_coarse_pinv(h);
   }
 }
+
+template <typename T>
+void op_apply(hhg_hier h, int l, int opmask, const T* x, const T* b, T* y, bool has_b, bool vel, bool prs);
 
 // Dense coarse operator from the device operator itself (columns = calA e_c
 // restricted to the unknowns, all n columns applied back to back), used when
@@ -538,8 +672,7 @@ void build_coarse_device(hhg_hier h) {
   launch_fill<double>(S(h), h->ce, (size_t)n * vw, 0.0);
   launch_unit_columns(S(h), h->ce, vw, h->unk, n);
   for (int c = 0; c < n; ++c)
-    launch_apply<double>(S(h), lv.g, lv.lc64, lv.tb64, h->ce + c * vw, nullptr, h->cy + c * vw, full_mask(h), false,
-                         true, true, lv.bnd, lv.nbnd);
+    op_apply<double>(h, h->lmin, full_mask(h), h->ce + c * vw, nullptr, h->cy + c * vw, false, true, true);
   std::vector<double> cols((size_t)n * vw), K((size_t)n * n);
   HHG_CHECK_HIP(hipMemcpyAsync(cols.data(), h->cy, cols.size() * sizeof(double), hipMemcpyDeviceToHost, S(h)));
   HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
@@ -585,6 +718,8 @@ template <typename T>
 void op_apply(hhg_hier h, int l, int opmask, const T* x, const T* b, T* y, bool has_b, bool vel, bool prs) {
   Level& lv = h->L(l);
   launch_apply<T>(S(h), lv.g, lconst<T>(lv), tables<T>(lv), x, b, y, opmask, has_b, vel, prs, lv.bnd, lv.nbnd);
+  if (vel && lv.neu_n)  // outflow-face velocity rows (boundary rows to the grid-wide kernels)
+    launch_neu_rows<T>(S(h), lv.g, neutab<T>(lv), lv.neu(), 0, lv.neu_n, x, b, y, opmask & 3, has_b);
   round_out<T>(h, l, y, 0, 0, lv.vec_words, 1);
 }
 
@@ -608,6 +743,8 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
   T* r = rbuf<T>(lv);
   auto colour = [&](int c) {  // colour c < 4 writes the vertex group, c >= 4 the edge group c - 3
     launch_gs_colour<T>(S(h), lv.g, lconst<T>(lv), x, b, c);
+    if (lv.neu_n)
+      launch_neu_gs<T>(S(h), lv.g, neutab<T>(lv), lv.neu(), lv.neu_coff[c], lv.neu_coff[c + 1] - lv.neu_coff[c], x, b);
     round_out<T>(h, l, x, lv.g.vstride, c < 4 ? 0 : (size_t)(c - 3) * lv.g.nn, lv.g.nn, 3);
   };
   for (int it = 0; it < iters; ++it) {
@@ -629,8 +766,19 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
   }
 }
 
+// Zero pressure mean (int p = 0, Sec. 2), the normalisation of the pressure
+// inside the solvers; with an outflow face the pressure is determined and
+// nothing is done.  hhg_project_mean_zero always projects (op_mean_zero_always).
+template <typename T>
+void op_mean_zero_always(hhg_hier h, int l, T* x) {
+  Level& lv = h->L(l);
+  T* p = x + 3 * (size_t)lv.g.vstride;
+  launch_mean_zero<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
+  round_out<T>(h, l, p, 0, 0, lv.g.nn, 1);
+}
 template <typename T>
 void op_mean_zero(hhg_hier h, int l, T* x) {
+  if (h->nf) return;
   Level& lv = h->L(l);
   T* p = x + 3 * (size_t)lv.g.vstride;
   launch_mean_zero<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
@@ -642,7 +790,9 @@ void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
   Level& f = h->L(lf);
   Level& c = h->L(lf - 1);
   launch_restrict<T>(S(h), f.g, c.g, ttables<T>(f), rf, rc);
+  if (c.neu_n) launch_neu_restrict<T>(S(h), f.g, c.g, neutab<T>(c), c.neu(), c.neu_n, rf, rc);
   round_out<T>(h, lf - 1, rc, 0, 0, c.vec_words, 1);
+  if (h->nf) return;  // no null vector: no compatibility shift
   T* p = rc + 3 * (size_t)c.g.vstride;
   launch_mean_zero<T>(S(h), c.g, tables<T>(c), p, h->partial, h->sums, 1);
   round_out<T>(h, lf - 1, p, 0, 0, c.g.nn, 1);
@@ -653,6 +803,8 @@ void op_prolong(hhg_hier h, int lc, const T* xc, T* xf, bool add, bool skip_bnd)
   Level& c = h->L(lc);
   Level& f = h->L(lc + 1);
   launch_prolong<T>(S(h), c.g, f.g, ttables<T>(f), xc, xf, add, skip_bnd);
+  if (add && skip_bnd && f.neu_n)  // the outflow sites the grid-wide kernel skipped as boundary
+    launch_neu_prolong<T>(S(h), c.g, f.g, ttables<T>(f), f.neu(), f.neu_n, xc, xf);
   round_out<T>(h, lc + 1, xf, 0, 0, f.vec_words, 1);
 }
 
@@ -804,7 +956,7 @@ void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_para
   // pseudo-inverse rebuild)
   const bool mlp_on = std::is_same<T, double>::value && h->mlp && !h->mlp_off;
   if (vel_sites(h->L(l)) <= h->fused_sites && !h->slv_stale && p.coarse_smooth == 0 && h->nunk > 0 && !mlp_on &&
-      h->rec_n >= h->rec_cap && !h->kp_stale && h->kp_ready &&
+      h->rec_n >= h->rec_cap && !h->kp_stale && h->kp_ready && h->nf == 0 &&
       (std::is_same<T, double>::value || h->L(h->lmin).cx32)) {
     SmallCycle<T> sc{};
     sc.nlev = l - h->lmin + 1;
@@ -1138,6 +1290,14 @@ hhg_status hhg_mesh_create(hhg_ctx ctx, const double* xyz, int nv, const int* te
   });
 }
 
+hhg_status hhg_mesh_set_outflow(hhg_mesh mesh, unsigned faces) {
+  return guard([&] {
+    HHG_REQUIRE(mesh, HHG_ERR_ARG, "null mesh");
+    HHG_REQUIRE(faces < 63u, HHG_ERR_ARG, "outflow faces: a mask of faces 0..5 with at least one Dirichlet face");
+    mesh->nf = faces;
+  });
+}
+
 hhg_status hhg_mesh_info(hhg_mesh mesh, int* nv, int* nt, int* macro_refine) {
   return guard([&] {
     HHG_REQUIRE(mesh, HHG_ERR_ARG, "null mesh");
@@ -1166,6 +1326,7 @@ hhg_status hhg_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg
     HHG_CHECK_HIP(hipSetDevice(ctx->device));
     std::unique_ptr<hhg_hier_s> h(new hhg_hier_s);
     h->ctx = ctx;
+    h->nf = (int)mesh->nf;
     h->disc = disc;
     h->mr = macro_refine;
     h->lmin = lmin;
@@ -1187,6 +1348,7 @@ hhg_status hhg_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg
       lv.g.nn = (N + 1) * (N + 1) * (N + 1);
       lv.g.G = h->G;
       lv.g.vstride = h->G * lv.g.nn;
+      lv.g.nf = h->nf;
       lv.h = 1.0 / N;
       lv.vec_words = 3 * (size_t)lv.g.vstride + lv.g.nn;
       build_level_tables(h.get(), lv, es);
@@ -1204,6 +1366,13 @@ hhg_status hhg_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg
       launch_fill<double>(ctx->stream, lv.xs, lv.vec_words, 0.0);
     }
     for (int l = lmin + 1; l <= lmax; ++l) build_transfer(h.get(), h->L(l - 1), h->L(l));
+    if (h->nf) build_neumann(h.get(), es);
+    for (int l = lmin; l <= lmax; ++l) {  // Schur diagonal per pressure node
+      Level& lv = h->L(l);
+      launch_schur_diag<double>(ctx->stream, lv.g, lv.tb64, nullptr, schur, lv.dinv64, lv.neu64);
+      launch_schur_diag<float>(ctx->stream, lv.g, lv.tb32, nullptr, schur, lv.dinv32, lv.neu32);
+    }
+    HHG_CHECK_HIP(hipGetLastError());
     build_coarse(h.get());
     small_kernel_attributes();
     refresh_small(h.get());
@@ -1321,6 +1490,7 @@ hhg_status hhg_rhs(hhg_hier h, int level, const void* f, void* b, hhg_prec prec)
     Level& lv = h->L(level);
     HHG_DISPATCH(prec, {
       launch_rhs<T>(S(h), lv.g, lconst<T>(lv), (const T*)f, (T*)b);
+      if (lv.neu_n) launch_neu_rhs<T>(S(h), lv.g, tables<T>(lv), lv.neu(), lv.neu_n, (const T*)f, (T*)b);
       round_out<T>(h, level, (T*)b, 0, 0, lv.vec_words, 1);
     });
     HHG_CHECK_HIP(hipGetLastError());
@@ -1373,7 +1543,7 @@ hhg_status hhg_project_mean_zero(hhg_hier h, int level, void* x, hhg_prec prec) 
   return guard([&] {
     check_level(h, level);
     HHG_REQUIRE(x, HHG_ERR_ARG, "null vector");
-    HHG_DISPATCH(prec, op_mean_zero<T>(h, level, (T*)x));
+    HHG_DISPATCH(prec, op_mean_zero_always<T>(h, level, (T*)x));
     HHG_CHECK_HIP(hipGetLastError());
   });
 }
@@ -1419,8 +1589,13 @@ hhg_status hhg_estimate_omega(hhg_hier h, int level, const double* v0, int iters
     for (int it = 0; it < iters; ++it) {
       op_apply<double>(h, level, 2, v, nullptr, y, false, true, false);   // B^T v
       launch_fill<double>(s, z, lv.vec_words, 0.0);
-      for (int c = 0; c < ncol; ++c) launch_gs_colour<double>(s, g, lv.lc64, z, y, c);
-      for (int c = ncol - 1; c >= 0; --c) launch_gs_colour<double>(s, g, lv.lc64, z, y, c);
+      auto colour = [&](int c) {
+        launch_gs_colour<double>(s, g, lv.lc64, z, y, c);
+        if (lv.neu_n)
+          launch_neu_gs<double>(s, g, lv.neu64, lv.neu(), lv.neu_coff[c], lv.neu_coff[c + 1] - lv.neu_coff[c], z, y);
+      };
+      for (int c = 0; c < ncol; ++c) colour(c);
+      for (int c = ncol - 1; c >= 0; --c) colour(c);
       launch_scaled_copy<double>(s, z + vs3, v + vs3, nullptr, g.nn, -1.0);
       op_apply<double>(h, level, full_mask(h) & 12, z, nullptr, y, false, false, true);  // B z + C v
       launch_scaled_copy<double>(s, v + vs3, y + vs3, lv.dinv64, g.nn, 1.0);         // w = D^{-1}(...)
@@ -1469,6 +1644,7 @@ hhg_status hhg_set_viscosity(hhg_hier h, int level, const double* nu) {
   return guard([&] {
     check_level(h, level);
     HHG_REQUIRE(nu, HHG_ERR_ARG, "null viscosity");
+    HHG_REQUIRE(h->nf == 0, HHG_ERR_STATE, "variable viscosity with an outflow face is not supported");
     Level& lv = h->L(level);
     hipStream_t s = S(h);
     const size_t nn = lv.g.nn;
@@ -1486,8 +1662,8 @@ hhg_status hhg_set_viscosity(hhg_hier h, int level, const double* nu) {
     lv.lc32.ainv_site = lv.ainvs32;
     launch_nu_diag<double>(s, lv.g, lv.lc64, lv.ainvs64);
     launch_nu_diag<float>(s, lv.g, lv.lc32, lv.ainvs32);
-    launch_schur_diag<double>(s, lv.g, lv.tb64, lv.ainvs64, h->schur, lv.dinv64);
-    launch_schur_diag<float>(s, lv.g, lv.tb32, lv.ainvs32, h->schur, lv.dinv32);
+    launch_schur_diag<double>(s, lv.g, lv.tb64, lv.ainvs64, h->schur, lv.dinv64, lv.neu64);
+    launch_schur_diag<float>(s, lv.g, lv.tb32, lv.ainvs32, h->schur, lv.dinv32, lv.neu32);
     h->slv_stale = true;
     if (h->fmg_exec) {  // a captured solve holds the old operator
       HHG_CHECK_HIP(hipGraphExecDestroy(h->fmg_exec));

@@ -5,9 +5,37 @@
 namespace hhg {
 
 // Geometry of one level: N intervals, n1 = N + 1 nodes per edge, nn = n1^3
-// words per lattice array, G velocity groups (1: P1, 8: P2), vstride = G nn.
+// words per lattice array, G velocity groups (1: P1, 8: P2), vstride = G nn,
+// nf = faces with the natural outflow condition (bit f: face f of the unit
+// cube, 0: x = 0, 1: x = 1, 2: y = 0, 3: y = 1, 4: z = 0, 5: z = 1; the
+// others are Dirichlet).
 struct Geom {
-  int N, n1, nn, G, vstride;
+  int N, n1, nn, G, vstride, nf;
+};
+
+// Outflow-face velocity rows (Sec. 2, natural boundary condition): sites on
+// Neumann faces (off the closed Dirichlet part) are unknowns whose rows are
+// the element sums inside the cube, i.e. the boundary-class rows of their
+// group.  Tables per (group, boundary class) = g * 27 + cls (cls = c_x + 3 c_y
+// + 9 c_z with c = 0 low face, 1 inside, 2 high face, for the site's doubled
+// coordinates): A rows (offsets relative to the site's array position,
+// weights scaled to the level), B^T rows (offsets relative to the group-0
+// index, three weights), 1 / a_ii, and the restriction rows from the next
+// finer level (offsets relative to the fine group-0 index of 2 (i, j, k),
+// fine group shift included) of the coarse sites of that level's list.
+constexpr int kNeuSlots = 8 * 27;
+template <typename T>
+struct NeuTables {
+  DStencil<T> A[kNeuSlots];
+  DStencil<T> BT[kNeuSlots];
+  DStencil<T> R[kNeuSlots];
+  T adiag_inv[kNeuSlots];
+};
+// One list of outflow sites of a level, ordered by Gauss-Seidel colour: site
+// q has array position pos[q] (group g nn + index) and table slot slot[q].
+struct NeuList {
+  const int* pos;
+  const int* slot;
 };
 
 // Per-level constants of the generated interior stencils (weights at h = 1):
@@ -55,7 +83,8 @@ enum KernelFamily {
   KF_OTHER = 9,
   KF_MLP = 10,      // MLP matrix products (work units: flops)
   KF_SMALL = 11,    // one-workgroup V-cycle over the small levels
-  KF_COUNT = 12
+  KF_NEUMANN = 12,  // outflow-face rows, Gauss-Seidel and transfers
+  KF_COUNT = 13
 };
 void timer_set_mask(unsigned mask);
 bool timer_enabled();
@@ -140,7 +169,28 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* 
 template <typename T>
 void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, const T* rp, T omega);
 template <typename T>
-void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* ainv_site, int mode, T* dinv);
+void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* ainv_site, int mode, T* dinv,
+                       const NeuTables<T>* nt);
+// Outflow-face kernels over the sites [first, first + n) of a level's list.
+// Rows: y = [b -] (A (opmask 1) + B^T (opmask 2)) x at the sites.
+template <typename T>
+void launch_neu_rows(hipStream_t s, const Geom& g, const NeuTables<T>* nt, NeuList L, int first, int n, const T* x,
+                     const T* b, T* y, int opmask, bool has_b);
+// One Gauss-Seidel colour at the sites (the caller passes that colour's range).
+template <typename T>
+void launch_neu_gs(hipStream_t s, const Geom& g, const NeuTables<T>* nt, NeuList L, int first, int n, T* x,
+                   const T* b);
+// b = M f at the sites (boundary-class velocity mass rows of tb).
+template <typename T>
+void launch_neu_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, NeuList L, int n, const T* f, T* b);
+// Coarse sites (list and tables of the coarse level): rc = R rf.
+template <typename T>
+void launch_neu_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const NeuTables<T>* ntc, NeuList Lc, int n,
+                         const T* rf, T* rc);
+// Fine sites (list of the fine level): xf += I xc (interpolation tables of the fine level).
+template <typename T>
+void launch_neu_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, NeuList Lf, int n,
+                        const T* xc, T* xf);
 template <typename T>
 void launch_nu_diag(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* ainv_site);
 template <typename T>

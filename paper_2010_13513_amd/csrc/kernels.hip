@@ -112,6 +112,21 @@ __device__ __forceinline__ bool vel_exists(int g, int i, int j, int k, int N) {
 }
 __device__ __forceinline__ int bcls3(int c, int N) { return c == 0 ? 0 : (c == N ? 2 : 1); }
 
+// Faces of the cube a velocity site lies on (bit f as in Geom::nf), from its
+// position in site units (doubled for P2).
+__device__ __forceinline__ int site_faces(int X, int Y, int Z, int M) {
+  return (X == 0) | ((X == M) << 1) | ((Y == 0) << 2) | ((Y == M) << 3) | ((Z == 0) << 4) | ((Z == M) << 5);
+}
+// The velocity site is an unknown: it exists and lies on no Dirichlet face
+// (interior sites, and sites whose faces are all outflow faces).
+template <int G>
+__device__ __forceinline__ bool vel_unknown(const Geom& g, int gr, int i, int j, int k) {
+  if (!vel_exists<G>(gr, i, j, k, g.N)) return false;
+  const int f = G == 1 ? site_faces(i, j, k, g.N)
+                       : site_faces(2 * i + gdx(gr), 2 * j + gdy(gr), 2 * k + gdz(gr), 2 * g.N);
+  return (f & ~g.nf) == 0;
+}
+
 unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // ------------------------------------------------------------ event timer
@@ -643,7 +658,7 @@ __global__ void __launch_bounds__(kBlock) k_pstep(int nn, const T* __restrict__ 
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_schur_diag(Geom g, const Tables<T>* __restrict__ tb,
                                                        const T* __restrict__ ainv_site, int mode,
-                                                       T* __restrict__ dinv) {
+                                                       T* __restrict__ dinv, const NeuTables<T>* __restrict__ nt) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= g.nn) return;
   int i, j, k;
@@ -663,10 +678,17 @@ __global__ void __launch_bounds__(kBlock) k_schur_diag(Geom g, const Tables<T>* 
       const int cc = code[e];
       const int gr = cc & 15;
       const int ii = i + ((cc >> 4) & 15) - 2, jj = j + ((cc >> 8) & 15) - 2, kk = k + ((cc >> 12) & 15) - 2;
-      if (!vel_interior<G>(gr, ii, jj, kk, N)) continue;
+      if (!vel_unknown<G>(g, gr, ii, jj, kk)) continue;
       const double w0 = s.w[3 * e], w1 = s.w[3 * e + 1], w2 = s.w[3 * e + 2];
-      const double ai = ainv_site ? (double)ainv_site[gr * g.nn + ii + g.n1 * (jj + g.n1 * kk)]
-                                  : (double)tb->adiag_inv[gr];
+      double ai;
+      if (!vel_interior<G>(gr, ii, jj, kk, N)) {  // outflow-face site: its boundary-class row
+        const int sx = G == 1 ? bcls3(ii, N) : (gdx(gr) ? 1 : bcls3(ii, N));
+        const int sy = G == 1 ? bcls3(jj, N) : (gdy(gr) ? 1 : bcls3(jj, N));
+        const int sz = G == 1 ? bcls3(kk, N) : (gdz(gr) ? 1 : bcls3(kk, N));
+        ai = (double)nt->adiag_inv[gr * 27 + sx + 3 * sy + 9 * sz];
+      } else {
+        ai = ainv_site ? (double)ainv_site[gr * g.nn + ii + g.n1 * (jj + g.n1 * kk)] : (double)tb->adiag_inv[gr];
+      }
       d += (w0 * w0 + w1 * w1 + w2 * w2) * ai;
     }
   }
@@ -913,7 +935,7 @@ __global__ void __launch_bounds__(kBlock) k_inject_boundary(Geom gf, Geom gc, co
   decode(t, gc.n1, i, j, k);
 #pragma unroll
   for (int gr = 0; gr < G; ++gr) {
-    if (!vel_exists<G>(gr, i, j, k, gc.N) || vel_interior<G>(gr, i, j, k, gc.N)) continue;
+    if (!vel_exists<G>(gr, i, j, k, gc.N) || vel_unknown<G>(gc, gr, i, j, k)) continue;
     int fi, fj, fk;
     if (G == 1) {
       fi = 2 * i, fj = 2 * j, fk = 2 * k;
@@ -936,7 +958,7 @@ __global__ void __launch_bounds__(kBlock) k_copy_boundary(Geom g, const T* __res
   decode(t, g.n1, i, j, k);
 #pragma unroll
   for (int gr = 0; gr < G; ++gr) {
-    if (!vel_exists<G>(gr, i, j, k, g.N) || vel_interior<G>(gr, i, j, k, g.N)) continue;
+    if (!vel_exists<G>(gr, i, j, k, g.N) || vel_unknown<G>(g, gr, i, j, k)) continue;
     const int pos = gr * g.nn + t;
     dst[pos] = src[pos];
     dst[g.vstride + pos] = src[g.vstride + pos];
@@ -1139,6 +1161,110 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_axpy(T* __restrict__ y, const T* __restrict__ x, long n, T a) {
   const long t = (long)blockIdx.x * kBlock + threadIdx.x;
   if (t < n) y[t] += a * x[t];
+}
+
+// ------------------------------------------------- outflow faces
+// Sites of a Neumann face (Sec. 2, natural outflow condition) are unknowns
+// with truncated rows: the elements outside the cube are missing.  Few sites
+// (O(N^2)), so the rows are table-driven (NeuTables, one per group and
+// boundary class); the grid-wide kernels treat these sites as boundary sites
+// and these kernels fill in their rows afterwards.  blockIdx.y = velocity
+// component d; every table offset stays inside the cube.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_neu_rows(Geom g, const NeuTables<T>* __restrict__ nt, NeuList L,
+                                                     int first, int n, const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y, int opmask,
+                                                     int has_b) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int d = blockIdx.y;
+  const int pos = L.pos[first + q], sl = L.slot[first + q];
+  const int t = pos % g.nn;
+  const T* ud = x + (size_t)d * g.vstride;
+  const T* p = x + 3 * (size_t)g.vstride;
+  T r = 0;
+  if (opmask & 1) {
+    const DStencil<T> A = nt->A[sl];
+    for (int e = 0; e < A.n; ++e) r += A.w[e] * ud[pos + A.off[e]];
+  }
+  if (opmask & 2) {
+    const DStencil<T> BT = nt->BT[sl];
+    for (int e = 0; e < BT.n; ++e) r += BT.w[3 * e + d] * p[t + BT.off[e]];
+  }
+  const size_t o = (size_t)d * g.vstride + pos;
+  y[o] = has_b ? b[o] - r : r;
+}
+
+// u_d += (f_d - A u_d - (B^T p)_d) / a_ii at the sites of one colour (no two
+// sites of a colour are coupled, so the order inside the launch is free).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_neu_gs(Geom g, const NeuTables<T>* __restrict__ nt, NeuList L, int first,
+                                                   int n, T* __restrict__ x, const T* __restrict__ b) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int d = blockIdx.y;
+  const int pos = L.pos[first + q], sl = L.slot[first + q];
+  const int t = pos % g.nn;
+  T* ud = x + (size_t)d * g.vstride;
+  const T* p = x + 3 * (size_t)g.vstride;
+  const DStencil<T> A = nt->A[sl];
+  const DStencil<T> BT = nt->BT[sl];
+  T r = b[(size_t)d * g.vstride + pos];
+  for (int e = 0; e < A.n; ++e) r -= A.w[e] * ud[pos + A.off[e]];
+  for (int e = 0; e < BT.n; ++e) r -= BT.w[3 * e + d] * p[t + BT.off[e]];
+  ud[pos] += r * nt->adiag_inv[sl];
+}
+
+// b = M f at the sites: the consistent velocity mass rows of the boundary
+// classes (Tables::Mfull, same slot numbering).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_neu_rhs(Geom g, const Tables<T>* __restrict__ tb, NeuList L, int n,
+                                                    const T* __restrict__ f, T* __restrict__ b) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int d = blockIdx.y;
+  const int pos = L.pos[q];
+  const DStencil<T> M = tb->Mfull[L.slot[q]];
+  const T* fd = f + (size_t)d * g.vstride;
+  T a = 0;
+  for (int e = 0; e < M.n; ++e) a += M.w[e] * fd[pos + M.off[e]];
+  b[(size_t)d * g.vstride + pos] = a;
+}
+
+// Coarse outflow sites: rc = sum of R-weights times the fine residual (the
+// transpose of the interpolation, limited to fine sites inside the cube).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_neu_restrict(Geom gf, Geom gc, const NeuTables<T>* __restrict__ ntc,
+                                                         NeuList Lc, int n, const T* __restrict__ rf,
+                                                         T* __restrict__ rc) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int d = blockIdx.y;
+  const int pos = Lc.pos[q];
+  const int t = pos % gc.nn;
+  int i, j, k;
+  decode(t, gc.n1, i, j, k);
+  const int fb = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
+  const DStencil<T> R = ntc->R[Lc.slot[q]];
+  const T* r = rf + (size_t)d * gf.vstride;
+  T a = 0;
+  for (int e = 0; e < R.n; ++e) a += R.w[e] * r[fb + R.off[e]];
+  rc[(size_t)d * gc.vstride + pos] = a;
+}
+
+// Fine outflow sites: xf += I xc, the interpolation of the grid-wide
+// prolongation at these sites (which it skips as boundary sites).
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_neu_prolong(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
+                                                        NeuList Lf, int n, const T* __restrict__ xc,
+                                                        T* __restrict__ xf) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int pos = Lf.pos[q];
+  const int gr = pos / gf.nn, t = pos - gr * gf.nn;
+  int i, j, k;
+  decode(t, gf.n1, i, j, k);
+  prolong_slice<T, G>(gc, gf, tt, xc, xf, 1, 0, t, i, j, k, 3 * gr + (int)blockIdx.y);
 }
 
 // ------------------------------------------------- small-level V-cycle
@@ -1632,11 +1758,54 @@ void launch_pressure_step(hipStream_t s, const Geom& g, const T* dinv, T* x, con
 }
 
 template <typename T>
-void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* ainv_site, int mode, T* dinv) {
+void launch_schur_diag(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* ainv_site, int mode, T* dinv,
+                       const NeuTables<T>* nt) {
   if (g.G == 1)
-    HHG_LAUNCH((k_schur_diag<T, 1>), nblocks(g.nn), s, g, tb, ainv_site, mode, dinv);
+    HHG_LAUNCH((k_schur_diag<T, 1>), nblocks(g.nn), s, g, tb, ainv_site, mode, dinv, nt);
   else
-    HHG_LAUNCH((k_schur_diag<T, 8>), nblocks(g.nn), s, g, tb, ainv_site, mode, dinv);
+    HHG_LAUNCH((k_schur_diag<T, 8>), nblocks(g.nn), s, g, tb, ainv_site, mode, dinv, nt);
+}
+
+template <typename T>
+void launch_neu_rows(hipStream_t s, const Geom& g, const NeuTables<T>* nt, NeuList L, int first, int n, const T* x,
+                     const T* b, T* y, int opmask, bool has_b) {
+  if (n <= 0 || !(opmask & 3)) return;
+  KScope ks(s, KF_NEUMANN, n);
+  hipLaunchKernelGGL((k_neu_rows<T>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, nt, L, first, n, x, b, y, opmask,
+                     (int)has_b);
+}
+
+template <typename T>
+void launch_neu_gs(hipStream_t s, const Geom& g, const NeuTables<T>* nt, NeuList L, int first, int n, T* x,
+                   const T* b) {
+  if (n <= 0) return;
+  KScope ks(s, KF_NEUMANN, n);
+  hipLaunchKernelGGL((k_neu_gs<T>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, nt, L, first, n, x, b);
+}
+
+template <typename T>
+void launch_neu_rhs(hipStream_t s, const Geom& g, const Tables<T>* tb, NeuList L, int n, const T* f, T* b) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_neu_rhs<T>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, g, tb, L, n, f, b);
+}
+
+template <typename T>
+void launch_neu_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const NeuTables<T>* ntc, NeuList Lc, int n,
+                         const T* rf, T* rc) {
+  if (n <= 0) return;
+  KScope ks(s, KF_NEUMANN, n);
+  hipLaunchKernelGGL((k_neu_restrict<T>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, gf, gc, ntc, Lc, n, rf, rc);
+}
+
+template <typename T>
+void launch_neu_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, NeuList Lf, int n,
+                        const T* xc, T* xf) {
+  if (n <= 0) return;
+  KScope ks(s, KF_NEUMANN, n);
+  if (gf.G == 1)
+    hipLaunchKernelGGL((k_neu_prolong<T, 1>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, gc, gf, tt, Lf, n, xc, xf);
+  else
+    hipLaunchKernelGGL((k_neu_prolong<T, 8>), dim3(nblocks(n), 3), dim3(kBlock), 0, s, gc, gf, tt, Lf, n, xc, xf);
 }
 
 template <typename T>
@@ -1870,7 +2039,16 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
                                 const T*, T*, int, bool, bool, bool, const int*, int);                              \
   template void launch_gs_colour<T>(hipStream_t, const Geom&, const LevelConst<T>&, T*, const T*, int);             \
   template void launch_pressure_step<T>(hipStream_t, const Geom&, const T*, T*, const T*, T);                       \
-  template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, int, T*);                \
+  template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, int, T*,                 \
+                                     const NeuTables<T>*);                                                          \
+  template void launch_neu_rows<T>(hipStream_t, const Geom&, const NeuTables<T>*, NeuList, int, int, const T*,      \
+                                   const T*, T*, int, bool);                                                        \
+  template void launch_neu_gs<T>(hipStream_t, const Geom&, const NeuTables<T>*, NeuList, int, int, T*, const T*);   \
+  template void launch_neu_rhs<T>(hipStream_t, const Geom&, const Tables<T>*, NeuList, int, const T*, T*);          \
+  template void launch_neu_restrict<T>(hipStream_t, const Geom&, const Geom&, const NeuTables<T>*, NeuList, int,    \
+                                       const T*, T*);                                                               \
+  template void launch_neu_prolong<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, NeuList,     \
+                                      int, const T*, T*);                                                           \
   template void launch_nu_diag<T>(hipStream_t, const Geom&, const LevelConst<T>&, T*);                              \
   template void launch_rhs<T>(hipStream_t, const Geom&, const LevelConst<T>&, const T*, T*);                        \
   template void launch_mass<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                           \

@@ -20,7 +20,7 @@ HHG_SCHUR_SD, HHG_SCHUR_ML = 0, 1
 
 SYMBOLS = [
     "hhg_ctx_create", "hhg_ctx_set_stream", "hhg_ctx_destroy", "hhg_last_error",
-    "hhg_mesh_cube", "hhg_mesh_create", "hhg_mesh_info", "hhg_mesh_destroy",
+    "hhg_mesh_cube", "hhg_mesh_create", "hhg_mesh_info", "hhg_mesh_destroy", "hhg_mesh_set_outflow",
     "hhg_hier_create", "hhg_hier_destroy", "hhg_vec_layout", "hhg_vec_from_lattice", "hhg_vec_to_lattice",
     "hhg_apply", "hhg_residual", "hhg_rhs", "hhg_smooth", "hhg_restrict", "hhg_prolong_add",
     "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
@@ -31,7 +31,7 @@ SYMBOLS = [
     "hhg_record_pairs", "hhg_recorded_pairs", "hhg_hier_set_fused_sites", "hhg_hier_set_bf16_levels",
 ]
 KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER, \
-    KF_MLP, KF_SMALL = range(12)
+    KF_MLP, KF_SMALL, KF_NEUMANN = range(13)
 
 
 class HHGError(RuntimeError):
@@ -78,6 +78,7 @@ def load():
         "hhg_mesh_create": [P, P, I, P, I, P],
         "hhg_mesh_info": [P, P, P, P],
         "hhg_mesh_destroy": [P],
+        "hhg_mesh_set_outflow": [P, ctypes.c_uint],
         "hhg_hier_create": [P, I, I, I, I, P],
         "hhg_hier_destroy": [P],
         "hhg_vec_layout": [P, I, P, P, P, P],
@@ -184,6 +185,10 @@ def hhg_mesh_info(mesh):
     nv, nt, mr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check(load().hhg_mesh_info(mesh, ctypes.byref(nv), ctypes.byref(nt), ctypes.byref(mr)))
     return nv.value, nt.value, mr.value
+
+
+def hhg_mesh_set_outflow(mesh, faces):
+    _check(load().hhg_mesh_set_outflow(mesh, int(faces)))
 
 
 def hhg_mesh_destroy(mesh):

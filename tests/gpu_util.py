@@ -16,7 +16,7 @@ def torch_cuda():
 class Lib:
     """One context + hierarchy on cuda:0, on torch's current stream."""
 
-    def __init__(self, disc, lmin, lmax, macro_refine=0, schur=hhg.HHG_SCHUR_SD):
+    def __init__(self, disc, lmin, lmax, macro_refine=0, schur=hhg.HHG_SCHUR_SD, outflow=0):
         torch = torch_cuda()
         self.torch = torch
         self.dev = torch.device("cuda:0")
@@ -24,6 +24,8 @@ class Lib:
         self.ctx = hhg.hhg_ctx_create(0, stream)
         mesh = hhg.hhg_mesh_cube(self.ctx, macro_refine)
         try:
+            if outflow:
+                hhg.hhg_mesh_set_outflow(mesh, outflow)
             self.h = hhg.hhg_hier_create(mesh, disc, lmin, lmax, schur)
         finally:
             hhg.hhg_mesh_destroy(mesh)
@@ -89,7 +91,7 @@ def assert_blocks(lib, level, got, want, tol, what=""):
     return eu, ep
 
 
-def coarse_tolerance(vorder, N, nu_nodes=None):
+def coarse_tolerance(vorder, N, nu_nodes=None, neumann=()):
     """Parity tolerance for results that pass through the coarsest-level
     solve.  Both sides apply a pseudo-inverse of the same dense coarse
     operator, each computed independently by a backward-stable decomposition
@@ -100,6 +102,6 @@ def coarse_tolerance(vorder, N, nu_nodes=None):
     than the 1e-12 of every other step."""
     from oracle import coarse as ocoarse, fe
     from oracle.stokes import Stokes
-    cs = ocoarse.CoarseSolver(Stokes(fe.Level(N, vorder, nu_nodes)))
+    cs = ocoarse.CoarseSolver(Stokes(fe.Level(N, vorder, nu_nodes, neumann)))
     kappa = float(cs.sv[0] / cs.sv[cs.rank - 1])
     return max(1e-12, 2.0 * kappa * 2.0 ** -52), kappa
