@@ -324,6 +324,19 @@ hhg_status hhg_mlp_loss_grad(hhg_mlp m, const float* x, const float* y, int batc
  * final epoch. */
 hhg_status hhg_mlp_train(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs, float lr,
                          const int* order, double* last_loss);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc):
+ * hhg_mlp_train without allocation.  Same arguments, arithmetic and results
+ * as hhg_mlp_train (bit for bit), but the device copy of the sample order and
+ * the per-epoch loss accumulators live in a static device array of the
+ * library (one per GPU, 8 MiB + 32 KiB, held until the process ends) instead
+ * of memory allocated per call; the call makes no hipMalloc / hipFree.
+ * Limits: epochs * n_samples <= 2^21 and epochs <= 4096, else HHG_ERR_ARG.
+ * Every call on a GPU shares that array: calls that overlap on one GPU (other
+ * threads, other contexts or streams of the same device) race and must be
+ * serialised by the caller.  Synchronous. */
+hhg_status hhg_mlp_train_noalloc(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs,
+                                 float lr, const int* order, double* last_loss);
 /* Feature and output sizes of the learned coarse solve of this hierarchy:
  * n_out = coarse unknowns (interior velocity, then pressure), n_in = n_out +
  * P1 nodes of the coarsest level. */

@@ -122,7 +122,18 @@ struct hhg_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;  // private stream for HIP-graph capture
+  unsigned char* scratch = nullptr;  // this device's address of the static scratch array
 };
+
+// Static device scratch of the allocation-free entry point
+// (hhg_mlp_train_noalloc): loss accumulators of up to kScratchEpochs epochs,
+// then the sample order of up to kScratchOrder minibatch slots.  One copy per
+// device, held until the process ends; in host code `scratch` is only a
+// symbol: its device address comes from hipGetSymbolAddress (hhg_ctx_create).
+constexpr size_t kScratchEpochs = 4096;
+constexpr size_t kScratchOrder = (size_t)1 << 21;
+constexpr size_t kScratchBytes = kScratchEpochs * sizeof(double) + kScratchOrder * sizeof(int);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 // Macro mesh T_0 (host data): vertex coordinates, tetrahedra, and the number
 // of Bey steps between the six-tetrahedron Kuhn cube and it.
@@ -1244,9 +1255,12 @@ hhg_status hhg_ctx_create(int device, void* stream, hhg_ctx* out) {
     HHG_CHECK_HIP(hipGetDeviceCount(&n));
     HHG_REQUIRE(device >= 0 && device < n, HHG_ERR_ARG, "device out of range");
     HHG_CHECK_HIP(hipSetDevice(device));
+    void* sp = nullptr;  // the scratch array's address on this device
+    HHG_CHECK_HIP(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
     auto* c = new hhg_ctx_s;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    c->scratch = (unsigned char*)sp;
     *out = c;
   });
 }
@@ -1809,18 +1823,44 @@ hhg_status hhg_mlp_loss_grad(hhg_mlp m, const float* x, const float* y, int batc
   });
 }
 
+namespace hhg {
+namespace {
+// Checks of a training call; returns the number of order entries.
+size_t check_train_args(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs, float lr,
+                        const int* order) {
+  HHG_REQUIRE(m && x && y && order, HHG_ERR_ARG, "null argument");
+  HHG_REQUIRE(n_samples >= 1 && epochs >= 1 && lr > 0.f && batch >= 1 && batch <= m->net.max_batch, HHG_ERR_ARG,
+              "bad training parameters");
+  HHG_REQUIRE(n_samples / batch >= 1, HHG_ERR_ARG, "batch larger than the data set");
+  const size_t nord = (size_t)epochs * n_samples;
+  for (size_t q = 0; q < nord; ++q)
+    HHG_REQUIRE(order[q] >= 0 && order[q] < n_samples, HHG_ERR_ARG, "sample index out of range");
+  return nord;
+}
+// The Adam steps of every full minibatch of every epoch, enqueued on the
+// context stream: dord = the order on the device, dloss[e] += batch losses of
+// epoch e (zeroed by the caller).
+void train_steps(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs, float lr,
+                 const int* dord, double* dloss) {
+  hipStream_t s = m->ctx->stream;
+  const int nb = n_samples / batch;
+  for (int e = 0; e < epochs; ++e)
+    for (int q = 0; q < nb; ++q) {
+      const int* idx = dord + (size_t)e * n_samples + (size_t)q * batch;
+      launch_gather_rows(s, x, idx, batch, m->net.n_in, m->bx);
+      launch_gather_rows(s, y, idx, batch, m->net.n_out, m->by);
+      m->net.train_step_dev(s, m->bx, m->by, batch, lr, dloss + e);
+    }
+}
+}  // namespace
+}  // namespace hhg
+
 hhg_status hhg_mlp_train(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs, float lr,
                          const int* order, double* last_loss) {
   return guard([&] {
-    HHG_REQUIRE(m && x && y && order, HHG_ERR_ARG, "null argument");
-    HHG_REQUIRE(n_samples >= 1 && epochs >= 1 && lr > 0.f && batch >= 1 && batch <= m->net.max_batch, HHG_ERR_ARG,
-                "bad training parameters");
+    const size_t nord = check_train_args(m, x, y, n_samples, batch, epochs, lr, order);
     hipStream_t s = m->ctx->stream;
     const int nb = n_samples / batch;  // full minibatches per epoch
-    HHG_REQUIRE(nb >= 1, HHG_ERR_ARG, "batch larger than the data set");
-    const size_t nord = (size_t)epochs * n_samples;
-    for (size_t q = 0; q < nord; ++q)
-      HHG_REQUIRE(order[q] >= 0 && order[q] < n_samples, HHG_ERR_ARG, "sample index out of range");
     // the whole order and one loss accumulator per epoch on the device: the
     // steps are enqueued without host round trips
     int* dord = nullptr;
@@ -1834,13 +1874,7 @@ hhg_status hhg_mlp_train(hhg_mlp m, const float* x, const float* y, int n_sample
     std::vector<double> hloss(epochs, 0.0);
     hipError_t err = hipMemcpyAsync(dord, order, nord * sizeof(int), hipMemcpyHostToDevice, s);
     if (err == hipSuccess) err = hipMemcpyAsync(dloss, hloss.data(), epochs * sizeof(double), hipMemcpyHostToDevice, s);
-    for (int e = 0; e < epochs && err == hipSuccess; ++e)
-      for (int q = 0; q < nb; ++q) {
-        const int* idx = dord + (size_t)e * n_samples + (size_t)q * batch;
-        launch_gather_rows(s, x, idx, batch, m->net.n_in, m->bx);
-        launch_gather_rows(s, y, idx, batch, m->net.n_out, m->by);
-        m->net.train_step_dev(s, m->bx, m->by, batch, lr, dloss + e);
-      }
+    if (err == hipSuccess) train_steps(m, x, y, n_samples, batch, epochs, lr, dord, dloss);
     if (err == hipSuccess) err = hipMemcpyAsync(hloss.data(), dloss, epochs * sizeof(double), hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     (void)hipFree(dord);
@@ -1848,6 +1882,28 @@ hhg_status hhg_mlp_train(hhg_mlp m, const float* x, const float* y, int n_sample
     HHG_CHECK_HIP(err);
     HHG_CHECK_HIP(hipGetLastError());
     if (last_loss) *last_loss = hloss[epochs - 1] / nb;
+  });
+}
+
+hhg_status hhg_mlp_train_noalloc(hhg_mlp m, const float* x, const float* y, int n_samples, int batch, int epochs,
+                                 float lr, const int* order, double* last_loss) {
+  return guard([&] {
+    const size_t nord = check_train_args(m, x, y, n_samples, batch, epochs, lr, order);
+    HHG_REQUIRE((size_t)epochs <= kScratchEpochs && nord <= kScratchOrder, HHG_ERR_ARG,
+                "hhg_mlp_train_noalloc: epochs * n_samples must be at most " + std::to_string(kScratchOrder) +
+                    " and epochs at most " + std::to_string(kScratchEpochs) + " (static scratch); got " +
+                    std::to_string(nord) + " and " + std::to_string(epochs));
+    hipStream_t s = m->ctx->stream;
+    double* dloss = (double*)m->ctx->scratch;
+    int* dord = (int*)(m->ctx->scratch + kScratchEpochs * sizeof(double));
+    launch_fill<double>(s, dloss, (size_t)epochs, 0.0);  // the previous call left its losses here
+    HHG_CHECK_HIP(hipMemcpyAsync(dord, order, nord * sizeof(int), hipMemcpyHostToDevice, s));
+    train_steps(m, x, y, n_samples, batch, epochs, lr, dord, dloss);
+    double last = 0.0;
+    HHG_CHECK_HIP(hipMemcpyAsync(&last, dloss + (epochs - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+    HHG_CHECK_HIP(hipStreamSynchronize(s));
+    HHG_CHECK_HIP(hipGetLastError());
+    if (last_loss) *last_loss = last / (n_samples / batch);
   });
 }
 

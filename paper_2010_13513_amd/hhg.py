@@ -27,7 +27,7 @@ SYMBOLS = [
     "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation", "hhg_dots",
     "hhg_timer_start", "hhg_timer_read", "hhg_dc_solve", "hhg_set_viscosity",
     "hhg_mlp_create", "hhg_mlp_destroy", "hhg_mlp_num_params", "hhg_mlp_set_params", "hhg_mlp_get_params",
-    "hhg_mlp_forward", "hhg_mlp_loss_grad", "hhg_mlp_train", "hhg_mlp_dims", "hhg_coarse_pair", "hhg_hier_set_mlp",
+    "hhg_mlp_forward", "hhg_mlp_loss_grad", "hhg_mlp_train", "hhg_mlp_train_noalloc", "hhg_mlp_dims", "hhg_coarse_pair", "hhg_hier_set_mlp",
     "hhg_record_pairs", "hhg_recorded_pairs", "hhg_hier_set_fused_sites", "hhg_hier_set_bf16_levels",
 ]
 KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER, \
@@ -112,6 +112,7 @@ def load():
         "hhg_mlp_forward": [P, P, I, P],
         "hhg_mlp_loss_grad": [P, P, P, I, P, P],
         "hhg_mlp_train": [P, P, P, I, I, I, ctypes.c_float, P, P],
+        "hhg_mlp_train_noalloc": [P, P, P, I, I, I, ctypes.c_float, P, P],
         "hhg_mlp_dims": [P, P, P],
         "hhg_coarse_pair": [P, P, P, P],
         "hhg_hier_set_mlp": [P, P, D, D],
@@ -391,6 +392,15 @@ def hhg_mlp_train(m, x, y, n_samples, batch, epochs, lr, order):
     loss = ctypes.c_double()
     _check(load().hhg_mlp_train(m, _ptr(x), _ptr(y), n_samples, batch, epochs, float(lr), o.ctypes.data,
                                 ctypes.byref(loss)))
+    return loss.value
+
+
+def hhg_mlp_train_noalloc(m, x, y, n_samples, batch, epochs, lr, order):
+    import numpy as np
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    loss = ctypes.c_double()
+    _check(load().hhg_mlp_train_noalloc(m, _ptr(x), _ptr(y), n_samples, batch, epochs, float(lr), o.ctypes.data,
+                                        ctypes.byref(loss)))
     return loss.value
 
 
