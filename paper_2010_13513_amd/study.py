@@ -122,12 +122,13 @@ def run(torch, P, prob, omega_inv, tuples, log=None, every=64):
 def best_under_bounds(rows, bounds=BOUNDS, kappa=1):
     """Tab. fmg-table: for each (gamma_u_hat, gamma_p_hat), the tuple with
     kappa = `kappa` and least work whose gammas are within the bounds (ties:
-    smaller gamma_p)."""
+    smaller gamma_p), and the one of least measured solve time."""
     out = []
     for gu, gp in bounds:
         ok = [r for r in rows if r["s"][3] == kappa and r["gamma_u"] <= gu and r["gamma_p"] <= gp]
         best = min(ok, key=lambda r: (round(r["wu"], 9), r["gamma_p"])) if ok else None
-        out.append({"bounds": [gu, gp], "best": best})
+        fastest = min(ok, key=lambda r: r["seconds"]) if ok else None
+        out.append({"bounds": [gu, gp], "best": best, "fastest": fastest})
     return out
 
 
