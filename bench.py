@@ -46,7 +46,12 @@ ALTERNATIVES = [((0, 1, 3, 1, 0, 3), "least work with gamma_u <= 2, gamma_p <= 1
 # HBM traffic of one launch of a kernel family from rocprofv3 counters
 # (FETCH_SIZE x 2 + WRITE_SIZE, per dispatch, the calibration factor of a plain
 # copy applied); valid for the kernel code the summary names.
-TRAFFIC = {}
+TRAFFIC = {
+    "gs_edge_colour": {"bytes_per_launch": 3.0e6,
+                       "source": "profiles/fmg_p2p1_level5_cube.md: FETCH_SIZE x 2 + WRITE_SIZE per k_gs_edge "
+                                 "dispatch, weighted with the solve's launch mix over levels 3-5"},
+}
+APPLY_TRAFFIC = {"f64": 11.09e9, "f32": 4.64e9}   # profiles/apply_p2p1_48tets_level7.md
 # algorithmic bytes per work unit (float64 words), see the design doc
 WORDS = {
     "apply_p2": 6.25,        # y = calA x per P2 site
@@ -79,6 +84,8 @@ def main():
     ap.add_argument("--test-seeds", type=int, default=1000)
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--sweep-out", default=None, help="sweep: write every row of the study to this JSON file")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiler runs: setup, the timed headline solves and a 1 GiB calibration copy only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
@@ -182,6 +189,24 @@ def main():
         du, dp = hhg.hhg_dots(Ev, L + 1, e, me)
         return float(np.sqrt(du)), float(np.sqrt(dp))
 
+    if args.profile:
+        prm = hhg.solver_params(*HEADLINE, omega_inv)
+        for q in range(args.warmup + args.steps):
+            x.copy_(x0)
+            hhg.hhg_fmg_solve(H, x, bs, prm, want_stats=False)
+        torch.cuda.synchronize()
+        n = 1 << 27
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] profile run: {args.warmup + args.steps} FMG{_tname(HEADLINE)} solves; calibration copy "
+            f"{n * 8} bytes read and written per launch")
+        for hh in (Ev, Hml, H):
+            hhg.hhg_hier_destroy(hh)
+        hhg.hhg_ctx_destroy(ctx)
+        return
     xd = x0.clone()
     st = hhg.hhg_fmg_solve(H, xd, bs, hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 3, omega_inv, rtol=1e-12,
                                                         max_cycles=200))
@@ -346,7 +371,7 @@ def bench_apply(torch, hhg, dev, stream, ctx, level=7, reps=20):
             b = sites * 6.25 * (8 if prec == hhg.HHG_F64 else 4)
             gbs = b / (avg * 1e-3) / 1e9
             res[name] = {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg, 4),
-                         "bytes_per_launch": int(b)}
+                         "bytes_per_launch": int(b), "traffic": APPLY_TRAFFIC[name] if level == 7 else None}
             del x, y
         res.update({"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "workload": f"P2-P1 apply, 48 macro-tets, level {level} ({sites} P2 sites)"})
