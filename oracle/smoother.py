@@ -32,7 +32,10 @@ from . import mesh
 
 
 def colours(lev):
-    """Colour of every velocity node (lattice order)."""
+    """Colour of every velocity node (lattice order); a level that carries its
+    own colouring (unstructured meshes, umesh.ULevel) gives it directly."""
+    if hasattr(lev, "colour"):
+        return lev.colour
     c = lev.vcoords
     if lev.vorder == 1:
         return (c.sum(axis=1)) % 4
@@ -70,7 +73,7 @@ class Uzawa:
         self.D = schur_diagonal(stokes, schur)
         lev = stokes.lev
         col = colours(lev)
-        self.ncol = n_colours(lev.vorder)
+        self.ncol = getattr(lev, "ncolours", n_colours(lev.vorder))
         self.rows = []
         for c in range(self.ncol):
             idx = np.nonzero((col == c) & lev.vint)[0]
