@@ -16,6 +16,23 @@
  * it.  Velocity is
  * Dirichlet on the whole boundary; the pressure is fixed by int p = 0.
  *
+ * Unstructured macro meshes (Sec. 2, 2.1: HHG on any T_0): hhg_mesh_create
+ * with a tetrahedral mesh that is not a Kuhn partition of the cube gives the
+ * per-cell path, P1-P1 PSPG in float64.  Each macro cell (vertices sorted by
+ * id, v0 < v1 < v2 < v3) is refined by Bey's rule; level l has n = 2^l
+ * intervals per macro edge.  Velocity is Dirichlet on the faces of T_0 that
+ * belong to one tetrahedron (and on their edges and vertices).  Nodes are
+ * numbered in "canonical order": nodes on vertices of T_0, then on edges,
+ * faces and cells; within one kind by the sorted vertex ids of the
+ * primitive, then lexicographically by the node's barycentric weights on
+ * those vertices (in vertex-id order).  Gauss-Seidel colours: nodes on
+ * vertices, edges and faces greedily in canonical order (the smallest colour
+ * that no earlier node sharing an element with it has), K colours, then the
+ * cell interiors in four colours K + (i + j + k) mod 4, (i, j, k) = (n - a0,
+ * n - a0 - a1, a3) from the weights a.  The library stores each cell's
+ * closed lattice with copies of the interface nodes; callers see the layout
+ * only through hhg_vec_layout and the conversions.
+ *
  * Vectors.  All vectors are caller-owned device buffers holding every DoF of a
  * level, Dirichlet velocity DoFs included (they carry the boundary data; the
  * lifting of Sec. 2 comes from applying the operator to them).  Layout (in
@@ -28,7 +45,9 @@
  *          position leaves [0, 2N]^3 are padding and stay zero.
  * hhg_vec_layout() reports the sizes; hhg_vec_from_lattice / _to_lattice
  * convert to and from the plain lattice order (u1, u2, u3 over the velocity
- * lattice X + (M+1)(Y + (M+1) Z), M = N or 2N, then p over the P1 lattice).
+ * lattice X + (M+1)(Y + (M+1) Z), M = N or 2N, then p over the P1 lattice);
+ * on an unstructured mesh the plain order is [u1 | u2 | u3 | p], each over
+ * the nodes in canonical order.
  *
  * Outputs: boundary velocity rows of every operator output are zero; pressure
  * rows exist at every pressure node.
@@ -129,8 +148,13 @@ const char* hhg_last_error(void);
  * lattice: the call accepts a partition of the unit cube into the Kuhn
  * tetrahedra of its N^3 sub-cubes, N = 1 or 2 (6 or 48 tetrahedra; every
  * vertex on the lattice within 1e-9, no duplicate or unused vertex, every
- * tetrahedron a Kuhn simplex, no tetrahedron twice), and returns
- * HHG_ERR_ARG with a message naming the first violation for any other mesh.
+ * tetrahedron a Kuhn simplex, no tetrahedron twice) as the lattice path; any
+ * other conforming tetrahedral mesh becomes an unstructured mesh (per-cell
+ * path; hhg_mesh_info reports macro_refine = -1).  Checked: indices in range,
+ * every vertex used, no tetrahedron with a repeated vertex, degenerate
+ * (|det| <= 1e-10 of its extent cubed) or given twice, no face in more than
+ * two tetrahedra; HHG_ERR_ARG with a message naming the first violation
+ * otherwise.  Conformity (faces meet whole faces) is the caller's to ensure.
  *
  * A hierarchy copies what it needs: the mesh may be destroyed after
  * hhg_hier_create.  hhg_mesh_info: vertex and tetrahedron counts and the
@@ -150,7 +174,8 @@ hhg_status hhg_mesh_info(hhg_mesh mesh, int* nv, int* nt, int* macro_refine);
  * (hhg_project_mean_zero still projects when called); the vectors keep their
  * layout (the outflow sites hold values, not boundary data:
  * hhg_copy_boundary skips them); variable viscosity is refused
- * (HHG_ERR_STATE) and the one-workgroup small-level V-cycle is not used. */
+ * (HHG_ERR_STATE) and the one-workgroup small-level V-cycle is not used.
+ * Unstructured meshes: faces must be 0 (HHG_ERR_ARG). */
 hhg_status hhg_mesh_set_outflow(hhg_mesh mesh, unsigned faces);
 hhg_status hhg_mesh_destroy(hhg_mesh mesh);
 
@@ -168,7 +193,13 @@ hhg_status hhg_mesh_destroy(hhg_mesh mesh);
  * cube edge.  Limits: 0 <= lmin < lmax, N(lmax) <= 512 (P1-P1) or 256
  * (P2-P1); Taylor-Hood needs N(lmin) >= 2 (a level-0 Taylor-Hood system on
  * six tetrahedra has spurious pressure modes).  The hierarchy runs on the
- * mesh's context.  Ownership: the hierarchy. */
+ * mesh's context.  Ownership: the hierarchy.
+ *
+ * Unstructured mesh: disc must be HHG_P1P1 and 0 <= lmin < lmax <= 9 (the
+ * whole vector under 2^31 words); every call on the hierarchy takes HHG_F64
+ * vectors (HHG_ERR_PREC otherwise); variable viscosity, defect correction,
+ * bfloat16 levels, the learned coarse solve and its recorder report
+ * HHG_ERR_STATE.  Work units are those of the P1-P1 model of Sec. 4. */
 hhg_status hhg_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg_schur schur, hhg_hier* out);
 hhg_status hhg_hier_destroy(hhg_hier h);
 
@@ -243,7 +274,9 @@ hhg_status hhg_dots(hhg_hier h, int level, const void* x, const void* y, double*
  * Gauss-Seidel colour, 3 edge-group Gauss-Seidel colour, 4 Uzawa pressure
  * step, 5 restriction, 6 prolongation, 7 coarse solve, 8 reductions, 9 other,
  * 10 MLP matrix products, 11 one-workgroup small-level V-cycle, 12
- * outflow-face rows, Gauss-Seidel sites and transfers)
+ * outflow-face rows, Gauss-Seidel sites and transfers, 13 interface-node
+ * rows, Gauss-Seidel colours and copies of unstructured meshes; on those
+ * meshes family 0 is the cell-interior rows and 2 the interior colours)
  * and clears earlier records; mask 0 disables it.  hhg_timer_read synchronises
  * and returns, for one family since the last read, the summed event time in
  * ms, the launches and the work units (sites processed: P2 sites or P1
@@ -266,6 +299,18 @@ hhg_status hhg_norms(hhg_hier h, int level, const void* x, double* norm_u, doubl
  * entries; HHG_ERR_ARG if more than max_entries. */
 hhg_status hhg_query_stencil(hhg_disc disc, char kind, int group, int i, int j, int k, int nbox, int max_entries,
                              int* n, int* code, double* w);
+/* Host-only view of level `level` (0..6) of an unstructured mesh (xyz, tet
+ * as for hhg_mesh_create; any valid tetrahedral mesh, Kuhn partitions
+ * included): the number of nodes, of Gauss-Seidel colours and of coarse
+ * unknowns (free velocity nodes times three, then every pressure node); per
+ * node in canonical order (arrays of nnodes entries, or NULL): position
+ * (3 doubles), colour, Schur diagonal D of option `schur`; and calA on the
+ * unknowns (nunk x nunk, row-major; velocity unknowns component-major, nodes
+ * ascending, then the pressure nodes) if nunk <= max_unknowns and K is not
+ * NULL.  Call once with NULL arrays for the sizes. */
+hhg_status hhg_query_umesh(const double* xyz, int nv, const int* tet, int nt, int level, hhg_schur schur,
+                           int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos, int* colour,
+                           double* schur_diag, double* K);
 /* Interpolation weights of Sec. 3.3 at a fine position inside one coarse
  * lattice cube: t = (tx, ty, tz) / q with q = 2 (linear) or 4 (quadratic)
  * and order 1 or 2.  Output: code[4 e ..] = (coarse group, di, dj, dk) from the

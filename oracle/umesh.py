@@ -42,48 +42,6 @@ from . import fe, mesh
 from .transfer import Transfer
 
 
-def cube24():
-    """The unit cube as 24 tetrahedra (the partition of the paper's cube
-    benchmark, Sec. 5.1.1): each face split into 4 triangles at its centre,
-    each joined to the cube's centre.  Returns (xyz (15, 3), tets (24, 4))."""
-    xyz = [(i, j, k) for k in (0, 1) for j in (0, 1) for i in (0, 1)]          # corners 0..7
-    cid = {c: n for n, c in enumerate(xyz)}
-    faces = []
-    for d in range(3):
-        for side in (0, 1):
-            cen = [0.5, 0.5, 0.5]
-            cen[d] = side
-            xyz.append(tuple(cen))
-            a, b = [e for e in range(3) if e != d]
-            ring = []
-            for (s, t) in ((0, 0), (1, 0), (1, 1), (0, 1)):     # around the face
-                c = [0, 0, 0]
-                c[d], c[a], c[b] = side, s, t
-                ring.append(cid[tuple(c)])
-            faces.append((len(xyz) - 1, ring))
-    xyz.append((0.5, 0.5, 0.5))
-    body = len(xyz) - 1
-    tets = []
-    for fc, ring in faces:
-        for q in range(4):
-            tets.append((body, fc, ring[q], ring[(q + 1) % 4]))
-    return np.array(xyz, dtype=float), np.array(tets, dtype=np.int64)
-
-
-def kuhn_cube(N):
-    """The Kuhn partition of the unit cube into N^3 sub-cubes of 6 tetrahedra."""
-    n1 = N + 1
-    xyz = np.array([(i, j, k) for k in range(n1) for j in range(n1) for i in range(n1)], float) / N
-    idx = lambda c: c[0] + n1 * (c[1] + n1 * c[2])
-    tets = []
-    for k in range(N):
-        for j in range(N):
-            for i in range(N):
-                for p in mesh.PERMS:
-                    tets.append([idx(v) for v in mesh.kuhn_tet((i, j, k), p)])
-    return xyz, np.array(tets, dtype=np.int64)
-
-
 def boundary_faces(tets):
     """Faces (sorted vertex triples) of T_0 that belong to one tetrahedron."""
     count = {}

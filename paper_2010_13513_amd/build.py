@@ -10,7 +10,7 @@ import sys
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["api.hip", "kernels.hip", "mlp.hip", "fe_host.cpp"]
+SRC = ["api.hip", "kernels.hip", "mlp.hip", "umesh.hip", "ukernels.hip", "fe_host.cpp"]
 GEN_SRC = ["gen_stencils.cpp", "fe_host.cpp"]
 GEN_OUT = os.path.join(HERE, "csrc", "generated", "stencils.inc")
 OBJ_DIR = os.path.join(HERE, "csrc", "generated", "obj")

@@ -16,6 +16,7 @@
 
 #include "kernels.h"
 #include "mlp.h"
+#include "umesh.h"
 
 namespace hhg {
 
@@ -141,6 +142,7 @@ struct hhg_mesh_s {
   hhg_ctx ctx = nullptr;
   int mr = 0;
   unsigned nf = 0;   // outflow faces (hhg_mesh_set_outflow)
+  bool general = false;  // not a Kuhn partition of the cube: unstructured path
   std::vector<double> xyz;
   std::vector<int> tet;
 };
@@ -152,6 +154,8 @@ struct hhg_hier_s {
   int G = 1;
   hhg::Arena arena;
   std::vector<hhg::Level> levels;
+  // unstructured macro mesh: level tables of the per-cell path (null on the lattice path)
+  std::unique_ptr<hhg::UHier> um;
   double* Kp = nullptr;
   int* unk = nullptr;
   int nunk = 0, rank = 0;
@@ -652,6 +656,22 @@ void build_coarse_device(hhg_hier h);
 // not been (host work: call outside graph capture).
 void ensure_coarse(hhg_hier h) {
   if (h->nunk == 0) return;
+  if (!h->kp_ready && h->um) {
+    HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
+    std::vector<int> unk;
+    std::vector<double> K, Kp;
+    u_coarse_system(*h->um, unk, K, 2048);
+    const int n = h->nunk;
+    for (int r = 0; r < n; ++r)
+      for (int c = r + 1; c < n; ++c) {
+        const double sym = 0.5 * (K[(size_t)r * n + c] + K[(size_t)c * n + r]);
+        K[(size_t)r * n + c] = K[(size_t)c * n + r] = sym;
+      }
+    h->rank = sym_pinv(n, K, Kp, 1e-12);
+    HHG_CHECK_HIP(hipMemcpy(h->Kp, Kp.data(), Kp.size() * sizeof(double), hipMemcpyHostToDevice));
+    h->kp_ready = true;
+    return;
+  }
   if (!h->kp_ready) {
     HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
     if (h->L(h->lmin).nu64 || h->nf)  // rows the host tables do not hold: from the device operator
@@ -663,6 +683,61 @@ void ensure_coarse(hhg_hier h) {
 
 template <typename T>
 void op_apply(hhg_hier h, int l, int opmask, const T* x, const T* b, T* y, bool has_b, bool vel, bool prs);
+
+// ------------------------------------------------ unstructured-mesh ops
+// The per-cell path of an unstructured T_0 (umesh.h), float64 only.
+template <typename T>
+void u_f64() {
+  if (!std::is_same<T, double>::value) throw Error{HHG_ERR_PREC, "unstructured macro meshes: float64 only"};
+}
+ULevelData& UL(hhg_hier h, int l) { return h->um->L(l); }
+void u_colour(hhg_hier h, int l, int c, double* x, const double* b) {
+  ULevelData& U = UL(h, l);
+  const int K = U.ncol_if;
+  if (c < K)
+    launch_u_gs_iface(S(h), U.L, U.lst, U.col_off[c], U.col_off[c + 1] - U.col_off[c], x, b);
+  else
+    launch_u_gs_inner(S(h), U.L, U.colour[c - K], x, b);
+}
+void u_smooth(hhg_hier h, int l, double* x, const double* b, int iters, int gs, int xi, double omega) {
+  ULevelData& U = UL(h, l);
+  const int ncol = U.ncol_if + 4;
+  double* r = h->L(l).r;
+  for (int it = 0; it < iters; ++it) {
+    for (int s = 0; s < xi; ++s) {
+      for (int c = 0; c < ncol; ++c) u_colour(h, l, c, x, b);
+      if (gs == HHG_GS_SYM)
+        for (int c = ncol - 1; c >= 0; --c) u_colour(h, l, c, x, b);
+    }
+    // r_p = g - B u + C p, then p -= omega D^{-1} r_p
+    launch_u_apply_rows(S(h), U.L, U.inner, U.lst, x, b, r, 12, true, false, false, true);
+    launch_u_pstep(S(h), U.L, U.dinv, x, r, omega);
+  }
+}
+// p -= (m^T p / m^T 1), m the lumped mass, over the nodes (owner slots)
+void u_mean_zero(hhg_hier h, int l, double* x) {
+  ULevelData& U = UL(h, l);
+  launch_u_dot(S(h), U.L, U.flags, U.ml_own, x, nullptr, 3, 1, h->partial, h->sums, 0);
+  launch_u_shift(S(h), U.L, x + 3 * U.L.vs, h->sums, 0, U.ml_total);
+}
+void u_norms_launch(hhg_hier h, int l, const double* x, const double* y) {
+  ULevelData& U = UL(h, l);
+  launch_u_dot(S(h), U.L, U.flags, nullptr, x, y, 0, 3, h->partial, h->sums, 0);
+  launch_u_dot(S(h), U.L, U.flags, nullptr, x, y, 3, 1, h->partial + 2 * kPartials, h->sums, 2);
+}
+// Boundary copies of Alg. fmg (Dirichlet velocity values) on either path.
+void op_copy_boundary(hhg_hier h, int l, const double* src, double* dst) {
+  if (h->um)
+    launch_u_copy_bnd(S(h), UL(h, l).L, UL(h, l).flags, src, dst);
+  else
+    launch_copy_boundary<double>(S(h), h->L(l).g, src, dst);
+}
+void op_inject(hhg_hier h, int lf, const double* xf, double* xc) {
+  if (h->um)
+    launch_u_inject(S(h), UL(h, lf).L, UL(h, lf - 1).L, UL(h, lf - 1).all, xf, xc);
+  else
+    launch_inject_boundary<double>(S(h), h->L(lf).g, h->L(lf - 1).g, xf, xc);
+}
 
 // Dense coarse operator from the device operator itself (columns = calA e_c
 // restricted to the unknowns, all n columns applied back to back), used when
@@ -727,6 +802,13 @@ void round_out(hhg_hier h, int l, T* v, size_t stride, size_t off, size_t n, int
 
 template <typename T>
 void op_apply(hhg_hier h, int l, int opmask, const T* x, const T* b, T* y, bool has_b, bool vel, bool prs) {
+  if (h->um) {
+    u_f64<T>();
+    ULevelData& U = UL(h, l);
+    launch_u_apply_rows(S(h), U.L, U.inner, U.lst, (const double*)x, (const double*)b, (double*)y, opmask, has_b,
+                        false, vel, prs);
+    return;
+  }
   Level& lv = h->L(l);
   launch_apply<T>(S(h), lv.g, lconst<T>(lv), tables<T>(lv), x, b, y, opmask, has_b, vel, prs, lv.bnd, lv.nbnd);
   if (vel && lv.neu_n)  // outflow-face velocity rows (boundary rows to the grid-wide kernels)
@@ -749,6 +831,11 @@ float* rbuf<float>(Level& lv) {
 
 template <typename T>
 void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, double omega) {
+  if (h->um) {
+    u_f64<T>();
+    u_smooth(h, l, (double*)x, (const double*)b, iters, gs, xi, omega);
+    return;
+  }
   Level& lv = h->L(l);
   const int ncol = h->G == 1 ? 4 : 11;
   T* r = rbuf<T>(lv);
@@ -782,6 +869,11 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
 // nothing is done.  hhg_project_mean_zero always projects (op_mean_zero_always).
 template <typename T>
 void op_mean_zero_always(hhg_hier h, int l, T* x) {
+  if (h->um) {
+    u_f64<T>();
+    u_mean_zero(h, l, (double*)x);
+    return;
+  }
   Level& lv = h->L(l);
   T* p = x + 3 * (size_t)lv.g.vstride;
   launch_mean_zero<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
@@ -790,6 +882,11 @@ void op_mean_zero_always(hhg_hier h, int l, T* x) {
 template <typename T>
 void op_mean_zero(hhg_hier h, int l, T* x) {
   if (h->nf) return;
+  if (h->um) {
+    u_f64<T>();
+    u_mean_zero(h, l, (double*)x);
+    return;
+  }
   Level& lv = h->L(l);
   T* p = x + 3 * (size_t)lv.g.vstride;
   launch_mean_zero<T>(S(h), lv.g, tables<T>(lv), p, h->partial, h->sums, 0);
@@ -798,6 +895,16 @@ void op_mean_zero(hhg_hier h, int l, T* x) {
 
 template <typename T>
 void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
+  if (h->um) {
+    u_f64<T>();
+    ULevelData& F = UL(h, lf);
+    ULevelData& C = UL(h, lf - 1);
+    launch_u_restrict(S(h), F.L, C.L, C.inner, C.lst, (const double*)rf, (double*)rc);
+    // compatibility with the null vector (0, 1): plain mean of the pressure nodes
+    launch_u_dot(S(h), C.L, C.flags, nullptr, (const double*)rc, nullptr, 3, 1, h->partial, h->sums, 0);
+    launch_u_shift(S(h), C.L, (double*)rc + 3 * C.L.vs, h->sums, 0, (double)C.nnodes);
+    return;
+  }
   Level& f = h->L(lf);
   Level& c = h->L(lf - 1);
   launch_restrict<T>(S(h), f.g, c.g, ttables<T>(f), rf, rc);
@@ -811,6 +918,12 @@ void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
 
 template <typename T>
 void op_prolong(hhg_hier h, int lc, const T* xc, T* xf, bool add, bool skip_bnd) {
+  if (h->um) {
+    u_f64<T>();
+    launch_u_prolong(S(h), UL(h, lc).L, UL(h, lc + 1).L, UL(h, lc + 1).all, (const double*)xc, (double*)xf, add,
+                     skip_bnd);
+    return;
+  }
   Level& c = h->L(lc);
   Level& f = h->L(lc + 1);
   launch_prolong<T>(S(h), c.g, f.g, ttables<T>(f), xc, xf, add, skip_bnd);
@@ -871,7 +984,7 @@ void fill_small(hhg_hier h, std::vector<SmallLevel<T>>& out, std::vector<int>& l
   }
 }
 void refresh_small(hhg_hier h) {
-  if (!h->slv_stale) return;
+  if (!h->slv_stale || h->um) return;  // no one-workgroup cycle on unstructured meshes
   if (!h->slv64) {
     h->slv64 = h->arena.alloc<SmallLevel<double>>(h->levels.size());
     h->slv32 = h->arena.alloc<SmallLevel<float>>(h->levels.size());
@@ -951,6 +1064,7 @@ void op_coarse(hhg_hier h, T* x, const T* b, bool allow_mlp = true, const hhg_so
     }
   }
   launch_coarse<T>(S(h), h->Kp, h->unk, h->nunk, r, x);
+  if (h->um) launch_u_sync(S(h), UL(h, h->lmin).L, UL(h, h->lmin).lst, (double*)x);
   round_out<T>(h, h->lmin, x, 0, 0, lv.vec_words, 1);
   op_mean_zero<T>(h, h->lmin, x);
 }
@@ -967,7 +1081,7 @@ void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_para
   // pseudo-inverse rebuild)
   const bool mlp_on = std::is_same<T, double>::value && h->mlp && !h->mlp_off;
   if (vel_sites(h->L(l)) <= h->fused_sites && !h->slv_stale && p.coarse_smooth == 0 && h->nunk > 0 && !mlp_on &&
-      h->rec_n >= h->rec_cap && !h->kp_stale && h->kp_ready && h->nf == 0 &&
+      h->rec_n >= h->rec_cap && !h->kp_stale && h->kp_ready && h->nf == 0 && !h->um &&
       (std::is_same<T, double>::value || h->L(h->lmin).cx32)) {
     SmallCycle<T> sc{};
     sc.nlev = l - h->lmin + 1;
@@ -1030,8 +1144,13 @@ void ensure_f32_vectors(hhg_hier h) {
 template <typename T>
 void norms(hhg_hier h, int l, const T* x, double* nu, double* np_) {
   Level& lv = h->L(l);
-  launch_vsumsq<T>(S(h), lv.g, x, 3 * lv.g.vstride, h->partial, h->sums);
-  launch_vsumsq<T>(S(h), lv.g, x + 3 * (size_t)lv.g.vstride, lv.g.nn, h->partial + 2 * kPartials, h->sums + 2);
+  if (h->um) {
+    u_f64<T>();
+    u_norms_launch(h, l, (const double*)x, (const double*)x);
+  } else {
+    launch_vsumsq<T>(S(h), lv.g, x, 3 * lv.g.vstride, h->partial, h->sums);
+    launch_vsumsq<T>(S(h), lv.g, x + 3 * (size_t)lv.g.vstride, lv.g.nn, h->partial + 2 * kPartials, h->sums + 2);
+  }
   HHG_CHECK_HIP(hipMemcpyAsync(h->hsums, h->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, S(h)));
   HHG_CHECK_HIP(hipStreamSynchronize(S(h)));
   *nu = std::sqrt(h->hsums[0]);
@@ -1075,18 +1194,17 @@ template <typename BL>
 void fmg_body(hhg_hier h, double* x, BL bl, const hhg_solver_params& p) {
   hipStream_t s = S(h);
   Level& top = h->L(h->lmax);
-  launch_copy_boundary<double>(s, top.g, x, top.w);
-  for (int l = h->lmax - 1; l >= h->lmin; --l)
-    launch_inject_boundary<double>(s, h->L(l + 1).g, h->L(l).g, h->L(l + 1).w, h->L(l).w);
+  op_copy_boundary(h, h->lmax, x, top.w);
+  for (int l = h->lmax - 1; l >= h->lmin; --l) op_inject(h, l + 1, h->L(l + 1).w, h->L(l).w);
   Level& bot = h->L(h->lmin);
   launch_fill<double>(s, bot.xs, bot.vec_words, 0.0);
-  launch_copy_boundary<double>(s, bot.g, bot.w, bot.xs);
+  op_copy_boundary(h, h->lmin, bot.w, bot.xs);
   op_coarse<double>(h, bot.xs, bl(h->lmin), true, &p);
   for (int l = h->lmin + 1; l <= h->lmax; ++l) {
     Level& lv = h->L(l);
     double* X = l == h->lmax ? x : lv.xs;
     op_prolong<double>(h, l - 1, h->L(l - 1).xs, X, false, false);
-    launch_copy_boundary<double>(s, lv.g, lv.w, X);
+    op_copy_boundary(h, l, lv.w, X);
     for (int c = 0; c < p.kappa; ++c) {
       vcycle(h, l, l, X, bl(l), p);
       op_mean_zero<double>(h, l, X);
@@ -1239,6 +1357,102 @@ hhg_status guard(F&& f) {
   }
 }
 
+// Hierarchy on an unstructured T_0 (P1-P1 only): the level tables of the
+// per-cell path, the work vectors of every level and the coarse unknowns.
+hhg_hier u_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg_schur schur) {
+  hhg_ctx ctx = mesh->ctx;
+  HHG_REQUIRE(disc == HHG_P1P1, HHG_ERR_ARG, "unstructured macro meshes: P1-P1 only");
+  HHG_REQUIRE(lmin >= 0 && lmin < lmax && lmax <= 9, HHG_ERR_ARG, "need 0 <= lmin < lmax <= 9");
+  HHG_REQUIRE(schur == HHG_SCHUR_SD || schur == HHG_SCHUR_ML, HHG_ERR_ARG, "unknown Schur option");
+  HHG_CHECK_HIP(hipSetDevice(ctx->device));
+  std::unique_ptr<hhg_hier_s> h(new hhg_hier_s);
+  h->ctx = ctx;
+  h->disc = disc;
+  h->mr = -1;
+  h->lmin = lmin;
+  h->lmax = lmax;
+  h->schur = schur;
+  h->G = 1;
+  h->um.reset(u_build(mesh->xyz.data(), (int)(mesh->xyz.size() / 3), mesh->tet.data(), (int)(mesh->tet.size() / 4),
+                      lmin, lmax, schur));
+  h->partial = h->arena.alloc<double>(4 * kPartials);
+  h->sums = h->arena.alloc<double>(16);
+  HHG_CHECK_HIP(hipHostMalloc((void**)&h->hsums, 16 * sizeof(double), hipHostMallocDefault));
+  h->levels.resize(lmax - lmin + 1);
+  for (int l = lmin; l <= lmax; ++l) {
+    Level& lv = h->L(l);
+    ULevelData& U = UL(h.get(), l);
+    lv.l = l;
+    lv.g.N = U.L.n;
+    lv.g.n1 = U.L.n + 1;
+    lv.g.nn = U.nnodes;
+    lv.g.G = 1;
+    lv.g.vstride = (int)U.L.vs;
+    lv.vec_words = 4 * (size_t)U.L.vs;
+    lv.r = h->arena.alloc<double>(lv.vec_words);
+    lv.w = h->arena.alloc<double>(lv.vec_words);
+    lv.xs = h->arena.alloc<double>(lv.vec_words);
+    if (l < lmax) {
+      lv.cx = h->arena.alloc<double>(lv.vec_words);
+      lv.cb = h->arena.alloc<double>(lv.vec_words);
+      launch_fill<double>(ctx->stream, lv.cx, lv.vec_words, 0.0);
+      launch_fill<double>(ctx->stream, lv.cb, lv.vec_words, 0.0);
+    }
+    launch_fill<double>(ctx->stream, lv.r, lv.vec_words, 0.0);
+    launch_fill<double>(ctx->stream, lv.w, lv.vec_words, 0.0);
+    launch_fill<double>(ctx->stream, lv.xs, lv.vec_words, 0.0);
+  }
+  std::vector<int> unk;
+  std::vector<double> K;
+  u_coarse_system(*h->um, unk, K, 0);
+  if (unk.size() <= 2048) {
+    h->nunk = (int)unk.size();
+    h->Kp = h->arena.alloc<double>(unk.size() * unk.size());
+    h->unk = h->arena.upload(unk);
+    h->unk_host = unk;
+  }
+  HHG_CHECK_HIP(hipGetLastError());
+  HHG_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  return h.release();
+}
+
+// Largest eigenvalue of D^{-1}(C + B A_s^{-1} B^T) by power iteration on the
+// per-cell path (eq. omega-eigenvalue-problem); v0 in canonical node order.
+double u_estimate_omega(hhg_hier h, int l, const double* v0, int iters) {
+  Level& lv = h->L(l);
+  ULevelData& U = UL(h, l);
+  const size_t vs = U.L.vs, vs3 = 3 * vs;
+  double* v = lv.xs;  // pressure part holds v
+  double* z = lv.w;   // velocity part: sweep iterate; pressure part: -v for C
+  double* y = lv.r;
+  hipStream_t s = S(h);
+  launch_fill<double>(s, v, lv.vec_words, 0.0);
+  launch_u_pfrom_canon(s, U.L, U.canon, v0, v + vs3);
+  op_mean_zero<double>(h, l, v);
+  launch_u_dot(s, U.L, U.flags, nullptr, v, v, 3, 1, h->partial, h->sums, 0);
+  launch_u_pscale(s, U.L, v + vs3, h->sums, 0);
+  const int ncol = U.ncol_if + 4;
+  for (int it = 0; it < iters; ++it) {
+    launch_u_apply_rows(s, U.L, U.inner, U.lst, v, nullptr, y, 2, false, false, true, false);  // B^T v
+    launch_fill<double>(s, z, lv.vec_words, 0.0);
+    for (int c = 0; c < ncol; ++c) u_colour(h, l, c, z, y);
+    for (int c = ncol - 1; c >= 0; --c) u_colour(h, l, c, z, y);
+    launch_scaled_copy<double>(s, z + vs3, v + vs3, nullptr, vs, -1.0);
+    launch_u_apply_rows(s, U.L, U.inner, U.lst, z, nullptr, y, 12, false, false, false, true);  // B z + C v
+    launch_scaled_copy<double>(s, v + vs3, y + vs3, U.dinv, vs, 1.0);
+    launch_u_dot(s, U.L, U.flags, nullptr, v, v, 3, 1, h->partial, h->sums, 0);
+    if (it + 1 < iters) launch_u_pscale(s, U.L, v + vs3, h->sums, 0);
+  }
+  HHG_CHECK_HIP(hipMemcpyAsync(h->hsums, h->sums, sizeof(double), hipMemcpyDeviceToHost, s));
+  HHG_CHECK_HIP(hipStreamSynchronize(s));
+  return std::sqrt(h->hsums[0]);
+}
+
+// Calls that exist for the lattice path only.
+void lattice_only(hhg_hier h, const char* what) {
+  HHG_REQUIRE(!h || !h->um, HHG_ERR_STATE, std::string(what) + " is not available on unstructured macro meshes");
+}
+
 }  // namespace
 }  // namespace hhg
 
@@ -1294,10 +1508,17 @@ hhg_status hhg_mesh_cube(hhg_ctx ctx, int macro_refine, hhg_mesh* out) {
 hhg_status hhg_mesh_create(hhg_ctx ctx, const double* xyz, int nv, const int* tet, int nt, hhg_mesh* out) {
   return guard([&] {
     HHG_REQUIRE(ctx && out && xyz && tet && nv > 0 && nt > 0, HHG_ERR_ARG, "null or empty argument");
-    const int N = kuhn_cube_refinement(xyz, nv, tet, nt);
+    int N = 0;
+    try {
+      N = kuhn_cube_refinement(xyz, nv, tet, nt);
+    } catch (const Error& e) {
+      if (e.code != HHG_ERR_ARG) throw;
+      validate_tet_mesh(xyz, nv, tet, nt);  // a general T_0: the per-cell path
+    }
     std::unique_ptr<hhg_mesh_s> m(new hhg_mesh_s);
     m->ctx = ctx;
-    m->mr = N == 1 ? 0 : 1;
+    m->general = N == 0;
+    m->mr = N == 0 ? -1 : (N == 1 ? 0 : 1);
     m->xyz.assign(xyz, xyz + 3 * (size_t)nv);
     m->tet.assign(tet, tet + 4 * (size_t)nt);
     *out = m.release();
@@ -1308,6 +1529,8 @@ hhg_status hhg_mesh_set_outflow(hhg_mesh mesh, unsigned faces) {
   return guard([&] {
     HHG_REQUIRE(mesh, HHG_ERR_ARG, "null mesh");
     HHG_REQUIRE(faces < 63u, HHG_ERR_ARG, "outflow faces: a mask of faces 0..5 with at least one Dirichlet face");
+    HHG_REQUIRE(!mesh->general || faces == 0, HHG_ERR_ARG,
+                "outflow faces are faces of the unit cube: Kuhn-partition meshes only");
     mesh->nf = faces;
   });
 }
@@ -1328,6 +1551,10 @@ hhg_status hhg_mesh_destroy(hhg_mesh mesh) {
 hhg_status hhg_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg_schur schur, hhg_hier* out) {
   return guard([&] {
     HHG_REQUIRE(mesh && out, HHG_ERR_ARG, "null argument");
+    if (mesh->general) {
+      *out = u_hier_create(mesh, disc, lmin, lmax, schur);
+      return;
+    }
     hhg_ctx ctx = mesh->ctx;
     const int macro_refine = mesh->mr;
     HHG_REQUIRE(disc == HHG_P1P1 || disc == HHG_P2P1, HHG_ERR_ARG, "unknown discretisation");
@@ -1415,7 +1642,7 @@ hhg_status hhg_vec_layout(hhg_hier h, int level, int* N, size_t* nn, size_t* vec
     if (nn) *nn = lv.g.nn;
     if (vec_words) *vec_words = lv.vec_words;
     const size_t m1 = (h->G == 1 ? lv.g.N : 2 * lv.g.N) + 1;
-    if (lattice_words) *lattice_words = 3 * m1 * m1 * m1 + lv.g.nn;
+    if (lattice_words) *lattice_words = h->um ? 4 * (size_t)lv.g.nn : 3 * m1 * m1 * m1 + lv.g.nn;
   });
 }
 
@@ -1437,6 +1664,14 @@ hhg_status hhg_vec_from_lattice(hhg_hier h, int level, const double* src, void* 
     check_level(h, level);
     HHG_REQUIRE(src && dst, HHG_ERR_ARG, "null vector");
     Level& lv = h->L(level);
+    if (h->um) {
+      HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
+      ULevelData& U = UL(h, level);
+      launch_fill<double>(S(h), (double*)dst, lv.vec_words, 0.0);
+      launch_u_from_canon(S(h), U.L, U.canon, U.nnodes, src, (double*)dst);
+      HHG_CHECK_HIP(hipGetLastError());
+      return;
+    }
     HHG_DISPATCH(prec, {
       launch_fill<T>(S(h), (T*)dst, lv.vec_words, T(0));
       launch_from_lattice<T>(S(h), lv.g, src, (T*)dst);
@@ -1451,6 +1686,13 @@ hhg_status hhg_vec_to_lattice(hhg_hier h, int level, const void* src, double* ds
     check_level(h, level);
     HHG_REQUIRE(src && dst, HHG_ERR_ARG, "null vector");
     Level& lv = h->L(level);
+    if (h->um) {
+      HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
+      ULevelData& U = UL(h, level);
+      launch_u_to_canon(S(h), U.L, U.canon, U.flags, U.nnodes, (const double*)src, dst);
+      HHG_CHECK_HIP(hipGetLastError());
+      return;
+    }
     HHG_DISPATCH(prec, launch_to_lattice<T>(S(h), lv.g, (const T*)src, dst));
     HHG_CHECK_HIP(hipGetLastError());
   });
@@ -1470,6 +1712,13 @@ hhg_status hhg_apply(hhg_hier h, int level, hhg_op op, const void* x, void* y, h
       case HHG_OP_C: mask = 8 | 16; break;
       case HHG_OP_MASS: mask = -1; break;
       default: throw Error{HHG_ERR_ARG, "operator not supported"};
+    }
+    if (mask < 0 && h->um) {
+      HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
+      ULevelData& U = UL(h, level);
+      launch_u_apply_rows(S(h), U.L, U.inner, U.lst, (const double*)x, nullptr, (double*)y, 0, false, true, true, true);
+      HHG_CHECK_HIP(hipGetLastError());
+      return;
     }
     if (mask < 0) {
       HHG_DISPATCH(prec, {
@@ -1502,6 +1751,14 @@ hhg_status hhg_rhs(hhg_hier h, int level, const void* f, void* b, hhg_prec prec)
     check_level(h, level);
     HHG_REQUIRE(f && b && f != b, HHG_ERR_ARG, "bad vectors");
     Level& lv = h->L(level);
+    if (h->um) {  // b = M I(f) on the free velocity rows, zero elsewhere
+      HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
+      ULevelData& U = UL(h, level);
+      launch_u_apply_rows(S(h), U.L, U.inner, U.lst, (const double*)f, nullptr, (double*)b, 0, false, true, true, true);
+      launch_u_rhs_fix(S(h), U.L, U.flags, (double*)b);
+      HHG_CHECK_HIP(hipGetLastError());
+      return;
+    }
     HHG_DISPATCH(prec, {
       launch_rhs<T>(S(h), lv.g, lconst<T>(lv), (const T*)f, (T*)b);
       if (lv.neu_n) launch_neu_rhs<T>(S(h), lv.g, tables<T>(lv), lv.neu(), lv.neu_n, (const T*)f, (T*)b);
@@ -1567,6 +1824,12 @@ hhg_status hhg_copy_boundary(hhg_hier h, int level, const void* src, void* dst, 
     check_level(h, level);
     HHG_REQUIRE(src && dst, HHG_ERR_ARG, "null vector");
     Level& lv = h->L(level);
+    if (h->um) {
+      HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
+      op_copy_boundary(h, level, (const double*)src, (double*)dst);
+      HHG_CHECK_HIP(hipGetLastError());
+      return;
+    }
     HHG_DISPATCH(prec, launch_copy_boundary<T>(S(h), lv.g, (const T*)src, (T*)dst));
     HHG_CHECK_HIP(hipGetLastError());
   });
@@ -1585,6 +1848,10 @@ hhg_status hhg_estimate_omega(hhg_hier h, int level, const double* v0, int iters
     check_level(h, level);
     HHG_REQUIRE(v0 && omega_inv && iters >= 1, HHG_ERR_ARG, "bad arguments");
     Level& lv = h->L(level);
+    if (h->um) {
+      *omega_inv = u_estimate_omega(h, level, v0, iters);
+      return;
+    }
     const Geom& g = lv.g;
     const size_t vs3 = 3 * (size_t)g.vstride;
     double* v = lv.xs;   // pressure part holds v; velocity part zero
@@ -1629,6 +1896,10 @@ hhg_status hhg_dots(hhg_hier h, int level, const void* x, const void* y, double*
     HHG_REQUIRE(x && y && dot_u && dot_p, HHG_ERR_ARG, "null argument");
     Level& lv = h->L(level);
     const size_t nv = 3 * (size_t)lv.g.vstride;
+    if (h->um) {
+      HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
+      u_norms_launch(h, level, (const double*)x, (const double*)y);
+    } else
     HHG_DISPATCH(prec, {
       launch_dot<T>(S(h), (const T*)x, (const T*)y, nv, h->partial, h->sums);
       launch_dot<T>(S(h), (const T*)x + nv, (const T*)y + nv, lv.g.nn, h->partial + 2 * kPartials, h->sums + 2);
@@ -1658,6 +1929,7 @@ hhg_status hhg_set_viscosity(hhg_hier h, int level, const double* nu) {
   return guard([&] {
     check_level(h, level);
     HHG_REQUIRE(nu, HHG_ERR_ARG, "null viscosity");
+    lattice_only(h, "variable viscosity");
     HHG_REQUIRE(h->nf == 0, HHG_ERR_STATE, "variable viscosity with an outflow face is not supported");
     Level& lv = h->L(level);
     hipStream_t s = S(h);
@@ -1699,6 +1971,7 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
                         int inner_cycles, double rtol, int max_outer, hhg_stats* stats) {
   return guard([&] {
     HHG_REQUIRE(h && xv && bv && prm, HHG_ERR_ARG, "null argument");
+    lattice_only(h, "defect correction");
     HHG_REQUIRE(inner_prec == HHG_F64 || inner_prec == HHG_F32, HHG_ERR_PREC, "inner precision must be F64 or F32");
     HHG_REQUIRE(inner_cycles >= 1 && rtol > 0.0 && max_outer >= 1, HHG_ERR_ARG, "bad iteration parameters");
     HHG_REQUIRE(prm->omega_inv > 0.0 && prm->xi >= 1, HHG_ERR_ARG, "bad solver parameters");
@@ -1910,6 +2183,7 @@ hhg_status hhg_mlp_train_noalloc(hhg_mlp m, const float* x, const float* y, int 
 hhg_status hhg_mlp_dims(hhg_hier h, int* n_in, int* n_out) {
   return guard([&] {
     HHG_REQUIRE(h && n_in && n_out, HHG_ERR_ARG, "null argument");
+    lattice_only(h, "the learned coarse solve");
     HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
     *n_in = h->nunk + h->L(h->lmin).g.nn;
     *n_out = h->nunk;
@@ -1927,6 +2201,7 @@ static void ensure_coarse_buffers(hhg_hier h) {
 hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* target) {
   return guard([&] {
     HHG_REQUIRE(h && r && features && target, HHG_ERR_ARG, "null argument");
+    lattice_only(h, "the learned coarse solve");
     HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
     ensure_coarse_buffers(h);
     Level& lv = h->L(h->lmin);
@@ -1943,6 +2218,7 @@ hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* 
 hhg_status hhg_hier_set_bf16_levels(hhg_hier h, int n) {
   return guard([&] {
     HHG_REQUIRE(h && n >= 0 && n <= h->lmax - h->lmin + 1, HHG_ERR_ARG, "bad number of levels");
+    lattice_only(h, "bfloat16 levels");
     h->bf16_levels = n;
   });
 }
@@ -1962,6 +2238,7 @@ hhg_status hhg_hier_set_fused_sites(hhg_hier h, long max_sites) {
 hhg_status hhg_record_pairs(hhg_hier h, float* features, float* targets, int capacity) {
   return guard([&] {
     HHG_REQUIRE(h && capacity >= 0, HHG_ERR_ARG, "bad arguments");
+    lattice_only(h, "the training-pair recorder");
     HHG_REQUIRE(capacity == 0 || (features && targets), HHG_ERR_ARG, "null buffers");
     HHG_REQUIRE(capacity == 0 || h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
     if (capacity > 0) {
@@ -1986,6 +2263,7 @@ hhg_status hhg_recorded_pairs(hhg_hier h, int* count) {
 hhg_status hhg_hier_set_mlp(hhg_hier h, hhg_mlp m, double rho_plain, double tau) {
   return guard([&] {
     HHG_REQUIRE(h, HHG_ERR_ARG, "null hierarchy");
+    if (m) lattice_only(h, "the learned coarse solve");
     if (m) {
       HHG_REQUIRE(h->nunk > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");
       HHG_REQUIRE(m->net.n_in == h->nunk + h->L(h->lmin).g.nn && m->net.n_out == h->nunk, HHG_ERR_ARG,
@@ -2023,6 +2301,16 @@ hhg_status hhg_query_stencil(hhg_disc disc, char kind, int group, int i, int j, 
   });
 }
 
+hhg_status hhg_query_umesh(const double* xyz, int nv, const int* tet, int nt, int level, hhg_schur schur,
+                           int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos, int* colour,
+                           double* schur_diag, double* K) {
+  return guard([&] {
+    HHG_REQUIRE(xyz && tet, HHG_ERR_ARG, "null mesh");
+    HHG_REQUIRE(schur == HHG_SCHUR_SD || schur == HHG_SCHUR_ML, HHG_ERR_ARG, "unknown Schur option");
+    u_query(xyz, nv, tet, nt, level, schur, max_unknowns, nnodes, ncolours, nunk, pos, colour, schur_diag, K);
+  });
+}
+
 hhg_status hhg_query_interpolation(int order, int tx, int ty, int tz, int q, int* n, int* code, double* w) {
   return guard([&] {
     HHG_REQUIRE(order == 1 || order == 2, HHG_ERR_ARG, "order must be 1 or 2");
@@ -2047,6 +2335,7 @@ hhg_status hhg_vcycle(hhg_hier h, int level, void* x, const void* b, const hhg_s
     check_level(h, level);
     HHG_REQUIRE(x && b && prm && prm->omega_inv > 0.0 && prm->xi >= 1, HHG_ERR_ARG, "bad arguments");
     HHG_REQUIRE(prec == HHG_F64 || prec == HHG_F32, HHG_ERR_PREC, "bad precision");
+    HHG_REQUIRE(!h->um || prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
     ensure_coarse(h);
     if (prec == HHG_F32) {
       HHG_REQUIRE(h->nunk > 0 || prm->coarse_smooth > 0, HHG_ERR_STATE, "no dense coarse solve on this hierarchy");

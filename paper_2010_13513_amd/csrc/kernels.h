@@ -84,7 +84,8 @@ enum KernelFamily {
   KF_MLP = 10,      // MLP matrix products (work units: flops)
   KF_SMALL = 11,    // one-workgroup V-cycle over the small levels
   KF_NEUMANN = 12,  // outflow-face rows, Gauss-Seidel and transfers
-  KF_COUNT = 13
+  KF_IFACE = 13,    // interface-node rows, Gauss-Seidel and copies of unstructured meshes
+  KF_COUNT = 14
 };
 void timer_set_mask(unsigned mask);
 bool timer_enabled();

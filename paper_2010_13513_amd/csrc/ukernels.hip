@@ -1,0 +1,636 @@
+// Kernels of the unstructured-mesh path (Sec. 2, 2.1, 3.2, 3.3), float64.
+//
+// Cell interiors run as lattice kernels: a workgroup of four wavefronts
+// takes four row segments of one cell (grid.y = cell), one lane per point,
+// with the cell's interior rows staged in LDS; neighbours are the 14
+// Freudenthal neighbours in the cell's packed slot order.  Interface nodes
+// (on vertices, edges and faces of T_0) run one thread per node: the row is
+// the sum, over the cells containing the node, of that cell's row of the
+// node's class, and the result goes to every copy of the node.
+#include "umesh.h"
+
+namespace hhg {
+namespace {
+
+constexpr int kUBlock = 256;
+
+__device__ __forceinline__ void unpack(int v, int& i, int& j, int& k) {
+  i = v & 1023;
+  j = (v >> 10) & 1023;
+  k = v >> 20;
+}
+
+// Slot offsets of the 15 stencil points relative to the centre.
+__device__ __forceinline__ void offsets(int i, int j, int k, int n, int (&off)[kUPoints]) {
+  const int c = uslot(i, j, k, n);
+#pragma unroll
+  for (int e = 0; e < kUPoints; ++e) off[e] = uslot(i + udir(e, 0), j + udir(e, 1), k + udir(e, 2), n) - c;
+}
+
+// Interior rows of cell c (class 0) into LDS: A, B^T (3), B (3), M.
+__device__ __forceinline__ void stage_inner(const UCell* __restrict__ cs, double (*w)[kUPoints]) {
+  for (int t = threadIdx.x; t < 8 * kUPoints; t += kUBlock) {
+    const int q = t / kUPoints, e = t % kUPoints;
+    double v;
+    if (q == 0) v = cs->A[0][e];
+    else if (q < 4) v = cs->BT[0][e][q - 1];
+    else if (q < 7) v = cs->B[0][e][q - 4];
+    else v = cs->M[0][e];
+    w[q][e] = v;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ apply
+// opmask bits: 1 A, 2 B^T, 4 B, 8 C, 16 C with + sign (the C block alone);
+// wv / wp: write the velocity / pressure rows.
+template <bool HB, bool MASS>
+__global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, const double* __restrict__ x,
+                                                           const double* __restrict__ b, double* __restrict__ y,
+                                                           int opmask, int wv, int wp) {
+  __shared__ double w[8][kUPoints];
+  const int c = blockIdx.y;
+  const UCell* cs = L.cs + c;
+  stage_inner(cs, w);
+  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (sid >= sg.n) return;
+  const int4 s = sg.s[sid];
+  if (lane >= s.w) return;
+  const int n = L.n, i = s.x + lane, j = s.y, k = s.z;
+  int off[kUPoints];
+  offsets(i, j, k, n, off);
+  const size_t t = (size_t)c * L.P + uslot(i, j, k, n);
+  const size_t vs = L.vs;
+  if (MASS) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const double* xf = x + f * vs + t;
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < kUPoints; ++e) a += w[7][e] * xf[off[e]];
+      y[f * vs + t] = a;
+    }
+    return;
+  }
+  const bool dA = opmask & 1, dBT = opmask & 2, dB = opmask & 4, dC = opmask & 24;
+  double au[3] = {0.0, 0.0, 0.0}, bp[3] = {0.0, 0.0, 0.0}, bu = 0.0, cp = 0.0;
+  const double *u0 = x + t, *u1 = x + vs + t, *u2 = x + 2 * vs + t, *p = x + 3 * vs + t;
+#pragma unroll
+  for (int e = 0; e < kUPoints; ++e) {
+    if (dA || dB) {
+      const double v0 = u0[off[e]], v1 = u1[off[e]], v2 = u2[off[e]];
+      if (dA) {
+        au[0] += w[0][e] * v0;
+        au[1] += w[0][e] * v1;
+        au[2] += w[0][e] * v2;
+      }
+      if (dB) bu += w[4][e] * v0 + w[5][e] * v1 + w[6][e] * v2;
+    }
+    if (dBT || dC) {
+      const double pe = p[off[e]];
+      if (dBT) {
+        bp[0] += w[1][e] * pe;
+        bp[1] += w[2][e] * pe;
+        bp[2] += w[3][e] * pe;
+      }
+      if (dC) cp += w[0][e] * pe;
+    }
+  }
+  const double cf = cs->cfac;
+  const double yp = bu + ((opmask & 16) ? cf * cp : -(cf * cp));
+  if (wv)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double v = au[d] + bp[d];
+      y[d * vs + t] = HB ? b[d * vs + t] - v : v;
+    }
+  if (wp) y[3 * vs + t] = HB ? b[3 * vs + t] - yp : yp;
+}
+
+template <bool HB, bool MASS>
+__global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, const double* __restrict__ x,
+                                                           const double* __restrict__ b, double* __restrict__ y,
+                                                           int opmask, int wv, int wp) {
+  const int q = blockIdx.x * kUBlock + threadIdx.x;
+  if (q >= lst.n) return;
+  const int n = L.n;
+  const size_t vs = L.vs;
+  const int o0 = lst.off[q], o1 = lst.off[q + 1];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, bp[3] = {0.0, 0.0, 0.0}, cp = 0.0;
+  const bool dA = opmask & 1, dBT = opmask & 2, dB = opmask & 4, dC = opmask & 24;
+  for (int o = o0; o < o1; ++o) {
+    const int2 oc = lst.occ[o];
+    int i, j, k;
+    unpack(oc.y, i, j, k);
+    const int m = uclass(i, j, k, n);
+    const UCell* cs = L.cs + oc.x;
+    const unsigned ins = cs->inside[m];
+    const size_t base = (size_t)oc.x * L.P;
+    const double cf = cs->cfac;
+    for (int e = 0; e < kUPoints; ++e) {
+      if (!((ins >> e) & 1)) continue;
+      const size_t sl = base + uslot(i + udir(e, 0), j + udir(e, 1), k + udir(e, 2), n);
+      if (MASS) {
+        const double mw = cs->M[m][e];
+        for (int f = 0; f < 4; ++f) acc[f] += mw * x[f * vs + sl];
+        continue;
+      }
+      if (dA || dB) {
+        const double v0 = x[sl], v1 = x[vs + sl], v2 = x[2 * vs + sl];
+        if (dA) {
+          const double a = cs->A[m][e];
+          acc[0] += a * v0;
+          acc[1] += a * v1;
+          acc[2] += a * v2;
+        }
+        if (dB) acc[3] += cs->B[m][e][0] * v0 + cs->B[m][e][1] * v1 + cs->B[m][e][2] * v2;
+      }
+      if (dBT || dC) {
+        const double pe = x[3 * vs + sl];
+        if (dBT) {
+          bp[0] += cs->BT[m][e][0] * pe;
+          bp[1] += cs->BT[m][e][1] * pe;
+          bp[2] += cs->BT[m][e][2] * pe;
+        }
+        if (dC) cp += cf * cs->A[m][e] * pe;
+      }
+    }
+  }
+  double out[4];
+  {
+    int i, j, k;
+    unpack(lst.occ[o0].y, i, j, k);
+    const size_t own = (size_t)lst.occ[o0].x * L.P + uslot(i, j, k, n);
+    const bool dir = q >= lst.nfree;
+    if (MASS) {
+      for (int f = 0; f < 4; ++f) out[f] = acc[f];
+    } else {
+      for (int d = 0; d < 3; ++d) {
+        const double v = acc[d] + bp[d];
+        out[d] = dir ? 0.0 : (HB ? b[d * vs + own] - v : v);
+      }
+      const double yp = acc[3] + ((opmask & 16) ? cp : -cp);
+      out[3] = HB ? b[3 * vs + own] - yp : yp;
+    }
+  }
+  for (int o = o0; o < o1; ++o) {
+    const int2 oc = lst.occ[o];
+    int i, j, k;
+    unpack(oc.y, i, j, k);
+    const size_t sl = (size_t)oc.x * L.P + uslot(i, j, k, n);
+    if (MASS || wv)
+      for (int d = 0; d < 3; ++d) y[d * vs + sl] = out[d];
+    if (MASS || wp) y[3 * vs + sl] = out[3];
+  }
+}
+
+// ----------------------------------------------------------- Gauss-Seidel
+// One interior colour: points (i, j, k) of the cell interiors with i + j + k
+// = colour (mod 4), segments of stride 4; u_d += (f_d - A u_d - B^T_d p) / a_00.
+__global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double* __restrict__ x,
+                                                        const double* __restrict__ b) {
+  __shared__ double w[8][kUPoints];
+  const int c = blockIdx.y;
+  const UCell* cs = L.cs + c;
+  stage_inner(cs, w);
+  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (sid >= sg.n) return;
+  const int4 s = sg.s[sid];
+  if (lane >= s.w) return;
+  const int n = L.n, i = s.x + 4 * lane, j = s.y, k = s.z;
+  int off[kUPoints];
+  offsets(i, j, k, n, off);
+  const size_t t = (size_t)c * L.P + uslot(i, j, k, n);
+  const size_t vs = L.vs;
+  const double* p = x + 3 * vs + t;
+  double r[3] = {b[t], b[vs + t], b[2 * vs + t]};
+#pragma unroll
+  for (int e = 0; e < kUPoints; ++e) {
+    const double pe = p[off[e]];
+    r[0] -= w[0][e] * x[t + off[e]] + w[1][e] * pe;
+    r[1] -= w[0][e] * x[vs + t + off[e]] + w[2][e] * pe;
+    r[2] -= w[0][e] * x[2 * vs + t + off[e]] + w[3][e] * pe;
+  }
+  const double ai = cs->ainv0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x[d * vs + t] += r[d] * ai;
+}
+
+// Free interface nodes [first, first + count) of one colour.
+__global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int first, int count,
+                                                        double* __restrict__ x, const double* __restrict__ b) {
+  const int t = blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= count) return;
+  const int q = first + t;
+  const int n = L.n;
+  const size_t vs = L.vs;
+  const int o0 = lst.off[q], o1 = lst.off[q + 1];
+  double r[3] = {0.0, 0.0, 0.0};
+  for (int o = o0; o < o1; ++o) {
+    const int2 oc = lst.occ[o];
+    int i, j, k;
+    unpack(oc.y, i, j, k);
+    const int m = uclass(i, j, k, n);
+    const UCell* cs = L.cs + oc.x;
+    const unsigned ins = cs->inside[m];
+    const size_t base = (size_t)oc.x * L.P;
+    for (int e = 0; e < kUPoints; ++e) {
+      if (!((ins >> e) & 1)) continue;
+      const size_t sl = base + uslot(i + udir(e, 0), j + udir(e, 1), k + udir(e, 2), n);
+      const double a = cs->A[m][e], pe = x[3 * vs + sl];
+      r[0] += a * x[sl] + cs->BT[m][e][0] * pe;
+      r[1] += a * x[vs + sl] + cs->BT[m][e][1] * pe;
+      r[2] += a * x[2 * vs + sl] + cs->BT[m][e][2] * pe;
+    }
+  }
+  int i, j, k;
+  unpack(lst.occ[o0].y, i, j, k);
+  const size_t own = (size_t)lst.occ[o0].x * L.P + uslot(i, j, k, n);
+  const double ai = lst.ainv[q];
+  double u[3];
+  for (int d = 0; d < 3; ++d) u[d] = x[d * vs + own] + (b[d * vs + own] - r[d]) * ai;
+  for (int o = o0; o < o1; ++o) {
+    const int2 oc = lst.occ[o];
+    unpack(oc.y, i, j, k);
+    const size_t sl = (size_t)oc.x * L.P + uslot(i, j, k, n);
+    for (int d = 0; d < 3; ++d) x[d * vs + sl] = u[d];
+  }
+}
+
+// p -= omega r_p dinv on every real slot (copies stay equal: same inputs).
+__global__ void __launch_bounds__(kUBlock) k_u_pstep(long nslots, long vs, const double* __restrict__ dinv,
+                                                     double* __restrict__ x, const double* __restrict__ r,
+                                                     double omega) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots) return;
+  x[3 * vs + t] -= omega * r[3 * vs + t] * dinv[t];
+}
+
+// --------------------------------------------------------------- transfer
+// Restriction at coarse interior points: r_c = r_f(2 p) + 1/2 sum of the 14
+// fine neighbours of 2 p (the midpoints of the coarse edges at p).
+__global__ void __launch_bounds__(kUBlock) k_u_restrict_inner(ULev Lf, ULev Lc, USegs sg,
+                                                              const double* __restrict__ rf,
+                                                              double* __restrict__ rc) {
+  const int c = blockIdx.y;
+  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (sid >= sg.n) return;
+  const int4 s = sg.s[sid];
+  if (lane >= s.w) return;
+  const int i = s.x + lane, j = s.y, k = s.z;
+  int off[kUPoints];
+  offsets(2 * i, 2 * j, 2 * k, Lf.n, off);
+  const size_t tf = (size_t)c * Lf.P + uslot(2 * i, 2 * j, 2 * k, Lf.n);
+  const size_t tc = (size_t)c * Lc.P + uslot(i, j, k, Lc.n);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const double* r = rf + f * Lf.vs + tf;
+    double a = 0.0;
+#pragma unroll
+    for (int e = 1; e < kUPoints; ++e) a += r[off[e]];
+    rc[f * Lc.vs + tc] = r[0] + 0.5 * a;
+  }
+}
+
+// Restriction at coarse interface nodes: the fine node at 2 q, plus half of
+// every fine midpoint next to it, each midpoint taken once (from the cell
+// that owns the primitive it lies on); fine Dirichlet velocity values count
+// as zero and the coarse Dirichlet velocity rows are zero.
+__global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, UList lst,
+                                                              const double* __restrict__ rf,
+                                                              double* __restrict__ rc) {
+  const int q = blockIdx.x * kUBlock + threadIdx.x;
+  if (q >= lst.n) return;
+  const int nc = Lc.n, nf = Lf.n;
+  const int o0 = lst.off[q], o1 = lst.off[q + 1];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int o = o0; o < o1; ++o) {
+    const int2 oc = lst.occ[o];
+    int i, j, k;
+    unpack(oc.y, i, j, k);
+    const int m = uclass(i, j, k, nc);
+    const UCell* cs = Lf.cs + oc.x;
+    const unsigned ins = cs->inside[m];
+    const size_t base = (size_t)oc.x * Lf.P;
+    for (int e = 1; e < kUPoints; ++e) {
+      if (!((ins >> e) & 1)) continue;
+      const int I = 2 * i + udir(e, 0), J = 2 * j + udir(e, 1), K = 2 * k + udir(e, 2);
+      const int mf = uclass(I, J, K, nf);
+      if (!((cs->owned >> mf) & 1)) continue;
+      const size_t sl = base + uslot(I, J, K, nf);
+      const bool fd = (cs->bnd >> mf) & 1;
+      for (int f = 0; f < 4; ++f) acc[f] += (f < 3 && fd) ? 0.0 : 0.5 * rf[f * Lf.vs + sl];
+    }
+  }
+  int i, j, k;
+  unpack(lst.occ[o0].y, i, j, k);
+  const size_t fown = (size_t)lst.occ[o0].x * Lf.P + uslot(2 * i, 2 * j, 2 * k, nf);
+  const bool dir = q >= lst.nfree;
+  double out[4];
+  for (int f = 0; f < 4; ++f) out[f] = (f < 3 && dir) ? 0.0 : rf[f * Lf.vs + fown] + acc[f];
+  for (int o = o0; o < o1; ++o) {
+    const int2 oc = lst.occ[o];
+    unpack(oc.y, i, j, k);
+    const size_t sl = (size_t)oc.x * Lc.P + uslot(i, j, k, nc);
+    for (int f = 0; f < 4; ++f) rc[f * Lc.vs + sl] = out[f];
+  }
+}
+
+// Linear interpolation at every fine slot of a cell (copies of interface
+// nodes included: every cell computes the same value for them).
+__global__ void __launch_bounds__(kUBlock) k_u_prolong(ULev Lc, ULev Lf, USegs sg, const double* __restrict__ xc,
+                                                       double* __restrict__ xf, int add, int skip_bnd) {
+  const int c = blockIdx.y;
+  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (sid >= sg.n) return;
+  const int4 s = sg.s[sid];
+  if (lane >= s.w) return;
+  const int I = s.x + lane, J = s.y, K = s.z;
+  const int nf = Lf.n, nc = Lc.n;
+  const size_t tf = (size_t)c * Lf.P + uslot(I, J, K, nf);
+  const size_t ta = (size_t)c * Lc.P + uslot(I >> 1, J >> 1, K >> 1, nc);
+  const size_t tb = (size_t)c * Lc.P + uslot((I + 1) >> 1, (J + 1) >> 1, (K + 1) >> 1, nc);
+  const bool even = !((I | J | K) & 1);
+  const bool fd = skip_bnd && ((Lf.cs[c].bnd >> uclass(I, J, K, nf)) & 1);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const double v = even ? xc[f * Lc.vs + ta] : 0.5 * (xc[f * Lc.vs + ta] + xc[f * Lc.vs + tb]);
+    double* o = xf + f * Lf.vs + tf;
+    if (!add) *o = v;
+    else if (!(f < 3 && fd)) *o += v;
+  }
+}
+
+// Dirichlet velocity slots of the coarse level <- the fine value at 2 (i, j, k).
+__global__ void __launch_bounds__(kUBlock) k_u_inject(ULev Lf, ULev Lc, USegs sg, const double* __restrict__ xf,
+                                                      double* __restrict__ xc) {
+  const int c = blockIdx.y;
+  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (sid >= sg.n) return;
+  const int4 s = sg.s[sid];
+  if (lane >= s.w) return;
+  const int i = s.x + lane, j = s.y, k = s.z;
+  if (!((Lc.cs[c].bnd >> uclass(i, j, k, Lc.n)) & 1)) return;
+  const size_t tc = (size_t)c * Lc.P + uslot(i, j, k, Lc.n);
+  const size_t tf = (size_t)c * Lf.P + uslot(2 * i, 2 * j, 2 * k, Lf.n);
+  for (int d = 0; d < 3; ++d) xc[d * Lc.vs + tc] = xf[d * Lf.vs + tf];
+}
+
+// ------------------------------------------------------------ flat kernels
+__global__ void __launch_bounds__(kUBlock) k_u_copy_bnd(long nslots, long vs, const unsigned char* __restrict__ fl,
+                                                        const double* __restrict__ src, double* __restrict__ dst) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots || !(fl[t] & 2)) return;
+  for (int d = 0; d < 3; ++d) dst[d * vs + t] = src[d * vs + t];
+}
+
+// Load vector of the right-hand side: zero Dirichlet velocity rows and the pressure rows.
+__global__ void __launch_bounds__(kUBlock) k_u_rhs_fix(long nslots, long vs, const unsigned char* __restrict__ fl,
+                                                       double* __restrict__ b) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots) return;
+  if (fl[t] & 2)
+    for (int d = 0; d < 3; ++d) b[d * vs + t] = 0.0;
+  b[3 * vs + t] = 0.0;
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_from_canon(long nslots, long vs, const int* __restrict__ canon,
+                                                          int nnodes, const double* __restrict__ src,
+                                                          double* __restrict__ dst) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots) return;
+  const int q = canon[t];
+  for (int f = 0; f < 4; ++f) dst[f * vs + t] = src[(size_t)f * nnodes + q];
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_to_canon(long nslots, long vs, const int* __restrict__ canon,
+                                                        const unsigned char* __restrict__ fl, int nnodes,
+                                                        const double* __restrict__ src, double* __restrict__ dst) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots || !(fl[t] & 1)) return;
+  const int q = canon[t];
+  for (int f = 0; f < 4; ++f) dst[(size_t)f * nnodes + q] = src[f * vs + t];
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_pfrom_canon(long nslots, const int* __restrict__ canon,
+                                                           const double* __restrict__ src, double* __restrict__ p) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots) return;
+  p[t] = src[canon[t]];
+}
+
+template <bool W, bool Y>
+__global__ void __launch_bounds__(kUBlock) k_u_dot(long nslots, long vs, const unsigned char* __restrict__ fl,
+                                                   const double* __restrict__ w, const double* __restrict__ x,
+                                                   const double* __restrict__ y, int f0, int nf,
+                                                   double* __restrict__ partial) {
+  __shared__ double sa[kUBlock];
+  double a = 0.0;
+  for (long t = (long)blockIdx.x * kUBlock + threadIdx.x; t < nslots; t += (long)gridDim.x * kUBlock) {
+    if (!(fl[t] & 1)) continue;
+    for (int f = f0; f < f0 + nf; ++f) {
+      const double v = x[f * vs + t] * (Y ? y[f * vs + t] : 1.0);
+      a += W ? w[t] * v : v;
+    }
+  }
+  sa[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = kUBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sa[threadIdx.x] += sa[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sa[0];
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_final(const double* __restrict__ partial, int nparts,
+                                                     double* __restrict__ out) {
+  __shared__ double sa[kUBlock];
+  double a = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += kUBlock) a += partial[q];
+  sa[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = kUBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sa[threadIdx.x] += sa[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sa[0];
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_shift(long nslots, double* __restrict__ p,
+                                                     const double* __restrict__ sums, int slot, double denom) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots) return;
+  p[t] -= sums[slot] / denom;
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_pscale(long nslots, double* __restrict__ p,
+                                                      const double* __restrict__ sums, int slot) {
+  const long t = (long)blockIdx.x * kUBlock + threadIdx.x;
+  if (t >= nslots) return;
+  p[t] *= 1.0 / sqrt(sums[slot]);
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_sync(ULev L, UList lst, double* __restrict__ x) {
+  const int q = blockIdx.x * kUBlock + threadIdx.x;
+  if (q >= lst.n) return;
+  const int o0 = lst.off[q], o1 = lst.off[q + 1];
+  int i, j, k;
+  unpack(lst.occ[o0].y, i, j, k);
+  const size_t own = (size_t)lst.occ[o0].x * L.P + uslot(i, j, k, L.n);
+  double v[4];
+  for (int f = 0; f < 4; ++f) v[f] = x[f * L.vs + own];
+  for (int o = o0 + 1; o < o1; ++o) {
+    const int2 oc = lst.occ[o];
+    unpack(oc.y, i, j, k);
+    const size_t sl = (size_t)oc.x * L.P + uslot(i, j, k, L.n);
+    for (int f = 0; f < 4; ++f) x[f * L.vs + sl] = v[f];
+  }
+}
+
+unsigned ublocks(long n) { return (unsigned)((n + kUBlock - 1) / kUBlock); }
+dim3 seg_grid(const USegs& s, int ncell) { return dim3((unsigned)((s.n + 3) / 4), (unsigned)ncell); }
+long real_slots(const ULev& L) { return (long)L.ncell * L.P; }
+constexpr int kUPartials = 512;
+
+}  // namespace
+
+void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList& lst, const double* x,
+                         const double* b, double* y, int opmask, bool has_b, bool mass, bool wv, bool wp) {
+  if (inner.n > 0) {
+    KScope ks(s, KF_APPLY, (double)inner.n * 64);
+    const dim3 g = seg_grid(inner, L.ncell);
+    if (mass)
+      hipLaunchKernelGGL((k_u_apply_inner<false, true>), g, dim3(kUBlock), 0, s, L, inner, x, b, y, opmask, 1, 1);
+    else if (has_b)
+      hipLaunchKernelGGL((k_u_apply_inner<true, false>), g, dim3(kUBlock), 0, s, L, inner, x, b, y, opmask, (int)wv,
+                         (int)wp);
+    else
+      hipLaunchKernelGGL((k_u_apply_inner<false, false>), g, dim3(kUBlock), 0, s, L, inner, x, b, y, opmask, (int)wv,
+                         (int)wp);
+  }
+  if (lst.n > 0) {
+    KScope ks(s, KF_IFACE, (double)lst.n);
+    const dim3 g(ublocks(lst.n));
+    if (mass)
+      hipLaunchKernelGGL((k_u_apply_iface<false, true>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, 1, 1);
+    else if (has_b)
+      hipLaunchKernelGGL((k_u_apply_iface<true, false>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, (int)wv,
+                         (int)wp);
+    else
+      hipLaunchKernelGGL((k_u_apply_iface<false, false>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, (int)wv,
+                         (int)wp);
+  }
+}
+
+void launch_u_gs_inner(hipStream_t s, const ULev& L, USegs seg, double* x, const double* b) {
+  if (seg.n == 0) return;
+  KScope ks(s, KF_GS_VERTEX, (double)seg.n * 64);
+  hipLaunchKernelGGL(k_u_gs_inner, seg_grid(seg, L.ncell), dim3(kUBlock), 0, s, L, seg, x, b);
+}
+
+void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first, int count, double* x,
+                       const double* b) {
+  if (count <= 0) return;
+  KScope ks(s, KF_IFACE, (double)count);
+  hipLaunchKernelGGL(k_u_gs_iface, dim3(ublocks(count)), dim3(kUBlock), 0, s, L, lst, first, count, x, b);
+}
+
+void launch_u_pstep(hipStream_t s, const ULev& L, const double* dinv, double* x, const double* r, double omega) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_PSTEP, (double)n);
+  hipLaunchKernelGGL(k_u_pstep, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, L.vs, dinv, x, r, omega);
+}
+
+void launch_u_restrict(hipStream_t s, const ULev& Lf, const ULev& Lc, USegs inner_c, const UList& lst_c,
+                       const double* rf, double* rc) {
+  KScope ks(s, KF_RESTRICT, (double)real_slots(Lc));
+  if (inner_c.n > 0)
+    hipLaunchKernelGGL(k_u_restrict_inner, seg_grid(inner_c, Lc.ncell), dim3(kUBlock), 0, s, Lf, Lc, inner_c, rf,
+                       rc);
+  if (lst_c.n > 0)
+    hipLaunchKernelGGL(k_u_restrict_iface, dim3(ublocks(lst_c.n)), dim3(kUBlock), 0, s, Lf, Lc, lst_c, rf, rc);
+}
+
+void launch_u_prolong(hipStream_t s, const ULev& Lc, const ULev& Lf, USegs all_f, const double* xc, double* xf,
+                      bool add, bool skip_bnd) {
+  if (all_f.n == 0) return;
+  KScope ks(s, KF_PROLONG, (double)real_slots(Lf));
+  hipLaunchKernelGGL(k_u_prolong, seg_grid(all_f, Lf.ncell), dim3(kUBlock), 0, s, Lc, Lf, all_f, xc, xf, (int)add,
+                     (int)skip_bnd);
+}
+
+void launch_u_inject(hipStream_t s, const ULev& Lf, const ULev& Lc, USegs all_c, const double* xf, double* xc) {
+  if (all_c.n == 0) return;
+  KScope ks(s, KF_OTHER, (double)real_slots(Lc));
+  hipLaunchKernelGGL(k_u_inject, seg_grid(all_c, Lc.ncell), dim3(kUBlock), 0, s, Lf, Lc, all_c, xf, xc);
+}
+
+void launch_u_copy_bnd(hipStream_t s, const ULev& L, const unsigned char* flags, const double* src, double* dst) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_OTHER, (double)n);
+  hipLaunchKernelGGL(k_u_copy_bnd, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, L.vs, flags, src, dst);
+}
+
+void launch_u_rhs_fix(hipStream_t s, const ULev& L, const unsigned char* flags, double* b) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_OTHER, (double)n);
+  hipLaunchKernelGGL(k_u_rhs_fix, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, L.vs, flags, b);
+}
+
+void launch_u_from_canon(hipStream_t s, const ULev& L, const int* canon, int nnodes, const double* src, double* dst) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_OTHER, (double)n);
+  hipLaunchKernelGGL(k_u_from_canon, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, L.vs, canon, nnodes, src, dst);
+}
+
+void launch_u_to_canon(hipStream_t s, const ULev& L, const int* canon, const unsigned char* flags, int nnodes,
+                       const double* src, double* dst) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_OTHER, (double)n);
+  hipLaunchKernelGGL(k_u_to_canon, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, L.vs, canon, flags, nnodes, src, dst);
+}
+
+void launch_u_pfrom_canon(hipStream_t s, const ULev& L, const int* canon, const double* src, double* p) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_OTHER, (double)n);
+  hipLaunchKernelGGL(k_u_pfrom_canon, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, canon, src, p);
+}
+
+void launch_u_dot(hipStream_t s, const ULev& L, const unsigned char* flags, const double* w, const double* x,
+                  const double* y, int f0, int nf, double* partial, double* sums, int out) {
+  const long n = real_slots(L);
+  const unsigned nb = std::min<unsigned>(ublocks(n), kUPartials);
+  KScope ks(s, KF_REDUCE, (double)n);
+  if (w && y)
+    hipLaunchKernelGGL((k_u_dot<true, true>), dim3(nb), dim3(kUBlock), 0, s, n, L.vs, flags, w, x, y, f0, nf, partial);
+  else if (w)
+    hipLaunchKernelGGL((k_u_dot<true, false>), dim3(nb), dim3(kUBlock), 0, s, n, L.vs, flags, w, x, y, f0, nf,
+                       partial);
+  else if (y)
+    hipLaunchKernelGGL((k_u_dot<false, true>), dim3(nb), dim3(kUBlock), 0, s, n, L.vs, flags, w, x, y, f0, nf,
+                       partial);
+  else
+    hipLaunchKernelGGL((k_u_dot<false, false>), dim3(nb), dim3(kUBlock), 0, s, n, L.vs, flags, w, x, y, f0, nf,
+                       partial);
+  hipLaunchKernelGGL(k_u_final, dim3(1), dim3(kUBlock), 0, s, partial, (int)nb, sums + out);
+}
+
+void launch_u_shift(hipStream_t s, const ULev& L, double* p, const double* sums, int slot, double denom) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_OTHER, (double)n);
+  hipLaunchKernelGGL(k_u_shift, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, p, sums, slot, denom);
+}
+
+void launch_u_pscale(hipStream_t s, const ULev& L, double* p, const double* sums, int slot) {
+  const long n = real_slots(L);
+  KScope ks(s, KF_OTHER, (double)n);
+  hipLaunchKernelGGL(k_u_pscale, dim3(ublocks(n)), dim3(kUBlock), 0, s, n, p, sums, slot);
+}
+
+void launch_u_sync(hipStream_t s, const ULev& L, const UList& lst, double* x) {
+  if (lst.n == 0) return;
+  KScope ks(s, KF_IFACE, (double)lst.n);
+  hipLaunchKernelGGL(k_u_sync, dim3(ublocks(lst.n)), dim3(kUBlock), 0, s, L, lst, x);
+}
+
+}  // namespace hhg

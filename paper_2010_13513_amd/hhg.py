@@ -24,14 +24,14 @@ SYMBOLS = [
     "hhg_hier_create", "hhg_hier_destroy", "hhg_vec_layout", "hhg_vec_from_lattice", "hhg_vec_to_lattice",
     "hhg_apply", "hhg_residual", "hhg_rhs", "hhg_smooth", "hhg_restrict", "hhg_prolong_add",
     "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
-    "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation", "hhg_dots",
+    "hhg_vcycle", "hhg_fmg_solve", "hhg_query_stencil", "hhg_query_interpolation", "hhg_query_umesh", "hhg_dots",
     "hhg_timer_start", "hhg_timer_read", "hhg_dc_solve", "hhg_set_viscosity",
     "hhg_mlp_create", "hhg_mlp_destroy", "hhg_mlp_num_params", "hhg_mlp_set_params", "hhg_mlp_get_params",
     "hhg_mlp_forward", "hhg_mlp_loss_grad", "hhg_mlp_train", "hhg_mlp_train_noalloc", "hhg_mlp_dims", "hhg_coarse_pair", "hhg_hier_set_mlp",
     "hhg_record_pairs", "hhg_recorded_pairs", "hhg_hier_set_fused_sites", "hhg_hier_set_bf16_levels",
 ]
 KF_APPLY, KF_PROW_BND, KF_GS_VERTEX, KF_GS_EDGE, KF_PSTEP, KF_RESTRICT, KF_PROLONG, KF_COARSE, KF_REDUCE, KF_OTHER, \
-    KF_MLP, KF_SMALL, KF_NEUMANN = range(13)
+    KF_MLP, KF_SMALL, KF_NEUMANN, KF_IFACE = range(14)
 
 
 class HHGError(RuntimeError):
@@ -99,6 +99,7 @@ def load():
         "hhg_fmg_solve": [P, P, P, P, P],
         "hhg_query_stencil": [I, ctypes.c_char, I, I, I, I, I, I, P, P, P],
         "hhg_query_interpolation": [I, I, I, I, I, P, P, P],
+        "hhg_query_umesh": [P, I, P, I, I, I, I, P, P, P, P, P, P, P],
         "hhg_dots": [P, I, P, P, P, P, I],
         "hhg_timer_start": [ctypes.c_uint],
         "hhg_timer_read": [I, P, P, P],
@@ -342,6 +343,30 @@ def hhg_query_interpolation(order, tx, ty, tz, q):
     _check(load().hhg_query_interpolation(order, tx, ty, tz, q, ctypes.byref(n), code, w))
     m = n.value
     return np.array(code[:4 * m]).reshape(m, 4), np.array(w[:m])
+
+
+def hhg_query_umesh(xyz, tet, level, schur=HHG_SCHUR_SD, max_unknowns=0):
+    """Host-only: tables of one level of an unstructured mesh.  Returns a dict
+    with nnodes, ncolours, nunk, pos (nnodes, 3), colour (nnodes,),
+    schur_diag (nnodes,) and K (nunk, nunk) or None."""
+    import numpy as np
+    x = np.ascontiguousarray(xyz, dtype=np.float64)
+    t = np.ascontiguousarray(tet, dtype=np.int32)
+    nn, nc, nu = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    lib = load()
+    args = (x.ctypes.data, x.shape[0], t.ctypes.data, t.shape[0], level, schur)
+    _check(lib.hhg_query_umesh(*args, 0, ctypes.byref(nn), ctypes.byref(nc), ctypes.byref(nu),
+                               None, None, None, None))
+    n = nn.value
+    pos = np.zeros((n, 3))
+    col = np.zeros(n, dtype=np.int32)
+    sd = np.zeros(n)
+    K = np.zeros((nu.value, nu.value)) if 0 < nu.value <= max_unknowns else None
+    _check(lib.hhg_query_umesh(*args, max_unknowns, ctypes.byref(nn), ctypes.byref(nc), ctypes.byref(nu),
+                               pos.ctypes.data, col.ctypes.data, sd.ctypes.data,
+                               None if K is None else K.ctypes.data))
+    return {"nnodes": n, "ncolours": nc.value, "nunk": nu.value, "pos": pos, "colour": col, "schur_diag": sd,
+            "K": K}
 
 
 # ------------------------------------------------------------ learned coarse solve

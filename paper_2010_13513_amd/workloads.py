@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs: manufactured solutions, forcing and viscosity fields.
+"""Seeded synthetic inputs: manufactured solutions, forcing and viscosity
+fields, and macro meshes T_0 (vertex coordinates and tetrahedra).
 
 Problem data only -- analytic fields evaluated at given coordinates and seeded
 random draws.  It contains none of the solver's arithmetic; both the library's
@@ -233,3 +234,88 @@ def lognormal_viscosity(seed, modes=8, kmax=2, ratio=100.0):
 def normal_vector(seed, n):
     """Seeded N(0,1) float64 vector."""
     return rng(seed).standard_normal(n)
+
+
+# ------------------------------------------------------------ macro meshes
+# Input geometry only: (xyz (nv, 3) float64, tets (nt, 4) int64).
+
+def cube24():
+    """The unit cube as 24 tetrahedra: each face split into 4 triangles at its
+    centre, each triangle joined to the cube's centre (15 vertices, 50 edges,
+    60 faces).  Uniform refinement gives 4.29e6 P1-P1 unknowns at L = 6 and
+    3.36e6 P2-P1 unknowns at L = 5, the counts quoted for the cube benchmark
+    of Sec. 5.1.1."""
+    xyz = [(i, j, k) for k in (0, 1) for j in (0, 1) for i in (0, 1)]          # corners 0..7
+    cid = {c: n for n, c in enumerate(xyz)}
+    faces = []
+    for d in range(3):
+        for side in (0, 1):
+            cen = [0.5, 0.5, 0.5]
+            cen[d] = side
+            xyz.append(tuple(cen))
+            a, b = [e for e in range(3) if e != d]
+            ring = []
+            for (s, t) in ((0, 0), (1, 0), (1, 1), (0, 1)):     # around the face
+                c = [0, 0, 0]
+                c[d], c[a], c[b] = side, s, t
+                ring.append(cid[tuple(c)])
+            faces.append((len(xyz) - 1, ring))
+    xyz.append((0.5, 0.5, 0.5))
+    body = len(xyz) - 1
+    tets = []
+    for fc, ring in faces:
+        for q in range(4):
+            tets.append((body, fc, ring[q], ring[(q + 1) % 4]))
+    return np.array(xyz, dtype=float), np.array(tets, dtype=np.int64)
+
+
+_KUHN_PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+
+
+def kuhn_cube(N):
+    """The unit cube as N^3 sub-cubes of 6 Kuhn tetrahedra each (vertices of
+    a tetrahedron along the path 0, e_a, e_a + e_b, (1,1,1))."""
+    n1 = N + 1
+    xyz = np.array([(i, j, k) for k in range(n1) for j in range(n1) for i in range(n1)], float) / N
+    idx = lambda c: c[0] + n1 * (c[1] + n1 * c[2])
+    tets = []
+    for k in range(N):
+        for j in range(N):
+            for i in range(N):
+                for p in _KUHN_PERMS:
+                    c = [i, j, k]
+                    t = [idx(c)]
+                    for a in p:
+                        c[a] += 1
+                        t.append(idx(c))
+                    tets.append(t)
+    return xyz, np.array(tets, dtype=np.int64)
+
+
+def jittered_cube(seed, N=2, amp=0.12):
+    """kuhn_cube(N) with every vertex moved by a seeded uniform offset of up
+    to amp / N per coordinate, except along the normals of the cube faces it
+    lies on (the domain stays the unit cube, the mesh is no Kuhn partition)."""
+    xyz, tets = kuhn_cube(N)
+    off = rng(seed).uniform(-amp / N, amp / N, size=xyz.shape)
+    on_face = (np.abs(xyz) < 1e-12) | (np.abs(xyz - 1.0) < 1e-12)
+    return xyz + np.where(on_face, 0.0, off), tets
+
+
+def box_cube24(nx, ny, nz):
+    """An nx x ny x nz box of unit cubes, each split as in cube24 (shared
+    vertices merged)."""
+    xyz0, tets0 = cube24()
+    pts, tets = {}, []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                ids = []
+                for v in xyz0 + np.array([i, j, k], float):
+                    key = tuple(np.round(v * 2).astype(int))
+                    ids.append(pts.setdefault(key, len(pts)))
+                tets += [[ids[a] for a in t] for t in tets0]
+    xyz = np.zeros((len(pts), 3))
+    for key, q in pts.items():
+        xyz[q] = np.array(key, float) / 2
+    return xyz, np.array(tets, dtype=np.int64)

@@ -16,13 +16,19 @@ def torch_cuda():
 class Lib:
     """One context + hierarchy on cuda:0, on torch's current stream."""
 
-    def __init__(self, disc, lmin, lmax, macro_refine=0, schur=hhg.HHG_SCHUR_SD, outflow=0):
+    def __init__(self, disc, lmin, lmax, macro_refine=0, schur=hhg.HHG_SCHUR_SD, outflow=0, mesh=None):
+        """mesh: optional (xyz, tets) macro mesh for hhg_mesh_create instead
+        of the Kuhn cube (a non-Kuhn mesh gives the unstructured path, whose
+        plain vector order is the oracle's node order)."""
         torch = torch_cuda()
         self.torch = torch
         self.dev = torch.device("cuda:0")
         stream = torch.cuda.current_stream(self.dev).cuda_stream
         self.ctx = hhg.hhg_ctx_create(0, stream)
-        mesh = hhg.hhg_mesh_cube(self.ctx, macro_refine)
+        if mesh is not None:
+            mesh = hhg.hhg_mesh_create(self.ctx, mesh[0], mesh[1])
+        else:
+            mesh = hhg.hhg_mesh_cube(self.ctx, macro_refine)
         try:
             if outflow:
                 hhg.hhg_mesh_set_outflow(mesh, outflow)

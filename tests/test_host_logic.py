@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import fe, mesh, transfer
+from paper_2010_13513_amd import workloads as W
 from paper_2010_13513_amd import hhg
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -165,3 +166,51 @@ def test_parameter_search_space_has_768_tuples():
     s = study.search_space()
     assert len(s) == 768 and len(set(s)) == 768
     assert {t[5] for t in s if t[4] == 0} == {1, 2, 3, 4} and {t[5] for t in s if t[4] == 1} == {1, 2}
+
+
+UMESHES = {
+    "cube24": lambda: W.cube24(),
+    "jittered": lambda: W.jittered_cube(W.SEED_BASE + 7000),
+    "box2": lambda: W.box_cube24(2, 1, 1),
+}
+
+
+@pytest.mark.parametrize("name,level", [("cube24", 0), ("cube24", 1), ("cube24", 2), ("jittered", 1),
+                                        ("jittered", 2), ("box2", 1)])
+@pytest.mark.parametrize("schur", ["sd", "ml"])
+def test_unstructured_tables_match_oracle(name, level, schur):
+    """Host tables of the unstructured path against oracle/umesh: node order
+    (positions), Gauss-Seidel colours (exact), Schur diagonal and the operator
+    on the coarse unknowns."""
+    from oracle import coarse as ocoarse, smoother, umesh
+    from oracle.stokes import Stokes
+    xyz, tets = UMESHES[name]()
+    code = hhg.HHG_SCHUR_SD if schur == "sd" else hhg.HHG_SCHUR_ML
+    q = hhg.hhg_query_umesh(xyz, tets, level, code, max_unknowns=1500)
+    U = umesh.ULevel(xyz, tets, level)
+    S = Stokes(U)
+    assert q["nnodes"] == U.nv and q["ncolours"] == U.ncolours
+    assert np.abs(q["pos"] - U.vpos()).max() <= 1e-15 * max(1.0, np.abs(xyz).max())
+    assert np.array_equal(q["colour"], U.colour)
+    d = smoother.schur_diagonal(S, schur)
+    assert np.abs(q["schur_diag"] - d).max() <= 1e-13 * np.abs(d).max()
+    if q["K"] is not None:
+        K, _ = ocoarse.dense_system(S)
+        assert K.shape == q["K"].shape
+        assert np.abs(q["K"] - K).max() <= 1e-13 * np.abs(K).max()
+
+
+def test_unstructured_query_rejects_bad_meshes():
+    xyz, tets = W.cube24()
+    bad = tets.copy()
+    bad[3, 2] = bad[3, 1]                         # repeated vertex
+    with pytest.raises(hhg.HHGError):
+        hhg.hhg_query_umesh(xyz, bad, 1)
+    flat = xyz.copy()
+    flat[14] = flat[8]                            # body centre onto a face centre: degenerate tetrahedra
+    with pytest.raises(hhg.HHGError):
+        hhg.hhg_query_umesh(flat, tets, 1)
+    with pytest.raises(hhg.HHGError):
+        hhg.hhg_query_umesh(xyz, np.vstack([tets, tets[:1]]), 1)   # tetrahedron twice
+    with pytest.raises(hhg.HHGError):
+        hhg.hhg_query_umesh(xyz, tets, 7)                          # query levels 0..6

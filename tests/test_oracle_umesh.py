@@ -45,7 +45,7 @@ def _perm_by_position(lev_a_pos, lev_b_pos):
 
 
 def test_cube24_partition():
-    xyz, tets = umesh.cube24()
+    xyz, tets = W.cube24()
     assert xyz.shape == (15, 3) and tets.shape == (24, 4)
     vols = [fe.geometry(xyz[t])[0] for t in tets]
     assert min(vols) > 0 and abs(sum(vols) - 1.0) < 1e-14
@@ -58,7 +58,7 @@ def test_cube24_partition():
 
 @pytest.mark.parametrize("which,level", [("cube24", 1), ("cube24", 2), ("kuhn2", 1)])
 def test_node_counts_from_primitive_counts(which, level):
-    xyz, tets = umesh.cube24() if which == "cube24" else umesh.kuhn_cube(2)
+    xyz, tets = W.cube24() if which == "cube24" else W.kuhn_cube(2)
     pr = _primitives(tets)
     n = 2 ** level
     want = sum(len(pr[d]) * _comb(n - 1, d - 1) for d in (1, 2, 3, 4))
@@ -73,7 +73,7 @@ def test_node_counts_from_primitive_counts(which, level):
 @pytest.mark.parametrize("Nmacro,level", [(1, 1), (1, 2), (2, 1)])
 def test_kuhn_partition_equals_lattice_level(Nmacro, level):
     """Kuhn T_0 refined by Bey's rule = Freudenthal lattice with N = Nmacro 2^l."""
-    xyz, tets = umesh.kuhn_cube(Nmacro)
+    xyz, tets = W.kuhn_cube(Nmacro)
     U = umesh.ULevel(xyz, tets, level)
     N = Nmacro * 2 ** level
     F = fe.Level(N, 1)
@@ -101,7 +101,7 @@ def test_closed_forms_equal_quadrature():
 
 @pytest.fixture(scope="module")
 def cube24_l2():
-    xyz, tets = umesh.cube24()
+    xyz, tets = W.cube24()
     R = np.linalg.qr(np.random.default_rng(3).standard_normal((3, 3)))[0]
     return umesh.ULevel(xyz, tets, 2), umesh.ULevel(1.7 * xyz @ R.T + 0.3, tets, 2), R
 
@@ -141,7 +141,7 @@ def test_colouring_is_conflict_free(cube24_l2):
 
 
 def test_prolongation_reproduces_linears():
-    xyz, tets = umesh.cube24()
+    xyz, tets = W.cube24()
     Lc, Lf = umesh.ULevel(xyz, tets, 1), umesh.ULevel(xyz, tets, 2)
     P = umesh.prolongation(Lc, Lf)
     assert np.allclose(P @ np.ones(Lc.nv), 1.0, atol=1e-15)
@@ -157,7 +157,7 @@ def test_prolongation_reproduces_linears():
 def test_fmg_reproduces_linear_solution_on_cube24():
     """Patch test of the whole solver: u = (y, z, x), p = 0 lies in the P1-P1
     space and solves the stabilised system exactly."""
-    xyz, tets = umesh.cube24()
+    xyz, tets = W.cube24()
     H = umesh.hierarchy(xyz, tets, 0, 2, schur="sd")
     prob = W.linear_exact()
     x = H.fmg(prob, mg.Params(2, 2, 0, 1, "f", 1, 2.0), cycles_on_finest=25)
@@ -166,7 +166,7 @@ def test_fmg_reproduces_linear_solution_on_cube24():
 
 
 def test_vcycle_contracts_on_cube24():
-    xyz, tets = umesh.cube24()
+    xyz, tets = W.cube24()
     H = umesh.hierarchy(xyz, tets, 0, 2, schur="sd")
     prob = W.sine_cube()
     b = H.rhs(2, prob)
@@ -187,7 +187,7 @@ def test_discretisation_orders_on_cube24():
     24-tetrahedron cube.  Levels 2 -> 3 are pre-asymptotic (rates 1.60 and
     1.67; levels 3 -> 4 give 1.85 and 1.78, too slow for the suite), so the
     bound is 1.5: a dropped term or a wrong sign leaves rates near 0 or 1."""
-    xyz, tets = umesh.cube24()
+    xyz, tets = W.cube24()
     H = umesh.hierarchy(xyz, tets, 1, 3, schur="sd")
     prob = W.sine_cube()
     errs = []
@@ -201,3 +201,16 @@ def test_discretisation_orders_on_cube24():
         errs.append((eu, ep))
     rate = np.log2(np.array(errs[0]) / np.array(errs[1]))
     assert rate[0] > 1.5 and rate[1] > 1.5, (errs, rate)
+
+
+def test_cube24_reproduces_the_papers_unknown_counts():
+    """Sec. 5.1.1: the 24-tetrahedron cube refined L = 6 times has about 4.3e6
+    P1-P1 unknowns, and about 3.4e6 P2-P1 unknowns at L = 5 (P2 velocity nodes
+    of level 5 = P1 nodes of level 6)."""
+    xyz, tets = W.cube24()
+    pr = _primitives(tets)
+    assert [len(pr[d]) for d in (1, 2, 3, 4)] == [15, 50, 60, 24]
+    nodes = lambda n: sum(len(pr[d]) * _comb(n - 1, d - 1) for d in (1, 2, 3, 4))
+    p1 = 4 * nodes(64)
+    p2 = 3 * nodes(64) + nodes(32)
+    assert abs(p1 / 4.3e6 - 1) < 0.01 and abs(p2 / 3.4e6 - 1) < 0.02, (p1, p2)
