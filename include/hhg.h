@@ -153,8 +153,10 @@ const char* hhg_last_error(void);
  * path; hhg_mesh_info reports macro_refine = -1).  Checked: indices in range,
  * every vertex used, no tetrahedron with a repeated vertex, degenerate
  * (|det| <= 1e-10 of its extent cubed) or given twice, no face in more than
- * two tetrahedra; HHG_ERR_ARG with a message naming the first violation
- * otherwise.  Conformity (faces meet whole faces) is the caller's to ensure.
+ * two tetrahedra, the two tetrahedra at a shared face on opposite sides of
+ * it; HHG_ERR_ARG with a message naming the first violation otherwise.
+ * Conformity (faces meet whole faces) and the absence of overlaps between
+ * tetrahedra that share no face are the caller's to ensure.
  *
  * A hierarchy copies what it needs: the mesh may be destroyed after
  * hhg_hier_create.  hhg_mesh_info: vertex and tetrahedron counts and the

@@ -137,7 +137,8 @@ void launch_u_sync(hipStream_t s, const ULev& L, const UList& lst, double* x);
 // Host side (umesh.hip).
 // Checks (xyz, tet) as a tetrahedral mesh: indices in range, every vertex
 // used, no degenerate or repeated tetrahedron, no face in more than two
-// tetrahedra (HHG_ERR_ARG naming the first violation otherwise).
+// tetrahedra, the two at a shared face on opposite sides of it (HHG_ERR_ARG
+// naming the first violation otherwise).
 void validate_tet_mesh(const double* xyz, int nv, const int* tet, int nt);
 
 // Levels lmin..lmax of an unstructured hierarchy (device tables in `mem`).

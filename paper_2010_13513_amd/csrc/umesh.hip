@@ -231,7 +231,7 @@ void validate_tet_mesh(const double* xyz, int nv, const int* tet, int nt) {
   HHG_REQUIRE(nv >= 4 && nt >= 1, HHG_ERR_ARG, "mesh: need at least 4 vertices and one tetrahedron");
   std::vector<int> used(nv, 0);
   std::set<std::array<int, 4>> seen;
-  std::map<std::array<int, 3>, int> faces;
+  std::map<std::array<int, 3>, int> faces;  // face -> opposite vertex, -1 once shared
   double scale = 0.0;
   for (int v = 0; v < 3 * nv; ++v) {
     HHG_REQUIRE(std::isfinite(xyz[v]), HHG_ERR_ARG, "mesh: vertex " + std::to_string(v / 3) + " is not finite");
@@ -268,8 +268,24 @@ void validate_tet_mesh(const double* xyz, int nv, const int* tet, int nt) {
       int w = 0;
       for (int q = 0; q < 4; ++q)
         if (q != drop) f[w++] = s[q];
-      HHG_REQUIRE(++faces[f] <= 2, HHG_ERR_ARG,
+      auto it = faces.find(f);
+      if (it == faces.end()) {
+        faces.emplace(f, s[drop]);  // the vertex opposite the face in its first tetrahedron
+        continue;
+      }
+      HHG_REQUIRE(it->second >= 0, HHG_ERR_ARG,
                   "mesh: a face of tetrahedron " + std::to_string(t) + " belongs to more than two tetrahedra");
+      // the two tetrahedra sharing a face lie on opposite sides of it
+      auto side = [&](int v) {
+        double J[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int d = 0; d < 3; ++d) J[a][d] = xyz[3 * (a < 2 ? f[a + 1] : v) + d] - xyz[3 * f[0] + d];
+        return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      };
+      HHG_REQUIRE(side(it->second) * side(s[drop]) < 0.0, HHG_ERR_ARG,
+                  "mesh: tetrahedron " + std::to_string(t) + " overlaps its neighbour across a shared face");
+      it->second = -1;  // shared by two tetrahedra
     }
   }
   for (int v = 0; v < nv; ++v)

@@ -165,8 +165,9 @@ def _kuhn_mesh(N, rng=None):
 def test_mesh_handle():
     """hhg_mesh_cube and hhg_mesh_create: the Kuhn cube meshes in any vertex
     and tetrahedron order give the hierarchy of hhg_mesh_cube (the same
-    operator on the same lattice); anything else is refused with HHG_ERR_ARG
-    (no hierarchy is built from it)."""
+    operator on the same lattice); other valid tetrahedral meshes become
+    unstructured meshes; invalid ones are refused with HHG_ERR_ARG (no
+    hierarchy is built from them)."""
     torch = torch_cuda()
     ctx = hhg.hhg_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     rng = np.random.default_rng(2024)
@@ -193,15 +194,23 @@ def test_mesh_handle():
             assert torch.equal(outs[0], outs[1])
         E = hhg.HHG_ERR_ARG
         xyz, tet = _kuhn_mesh(2)
+        # meshes that are no Kuhn partition of the unit cube but valid
+        # tetrahedral meshes: the unstructured path (macro_refine -1)
+        general = {
+            "47 tetrahedra": (xyz, tet[:47]),
+            "vertex off the lattice": (xyz + np.array([[0.0, 0.0, 0.1]] * len(xyz)) * (np.arange(len(xyz)) == 13)[:, None], tet),
+            "outside the unit cube": (xyz * 2.0, tet),
+        }
+        for why, (x_, t_) in general.items():
+            m = hhg.hhg_mesh_create(ctx, x_, t_)
+            assert hhg.hhg_mesh_info(m)[2] == -1, why
+            hhg.hhg_mesh_destroy(m)
         bad = {
-            "not 6 or 48 tetrahedra": (xyz, tet[:47]),
-            "vertex off the lattice": (xyz + np.array([[0.0, 0.0, 0.1]] * len(xyz)) * (np.arange(len(xyz)) == 4)[:, None], tet),
-            "duplicate vertex": (np.vstack([xyz[:-1], xyz[:1]]), tet),
-            "non-Kuhn tetrahedron": (xyz, np.vstack([tet[:-1], [[0, 1, 4, 26]]])),
+            "folded: a vertex moved through a face": (np.vstack([xyz[:-1], xyz[:1]]), tet),
+            "degenerate tetrahedron": (xyz, np.vstack([tet[:-1], [[0, 1, 2, 26]]])),
             "tetrahedron twice": (xyz, np.vstack([tet[:-1], tet[:1]])),
             "vertex index out of range": (xyz, np.vstack([tet[:-1], [[0, 1, 4, 27]]])),
             "unused vertex": (np.vstack([xyz, [[0.5, 0.5, 0.5]]]), tet),
-            "outside the unit cube": (xyz * 2.0, tet),
         }
         for why, (x_, t_) in bad.items():
             assert _status(hhg.hhg_mesh_create, ctx, x_, t_) == E, why

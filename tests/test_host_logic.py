@@ -214,3 +214,7 @@ def test_unstructured_query_rejects_bad_meshes():
         hhg.hhg_query_umesh(xyz, np.vstack([tets, tets[:1]]), 1)   # tetrahedron twice
     with pytest.raises(hhg.HHGError):
         hhg.hhg_query_umesh(xyz, tets, 7)                          # query levels 0..6
+    folded = xyz.copy()
+    folded[14] = [0.5, 0.5, 1.2]                  # body centre pushed through the top face
+    with pytest.raises(hhg.HHGError, match="overlaps"):
+        hhg.hhg_query_umesh(folded, tets, 1)
