@@ -19,7 +19,12 @@ roofline at the largest throughput size (P2-P1, 48 tets, level 7); and the
 CPU oracle timed on the same workload on one and on all host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       python bench.py --mode {apply,dc,learned,sweep,c3}
+       python bench.py --mode {apply,dc,learned,sweep,c3,umesh}
+
+--mode umesh: the cube benchmark exactly as the paper configures it (Sec.
+5.1.1): P1-P1 PSPG on the unit cube split into 24 tetrahedra, level 6
+(4.29e6 DoFs), on the library's unstructured (per-cell) path, with the
+paper's three P1-P1 tuples of Tab. fmg-table.
 """
 import argparse
 import json
@@ -75,7 +80,7 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-apply-roofline", action="store_true")
-    ap.add_argument("--mode", choices=["fmg", "apply", "learned", "dc", "sweep", "c3"], default="fmg",
+    ap.add_argument("--mode", choices=["fmg", "apply", "learned", "dc", "sweep", "c3", "umesh"], default="fmg",
                     help="apply: only the operator-apply roofline (for counter runs); learned: the "
                          "learned coarse-solve workload (pairs, GPU training, held-out evaluation)")
     ap.add_argument("--pairs", type=int, default=20000)
@@ -102,6 +107,11 @@ def main():
     prob = W.paper_cube()
 
     ctx = hhg.hhg_ctx_create(0, stream.cuda_stream)
+    if args.mode == "umesh":
+        res = bench_umesh(torch, hhg, dev, stream, ctx, args)
+        print(json.dumps(res), flush=True)
+        hhg.hhg_ctx_destroy(ctx)
+        return
     if args.mode == "dc":
         res = bench_dc(torch, hhg, ctx, level=args.level if args.level != 5 else 7)
         print(json.dumps(res), flush=True)
@@ -684,6 +694,237 @@ def bench_sweep(torch, hhg, ctx, args):
         with open(args.sweep_out, "w") as f:
             json.dump(allrows, f)
     return out
+
+
+# Tab. fmg-table, P1-P1 rows (24-tetrahedron cube, L = 6): tuple, bounds
+# (gamma_u_hat, gamma_p_hat), the paper's work units and gammas
+PAPER_P1_TUPLES = [((2, 3, 2, 1, 1, 1), (1.1, 2.0), 10.77, 1.10, 1.51),
+                   ((3, 1, 3, 1, 1, 1), (1.1, 5.0), 9.55, 1.10, 2.91),
+                   ((1, 0, 2, 1, 1, 1), (2.0, 10.0), 3.97, 1.62, 8.52)]
+UMESH_HEADLINE = PAPER_P1_TUPLES[0][0]
+
+
+def bench_umesh(torch, hhg, dev, stream, ctx, args, L=6):
+    """FMG on the paper's cube benchmark configuration on the unstructured
+    path: the unit cube as 24 tetrahedra (workloads.cube24, 15 vertices),
+    P1-P1 PSPG, levels 0..L (L = 6: 1,073,409 nodes, 4,293,636 DoFs with the
+    Dirichlet ones), the paper's analytic cube solution, omega^{-1} from 100
+    power iterations on level L, Schur diagonal SD.  Step = one FMG solve of
+    the paper's first P1-P1 tuple of Tab. fmg-table (graph-replayed); the
+    other two tuples and their gammas (eq. gamma: errors of eq. error on
+    level L + 1 against a solve converged to 1e-12) next to the paper's."""
+    from paper_2010_13513_amd import workloads as W
+    xyz, tets = W.cube24()
+    prob = W.paper_cube()
+    mesh = hhg.hhg_mesh_create(ctx, xyz, tets)
+    H = hhg.hhg_hier_create(mesh, hhg.HHG_P1P1, 0, L, hhg.HHG_SCHUR_SD)
+    Ev = hhg.hhg_hier_create(mesh, hhg.HHG_P1P1, L, L + 1, hhg.HHG_SCHUR_SD)   # error evaluation only
+    hhg.hhg_mesh_destroy(mesh)
+
+    def upload(hier, level, arr):
+        _, _, vw, _ = hhg.hhg_vec_layout(hier, level)
+        dst = torch.zeros(vw, dtype=torch.float64, device=dev)
+        hhg.hhg_vec_from_lattice(hier, level, torch.from_numpy(np.ascontiguousarray(arr)).to(dev), dst)
+        return dst
+
+    def download(hier, level, vec):
+        _, _, _, lw = hhg.hhg_vec_layout(hier, level)
+        out = torch.empty(lw, dtype=torch.float64, device=dev)
+        hhg.hhg_vec_to_lattice(hier, level, vec, out)
+        return out.cpu().numpy()
+
+    # node positions (canonical order): host tables up to level L, level L+1
+    # by prolongation of the coordinate fields (exact for linear fields)
+    pos = {l: hhg.hhg_query_umesh(xyz, tets, l)["pos"] for l in range(0, L + 1)}
+    nn_f = hhg.hhg_vec_layout(Ev, L + 1)[1]
+    fine = []
+    for d in range(3):
+        e = upload(Ev, L + 1, np.zeros(4 * nn_f))
+        hhg.hhg_prolong_add(Ev, L, upload(Ev, L, np.concatenate([pos[L][:, d]] * 4)), e)
+        fine.append(download(Ev, L + 1, e)[:nn_f])
+    pos[L + 1] = np.stack(fine, axis=1)
+
+    def fields(level, fn_u, fn_p=None):
+        P = pos[level]
+        u = fn_u(P[:, 0], P[:, 1], P[:, 2])
+        p = np.zeros(P.shape[0]) if fn_p is None else fn_p(P[:, 0], P[:, 1], P[:, 2])
+        return np.concatenate([u[0], u[1], u[2], p])
+
+    bs = []
+    for l in range(0, L + 1):
+        f_nod = upload(H, l, fields(l, prob.f))
+        b = torch.zeros_like(f_nod)
+        hhg.hhg_rhs(H, l, f_nod, b)
+        bs.append(b)
+    x0 = upload(H, L, fields(L, prob.u))
+    nn = pos[L].shape[0]
+    dofs = 4 * nn
+    v0 = torch.from_numpy(W.normal_vector(W.SEED_BASE + 8000, nn)).to(dev)
+    omega_inv = hhg.hhg_estimate_omega(H, L, v0, 100)
+    log(f"[umesh] cube24 P1-P1 L={L}: {nn} nodes, {dofs} DoFs, omega_inv {omega_inv:.6f}")
+    xs_fine = upload(Ev, L + 1, fields(L + 1, prob.u, prob.p))
+
+    def errors(xL):
+        e = torch.zeros_like(xs_fine)
+        hhg.hhg_prolong_add(Ev, L, xL, e)
+        e -= xs_fine
+        hhg.hhg_project_mean_zero(Ev, L + 1, e)
+        me = torch.empty_like(e)
+        hhg.hhg_apply(Ev, L + 1, hhg.HHG_OP_MASS, e, me)
+        du, dp = hhg.hhg_dots(Ev, L + 1, e, me)
+        return float(np.sqrt(du)), float(np.sqrt(dp))
+
+    xd = x0.clone()
+    st = hhg.hhg_fmg_solve(H, xd, bs, hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_SYM, 1, omega_inv, rtol=1e-12,
+                                                        max_cycles=200))
+    eud, epd = errors(xd)
+    log(f"[umesh] discrete solution ({st.cycles} cycles, rel res {st.rel_res:.1e}): errors u {eud:.4e} p {epd:.4e}")
+    x = torch.zeros_like(x0)
+
+    def run_tuple(s, steps, warmup):
+        prm = hhg.solver_params(*s, omega_inv)
+
+        def step():
+            x.copy_(x0)
+            hhg.hhg_fmg_solve(H, x, bs, prm, want_stats=False)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        eu, ep = errors(x)
+        wu = hhg.hhg_fmg_solve(H, x0.clone(), bs, prm).work_units
+        return ms, eu / eud, ep / epd, wu, step
+
+    rows = []
+    step = None
+    for s_t, bounds, w_p, gu_p, gp_p in PAPER_P1_TUPLES:
+        steps = args.steps if s_t == UMESH_HEADLINE else max(5, args.steps // 2)
+        ms, gu, gp, wu, st_fn = run_tuple(s_t, steps, args.warmup)
+        if s_t == UMESH_HEADLINE:
+            step, ms_step, g_head, wu_head = st_fn, ms, (gu, gp), wu
+        rows.append({"fmg": _tname(s_t), "bounds": list(bounds), "work_units": round(wu, 3),
+                     "ms_per_solve": round(ms, 4), "dofs_per_s": dofs / (ms * 1e-3),
+                     "gamma_u": round(gu, 4), "gamma_p": round(gp, 4),
+                     "paper": {"work_units": w_p, "gamma_u": gu_p, "gamma_p": gp_p}})
+        log(f"[umesh] FMG{_tname(s_t)}: {ms:.3f} ms, {dofs / (ms * 1e-3):.3e} DoF/s, {wu:.2f} WU, "
+            f"gamma ({gu:.3f}, {gp:.3f}); paper {w_p} WU, ({gu_p}, {gp_p})")
+    value = dofs / (ms_step * 1e-3)
+
+    # kernel families of one headline step
+    fams = {hhg.KF_APPLY: "cell_interior_rows", hhg.KF_IFACE: "interface_nodes",
+            hhg.KF_GS_VERTEX: "gs_interior_colour", hhg.KF_PSTEP: "uzawa_pressure_step",
+            hhg.KF_RESTRICT: "restrict", hhg.KF_PROLONG: "prolong", hhg.KF_COARSE: "coarse_gemv",
+            hhg.KF_REDUCE: "reductions", hhg.KF_OTHER: "other"}
+    rsteps = max(2, min(args.steps, 5))
+    hhg.hhg_timer_start(sum(1 << f for f in fams))
+    for _ in range(rsteps):
+        step()
+    torch.cuda.synchronize()
+    per_fam = {}
+    for f, name in fams.items():
+        ms, n, units = hhg.hhg_timer_read(f)
+        per_fam[name] = (ms / rsteps, n // rsteps, units / rsteps)
+    hhg.hhg_timer_start(0)
+    log("[umesh] kernel families per step: " + ", ".join(
+        f"{k} {v[0]:.3f} ms/{v[1]}" for k, v in sorted(per_fam.items(), key=lambda kv: -kv[1][0])))
+    dom = max(("gs_interior_colour", "cell_interior_rows"), key=lambda k: per_fam[k][0])
+    ms_d, n_d, units_d = per_fam[dom]
+    words = 10.0 if dom == "gs_interior_colour" else 8.0
+    bytes_launch = units_d / max(n_d, 1) * words * 8
+    avg_ms = ms_d / max(n_d, 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": int(bytes_launch),
+                "launches_per_step": n_d, "share_of_step": round(ms_d / ms_step, 3),
+                "timing": "HIP events recorded around each launch",
+                "families_ms_per_step": {k: round(v[0], 4) for k, v in per_fam.items()}}
+
+    # apply roofline at level L + 1 (8.5e6 nodes): interior rows of y = calA x
+    nn7 = hhg.hhg_vec_layout(Ev, L + 1)[1]
+    xa = upload(Ev, L + 1, W.normal_vector(W.SEED_BASE + 8001, 4 * nn7))
+    ya = torch.empty_like(xa)
+    for _ in range(3):
+        hhg.hhg_apply(Ev, L + 1, hhg.HHG_OP_FULL, xa, ya)
+    hhg.hhg_timer_start((1 << hhg.KF_APPLY) | (1 << hhg.KF_IFACE))
+    for _ in range(args.apply_reps):
+        hhg.hhg_apply(Ev, L + 1, hhg.HHG_OP_FULL, xa, ya)
+    torch.cuda.synchronize()
+    ms_a, n_a, units_a = hhg.hhg_timer_read(hhg.KF_APPLY)
+    ms_i, n_i, units_i = hhg.hhg_timer_read(hhg.KF_IFACE)
+    hhg.hhg_timer_start(0)
+    b_a = units_a / n_a * 64.0
+    gbs = b_a / (ms_a / n_a * 1e-3) / 1e9
+    apply_roofline = {"bound": "hbm", "kernel": "cell_interior_rows", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms_a / n_a, 4),
+                      "bytes_per_launch": int(b_a), "interface_ms": round(ms_i / max(n_i, 1), 4),
+                      "interface_nodes": int(units_i / max(n_i, 1)),
+                      "workload": f"y = calA x, 24-tetrahedron cube, level {L + 1} ({nn7} nodes), float64"}
+    log(f"[umesh] apply roofline: {apply_roofline}")
+    out = {
+        "metric": "FMG Stokes DoF/s at discretization accuracy; operator-apply HBM GB/s vs peak",
+        "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"P1-P1 PSPG Stokes, unit cube split into 24 tetrahedra (the cube benchmark's "
+                               f"partition, unstructured path), level {L} ({dofs} DoFs), paper cube solution, "
+                               f"FMG{_tname(UMESH_HEADLINE)} from level 0 (the paper's tuple for bounds (1.1, 2))",
+                   "dofs": dofs, "level": L, "omega_inv": omega_inv, "schur": "SD",
+                   "work_units": round(wu_head, 3), "gamma_u": round(g_head[0], 4), "gamma_p": round(g_head[1], 4),
+                   "disc_err_u": eud, "disc_err_p": epd},
+        "paper_tuples": rows,
+        "roofline": roofline,
+        "apply_roofline": apply_roofline,
+    }
+    hhg.hhg_hier_destroy(Ev)
+    hhg.hhg_hier_destroy(H)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_umesh(omega_inv)
+    return out
+
+
+def _oracle_umesh_worker(args):
+    """Oracle FMG solves of the 24-tetrahedron cube workload at a small level
+    for about budget_s seconds (setup not timed).  Returns (solves, s, dofs)."""
+    Ls, omega_inv, budget_s = args
+    from oracle import multigrid as mg, umesh
+    from paper_2010_13513_amd import workloads as W
+    prob = W.paper_cube()
+    H = umesh.hierarchy(*W.cube24(), 0, Ls, schur="sd")
+    bs = {l: H.rhs(l, prob) for l in range(0, Ls + 1)}
+    s = UMESH_HEADLINE
+    prm = mg.Params(s[0], s[1], s[2], s[3], "f" if s[4] == 0 else "s", s[5], omega_inv)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        H.fmg(prob, prm, b=bs)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 200:
+            break
+    return n, el, H.S[Ls].n
+
+
+def cpu_baseline_umesh(omega_inv, Ls=4, budget_s=12.0):
+    """The oracle (as it stands) on the same FMG tuple and mesh at level Ls
+    (the whole oracle hierarchy of level 6 does not fit a bounded sample),
+    one single-threaded process; DoF/s of level Ls."""
+    import multiprocessing as mp
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(1) as pool:
+        n, el, dofs = pool.map(_oracle_umesh_worker, [(Ls, omega_inv, budget_s)])[0]
+    v = dofs * n / el
+    log(f"[umesh] cpu oracle: {n} FMG solves of level {Ls} ({dofs} DoFs) in {el:.1f} s -> {v:.3e} DoF/s")
+    return {"value": v, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} complete FMG{_tname(UMESH_HEADLINE)} solves of the same mesh at level {Ls} "
+                      f"({dofs} DoFs; setup excluded) in one single-threaded numpy/scipy float64 process"}
 
 
 def W_normal(P, level):

@@ -107,77 +107,91 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, con
   if (wp) y[3 * vs + t] = HB ? b[3 * vs + t] - yp : yp;
 }
 
+// Interface nodes: 16 lanes per node, lane e < 15 takes stencil point e of
+// every occurrence (cell) of the node; the lane sums are combined by shuffles
+// within the 16-lane group.  Points outside an occurrence's closed cell add
+// nothing.  (Face nodes follow each other in node order, so neighbouring
+// groups read neighbouring rows; one lane per node would leave most compute
+// units idle on the few thousand nodes of one colour.)
+constexpr int kIfGroup = 16;
+constexpr int kIfNodes = kUBlock / kIfGroup;
+
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = kIfGroup / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kIfGroup);
+  return v;
+}
+__device__ __forceinline__ size_t occ_centre(const ULev& L, int2 oc) {
+  int i, j, k;
+  unpack(oc.y, i, j, k);
+  return (size_t)oc.x * L.P + uslot(i, j, k, L.n);
+}
+// Slot of stencil point e of occurrence oc, or -1 outside the closed cell;
+// cs / m: the occurrence's cell rows and class.
+__device__ __forceinline__ long occ_point(const ULev& L, int2 oc, int e, const UCell*& cs, int& m) {
+  int i, j, k;
+  unpack(oc.y, i, j, k);
+  m = uclass(i, j, k, L.n);
+  cs = L.cs + oc.x;
+  if (e >= kUPoints || !((cs->inside[m] >> e) & 1)) return -1;
+  return (long)oc.x * L.P + uslot(i + udir(e, 0), j + udir(e, 1), k + udir(e, 2), L.n);
+}
+
 template <bool HB, bool MASS>
 __global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, const double* __restrict__ x,
                                                            const double* __restrict__ b, double* __restrict__ y,
                                                            int opmask, int wv, int wp) {
-  const int q = blockIdx.x * kUBlock + threadIdx.x;
+  const int q = blockIdx.x * kIfNodes + (threadIdx.x / kIfGroup), e = threadIdx.x % kIfGroup;
   if (q >= lst.n) return;
-  const int n = L.n;
   const size_t vs = L.vs;
   const int o0 = lst.off[q], o1 = lst.off[q + 1];
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, bp[3] = {0.0, 0.0, 0.0}, cp = 0.0;
   const bool dA = opmask & 1, dBT = opmask & 2, dB = opmask & 4, dC = opmask & 24;
   for (int o = o0; o < o1; ++o) {
-    const int2 oc = lst.occ[o];
-    int i, j, k;
-    unpack(oc.y, i, j, k);
-    const int m = uclass(i, j, k, n);
-    const UCell* cs = L.cs + oc.x;
-    const unsigned ins = cs->inside[m];
-    const size_t base = (size_t)oc.x * L.P;
-    const double cf = cs->cfac;
-    for (int e = 0; e < kUPoints; ++e) {
-      if (!((ins >> e) & 1)) continue;
-      const size_t sl = base + uslot(i + udir(e, 0), j + udir(e, 1), k + udir(e, 2), n);
-      if (MASS) {
-        const double mw = cs->M[m][e];
-        for (int f = 0; f < 4; ++f) acc[f] += mw * x[f * vs + sl];
-        continue;
+    const UCell* cs;
+    int m;
+    const long sl = occ_point(L, lst.occ[o], e, cs, m);
+    if (sl < 0) continue;
+    if (MASS) {
+      const double mw = cs->M[m][e];
+      for (int f = 0; f < 4; ++f) acc[f] += mw * x[f * vs + sl];
+      continue;
+    }
+    if (dA || dB) {
+      const double v0 = x[sl], v1 = x[vs + sl], v2 = x[2 * vs + sl];
+      if (dA) {
+        const double a = cs->A[m][e];
+        acc[0] += a * v0;
+        acc[1] += a * v1;
+        acc[2] += a * v2;
       }
-      if (dA || dB) {
-        const double v0 = x[sl], v1 = x[vs + sl], v2 = x[2 * vs + sl];
-        if (dA) {
-          const double a = cs->A[m][e];
-          acc[0] += a * v0;
-          acc[1] += a * v1;
-          acc[2] += a * v2;
-        }
-        if (dB) acc[3] += cs->B[m][e][0] * v0 + cs->B[m][e][1] * v1 + cs->B[m][e][2] * v2;
+      if (dB) acc[3] += cs->B[m][e][0] * v0 + cs->B[m][e][1] * v1 + cs->B[m][e][2] * v2;
+    }
+    if (dBT || dC) {
+      const double pe = x[3 * vs + sl];
+      if (dBT) {
+        bp[0] += cs->BT[m][e][0] * pe;
+        bp[1] += cs->BT[m][e][1] * pe;
+        bp[2] += cs->BT[m][e][2] * pe;
       }
-      if (dBT || dC) {
-        const double pe = x[3 * vs + sl];
-        if (dBT) {
-          bp[0] += cs->BT[m][e][0] * pe;
-          bp[1] += cs->BT[m][e][1] * pe;
-          bp[2] += cs->BT[m][e][2] * pe;
-        }
-        if (dC) cp += cf * cs->A[m][e] * pe;
-      }
+      if (dC) cp += cs->cfac * cs->A[m][e] * pe;
     }
   }
   double out[4];
-  {
-    int i, j, k;
-    unpack(lst.occ[o0].y, i, j, k);
-    const size_t own = (size_t)lst.occ[o0].x * L.P + uslot(i, j, k, n);
+  const size_t own = occ_centre(L, lst.occ[o0]);
+  if (MASS) {
+    for (int f = 0; f < 4; ++f) out[f] = group_sum(acc[f]);
+  } else {
     const bool dir = q >= lst.nfree;
-    if (MASS) {
-      for (int f = 0; f < 4; ++f) out[f] = acc[f];
-    } else {
-      for (int d = 0; d < 3; ++d) {
-        const double v = acc[d] + bp[d];
-        out[d] = dir ? 0.0 : (HB ? b[d * vs + own] - v : v);
-      }
-      const double yp = acc[3] + ((opmask & 16) ? cp : -cp);
-      out[3] = HB ? b[3 * vs + own] - yp : yp;
+    for (int d = 0; d < 3; ++d) {
+      const double v = group_sum(acc[d] + bp[d]);
+      out[d] = dir ? 0.0 : (HB ? b[d * vs + own] - v : v);
     }
+    const double yp = group_sum(acc[3] + ((opmask & 16) ? cp : -cp));
+    out[3] = HB ? b[3 * vs + own] - yp : yp;
   }
-  for (int o = o0; o < o1; ++o) {
-    const int2 oc = lst.occ[o];
-    int i, j, k;
-    unpack(oc.y, i, j, k);
-    const size_t sl = (size_t)oc.x * L.P + uslot(i, j, k, n);
+  for (int o = o0 + e; o < o1; o += kIfGroup) {
+    const size_t sl = occ_centre(L, lst.occ[o]);
     if (MASS || wv)
       for (int d = 0; d < 3; ++d) y[d * vs + sl] = out[d];
     if (MASS || wp) y[3 * vs + sl] = out[3];
@@ -216,44 +230,34 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double
   for (int d = 0; d < 3; ++d) x[d * vs + t] += r[d] * ai;
 }
 
-// Free interface nodes [first, first + count) of one colour.
+// Free interface nodes [first, first + count) of one colour, 16 lanes per
+// node as in k_u_apply_iface.  Every lane of a group reads the node's old
+// value before any lane writes a copy (one wavefront, program order).
 __global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int first, int count,
                                                         double* __restrict__ x, const double* __restrict__ b) {
-  const int t = blockIdx.x * kUBlock + threadIdx.x;
+  const int t = blockIdx.x * kIfNodes + (threadIdx.x / kIfGroup), e = threadIdx.x % kIfGroup;
   if (t >= count) return;
   const int q = first + t;
-  const int n = L.n;
   const size_t vs = L.vs;
   const int o0 = lst.off[q], o1 = lst.off[q + 1];
   double r[3] = {0.0, 0.0, 0.0};
   for (int o = o0; o < o1; ++o) {
-    const int2 oc = lst.occ[o];
-    int i, j, k;
-    unpack(oc.y, i, j, k);
-    const int m = uclass(i, j, k, n);
-    const UCell* cs = L.cs + oc.x;
-    const unsigned ins = cs->inside[m];
-    const size_t base = (size_t)oc.x * L.P;
-    for (int e = 0; e < kUPoints; ++e) {
-      if (!((ins >> e) & 1)) continue;
-      const size_t sl = base + uslot(i + udir(e, 0), j + udir(e, 1), k + udir(e, 2), n);
-      const double a = cs->A[m][e], pe = x[3 * vs + sl];
-      r[0] += a * x[sl] + cs->BT[m][e][0] * pe;
-      r[1] += a * x[vs + sl] + cs->BT[m][e][1] * pe;
-      r[2] += a * x[2 * vs + sl] + cs->BT[m][e][2] * pe;
-    }
+    const UCell* cs;
+    int m;
+    const long sl = occ_point(L, lst.occ[o], e, cs, m);
+    if (sl < 0) continue;
+    const double a = cs->A[m][e], pe = x[3 * vs + sl];
+    r[0] += a * x[sl] + cs->BT[m][e][0] * pe;
+    r[1] += a * x[vs + sl] + cs->BT[m][e][1] * pe;
+    r[2] += a * x[2 * vs + sl] + cs->BT[m][e][2] * pe;
   }
-  int i, j, k;
-  unpack(lst.occ[o0].y, i, j, k);
-  const size_t own = (size_t)lst.occ[o0].x * L.P + uslot(i, j, k, n);
+  const size_t own = occ_centre(L, lst.occ[o0]);
   const double ai = lst.ainv[q];
-  double u[3];
-  for (int d = 0; d < 3; ++d) u[d] = x[d * vs + own] + (b[d * vs + own] - r[d]) * ai;
-  for (int o = o0; o < o1; ++o) {
-    const int2 oc = lst.occ[o];
-    unpack(oc.y, i, j, k);
-    const size_t sl = (size_t)oc.x * L.P + uslot(i, j, k, n);
-    for (int d = 0; d < 3; ++d) x[d * vs + sl] = u[d];
+  double v[3];
+  for (int d = 0; d < 3; ++d) v[d] = x[d * vs + own] + (b[d * vs + own] - group_sum(r[d])) * ai;
+  for (int o = o0 + e; o < o1; o += kIfGroup) {
+    const size_t sl = occ_centre(L, lst.occ[o]);
+    for (int d = 0; d < 3; ++d) x[d * vs + sl] = v[d];
   }
 }
 
@@ -312,14 +316,19 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, 
     const UCell* cs = Lf.cs + oc.x;
     const unsigned ins = cs->inside[m];
     const size_t base = (size_t)oc.x * Lf.P;
+    const int c0 = uslot(2 * i, 2 * j, 2 * k, nf);
+#pragma unroll
     for (int e = 1; e < kUPoints; ++e) {
-      if (!((ins >> e) & 1)) continue;
       const int I = 2 * i + udir(e, 0), J = 2 * j + udir(e, 1), K = 2 * k + udir(e, 2);
       const int mf = uclass(I, J, K, nf);
-      if (!((cs->owned >> mf) & 1)) continue;
-      const size_t sl = base + uslot(I, J, K, nf);
+      const bool take = ((ins >> e) & 1) && ((cs->owned >> mf) & 1);
+      const size_t sl = base + (take ? uslot(I, J, K, nf) : c0);
       const bool fd = (cs->bnd >> mf) & 1;
-      for (int f = 0; f < 4; ++f) acc[f] += (f < 3 && fd) ? 0.0 : 0.5 * rf[f * Lf.vs + sl];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const double v = rf[f * Lf.vs + sl];
+        acc[f] += (take && !(f < 3 && fd)) ? 0.5 * v : 0.0;
+      }
     }
   }
   int i, j, k;
@@ -497,7 +506,7 @@ constexpr int kUPartials = 512;
 void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList& lst, const double* x,
                          const double* b, double* y, int opmask, bool has_b, bool mass, bool wv, bool wp) {
   if (inner.n > 0) {
-    KScope ks(s, KF_APPLY, (double)inner.n * 64);
+    KScope ks(s, KF_APPLY, (double)inner.pts * L.ncell);
     const dim3 g = seg_grid(inner, L.ncell);
     if (mass)
       hipLaunchKernelGGL((k_u_apply_inner<false, true>), g, dim3(kUBlock), 0, s, L, inner, x, b, y, opmask, 1, 1);
@@ -510,7 +519,7 @@ void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList&
   }
   if (lst.n > 0) {
     KScope ks(s, KF_IFACE, (double)lst.n);
-    const dim3 g(ublocks(lst.n));
+    const dim3 g((unsigned)((lst.n + kIfNodes - 1) / kIfNodes));
     if (mass)
       hipLaunchKernelGGL((k_u_apply_iface<false, true>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, 1, 1);
     else if (has_b)
@@ -524,7 +533,7 @@ void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList&
 
 void launch_u_gs_inner(hipStream_t s, const ULev& L, USegs seg, double* x, const double* b) {
   if (seg.n == 0) return;
-  KScope ks(s, KF_GS_VERTEX, (double)seg.n * 64);
+  KScope ks(s, KF_GS_VERTEX, (double)seg.pts * L.ncell);
   hipLaunchKernelGGL(k_u_gs_inner, seg_grid(seg, L.ncell), dim3(kUBlock), 0, s, L, seg, x, b);
 }
 
@@ -532,7 +541,8 @@ void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first
                        const double* b) {
   if (count <= 0) return;
   KScope ks(s, KF_IFACE, (double)count);
-  hipLaunchKernelGGL(k_u_gs_iface, dim3(ublocks(count)), dim3(kUBlock), 0, s, L, lst, first, count, x, b);
+  hipLaunchKernelGGL(k_u_gs_iface, dim3((unsigned)((count + kIfNodes - 1) / kIfNodes)), dim3(kUBlock), 0, s, L, lst,
+                     first, count, x, b);
 }
 
 void launch_u_pstep(hipStream_t s, const ULev& L, const double* dinv, double* x, const double* r, double omega) {

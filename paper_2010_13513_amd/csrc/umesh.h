@@ -79,6 +79,7 @@ struct UList {
 struct USegs {
   const int4* s;
   int n;
+  long pts;  // points in all segments (timer work units)
 };
 
 // Host-side state of one level of an unstructured hierarchy.

@@ -219,7 +219,11 @@ T* upload(UHier& u, const std::vector<T>& v) {
   return (T*)p;
 }
 
-USegs upload_segs(UHier& u, const std::vector<int4>& v) { return USegs{upload(u, v), (int)v.size()}; }
+USegs upload_segs(UHier& u, const std::vector<int4>& v) {
+  long pts = 0;
+  for (const int4& q : v) pts += q.w;
+  return USegs{upload(u, v), (int)v.size(), pts};
+}
 
 }  // namespace
 
