@@ -122,7 +122,8 @@ typedef struct {
   double work_units;      /* Sec. 4 model, in W(calA_L)                      */
   double seconds;         /* device time of the call on the context stream
                              (HIP events around its work)                   */
-  int fallbacks;          /* learned coarse solve switched off (hhg_hier_set_mlp) */
+  int fallbacks;          /* learned coarse solve switched off (hhg_hier_set_mlp),
+                             or float32 corrections given up (hhg_dc_solve) */
 } hhg_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -340,9 +341,12 @@ hhg_status hhg_fmg_solve(hhg_hier h, void* x, const void* const* b_levels, const
  * (prm's smoothing parameters, arithmetic and storage in inner_prec, the
  * coarsest-level pseudo-inverse applied in float64) on calA e = r from e = 0,
  * x += e in float64 and project the pressure to zero mean in float64.  x holds
- * the boundary data and the start vector.  Stats: cycles = inner V-cycles in
- * total, residual norms of the final x.  HHG_ERR_NOT_CONVERGED if rtol is not
- * reached. */
+ * the boundary data and the start vector.  Fallback: when a float32
+ * correction does not reduce the float64 residual norm (or makes it not
+ * finite), it is undone and the remaining corrections use float64 inner
+ * cycles (stats->fallbacks = 1).  Stats: cycles = inner V-cycles in total
+ * (an undone correction's included), residual norms of the final x.
+ * HHG_ERR_NOT_CONVERGED if rtol is not reached. */
 hhg_status hhg_dc_solve(hhg_hier h, void* x, const void* b, const hhg_solver_params* prm, hhg_prec inner_prec,
                         int inner_cycles, double rtol, int max_outer, hhg_stats* stats);
 

@@ -95,8 +95,9 @@ struct Level {
   float* r32 = nullptr;
   // float32 V-cycle vectors (allocated on first mixed-precision use)
   float *cx32 = nullptr, *cb32 = nullptr;
-  // finest-level correction and right-hand side of a float64 inner solve
-  double *dc_e = nullptr, *dc_r = nullptr;
+  // finest-level correction and right-hand side of a float64 inner solve;
+  // the iterate before a float32 correction (undone if it does not help)
+  double *dc_e = nullptr, *dc_r = nullptr, *dc_bk = nullptr;
   // host copies of the double tables (coarse assembly)
   std::vector<HostStencil> hA, hBT, hB, hC;
   double adiag[8] = {0};
@@ -1988,16 +1989,34 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
     double bu, bp, ru = 0, rp = 0;
     norms<double>(h, L, b, &bu, &bp);
     const double bn = std::sqrt(bu * bu + bp * bp);
-    int outer = 0, cycles = 0;
-    if (inner_prec == HHG_F64 && !top.dc_e) {
-      top.dc_e = h->arena.alloc<double>(top.vec_words);
-      top.dc_r = h->arena.alloc<double>(top.vec_words);
-    }
+    int outer = 0, cycles = 0, fallbacks = 0;
+    bool f32 = inner_prec == HHG_F32;
+    auto ensure_f64_work = [&]() {
+      if (!top.dc_e) {
+        top.dc_e = h->arena.alloc<double>(top.vec_words);
+        top.dc_r = h->arena.alloc<double>(top.vec_words);
+      }
+    };
+    if (!f32) ensure_f64_work();
+    if (f32 && !top.dc_bk) top.dc_bk = h->arena.alloc<double>(top.vec_words);
+    double prev = -1.0;
     for (;;) {
       op_apply<double>(h, L, full_mask(h), x, b, top.r, true, true, true);   // r = b - A x (float64)
       norms<double>(h, L, top.r, &ru, &rp);
-      if (std::sqrt(ru * ru + rp * rp) <= rtol * bn || outer >= max_outer) break;
-      if (inner_prec == HHG_F32) {
+      const double rn = std::sqrt(ru * ru + rp * rp);
+      if (f32 && prev >= 0.0 && !(rn < prev)) {
+        // the last float32 correction did not reduce the float64 residual (or
+        // made it non-finite): undo it, finish with float64 inner cycles
+        HHG_CHECK_HIP(hipMemcpyAsync(x, top.dc_bk, top.vec_words * sizeof(double), hipMemcpyDeviceToDevice, s));
+        f32 = false;
+        ++fallbacks;
+        ensure_f64_work();
+        continue;
+      }
+      if (rn <= rtol * bn || outer >= max_outer) break;
+      prev = rn;
+      if (f32) {
+        HHG_CHECK_HIP(hipMemcpyAsync(top.dc_bk, x, top.vec_words * sizeof(double), hipMemcpyDeviceToDevice, s));
         launch_to_f32(s, top.r, top.cb32, top.vec_words);                     // RNE
         round_out<float>(h, L, top.cb32, 0, 0, top.vec_words, 1);
         launch_fill<float>(s, top.cx32, top.vec_words, 0.0f);
@@ -2021,7 +2040,7 @@ hhg_status hhg_dc_solve(hhg_hier h, void* xv, const void* bv, const hhg_solver_p
       stats->rel_res = bn > 0 ? std::sqrt(ru * ru + rp * rp) / bn : 0.0;
       stats->work_units = cycles * vcycle_work_units(h, *prm);
       stats->seconds = clock.seconds();
-      stats->fallbacks = 0;
+      stats->fallbacks = fallbacks;
     }
     if (std::sqrt(ru * ru + rp * rp) > rtol * bn)
       throw Error{HHG_ERR_NOT_CONVERGED, "relative residual above rtol after max_outer corrections"};

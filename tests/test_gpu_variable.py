@@ -118,3 +118,28 @@ def test_defect_correction_float32(libs, disc, lmin, L, varnu):
     for k in (0, 1):
         assert err[hhg.HHG_F64][k] < 1e-8
         assert err[hhg.HHG_F32][k] < 10 * err[hhg.HHG_F64][k] + 1e-10
+
+
+def test_defect_correction_fallback(libs):
+    """A float32 correction that does not reduce the float64 residual is
+    undone and the solve continues with float64 inner cycles.  Forced from
+    the host: omega_inv = 0.05 (omega 40 times the power-iteration value's
+    inverse) makes the Uzawa pressure update overshoot, so the first float32
+    correction raises the residual, is given up (stats.fallbacks = 1) and the
+    returned x stays finite.  With omega_inv = 2.3 no correction is undone."""
+    lib = libs(P2, 1, 3, False)
+    H = mg.Hierarchy(2, 1, 3, schur="sd")
+    prob = W.fourier_forcing(W.SEED_BASE + 2000)
+    db = lib.from_lattice(3, H.rhs(3, prob))
+    x0 = H.initial(3, prob)
+    dx = lib.from_lattice(3, x0)
+    st = hhg.hhg_dc_solve(lib.h, dx, db, hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 3, 0.05), hhg.HHG_F32, 1,
+                          1e-12, 3, check=False)
+    print(f"[dc fallback] omega_inv 0.05: fallbacks {st.fallbacks}, cycles {st.cycles}, rel res {st.rel_res:.2e}",
+          flush=True)
+    assert st.fallbacks == 1
+    assert np.isfinite(lib.to_lattice(3, dx)).all() and np.isfinite(st.rel_res)
+    dx = lib.from_lattice(3, x0)
+    st = hhg.hhg_dc_solve(lib.h, dx, db, hhg.solver_params(3, 3, 0, 1, hhg.HHG_GS_FWD, 3, 2.3), hhg.HHG_F32, 1,
+                          1e-12, 200)
+    assert st.fallbacks == 0 and st.rel_res <= 1e-12
