@@ -2139,9 +2139,7 @@ void train_steps(hhg_mlp m, const float* x, const float* y, int n_samples, int b
   for (int e = 0; e < epochs; ++e)
     for (int q = 0; q < nb; ++q) {
       const int* idx = dord + (size_t)e * n_samples + (size_t)q * batch;
-      launch_gather_rows(s, x, idx, batch, m->net.n_in, m->bx);
-      launch_gather_rows(s, y, idx, batch, m->net.n_out, m->by);
-      m->net.train_step_dev(s, m->bx, m->by, batch, lr, dloss + e);
+      m->net.train_step_dev(s, x, y, idx, batch, lr, dloss + e);
     }
 }
 }  // namespace
