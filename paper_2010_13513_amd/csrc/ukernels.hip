@@ -1,7 +1,7 @@
 // Kernels of the unstructured-mesh path (Sec. 2, 2.1, 3.2, 3.3), float64.
 //
 // Cell interiors run as lattice kernels: a workgroup of four wavefronts
-// takes four row segments of one cell (grid.y = cell), one lane per point,
+// takes 256 / lps row segments of one cell (grid.y = cell), one lane per point,
 // with the cell's interior rows staged in LDS; neighbours are the 14
 // Freudenthal neighbours in the cell's packed slot order.  Interface nodes
 // (on vertices, edges and faces of T_0) run one thread per node: the row is
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, con
   const int c = blockIdx.y;
   const UCell* cs = L.cs + c;
   stage_inner(cs, w);
-  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
   if (sid >= sg.n) return;
   const int4 s = sg.s[sid];
   if (lane >= s.w) return;
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double
   const int c = blockIdx.y;
   const UCell* cs = L.cs + c;
   stage_inner(cs, w);
-  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
   if (sid >= sg.n) return;
   const int4 s = sg.s[sid];
   if (lane >= s.w) return;
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_inner(ULev Lf, ULev Lc, 
                                                               const double* __restrict__ rf,
                                                               double* __restrict__ rc) {
   const int c = blockIdx.y;
-  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
   if (sid >= sg.n) return;
   const int4 s = sg.s[sid];
   if (lane >= s.w) return;
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, 
 __global__ void __launch_bounds__(kUBlock) k_u_prolong(ULev Lc, ULev Lf, USegs sg, const double* __restrict__ xc,
                                                        double* __restrict__ xf, int add, int skip_bnd) {
   const int c = blockIdx.y;
-  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
   if (sid >= sg.n) return;
   const int4 s = sg.s[sid];
   if (lane >= s.w) return;
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(kUBlock) k_u_prolong(ULev Lc, ULev Lf, USegs s
 __global__ void __launch_bounds__(kUBlock) k_u_inject(ULev Lf, ULev Lc, USegs sg, const double* __restrict__ xf,
                                                       double* __restrict__ xc) {
   const int c = blockIdx.y;
-  const int sid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
   if (sid >= sg.n) return;
   const int4 s = sg.s[sid];
   if (lane >= s.w) return;
@@ -497,7 +497,10 @@ __global__ void __launch_bounds__(kUBlock) k_u_sync(ULev L, UList lst, double* _
 }
 
 unsigned ublocks(long n) { return (unsigned)((n + kUBlock - 1) / kUBlock); }
-dim3 seg_grid(const USegs& s, int ncell) { return dim3((unsigned)((s.n + 3) / 4), (unsigned)ncell); }
+dim3 seg_grid(const USegs& s, int ncell) {
+  const int per = kUBlock / s.lps;
+  return dim3((unsigned)((s.n + per - 1) / per), (unsigned)ncell);
+}
 long real_slots(const ULev& L) { return (long)L.ncell * L.P; }
 constexpr int kUPartials = 512;
 

@@ -74,12 +74,14 @@ struct UList {
   int nfree, n;
 };
 
-// Row segments of up to 64 points (i0, j, k, count): stride 1 for the apply
-// and transfer lists, stride 4 for one interior colour.
+// Row segments (i0, j, k, count) of up to lps points, one lane per point
+// (lps a power of two <= 64: several short rows share a wavefront): stride 1
+// for the apply and transfer lists, stride 4 for one interior colour.
 struct USegs {
   const int4* s;
   int n;
   long pts;  // points in all segments (timer work units)
+  int lps;
 };
 
 // Host-side state of one level of an unstructured hierarchy.

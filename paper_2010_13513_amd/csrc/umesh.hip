@@ -204,8 +204,15 @@ Prims primitives(const std::vector<std::array<int, 4>>& cells) {
   return P;
 }
 
-void push_segments(std::vector<int4>& out, int i0, int count, int j, int k, int stride) {
-  for (int a = 0; a < count; a += 64) out.push_back(int4{i0 + a * stride, j, k, std::min(64, count - a)});
+// Lanes per segment: the smallest power of two >= the longest row (at most
+// 64), so that short rows on the small levels share a wavefront.
+int lanes_for(int longest) {
+  int l = 1;
+  while (l < longest && l < 64) l <<= 1;
+  return l;
+}
+void push_segments(std::vector<int4>& out, int i0, int count, int j, int k, int stride, int lps) {
+  for (int a = 0; a < count; a += lps) out.push_back(int4{i0 + a * stride, j, k, std::min(lps, count - a)});
 }
 
 template <typename T>
@@ -219,10 +226,10 @@ T* upload(UHier& u, const std::vector<T>& v) {
   return (T*)p;
 }
 
-USegs upload_segs(UHier& u, const std::vector<int4>& v) {
+USegs upload_segs(UHier& u, const std::vector<int4>& v, int lps) {
   long pts = 0;
   for (const int4& q : v) pts += q.w;
-  return USegs{upload(u, v), (int)v.size(), pts};
+  return USegs{upload(u, v), (int)v.size(), pts, lps};
 }
 
 }  // namespace
@@ -304,6 +311,7 @@ struct UHostLevel {
   std::vector<unsigned char> flags;
   std::vector<double> ainv, dinv, mlown;
   std::vector<int4> all, inner, cseg[4];
+  int lps_all = 64, lps_inner = 64, lps_col = 64;  // lanes per segment of each list
   int nfree = 0, nlist = 0;
 };
 
@@ -417,17 +425,34 @@ void u_level_host(const UMeshPrims& M, const double* xyz, int l, int schur, ULev
     K = std::max(K, cq + 1);
   }
   lv.ncol_if = K;
-  // interface list: free nodes by (colour, canonical), then Dirichlet ones
+  // interface list: free nodes by colour, then the Dirichlet ones; inside a
+  // group by the owner copy's slot (cell, then i fastest), so that the
+  // threads of a launch read neighbouring memory (the order inside a colour
+  // does not change the result: its nodes are not coupled)
+  auto owner_slot = [&](long q) {
+    const int2 o = occ[q][0];
+    return (long)o.x * P + uslot(o.y & 1023, (o.y >> 10) & 1023, o.y >> 20, n);
+  };
   std::vector<long> order;
-  for (int cc = 0; cc < K; ++cc)
-    for (long q = 0; q < nif; ++q)
-      if (!ifd[q] && col[q] == cc) order.push_back(q);
+  auto append_sorted = [&](std::vector<long>& grp) {
+    std::sort(grp.begin(), grp.end(), [&](long a, long b) { return owner_slot(a) < owner_slot(b); });
+    order.insert(order.end(), grp.begin(), grp.end());
+  };
+  std::vector<std::vector<long>> by_col(K);
+  std::vector<long> dir_nodes;
+  for (long q = 0; q < nif; ++q) {
+    if (ifd[q])
+      dir_nodes.push_back(q);
+    else
+      by_col[col[q]].push_back(q);
+  }
   lv.col_off.assign(K + 1, 0);
-  for (long t = 0; t < (long)order.size(); ++t) ++lv.col_off[col[order[t]] + 1];
-  for (int cc = 0; cc < K; ++cc) lv.col_off[cc + 1] += lv.col_off[cc];
+  for (int cc = 0; cc < K; ++cc) {
+    append_sorted(by_col[cc]);
+    lv.col_off[cc + 1] = (int)order.size();
+  }
   const int nfree = (int)order.size();
-  for (long q = 0; q < nif; ++q)
-    if (ifd[q]) order.push_back(q);
+  append_sorted(dir_nodes);
   lv.h_off.assign(1, 0);
   lv.h_occ.clear();
   H.ainv.assign(order.size(), 0.0);
@@ -499,16 +524,19 @@ void u_level_host(const UMeshPrims& M, const double* xyz, int l, int schur, ULev
   lv.ml_total = mltot;
   // segments
   std::vector<int4>&all = H.all, &inner = H.inner, *cseg = H.cseg;
+  H.lps_all = lanes_for(n + 1);
+  H.lps_inner = lanes_for(n - 2);
+  H.lps_col = lanes_for((n - 2 + 3) / 4);
   for (int k = 0; k <= n; ++k)
-    for (int j = k; j <= n; ++j) push_segments(all, j, n - j + 1, j, k, 1);
+    for (int j = k; j <= n; ++j) push_segments(all, j, n - j + 1, j, k, 1, H.lps_all);
   for (int k = 1; k <= n; ++k)
     for (int j = k + 1; j <= n; ++j) {
       const int i0 = j + 1, i1 = n - 1;
       if (i0 > i1) continue;
-      push_segments(inner, i0, i1 - i0 + 1, j, k, 1);
+      push_segments(inner, i0, i1 - i0 + 1, j, k, 1, H.lps_inner);
       for (int r = 0; r < 4; ++r) {
         const int f = i0 + ((((r - i0 - j - k) % 4) + 4) % 4);
-        if (f <= i1) push_segments(cseg[r], f, (i1 - f) / 4 + 1, j, k, 4);
+        if (f <= i1) push_segments(cseg[r], f, (i1 - f) / 4 + 1, j, k, 4, H.lps_col);
       }
     }
   H.nfree = nfree;
@@ -534,9 +562,9 @@ UHier* u_build(const double* xyz, int nv, const int* tet, int nt, int lmin, int 
     UHostLevel H;
     u_level_host(M, xyz, l, schur, lv, H);
     lv.L.cs = upload(*u, lv.hcs);
-    lv.all = upload_segs(*u, H.all);
-    lv.inner = upload_segs(*u, H.inner);
-    for (int r = 0; r < 4; ++r) lv.colour[r] = upload_segs(*u, H.cseg[r]);
+    lv.all = upload_segs(*u, H.all, H.lps_all);
+    lv.inner = upload_segs(*u, H.inner, H.lps_inner);
+    for (int r = 0; r < 4; ++r) lv.colour[r] = upload_segs(*u, H.cseg[r], H.lps_col);
     lv.lst.off = upload(*u, lv.h_off);
     lv.lst.occ = upload(*u, lv.h_occ);
     lv.lst.ainv = upload(*u, H.ainv);
