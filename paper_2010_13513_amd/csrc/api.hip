@@ -853,11 +853,10 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
         for (int c = ncol - 1; c >= 0; --c) colour(c);
     }
     // r_p = g - B u + C p, then p -= omega D^{-1} r_p.  With constant
-    // coefficients the k-marching form of the whole operator is cheaper than
-    // the pressure rows alone (a few loads per lattice point against a load
-    // per stencil entry); its velocity rows land in the scratch residual.
+    // coefficients the k-marching apply in its pressure-rows-only form (a
+    // few loads per lattice point, no velocity rows written).
     if (!lv.nu64)
-      op_apply<T>(h, l, full_mask(h), x, b, r, true, true, true);
+      op_apply<T>(h, l, full_mask(h), x, b, r, true, false, true);
     else
       op_apply<T>(h, l, full_mask(h) & 12, x, b, r, true, false, true);
     launch_pressure_step<T>(S(h), lv.g, dinv<T>(lv), x, r, (T)omega);

@@ -454,7 +454,7 @@ struct ZmCol {
   T sv, sp;  // units of the accumulated velocity and pressure rows
 };
 
-template <typename T, int G, int D, int Q>
+template <typename T, int G, int D, int Q, bool VEL>
 __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
                                         const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol<T>& c, int q,
                                         T (&acc)[3][G + 1], T (*pshare)[3][kZmCols]) {
@@ -472,7 +472,7 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
   const int lane = threadIdx.x & (kZmCols - 1);
   if (kr >= c.k0 && kr < c.k1) {  // uniform over the block
     const int at = c.col + kr * s2;
-    if (c.valid) {
+    if (VEL && c.valid) {
 #pragma unroll
       for (int gr = 0; gr < G; ++gr) {
         const int pos = D * vs + gr * nn + at;
@@ -492,7 +492,7 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
   for (int r = 0; r <= G; ++r) acc[S][r] = T(0);
 }
 
-template <typename T, int G, int D>
+template <typename T, int G, int D, bool VEL>
 __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
                                        const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol<T>& c,
                                        T (*pshare)[3][kZmCols]) {
@@ -503,13 +503,13 @@ __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, c
     for (int r = 0; r <= G; ++r) acc[s][r] = T(0);
   const int nq = c.k1 - c.k0 + 2;
   for (int q = 0; q < nq; q += 3) {
-    zm_step<T, G, D, 0>(g, lc, x, b, y, has_b, c, q, acc, pshare);
-    if (q + 1 < nq) zm_step<T, G, D, 1>(g, lc, x, b, y, has_b, c, q + 1, acc, pshare);
-    if (q + 2 < nq) zm_step<T, G, D, 2>(g, lc, x, b, y, has_b, c, q + 2, acc, pshare);
+    zm_step<T, G, D, 0, VEL>(g, lc, x, b, y, has_b, c, q, acc, pshare);
+    if (q + 1 < nq) zm_step<T, G, D, 1, VEL>(g, lc, x, b, y, has_b, c, q + 1, acc, pshare);
+    if (q + 2 < nq) zm_step<T, G, D, 2, VEL>(g, lc, x, b, y, has_b, c, q + 2, acc, pshare);
   }
 }
 
-template <typename T, int G>
+template <typename T, int G, bool VEL>
 __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
                                                           const T* __restrict__ b, T* __restrict__ y, int has_b, int kc,
                                                           int ncb, const int* __restrict__ bnd, int nbnd, int nmain) {
@@ -542,11 +542,11 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
   for (int dj = -1; dj <= 1; ++dj) c.nb[dj + 1] = min(max(c.col + dj * n1, 0), ncol - 1);
   const int wave = threadIdx.x / kZmCols;  // velocity component
   if (wave == 0)
-    zm_run<T, G, 0>(g, lc, x, b, y, has_b, c, pshare);
+    zm_run<T, G, 0, VEL>(g, lc, x, b, y, has_b, c, pshare);
   else if (wave == 1)
-    zm_run<T, G, 1>(g, lc, x, b, y, has_b, c, pshare);
+    zm_run<T, G, 1, VEL>(g, lc, x, b, y, has_b, c, pshare);
   else
-    zm_run<T, G, 2>(g, lc, x, b, y, has_b, c, pshare);
+    zm_run<T, G, 2, VEL>(g, lc, x, b, y, has_b, c, pshare);
 }
 
 // Pressure rows at boundary nodes (list), boundary-class stencils.
@@ -1651,7 +1651,7 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
   const int hb = has_b, vr = vel_rows, pr = p_rows;
   const int full = g.G == 1 ? 15 : 7;
   const int nb_bnd = p_rows ? nbnd : 0;
-  if (!lc.nu && opmask == full && vel_rows && p_rows) {
+  if (!lc.nu && opmask == full && p_rows) {
     // k-marching form: 62 output columns per block, k in chunks of kc planes;
     // the boundary pressure rows in extra blocks of 192 threads
     // chunk length: HHG_ZM_KC planes, halved (down to 2) while the grid has
@@ -1672,11 +1672,25 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     // 2 -> 1.36 ms).  Unused dynamic LDS caps residency at 3 of the CU's
     // 160 KiB; float64 is already held to 4 by its registers and does not
     // gain from fewer.
+    // vel_rows false: the pressure rows only (the Uzawa pressure residual):
+    // the velocity words are still loaded for B u, the velocity rows are
+    // neither accumulated nor written and their b words not read
     const unsigned dyn = sizeof(T) == 4 ? kZmF32Lds : 0;
-    if (g.G == 1)
-      hipLaunchKernelGGL((k_apply_zm<T, 1>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
-    else
-      hipLaunchKernelGGL((k_apply_zm<T, 8>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd, nmain);
+    if (g.G == 1) {
+      if (vel_rows)
+        hipLaunchKernelGGL((k_apply_zm<T, 1, true>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
+                           nmain);
+      else
+        hipLaunchKernelGGL((k_apply_zm<T, 1, false>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
+                           nmain);
+    } else {
+      if (vel_rows)
+        hipLaunchKernelGGL((k_apply_zm<T, 8, true>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
+                           nmain);
+      else
+        hipLaunchKernelGGL((k_apply_zm<T, 8, false>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
+                           nmain);
+    }
   } else {
     const int nmain = (int)nblocks8(g.nn);
     const unsigned nb = (unsigned)(nmain + (nb_bnd + kBlock - 1) / kBlock);
