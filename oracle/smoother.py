@@ -27,6 +27,8 @@ power iteration.  Two choices of D:
   Schur complement is much smaller than M_L.
 """
 import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import mesh
 
@@ -142,3 +144,30 @@ class Uzawa:
             lam = np.linalg.norm(w)
             v = w / lam
         return lam
+
+
+class LexUzawa(Uzawa):
+    """The paper's ordering (Sec. 5.2.1: lexicographic update inside each
+    primitive, primitives in turn): pointwise Gauss-Seidel over the velocity
+    unknowns in node order -- lattice order on the lattice levels, canonical
+    order (vertices, edges, faces, cells of T_0; lexicographic inside) on
+    unstructured levels.  A forward sweep is u <- u + (D + L)^{-1}(f - B^T p
+    - A u) over the interior rows, D + L the lower triangle of A in that
+    order (backward: the upper triangle), solved as a triangular system;
+    for comparison with the multicolour order only."""
+
+    def __init__(self, stokes, schur="ml"):
+        super().__init__(stokes, schur)
+        lev = stokes.lev
+        self.vi = np.nonzero(lev.vint)[0]
+        Aii = lev.A[self.vi][:, self.vi]
+        self.lower = sp.tril(Aii, format="csr")
+        self.upper = sp.triu(Aii, format="csr")
+        self.Afull = lev.A
+
+    def sweep(self, us, f_us, p, forward=True):
+        T = self.lower if forward else self.upper
+        bt = self.S.apply_BT(p)
+        for d in range(3):
+            r = (f_us[d] - self.Afull @ us[d] - bt[d])[self.vi]
+            us[d][self.vi] = us[d][self.vi] + spla.spsolve_triangular(T, r, lower=forward)
