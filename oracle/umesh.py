@@ -68,14 +68,20 @@ class ULevel:
     with the attributes of fe.Level that the Stokes, smoother, coarse-solve
     and multigrid code reads."""
 
-    def __init__(self, xyz, tets, level, bfaces=None):
+    def __init__(self, xyz, tets, level, bfaces=None, outflow=()):
+        """outflow: boundary faces (vertex triples) with the natural outflow
+        condition (Sec. 2, du/dn = n p); the other boundary faces are
+        Dirichlet, their closure included."""
         self.vorder = 1
         self.N = 2 ** level
-        self.neumann = ()
+        outflow = {tuple(sorted(int(v) for v in f)) for f in outflow}
+        self.neumann = tuple(sorted(outflow))
         n = self.N
         xyz = np.asarray(xyz, dtype=float)
         self.tets0 = [tuple(sorted(int(v) for v in t)) for t in tets]
         bfaces = boundary_faces(tets) if bfaces is None else bfaces
+        assert outflow <= set(bfaces), "outflow faces must be boundary faces"
+        bfaces = set(bfaces) - outflow          # the Dirichlet faces
         # refined elements of every macro cell, in barycentric weights (sum n)
         keyset = {}
         elems = []           # (cell index, 4 keys)
@@ -215,18 +221,20 @@ class UTransfer(Transfer):
         self.Rv = self.Rp = P.T.tocsr()
 
 
-def hierarchy(xyz, tets, Lmin, Lmax, schur="ml"):
-    """multigrid.Hierarchy on the levels Lmin..Lmax of T_0 = (xyz, tets)."""
+def hierarchy(xyz, tets, Lmin, Lmax, schur="ml", outflow=()):
+    """multigrid.Hierarchy on the levels Lmin..Lmax of T_0 = (xyz, tets),
+    `outflow` boundary faces with the natural outflow condition."""
     from . import multigrid as mg
     from .coarse import CoarseSolver
     from .smoother import Uzawa
     from .stokes import Stokes
     H = mg.Hierarchy.__new__(mg.Hierarchy)
-    H.vorder, H.Lmin, H.Lmax, H.mr, H.nu_fn, H.neumann = 1, Lmin, Lmax, 0, None, ()
+    H.vorder, H.Lmin, H.Lmax, H.mr, H.nu_fn = 1, Lmin, Lmax, 0, None
+    H.neumann = tuple(sorted(tuple(sorted(int(v) for v in f)) for f in outflow))
     H.S, H.U, H.T = {}, {}, {}
     bf = boundary_faces(tets)
     for l in range(Lmin, Lmax + 1):
-        H.S[l] = Stokes(ULevel(xyz, tets, l, bf))
+        H.S[l] = Stokes(ULevel(xyz, tets, l, bf, outflow))
         H.U[l] = Uzawa(H.S[l], schur)
     for l in range(Lmin + 1, Lmax + 1):
         H.T[l] = UTransfer(H.S[l - 1], H.S[l])

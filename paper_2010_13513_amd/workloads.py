@@ -319,3 +319,25 @@ def box_cube24(nx, ny, nz):
     for key, q in pts.items():
         xyz[q] = np.array(key, float) / 2
     return xyz, np.array(tets, dtype=np.int64)
+
+
+def boundary_faces_on_planes(xyz, tets, faces):
+    """Boundary triangles (sorted vertex triples) of the mesh that lie on the
+    listed faces of the unit cube (0: x = 0, 1: x = 1, 2: y = 0, 3: y = 1,
+    4: z = 0, 5: z = 1)."""
+    count = {}
+    for t in tets:
+        for drop in range(4):
+            f = tuple(sorted(int(v) for q, v in enumerate(t) if q != drop))
+            count[f] = count.get(f, 0) + 1
+    out = []
+    for f, c in sorted(count.items()):
+        if c != 1:
+            continue
+        P = np.asarray(xyz)[list(f)]
+        for face in faces:
+            d, val = face // 2, float(face % 2)
+            if np.all(np.abs(P[:, d] - val) < 1e-12):
+                out.append(f)
+                break
+    return out

@@ -244,3 +244,32 @@ def test_lexicographic_sweep_is_pointwise_gauss_seidel():
                 want[d][q] += r / A[q, q]
         for d in range(3):
             assert np.allclose(got[d], want[d], rtol=1e-12, atol=1e-12)
+
+
+def test_outflow_kuhn_partition_equals_lattice_level():
+    """Outflow face x = 1 on a Kuhn partition = the lattice level with that
+    outflow face (fe.Level, pinned in test_oracle_neumann)."""
+    xyz, tets = W.kuhn_cube(1)
+    of = W.boundary_faces_on_planes(xyz, tets, (1,))
+    assert len(of) == 2
+    U = umesh.ULevel(xyz, tets, 2, outflow=of)
+    F = fe.Level(4, 1, neumann=(1,))
+    pi = _perm_by_position(U.vpos(), F.vpos())
+    for a, b in ((U.A, F.A), (U.C, F.C)) + tuple(zip(U.B, F.B)):
+        assert np.abs(a.toarray() - b[pi][:, pi].toarray()).max() <= 1e-13 * np.abs(b).max()
+    assert np.array_equal(U.vbnd, F.vbnd[pi]) and U.neumann and F.neumann
+
+
+@pytest.mark.parametrize("which", ["cube24", "jittered"])
+def test_outflow_polynomial_reproduced_on_unstructured_meshes(which):
+    """u = (x, -y, 0), p = 1 satisfies du/dn = n p on x = 1 and lies in the
+    P1-P1 space: the discrete solution with that outflow face reproduces it
+    (no mean-zero step anywhere: the pressure is determined)."""
+    xyz, tets = W.cube24() if which == "cube24" else W.jittered_cube(W.SEED_BASE + 7000)
+    of = W.boundary_faces_on_planes(xyz, tets, (1,))
+    H = umesh.hierarchy(xyz, tets, 0, 2, schur="sd", outflow=of)
+    prob = W.outflow_polynomial(1)
+    xs = H.S[2].interpolate(prob.u, prob.p)
+    assert np.abs(H.exact_discrete(2, prob) - xs).max() < 1e-9
+    x = H.fmg(prob, mg.Params(2, 2, 0, 1, "s", 1, 2.3), cycles_on_finest=30)
+    assert np.abs(x - xs).max() < 1e-8
