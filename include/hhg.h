@@ -178,8 +178,19 @@ hhg_status hhg_mesh_info(hhg_mesh mesh, int* nv, int* nt, int* macro_refine);
  * layout (the outflow sites hold values, not boundary data:
  * hhg_copy_boundary skips them); variable viscosity is refused
  * (HHG_ERR_STATE) and the one-workgroup small-level V-cycle is not used.
- * Unstructured meshes: faces must be 0 (HHG_ERR_ARG). */
+ * Unstructured meshes: the boundary triangles of the mesh lying on those
+ * planes of the unit cube (within 1e-12) become outflow faces (HHG_ERR_ARG if
+ * there is none, or if no boundary face would stay Dirichlet); the other
+ * boundary faces and their closure stay Dirichlet. */
 hhg_status hhg_mesh_set_outflow(hhg_mesh mesh, unsigned faces);
+/* Unstructured meshes: outflow faces given as boundary triangles, tri = ntri
+ * x 3 vertex indices (host, any vertex order; ntri = 0 clears them).  Every
+ * triangle must be a face of exactly one tetrahedron and at least one
+ * boundary face must stay Dirichlet, else HHG_ERR_ARG; Kuhn-partition meshes
+ * refuse the call (they take hhg_mesh_set_outflow).  As there, the solvers
+ * then do no mean-zero projection.  Applies to hierarchies created
+ * afterwards. */
+hhg_status hhg_mesh_set_outflow_faces(hhg_mesh mesh, const int* tri, int ntri);
 hhg_status hhg_mesh_destroy(hhg_mesh mesh);
 
 /* ------------------------------------------------------------- hierarchy */
@@ -304,16 +315,17 @@ hhg_status hhg_query_stencil(hhg_disc disc, char kind, int group, int i, int j, 
                              int* n, int* code, double* w);
 /* Host-only view of level `level` (0..6) of an unstructured mesh (xyz, tet
  * as for hhg_mesh_create; any valid tetrahedral mesh, Kuhn partitions
- * included): the number of nodes, of Gauss-Seidel colours and of coarse
+ * included; cube_outflow: outflow faces as for hhg_mesh_set_outflow on an
+ * unstructured mesh, 0 for none): the number of nodes, of Gauss-Seidel colours and of coarse
  * unknowns (free velocity nodes times three, then every pressure node); per
  * node in canonical order (arrays of nnodes entries, or NULL): position
  * (3 doubles), colour, Schur diagonal D of option `schur`; and calA on the
  * unknowns (nunk x nunk, row-major; velocity unknowns component-major, nodes
  * ascending, then the pressure nodes) if nunk <= max_unknowns and K is not
  * NULL.  Call once with NULL arrays for the sizes. */
-hhg_status hhg_query_umesh(const double* xyz, int nv, const int* tet, int nt, int level, hhg_schur schur,
-                           int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos, int* colour,
-                           double* schur_diag, double* K);
+hhg_status hhg_query_umesh(const double* xyz, int nv, const int* tet, int nt, unsigned cube_outflow, int level,
+                           hhg_schur schur, int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos,
+                           int* colour, double* schur_diag, double* K);
 /* Interpolation weights of Sec. 3.3 at a fine position inside one coarse
  * lattice cube: t = (tx, ty, tz) / q with q = 2 (linear) or 4 (quadratic)
  * and order 1 or 2.  Output: code[4 e ..] = (coarse group, di, dj, dk) from the

@@ -6,6 +6,7 @@
 // step runs in the kernels of kernels.hip; this file builds tables, owns work
 // memory and sequences launches on the context stream.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -144,6 +145,7 @@ struct hhg_mesh_s {
   int mr = 0;
   unsigned nf = 0;   // outflow faces (hhg_mesh_set_outflow)
   bool general = false;  // not a Kuhn partition of the cube: unstructured path
+  std::vector<std::array<int, 3>> outflow;  // unstructured path: outflow boundary faces (sorted vertex triples)
   std::vector<double> xyz;
   std::vector<int> tet;
 };
@@ -900,6 +902,7 @@ void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
     ULevelData& F = UL(h, lf);
     ULevelData& C = UL(h, lf - 1);
     launch_u_restrict(S(h), F.L, C.L, C.inner, C.lst, (const double*)rf, (double*)rc);
+    if (h->nf) return;  // outflow faces: no null vector, no compatibility shift
     // compatibility with the null vector (0, 1): plain mean of the pressure nodes
     launch_u_dot(S(h), C.L, C.flags, nullptr, (const double*)rc, nullptr, 3, 1, h->partial, h->sums, 0);
     launch_u_shift(S(h), C.L, (double*)rc + 3 * C.L.vs, h->sums, 0, (double)C.nnodes);
@@ -1373,8 +1376,9 @@ hhg_hier u_hier_create(hhg_mesh mesh, hhg_disc disc, int lmin, int lmax, hhg_sch
   h->lmax = lmax;
   h->schur = schur;
   h->G = 1;
+  h->nf = mesh->outflow.empty() ? 0 : 1;  // the pressure is determined: no mean-zero steps
   h->um.reset(u_build(mesh->xyz.data(), (int)(mesh->xyz.size() / 3), mesh->tet.data(), (int)(mesh->tet.size() / 4),
-                      lmin, lmax, schur));
+                      mesh->outflow, lmin, lmax, schur));
   h->partial = h->arena.alloc<double>(4 * kPartials);
   h->sums = h->arena.alloc<double>(16);
   HHG_CHECK_HIP(hipHostMalloc((void**)&h->hsums, 16 * sizeof(double), hipHostMallocDefault));
@@ -1529,9 +1533,32 @@ hhg_status hhg_mesh_set_outflow(hhg_mesh mesh, unsigned faces) {
   return guard([&] {
     HHG_REQUIRE(mesh, HHG_ERR_ARG, "null mesh");
     HHG_REQUIRE(faces < 63u, HHG_ERR_ARG, "outflow faces: a mask of faces 0..5 with at least one Dirichlet face");
-    HHG_REQUIRE(!mesh->general || faces == 0, HHG_ERR_ARG,
-                "outflow faces are faces of the unit cube: Kuhn-partition meshes only");
+    if (mesh->general) {  // the boundary triangles on those planes of the unit cube
+      const int nv = (int)(mesh->xyz.size() / 3), nt = (int)(mesh->tet.size() / 4);
+      std::vector<std::array<int, 3>> of = boundary_faces_on_cube(mesh->xyz.data(), nv, mesh->tet.data(), nt, faces);
+      HHG_REQUIRE(faces == 0 || !of.empty(), HHG_ERR_ARG, "outflow: no boundary face of the mesh on those planes");
+      check_outflow_faces(mesh->tet.data(), nt, of);
+      mesh->outflow = of;
+    }
     mesh->nf = faces;
+  });
+}
+
+hhg_status hhg_mesh_set_outflow_faces(hhg_mesh mesh, const int* tri, int ntri) {
+  return guard([&] {
+    HHG_REQUIRE(mesh && (tri || ntri == 0) && ntri >= 0, HHG_ERR_ARG, "bad arguments");
+    HHG_REQUIRE(mesh->general, HHG_ERR_ARG,
+                "explicit outflow faces: unstructured meshes only (Kuhn partitions: hhg_mesh_set_outflow)");
+    std::vector<std::array<int, 3>> of(ntri);
+    for (int q = 0; q < ntri; ++q) {
+      for (int a = 0; a < 3; ++a) of[q][a] = tri[3 * q + a];
+      std::sort(of[q].begin(), of[q].end());
+    }
+    std::sort(of.begin(), of.end());
+    of.erase(std::unique(of.begin(), of.end()), of.end());
+    check_outflow_faces(mesh->tet.data(), (int)(mesh->tet.size() / 4), of);
+    mesh->outflow = of;
+    mesh->nf = of.empty() ? 0u : 64u;  // bit 6: explicit faces
   });
 }
 
@@ -2317,13 +2344,15 @@ hhg_status hhg_query_stencil(hhg_disc disc, char kind, int group, int i, int j, 
   });
 }
 
-hhg_status hhg_query_umesh(const double* xyz, int nv, const int* tet, int nt, int level, hhg_schur schur,
-                           int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos, int* colour,
-                           double* schur_diag, double* K) {
+hhg_status hhg_query_umesh(const double* xyz, int nv, const int* tet, int nt, unsigned cube_outflow, int level,
+                           hhg_schur schur, int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos,
+                           int* colour, double* schur_diag, double* K) {
   return guard([&] {
     HHG_REQUIRE(xyz && tet, HHG_ERR_ARG, "null mesh");
     HHG_REQUIRE(schur == HHG_SCHUR_SD || schur == HHG_SCHUR_ML, HHG_ERR_ARG, "unknown Schur option");
-    u_query(xyz, nv, tet, nt, level, schur, max_unknowns, nnodes, ncolours, nunk, pos, colour, schur_diag, K);
+    HHG_REQUIRE(cube_outflow < 64u, HHG_ERR_ARG, "outflow faces: a mask of faces 0..5");
+    u_query(xyz, nv, tet, nt, cube_outflow, level, schur, max_unknowns, nnodes, ncolours, nunk, pos, colour,
+            schur_diag, K);
   });
 }
 

@@ -21,6 +21,8 @@
 // value at all times: kernels that write an interface node write every copy.
 // A vector is [u1 | u2 | u3 | p], each `vs` words (cells times P, rounded up).
 #pragma once
+#include <array>
+
 #include "kernels.h"
 
 namespace hhg {
@@ -143,6 +145,13 @@ void launch_u_sync(hipStream_t s, const ULev& L, const UList& lst, double* x);
 // tetrahedra, the two at a shared face on opposite sides of it (HHG_ERR_ARG
 // naming the first violation otherwise).
 void validate_tet_mesh(const double* xyz, int nv, const int* tet, int nt);
+// Boundary faces (sorted vertex triples) lying on the listed planes of the
+// unit cube (bit f: 0 x = 0, 1 x = 1, 2 y = 0, 3 y = 1, 4 z = 0, 5 z = 1).
+std::vector<std::array<int, 3>> boundary_faces_on_cube(const double* xyz, int nv, const int* tet, int nt,
+                                                       unsigned faces);
+// Every outflow face a boundary face of the mesh, at least one boundary face
+// left Dirichlet (HHG_ERR_ARG otherwise).
+void check_outflow_faces(const int* tet, int nt, const std::vector<std::array<int, 3>>& outflow);
 
 // Levels lmin..lmax of an unstructured hierarchy (device tables in `mem`).
 struct UHier {
@@ -153,15 +162,19 @@ struct UHier {
   ~UHier();
 };
 // Builds every level (cell rows, slot tables, interface lists and colours,
-// segments, the Schur diagonal of option `schur`).  Synchronous.
-UHier* u_build(const double* xyz, int nv, const int* tet, int nt, int lmin, int lmax, int schur);
+// segments, the Schur diagonal of option `schur`); `outflow`: boundary
+// faces (sorted vertex triples) with the natural outflow condition, the
+// other boundary faces (and their closure) Dirichlet.  Synchronous.
+UHier* u_build(const double* xyz, int nv, const int* tet, int nt, const std::vector<std::array<int, 3>>& outflow,
+               int lmin, int lmax, int schur);
 // Coarse unknowns of level lmin (array positions of the free velocity nodes'
 // owner slots in three components, then of every pressure node) and the
 // operator calA restricted to them (row-major, n x n), assembled on the host
 // from the cell rows; K is left empty when there are more than max_n unknowns.
 void u_coarse_system(UHier& u, std::vector<int>& unk, std::vector<double>& K, int max_n);
 // Host-only view of one level's tables (hhg_query_umesh).
-void u_query(const double* xyz, int nv, const int* tet, int nt, int level, int schur, int max_unknowns,
-             int* nnodes, int* ncolours, int* nunk, double* pos, int* colour, double* sdiag, double* K);
+void u_query(const double* xyz, int nv, const int* tet, int nt, unsigned cube_outflow, int level, int schur,
+             int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos, int* colour, double* sdiag,
+             double* K);
 
 }  // namespace hhg

@@ -161,7 +161,7 @@ Tup sub_tuple(const std::array<int, 4>& v, int m) {
   return t;
 }
 
-Prims primitives(const std::vector<std::array<int, 4>>& cells) {
+Prims primitives(const std::vector<std::array<int, 4>>& cells, const std::vector<std::array<int, 3>>& outflow) {
   Prims P;
   P.list.resize(4);
   std::vector<std::map<Tup, int>> first(4);
@@ -180,9 +180,13 @@ Prims primitives(const std::vector<std::array<int, 4>>& cells) {
       rk[d][kv.first] = r++;
     }
   }
-  std::set<Tup> dirichlet;  // sub-primitives of faces that belong to one cell
+  std::set<Tup> outf;
+  for (const auto& f : outflow) outf.insert(Tup(f.begin(), f.end()));
+  // Dirichlet: sub-primitives of the faces that belong to one cell and are
+  // not outflow faces
+  std::set<Tup> dirichlet;
   for (auto& kv : face_count)
-    if (kv.second == 1) {
+    if (kv.second == 1 && !outf.count(kv.first)) {
       const Tup& f = kv.first;
       for (int mask = 1; mask < 8; ++mask) {
         Tup t;
@@ -236,6 +240,62 @@ USegs upload_segs(UHier& u, const std::vector<int4>& v, int lps) {
 
 UHier::~UHier() {
   for (void* p : mem) (void)hipFree(p);
+}
+
+std::vector<std::array<int, 3>> boundary_faces_on_cube(const double* xyz, int nv, const int* tet, int nt,
+                                                       unsigned faces) {
+  (void)nv;
+  std::map<std::array<int, 3>, int> count;
+  for (int t = 0; t < nt; ++t)
+    for (int drop = 0; drop < 4; ++drop) {
+      std::array<int, 3> f;
+      int w = 0;
+      for (int q = 0; q < 4; ++q)
+        if (q != drop) f[w++] = tet[4 * t + q];
+      std::sort(f.begin(), f.end());
+      ++count[f];
+    }
+  std::vector<std::array<int, 3>> out;
+  for (const auto& kv : count) {
+    if (kv.second != 1) continue;
+    for (int face = 0; face < 6; ++face) {
+      if (!((faces >> face) & 1)) continue;
+      const int d = face / 2;
+      const double val = face % 2;
+      bool on = true;
+      for (int v : kv.first) on = on && std::fabs(xyz[3 * v + d] - val) < 1e-12;
+      if (on) {
+        out.push_back(kv.first);
+        break;
+      }
+    }
+  }
+  return out;
+}
+
+void check_outflow_faces(const int* tet, int nt, const std::vector<std::array<int, 3>>& outflow) {
+  std::map<std::array<int, 3>, int> count;
+  for (int t = 0; t < nt; ++t)
+    for (int drop = 0; drop < 4; ++drop) {
+      std::array<int, 3> f;
+      int w = 0;
+      for (int q = 0; q < 4; ++q)
+        if (q != drop) f[w++] = tet[4 * t + q];
+      std::sort(f.begin(), f.end());
+      ++count[f];
+    }
+  long nbnd = 0;
+  for (const auto& kv : count) nbnd += kv.second == 1;
+  std::set<std::array<int, 3>> seen;
+  for (const auto& f : outflow) {
+    auto it = count.find(f);
+    HHG_REQUIRE(it != count.end() && it->second == 1, HHG_ERR_ARG,
+                "outflow face (" + std::to_string(f[0]) + ", " + std::to_string(f[1]) + ", " + std::to_string(f[2]) +
+                    ") is not a boundary face of the mesh");
+    seen.insert(f);
+  }
+  HHG_REQUIRE((long)seen.size() < nbnd, HHG_ERR_ARG,
+              "outflow faces: at least one boundary face must stay Dirichlet (the velocity would have a null space)");
 }
 
 void validate_tet_mesh(const double* xyz, int nv, const int* tet, int nt) {
@@ -321,14 +381,14 @@ struct UMeshPrims {
   long nprim[4];
 };
 
-UMeshPrims mesh_prims(const int* tet, int nt) {
+UMeshPrims mesh_prims(const int* tet, int nt, const std::vector<std::array<int, 3>>& outflow) {
   UMeshPrims M;
   M.cells.resize(nt);
   for (int c = 0; c < nt; ++c) {
     for (int q = 0; q < 4; ++q) M.cells[c][q] = tet[4 * c + q];
     std::sort(M.cells[c].begin(), M.cells[c].end());
   }
-  M.pr = primitives(M.cells);
+  M.pr = primitives(M.cells, outflow);
   for (int d = 0; d < 4; ++d) M.nprim[d] = (long)M.pr.list[d].size();
   return M;
 }
@@ -549,13 +609,14 @@ void u_level_host(const UMeshPrims& M, const double* xyz, int l, int schur, ULev
 
 }  // namespace
 
-UHier* u_build(const double* xyz, int nv, const int* tet, int nt, int lmin, int lmax, int schur) {
+UHier* u_build(const double* xyz, int nv, const int* tet, int nt, const std::vector<std::array<int, 3>>& outflow,
+               int lmin, int lmax, int schur) {
   (void)nv;
   std::unique_ptr<UHier> u(new UHier);
   u->lmin = lmin;
   u->lmax = lmax;
   u->ncell = nt;
-  const UMeshPrims M = mesh_prims(tet, nt);
+  const UMeshPrims M = mesh_prims(tet, nt, outflow);
   u->lv.resize(lmax - lmin + 1);
   for (int l = lmin; l <= lmax; ++l) {
     ULevelData& lv = u->L(l);
@@ -647,11 +708,12 @@ void u_coarse_system(UHier& u, std::vector<int>& unk, std::vector<double>& K, in
   u_level_system(lv, lv.h_canon, unk, K, max_n);
 }
 
-void u_query(const double* xyz, int nv, const int* tet, int nt, int level, int schur, int max_unknowns,
-             int* nnodes, int* ncolours, int* nunk, double* pos, int* colour, double* sdiag, double* Kout) {
+void u_query(const double* xyz, int nv, const int* tet, int nt, unsigned cube_outflow, int level, int schur,
+             int max_unknowns, int* nnodes, int* ncolours, int* nunk, double* pos, int* colour, double* sdiag,
+             double* Kout) {
   validate_tet_mesh(xyz, nv, tet, nt);
   HHG_REQUIRE(level >= 0 && level <= 6, HHG_ERR_ARG, "query: level must be 0..6");
-  const UMeshPrims M = mesh_prims(tet, nt);
+  const UMeshPrims M = mesh_prims(tet, nt, boundary_faces_on_cube(xyz, nv, tet, nt, cube_outflow));
   ULevelData lv;
   UHostLevel H;
   u_level_host(M, xyz, level, schur, lv, H);

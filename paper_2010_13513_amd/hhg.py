@@ -21,6 +21,7 @@ HHG_SCHUR_SD, HHG_SCHUR_ML = 0, 1
 SYMBOLS = [
     "hhg_ctx_create", "hhg_ctx_set_stream", "hhg_ctx_destroy", "hhg_last_error",
     "hhg_mesh_cube", "hhg_mesh_create", "hhg_mesh_info", "hhg_mesh_destroy", "hhg_mesh_set_outflow",
+    "hhg_mesh_set_outflow_faces",
     "hhg_hier_create", "hhg_hier_destroy", "hhg_vec_layout", "hhg_vec_from_lattice", "hhg_vec_to_lattice",
     "hhg_apply", "hhg_residual", "hhg_rhs", "hhg_smooth", "hhg_restrict", "hhg_prolong_add",
     "hhg_coarse_solve", "hhg_project_mean_zero", "hhg_copy_boundary", "hhg_estimate_omega", "hhg_norms",
@@ -79,6 +80,7 @@ def load():
         "hhg_mesh_info": [P, P, P, P],
         "hhg_mesh_destroy": [P],
         "hhg_mesh_set_outflow": [P, ctypes.c_uint],
+        "hhg_mesh_set_outflow_faces": [P, P, I],
         "hhg_hier_create": [P, I, I, I, I, P],
         "hhg_hier_destroy": [P],
         "hhg_vec_layout": [P, I, P, P, P, P],
@@ -99,7 +101,7 @@ def load():
         "hhg_fmg_solve": [P, P, P, P, P],
         "hhg_query_stencil": [I, ctypes.c_char, I, I, I, I, I, I, P, P, P],
         "hhg_query_interpolation": [I, I, I, I, I, P, P, P],
-        "hhg_query_umesh": [P, I, P, I, I, I, I, P, P, P, P, P, P, P],
+        "hhg_query_umesh": [P, I, P, I, ctypes.c_uint, I, I, I, P, P, P, P, P, P, P],
         "hhg_dots": [P, I, P, P, P, P, I],
         "hhg_timer_start": [ctypes.c_uint],
         "hhg_timer_read": [I, P, P, P],
@@ -191,6 +193,13 @@ def hhg_mesh_info(mesh):
 
 def hhg_mesh_set_outflow(mesh, faces):
     _check(load().hhg_mesh_set_outflow(mesh, int(faces)))
+
+
+def hhg_mesh_set_outflow_faces(mesh, tri):
+    """tri: (ntri, 3) vertex indices of boundary triangles (unstructured meshes)."""
+    import numpy as np
+    t = np.ascontiguousarray(np.asarray(tri, dtype=np.int32).reshape(-1, 3))
+    _check(load().hhg_mesh_set_outflow_faces(mesh, t.ctypes.data if t.size else None, t.shape[0]))
 
 
 def hhg_mesh_destroy(mesh):
@@ -345,7 +354,7 @@ def hhg_query_interpolation(order, tx, ty, tz, q):
     return np.array(code[:4 * m]).reshape(m, 4), np.array(w[:m])
 
 
-def hhg_query_umesh(xyz, tet, level, schur=HHG_SCHUR_SD, max_unknowns=0):
+def hhg_query_umesh(xyz, tet, level, schur=HHG_SCHUR_SD, max_unknowns=0, outflow=0):
     """Host-only: tables of one level of an unstructured mesh.  Returns a dict
     with nnodes, ncolours, nunk, pos (nnodes, 3), colour (nnodes,),
     schur_diag (nnodes,) and K (nunk, nunk) or None."""
@@ -354,7 +363,7 @@ def hhg_query_umesh(xyz, tet, level, schur=HHG_SCHUR_SD, max_unknowns=0):
     t = np.ascontiguousarray(tet, dtype=np.int32)
     nn, nc, nu = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     lib = load()
-    args = (x.ctypes.data, x.shape[0], t.ctypes.data, t.shape[0], level, schur)
+    args = (x.ctypes.data, x.shape[0], t.ctypes.data, t.shape[0], int(outflow), level, schur)
     _check(lib.hhg_query_umesh(*args, 0, ctypes.byref(nn), ctypes.byref(nc), ctypes.byref(nu),
                                None, None, None, None))
     n = nn.value

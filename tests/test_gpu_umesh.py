@@ -365,3 +365,80 @@ def test_full_size_fmg_converges(big):
     rate = (st.rel_res / 1e-1) ** (1.0 / max(st.cycles - 1, 1))
     print(f"[umesh] level 7 FMG: {st.cycles} cycles, rel res {st.rel_res:.2e}, mean rate {rate:.3f}", flush=True)
     assert st.rel_res <= 1e-8 and rate <= 0.6
+
+
+# ------------------------------------------------------------ outflow faces
+@pytest.fixture(scope="module")
+def outflow_case():
+    """24-tetrahedron cube with the outflow face x = 1 (bit 1), levels 0..3,
+    and the oracle hierarchy of the same problem."""
+    xyz, tets = W.cube24()
+    of = W.boundary_faces_on_planes(xyz, tets, (1,))
+    lib = Lib(hhg.HHG_P1P1, 0, 3, mesh=(xyz, tets), outflow=2)
+    H = umesh.hierarchy(xyz, tets, 0, 3, schur="sd", outflow=of)
+    yield lib, H
+    lib.close()
+
+
+def test_outflow_operators(outflow_case):
+    lib, H = outflow_case
+    L = 3
+    S = H.S[L]
+    x = _rand(S, 81)
+    dy = lib.empty(L)
+    hhg.hhg_apply(lib.h, L, hhg.HHG_OP_FULL, lib.from_lattice(L, x), dy)
+    assert_blocks(lib, L, lib.to_lattice(L, dy), S.apply(x), 1e-12, "outflow apply")
+    b = _rand(S, 82, zero_bnd=True)
+    want = H.U[L].iterate(H.U[L].iterate(x, b, "s", 1, 0.5), b, "s", 1, 0.5)
+    dx = lib.from_lattice(L, x)
+    hhg.hhg_smooth(lib.h, L, dx, lib.from_lattice(L, b), 2, hhg.HHG_GS_SYM, 1, 2.0)
+    assert_blocks(lib, L, lib.to_lattice(L, dx), want, 1e-12, "outflow smooth")
+    rf = _rand(S, 83)
+    drc = lib.empty(L - 1)
+    hhg.hhg_restrict(lib.h, L, lib.from_lattice(L, rf), drc)
+    assert_blocks(lib, L - 1, lib.to_lattice(L - 1, drc), H.T[L].restrict(rf), 1e-12, "outflow restrict")
+    tol, cs = _coarse_tol(H.S[0])
+    x0, b0 = _rand(H.S[0], 84), _rand(H.S[0], 85, zero_bnd=True)
+    dx0 = lib.from_lattice(0, x0)
+    hhg.hhg_coarse_solve(lib.h, dx0, lib.from_lattice(0, b0))
+    assert_blocks(lib, 0, lib.to_lattice(0, dx0), cs.solve(x0, b0), tol, "outflow coarse solve")
+
+
+def test_outflow_fmg(outflow_case):
+    """FMG on the smooth outflow solution matches the oracle; the P1 outflow
+    polynomial u = (x, -y, 0), p = 1 is reproduced."""
+    lib, H = outflow_case
+    L = 3
+    tol, _ = _coarse_tol(H.S[0])
+    for prob, extra in ((W.outflow_cube(), 1), (W.outflow_polynomial(1), 30)):
+        prm = mg.Params(2, 2, 0, 1, "s", 1, 2.3)
+        want = H.fmg(prob, prm, cycles_on_finest=extra)
+        bs = [lib.from_lattice(l, H.rhs(l, prob)) for l in range(0, L + 1)]
+        dx = lib.from_lattice(L, H.initial(L, prob))
+        hhg.hhg_fmg_solve(lib.h, dx, bs, hhg.solver_params(2, 2, 0, 1, hhg.HHG_GS_SYM, 1, 2.3, extra_cycles=extra))
+        got = lib.to_lattice(L, dx)
+        assert_blocks(lib, L, got, want, tol, f"outflow FMG {prob.name}")
+        if prob.name.startswith("outflow_polynomial"):
+            assert np.abs(got - H.S[L].interpolate(prob.u, prob.p)).max() < 1e-8
+
+
+def test_outflow_face_refusals(libs):
+    lib = libs("box2", 0, 2)
+    ctx = lib.ctx
+    xyz, tets = W.cube24()
+    mesh = hhg.hhg_mesh_create(ctx, xyz, tets)
+    try:
+        with pytest.raises(hhg.HHGError):
+            hhg.hhg_mesh_set_outflow_faces(mesh, [[0, 1, 14]])          # not a boundary face
+        every = W.boundary_faces_on_planes(xyz, tets, range(6))
+        with pytest.raises(hhg.HHGError):
+            hhg.hhg_mesh_set_outflow_faces(mesh, every)                 # no Dirichlet face left
+        hhg.hhg_mesh_set_outflow_faces(mesh, W.boundary_faces_on_planes(xyz, tets, (1,)))
+    finally:
+        hhg.hhg_mesh_destroy(mesh)
+    cube = hhg.hhg_mesh_cube(ctx, 0)
+    try:
+        with pytest.raises(hhg.HHGError):
+            hhg.hhg_mesh_set_outflow_faces(cube, [[0, 1, 3]])           # Kuhn meshes: hhg_mesh_set_outflow
+    finally:
+        hhg.hhg_mesh_destroy(cube)

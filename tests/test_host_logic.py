@@ -175,19 +175,22 @@ UMESHES = {
 }
 
 
-@pytest.mark.parametrize("name,level", [("cube24", 0), ("cube24", 1), ("cube24", 2), ("jittered", 1),
-                                        ("jittered", 2), ("box2", 1)])
+@pytest.mark.parametrize("name,level,outflow", [("cube24", 0, 0), ("cube24", 1, 0), ("cube24", 2, 0),
+                                                ("jittered", 1, 0), ("jittered", 2, 0), ("box2", 1, 0),
+                                                ("cube24", 2, 2), ("jittered", 2, 2 | 16)])
 @pytest.mark.parametrize("schur", ["sd", "ml"])
-def test_unstructured_tables_match_oracle(name, level, schur):
+def test_unstructured_tables_match_oracle(name, level, outflow, schur):
     """Host tables of the unstructured path against oracle/umesh: node order
     (positions), Gauss-Seidel colours (exact), Schur diagonal and the operator
-    on the coarse unknowns."""
+    on the coarse unknowns; with outflow faces (bit 1: x = 1, bit 4: z = 0)
+    the face nodes off the Dirichlet closure are unknowns."""
     from oracle import coarse as ocoarse, smoother, umesh
     from oracle.stokes import Stokes
     xyz, tets = UMESHES[name]()
     code = hhg.HHG_SCHUR_SD if schur == "sd" else hhg.HHG_SCHUR_ML
-    q = hhg.hhg_query_umesh(xyz, tets, level, code, max_unknowns=1500)
-    U = umesh.ULevel(xyz, tets, level)
+    q = hhg.hhg_query_umesh(xyz, tets, level, code, max_unknowns=1500, outflow=outflow)
+    faces = [f for f in range(6) if (outflow >> f) & 1]
+    U = umesh.ULevel(xyz, tets, level, outflow=W.boundary_faces_on_planes(xyz, tets, faces))
     S = Stokes(U)
     assert q["nnodes"] == U.nv and q["ncolours"] == U.ncolours
     assert np.abs(q["pos"] - U.vpos()).max() <= 1e-15 * max(1.0, np.abs(xyz).max())
