@@ -4,9 +4,10 @@
 // takes 256 / lps row segments of one cell (grid.y = cell), one lane per point,
 // with the cell's interior rows staged in LDS; neighbours are the 14
 // Freudenthal neighbours in the cell's packed slot order.  Interface nodes
-// (on vertices, edges and faces of T_0) run one thread per node: the row is
-// the sum, over the cells containing the node, of that cell's row of the
-// node's class, and the result goes to every copy of the node.
+// (on vertices, edges and faces of T_0) run 16 lanes per node, one per
+// stencil point: the row is the sum, over the cells containing the node, of
+// that cell's row of the node's class, and the result goes to every copy of
+// the node.
 #include "umesh.h"
 
 namespace hhg {
@@ -126,15 +127,43 @@ __device__ __forceinline__ size_t occ_centre(const ULev& L, int2 oc) {
   unpack(oc.y, i, j, k);
   return (size_t)oc.x * L.P + uslot(i, j, k, L.n);
 }
-// Slot of stencil point e of occurrence oc, or -1 outside the closed cell;
-// cs / m: the occurrence's cell rows and class.
-__device__ __forceinline__ long occ_point(const ULev& L, int2 oc, int e, const UCell*& cs, int& m) {
+// The occurrences of a node are taken in batches of 16: lane l of the
+// node's group loads the record of occurrence base + l (cell, packed point,
+// class, the class's inside mask), then the group walks the batch in order
+// with the records passed round by shuffles.  The loads of one occurrence
+// then depend on no load of another, and a node in many cells costs one
+// batch of round trips instead of a chain of three per occurrence.
+struct OccRec {
+  int cell, pt, m;
+  unsigned in;
+};
+__device__ __forceinline__ OccRec occ_record(const ULev& L, const UList& lst, int o0, int no, int idx) {
+  OccRec r{0, 0, 0, 0u};
+  if (idx < no) {
+    const int2 oc = lst.occ[o0 + idx];
+    int i, j, k;
+    unpack(oc.y, i, j, k);
+    r.cell = oc.x;
+    r.pt = oc.y;
+    r.m = uclass(i, j, k, L.n);
+    r.in = L.cs[oc.x].inside[r.m];
+  }
+  return r;
+}
+__device__ __forceinline__ OccRec occ_share(const OccRec& r, int u) {
+  return OccRec{__shfl(r.cell, u, kIfGroup), __shfl(r.pt, u, kIfGroup), __shfl(r.m, u, kIfGroup),
+                (unsigned)__shfl((int)r.in, u, kIfGroup)};
+}
+// Stencil point e of occurrence r: ok (inside the closed cell) and its slot;
+// outside, the slot of the centre (a valid address whose words are then
+// weighted by zero) -- no branch, so the loads of consecutive occurrences
+// can be in flight together.
+__device__ __forceinline__ long occ_slot(const ULev& L, const OccRec& r, int e, bool& ok) {
+  ok = e < kUPoints && ((r.in >> e) & 1u);
+  const int ee = ok ? e : 0;
   int i, j, k;
-  unpack(oc.y, i, j, k);
-  m = uclass(i, j, k, L.n);
-  cs = L.cs + oc.x;
-  if (e >= kUPoints || !((cs->inside[m] >> e) & 1)) return -1;
-  return (long)oc.x * L.P + uslot(i + udir(e, 0), j + udir(e, 1), k + udir(e, 2), L.n);
+  unpack(r.pt, i, j, k);
+  return (long)r.cell * L.P + uslot(i + udir(ee, 0), j + udir(ee, 1), k + udir(ee, 2), L.n);
 }
 
 template <bool HB, bool MASS>
@@ -144,37 +173,45 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, co
   const int q = blockIdx.x * kIfNodes + (threadIdx.x / kIfGroup), e = threadIdx.x % kIfGroup;
   if (q >= lst.n) return;
   const size_t vs = L.vs;
-  const int o0 = lst.off[q], o1 = lst.off[q + 1];
+  const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, bp[3] = {0.0, 0.0, 0.0}, cp = 0.0;
   const bool dA = opmask & 1, dBT = opmask & 2, dB = opmask & 4, dC = opmask & 24;
-  for (int o = o0; o < o1; ++o) {
-    const UCell* cs;
-    int m;
-    const long sl = occ_point(L, lst.occ[o], e, cs, m);
-    if (sl < 0) continue;
-    if (MASS) {
-      const double mw = cs->M[m][e];
-      for (int f = 0; f < 4; ++f) acc[f] += mw * x[f * vs + sl];
-      continue;
-    }
-    if (dA || dB) {
-      const double v0 = x[sl], v1 = x[vs + sl], v2 = x[2 * vs + sl];
-      if (dA) {
-        const double a = cs->A[m][e];
-        acc[0] += a * v0;
-        acc[1] += a * v1;
-        acc[2] += a * v2;
+  const int ew = e < kUPoints ? e : 0;  // weight column of the lane (lane 15: weighted by zero)
+  for (int base = 0; base < no; base += kIfGroup) {
+    const OccRec mine = occ_record(L, lst, o0, no, base + e);
+    const int cnt = min(kIfGroup, no - base);
+    for (int u = 0; u < cnt; ++u) {
+      const OccRec r = occ_share(mine, u);
+      bool ok;
+      const long sl = occ_slot(L, r, e, ok);
+      const double z = ok ? 1.0 : 0.0;
+      const UCell* cs = L.cs + r.cell;
+      const int m = r.m;
+      if (MASS) {
+        const double mw = z * cs->M[m][ew];
+        for (int f = 0; f < 4; ++f) acc[f] += mw * x[f * vs + sl];
+        continue;
       }
-      if (dB) acc[3] += cs->B[m][e][0] * v0 + cs->B[m][e][1] * v1 + cs->B[m][e][2] * v2;
-    }
-    if (dBT || dC) {
-      const double pe = x[3 * vs + sl];
-      if (dBT) {
-        bp[0] += cs->BT[m][e][0] * pe;
-        bp[1] += cs->BT[m][e][1] * pe;
-        bp[2] += cs->BT[m][e][2] * pe;
+      if (dA || dB) {
+        const double v0 = x[sl], v1 = x[vs + sl], v2 = x[2 * vs + sl];
+        if (dA) {
+          const double a = z * cs->A[m][ew];
+          acc[0] += a * v0;
+          acc[1] += a * v1;
+          acc[2] += a * v2;
+        }
+        if (dB)
+          acc[3] += (z * cs->B[m][ew][0]) * v0 + (z * cs->B[m][ew][1]) * v1 + (z * cs->B[m][ew][2]) * v2;
       }
-      if (dC) cp += cs->cfac * cs->A[m][e] * pe;
+      if (dBT || dC) {
+        const double pe = x[3 * vs + sl];
+        if (dBT) {
+          bp[0] += (z * cs->BT[m][ew][0]) * pe;
+          bp[1] += (z * cs->BT[m][ew][1]) * pe;
+          bp[2] += (z * cs->BT[m][ew][2]) * pe;
+        }
+        if (dC) cp += cs->cfac * (z * cs->A[m][ew]) * pe;
+      }
     }
   }
   double out[4];
@@ -239,17 +276,24 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int f
   if (t >= count) return;
   const int q = first + t;
   const size_t vs = L.vs;
-  const int o0 = lst.off[q], o1 = lst.off[q + 1];
+  const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double r[3] = {0.0, 0.0, 0.0};
-  for (int o = o0; o < o1; ++o) {
-    const UCell* cs;
-    int m;
-    const long sl = occ_point(L, lst.occ[o], e, cs, m);
-    if (sl < 0) continue;
-    const double a = cs->A[m][e], pe = x[3 * vs + sl];
-    r[0] += a * x[sl] + cs->BT[m][e][0] * pe;
-    r[1] += a * x[vs + sl] + cs->BT[m][e][1] * pe;
-    r[2] += a * x[2 * vs + sl] + cs->BT[m][e][2] * pe;
+  const int ew = e < kUPoints ? e : 0;
+  for (int base = 0; base < no; base += kIfGroup) {
+    const OccRec mine = occ_record(L, lst, o0, no, base + e);
+    const int cnt = min(kIfGroup, no - base);
+    for (int u = 0; u < cnt; ++u) {
+      const OccRec rc = occ_share(mine, u);
+      bool ok;
+      const long sl = occ_slot(L, rc, e, ok);
+      const double z = ok ? 1.0 : 0.0;
+      const UCell* cs = L.cs + rc.cell;
+      const int m = rc.m;
+      const double a = z * cs->A[m][ew], pe = x[3 * vs + sl];
+      r[0] += a * x[sl] + (z * cs->BT[m][ew][0]) * pe;
+      r[1] += a * x[vs + sl] + (z * cs->BT[m][ew][1]) * pe;
+      r[2] += a * x[2 * vs + sl] + (z * cs->BT[m][ew][2]) * pe;
+    }
   }
   const size_t own = occ_centre(L, lst.occ[o0]);
   const double ai = lst.ainv[q];
@@ -299,31 +343,47 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_inner(ULev Lf, ULev Lc, 
 // Restriction at coarse interface nodes: the fine node at 2 q, plus half of
 // every fine midpoint next to it, each midpoint taken once (from the cell
 // that owns the primitive it lies on); fine Dirichlet velocity values count
-// as zero and the coarse Dirichlet velocity rows are zero.
+// as zero and the coarse Dirichlet velocity rows are zero.  16 lanes per
+// node, lane e the midpoint in direction e of every occurrence, occurrence
+// records in batches as in the interface rows above.
 __global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, UList lst,
                                                               const double* __restrict__ rf,
                                                               double* __restrict__ rc) {
-  const int q = blockIdx.x * kUBlock + threadIdx.x;
+  const int q = blockIdx.x * kIfNodes + (threadIdx.x / kIfGroup), e = threadIdx.x % kIfGroup;
   if (q >= lst.n) return;
   const int nc = Lc.n, nf = Lf.n;
-  const int o0 = lst.off[q], o1 = lst.off[q + 1];
+  const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int o = o0; o < o1; ++o) {
-    const int2 oc = lst.occ[o];
-    int i, j, k;
-    unpack(oc.y, i, j, k);
-    const int m = uclass(i, j, k, nc);
-    const UCell* cs = Lf.cs + oc.x;
-    const unsigned ins = cs->inside[m];
-    const size_t base = (size_t)oc.x * Lf.P;
-    const int c0 = uslot(2 * i, 2 * j, 2 * k, nf);
-#pragma unroll
-    for (int e = 1; e < kUPoints; ++e) {
-      const int I = 2 * i + udir(e, 0), J = 2 * j + udir(e, 1), K = 2 * k + udir(e, 2);
+  const bool lane_pt = e >= 1 && e < kUPoints;
+  const int ee = lane_pt ? e : 1;
+  for (int base = 0; base < no; base += kIfGroup) {
+    // record of occurrence base + e: cell, coarse point, and the fine cell's
+    // inside mask of the coarse class, ownership and Dirichlet masks
+    int mc = 0, mp = 0;
+    unsigned mi = 0u, mo = 0u, mb = 0u;
+    if (base + e < no) {
+      const int2 oc = lst.occ[o0 + base + e];
+      int i, j, k;
+      unpack(oc.y, i, j, k);
+      const UCell* cs = Lf.cs + oc.x;
+      mc = oc.x;
+      mp = oc.y;
+      mi = cs->inside[uclass(i, j, k, nc)];
+      mo = cs->owned;
+      mb = cs->bnd;
+    }
+    const int cnt = min(kIfGroup, no - base);
+    for (int u = 0; u < cnt; ++u) {
+      const int cell = __shfl(mc, u, kIfGroup), pt = __shfl(mp, u, kIfGroup);
+      const unsigned ins = (unsigned)__shfl((int)mi, u, kIfGroup), own = (unsigned)__shfl((int)mo, u, kIfGroup),
+                     bnd = (unsigned)__shfl((int)mb, u, kIfGroup);
+      int i, j, k;
+      unpack(pt, i, j, k);
+      const int I = 2 * i + udir(ee, 0), J = 2 * j + udir(ee, 1), K = 2 * k + udir(ee, 2);
       const int mf = uclass(I, J, K, nf);
-      const bool take = ((ins >> e) & 1) && ((cs->owned >> mf) & 1);
-      const size_t sl = base + (take ? uslot(I, J, K, nf) : c0);
-      const bool fd = (cs->bnd >> mf) & 1;
+      const bool take = lane_pt && ((ins >> e) & 1) && ((own >> mf) & 1);
+      const size_t sl = (size_t)cell * Lf.P + (take ? uslot(I, J, K, nf) : uslot(2 * i, 2 * j, 2 * k, nf));
+      const bool fd = (bnd >> mf) & 1;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const double v = rf[f * Lf.vs + sl];
@@ -331,13 +391,15 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, 
       }
     }
   }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) acc[f] = group_sum(acc[f]);
   int i, j, k;
   unpack(lst.occ[o0].y, i, j, k);
   const size_t fown = (size_t)lst.occ[o0].x * Lf.P + uslot(2 * i, 2 * j, 2 * k, nf);
   const bool dir = q >= lst.nfree;
   double out[4];
   for (int f = 0; f < 4; ++f) out[f] = (f < 3 && dir) ? 0.0 : rf[f * Lf.vs + fown] + acc[f];
-  for (int o = o0; o < o1; ++o) {
+  for (int o = o0 + e; o < o1; o += kIfGroup) {
     const int2 oc = lst.occ[o];
     unpack(oc.y, i, j, k);
     const size_t sl = (size_t)oc.x * Lc.P + uslot(i, j, k, nc);
@@ -561,7 +623,8 @@ void launch_u_restrict(hipStream_t s, const ULev& Lf, const ULev& Lc, USegs inne
     hipLaunchKernelGGL(k_u_restrict_inner, seg_grid(inner_c, Lc.ncell), dim3(kUBlock), 0, s, Lf, Lc, inner_c, rf,
                        rc);
   if (lst_c.n > 0)
-    hipLaunchKernelGGL(k_u_restrict_iface, dim3(ublocks(lst_c.n)), dim3(kUBlock), 0, s, Lf, Lc, lst_c, rf, rc);
+    hipLaunchKernelGGL(k_u_restrict_iface, dim3((unsigned)((lst_c.n + kIfNodes - 1) / kIfNodes)), dim3(kUBlock), 0, s,
+                       Lf, Lc, lst_c, rf, rc);
 }
 
 void launch_u_prolong(hipStream_t s, const ULev& Lc, const ULev& Lf, USegs all_f, const double* xc, double* xf,

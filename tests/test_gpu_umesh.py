@@ -233,8 +233,11 @@ def test_refusals(libs):
         assert hhg.hhg_mesh_info(mesh)[2] == -1
         with pytest.raises(hhg.HHGError):
             hhg.hhg_hier_create(mesh, hhg.HHG_P2P1, 0, 2)
-        with pytest.raises(hhg.HHGError):
-            hhg.hhg_mesh_set_outflow(mesh, 1)
+        with pytest.raises(hhg.HHGError) as e:
+            hhg.hhg_mesh_set_outflow(mesh, 63)                          # no Dirichlet face left
+        assert e.value.status == hhg.HHG_ERR_ARG
+        hhg.hhg_mesh_set_outflow(mesh, 1)                               # the x = 0 plane's triangles
+        hhg.hhg_mesh_set_outflow(mesh, 0)
     finally:
         hhg.hhg_mesh_destroy(mesh)
 
