@@ -698,7 +698,7 @@ void u_colour(hhg_hier h, int l, int c, double* x, const double* b) {
   ULevelData& U = UL(h, l);
   const int K = U.ncol_if;
   if (c < K)
-    launch_u_gs_iface(S(h), U.L, U.lst, U.col_off[c], U.col_off[c + 1] - U.col_off[c], x, b);
+    launch_u_gs_iface(S(h), U.L, U.lst, U.col_off[c], U.col_off[c + 1] - U.col_off[c], U.col_maxocc[c], x, b);
   else
     launch_u_gs_inner(S(h), U.L, U.colour[c - K], x, b);
 }

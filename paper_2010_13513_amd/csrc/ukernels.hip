@@ -8,6 +8,8 @@
 // stencil point: the row is the sum, over the cells containing the node, of
 // that cell's row of the node's class, and the result goes to every copy of
 // the node.
+#include <type_traits>
+
 #include "umesh.h"
 
 namespace hhg {
@@ -108,18 +110,23 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, con
   if (wp) y[3 * vs + t] = HB ? b[3 * vs + t] - yp : yp;
 }
 
-// Interface nodes: 16 lanes per node, lane e < 15 takes stencil point e of
-// every occurrence (cell) of the node; the lane sums are combined by shuffles
-// within the 16-lane group.  Points outside an occurrence's closed cell add
-// nothing.  (Face nodes follow each other in node order, so neighbouring
-// groups read neighbouring rows; one lane per node would leave most compute
-// units idle on the few thousand nodes of one colour.)
-constexpr int kIfGroup = 16;
-constexpr int kIfNodes = kUBlock / kIfGroup;
+// Interface nodes: a group of 16 SL lanes per node (SL = 1, 2 or 4 slots,
+// set per launch by the most occurrences of one of its nodes).  Lane l
+// takes stencil point e = l mod 16 (e < 15) of the node's occurrences (cells)
+// l / 16, l / 16 + SL, ...; the lane sums are combined by shuffles within
+// the group.  Points outside an occurrence's closed cell add nothing.  (Face
+// nodes follow each other in node order, so neighbouring groups read
+// neighbouring rows; one lane per node would leave most compute units idle
+// on the few thousand nodes of one colour, and a node in many cells -- the
+// vertices and edges of T_0 -- would walk them one after the other.)
+constexpr int kIfPts = 16;
 
+__host__ __device__ constexpr int if_nodes(int sl) { return kUBlock / (kIfPts * sl); }
+
+template <int GW>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-  for (int off = kIfGroup / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kIfGroup);
+  for (int off = GW / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, GW);
   return v;
 }
 __device__ __forceinline__ size_t occ_centre(const ULev& L, int2 oc) {
@@ -127,12 +134,13 @@ __device__ __forceinline__ size_t occ_centre(const ULev& L, int2 oc) {
   unpack(oc.y, i, j, k);
   return (size_t)oc.x * L.P + uslot(i, j, k, L.n);
 }
-// The occurrences of a node are taken in batches of 16: lane l of the
+// The occurrences of a node are taken in batches of 16 SL: lane l of the
 // node's group loads the record of occurrence base + l (cell, packed point,
-// class, the class's inside mask), then the group walks the batch in order
-// with the records passed round by shuffles.  The loads of one occurrence
-// then depend on no load of another, and a node in many cells costs one
-// batch of round trips instead of a chain of three per occurrence.
+// class, the class's inside mask), then the group walks the batch in order,
+// SL occurrences at a time, with the records passed round by shuffles.  The
+// loads of one occurrence then depend on no load of another, and a node in
+// many cells costs one batch of round trips instead of a chain of three per
+// occurrence.
 struct OccRec {
   int cell, pt, m;
   unsigned in;
@@ -150,40 +158,42 @@ __device__ __forceinline__ OccRec occ_record(const ULev& L, const UList& lst, in
   }
   return r;
 }
+template <int GW>
 __device__ __forceinline__ OccRec occ_share(const OccRec& r, int u) {
-  return OccRec{__shfl(r.cell, u, kIfGroup), __shfl(r.pt, u, kIfGroup), __shfl(r.m, u, kIfGroup),
-                (unsigned)__shfl((int)r.in, u, kIfGroup)};
+  return OccRec{__shfl(r.cell, u, GW), __shfl(r.pt, u, GW), __shfl(r.m, u, GW), (unsigned)__shfl((int)r.in, u, GW)};
 }
-// Stencil point e of occurrence r: ok (inside the closed cell) and its slot;
-// outside, the slot of the centre (a valid address whose words are then
-// weighted by zero) -- no branch, so the loads of consecutive occurrences
-// can be in flight together.
-__device__ __forceinline__ long occ_slot(const ULev& L, const OccRec& r, int e, bool& ok) {
-  ok = e < kUPoints && ((r.in >> e) & 1u);
+// Stencil point e of occurrence r: ok (a real occurrence and the point
+// inside its closed cell) and its slot; otherwise the slot of the centre (a
+// valid address whose words are then weighted by zero) -- no branch, so the
+// loads of consecutive occurrences can be in flight together.
+__device__ __forceinline__ long occ_slot(const ULev& L, const OccRec& r, int e, bool real, bool& ok) {
+  ok = real && e < kUPoints && ((r.in >> e) & 1u);
   const int ee = ok ? e : 0;
   int i, j, k;
   unpack(r.pt, i, j, k);
   return (long)r.cell * L.P + uslot(i + udir(ee, 0), j + udir(ee, 1), k + udir(ee, 2), L.n);
 }
 
-template <bool HB, bool MASS>
+template <bool HB, bool MASS, int SL>
 __global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, const double* __restrict__ x,
                                                            const double* __restrict__ b, double* __restrict__ y,
                                                            int opmask, int wv, int wp) {
-  const int q = blockIdx.x * kIfNodes + (threadIdx.x / kIfGroup), e = threadIdx.x % kIfGroup;
+  constexpr int GW = kIfPts * SL;
+  const int q = blockIdx.x * if_nodes(SL) + (threadIdx.x / GW), l = threadIdx.x % GW, e = l % kIfPts;
   if (q >= lst.n) return;
   const size_t vs = L.vs;
   const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, bp[3] = {0.0, 0.0, 0.0}, cp = 0.0;
   const bool dA = opmask & 1, dBT = opmask & 2, dB = opmask & 4, dC = opmask & 24;
   const int ew = e < kUPoints ? e : 0;  // weight column of the lane (lane 15: weighted by zero)
-  for (int base = 0; base < no; base += kIfGroup) {
-    const OccRec mine = occ_record(L, lst, o0, no, base + e);
-    const int cnt = min(kIfGroup, no - base);
-    for (int u = 0; u < cnt; ++u) {
-      const OccRec r = occ_share(mine, u);
+  for (int base = 0; base < no; base += GW) {
+    const OccRec mine = occ_record(L, lst, o0, no, base + l);
+    const int cnt = min(GW, no - base);
+    for (int u0 = 0; u0 < cnt; u0 += SL) {
+      const int u = u0 + l / kIfPts;
+      const OccRec r = occ_share<GW>(mine, u);
       bool ok;
-      const long sl = occ_slot(L, r, e, ok);
+      const long sl = occ_slot(L, r, e, u < cnt, ok);
       const double z = ok ? 1.0 : 0.0;
       const UCell* cs = L.cs + r.cell;
       const int m = r.m;
@@ -217,17 +227,17 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, co
   double out[4];
   const size_t own = occ_centre(L, lst.occ[o0]);
   if (MASS) {
-    for (int f = 0; f < 4; ++f) out[f] = group_sum(acc[f]);
+    for (int f = 0; f < 4; ++f) out[f] = group_sum<GW>(acc[f]);
   } else {
     const bool dir = q >= lst.nfree;
     for (int d = 0; d < 3; ++d) {
-      const double v = group_sum(acc[d] + bp[d]);
+      const double v = group_sum<GW>(acc[d] + bp[d]);
       out[d] = dir ? 0.0 : (HB ? b[d * vs + own] - v : v);
     }
-    const double yp = group_sum(acc[3] + ((opmask & 16) ? cp : -cp));
+    const double yp = group_sum<GW>(acc[3] + ((opmask & 16) ? cp : -cp));
     out[3] = HB ? b[3 * vs + own] - yp : yp;
   }
-  for (int o = o0 + e; o < o1; o += kIfGroup) {
+  for (int o = o0 + l; o < o1; o += GW) {
     const size_t sl = occ_centre(L, lst.occ[o]);
     if (MASS || wv)
       for (int d = 0; d < 3; ++d) y[d * vs + sl] = out[d];
@@ -267,25 +277,29 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double
   for (int d = 0; d < 3; ++d) x[d * vs + t] += r[d] * ai;
 }
 
-// Free interface nodes [first, first + count) of one colour, 16 lanes per
-// node as in k_u_apply_iface.  Every lane of a group reads the node's old
-// value before any lane writes a copy (one wavefront, program order).
+// Free interface nodes [first, first + count) of one colour, a group of
+// 16 SL lanes per node as in k_u_apply_iface.  Every lane of a group reads the
+// node's old value before any lane writes a copy (one wavefront, program
+// order).
+template <int SL>
 __global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int first, int count,
                                                         double* __restrict__ x, const double* __restrict__ b) {
-  const int t = blockIdx.x * kIfNodes + (threadIdx.x / kIfGroup), e = threadIdx.x % kIfGroup;
+  constexpr int GW = kIfPts * SL;
+  const int t = blockIdx.x * if_nodes(SL) + (threadIdx.x / GW), l = threadIdx.x % GW, e = l % kIfPts;
   if (t >= count) return;
   const int q = first + t;
   const size_t vs = L.vs;
   const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double r[3] = {0.0, 0.0, 0.0};
   const int ew = e < kUPoints ? e : 0;
-  for (int base = 0; base < no; base += kIfGroup) {
-    const OccRec mine = occ_record(L, lst, o0, no, base + e);
-    const int cnt = min(kIfGroup, no - base);
-    for (int u = 0; u < cnt; ++u) {
-      const OccRec rc = occ_share(mine, u);
+  for (int base = 0; base < no; base += GW) {
+    const OccRec mine = occ_record(L, lst, o0, no, base + l);
+    const int cnt = min(GW, no - base);
+    for (int u0 = 0; u0 < cnt; u0 += SL) {
+      const int u = u0 + l / kIfPts;
+      const OccRec rc = occ_share<GW>(mine, u);
       bool ok;
-      const long sl = occ_slot(L, rc, e, ok);
+      const long sl = occ_slot(L, rc, e, u < cnt, ok);
       const double z = ok ? 1.0 : 0.0;
       const UCell* cs = L.cs + rc.cell;
       const int m = rc.m;
@@ -298,8 +312,8 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int f
   const size_t own = occ_centre(L, lst.occ[o0]);
   const double ai = lst.ainv[q];
   double v[3];
-  for (int d = 0; d < 3; ++d) v[d] = x[d * vs + own] + (b[d * vs + own] - group_sum(r[d])) * ai;
-  for (int o = o0 + e; o < o1; o += kIfGroup) {
+  for (int d = 0; d < 3; ++d) v[d] = x[d * vs + own] + (b[d * vs + own] - group_sum<GW>(r[d])) * ai;
+  for (int o = o0 + l; o < o1; o += GW) {
     const size_t sl = occ_centre(L, lst.occ[o]);
     for (int d = 0; d < 3; ++d) x[d * vs + sl] = v[d];
   }
@@ -343,26 +357,29 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_inner(ULev Lf, ULev Lc, 
 // Restriction at coarse interface nodes: the fine node at 2 q, plus half of
 // every fine midpoint next to it, each midpoint taken once (from the cell
 // that owns the primitive it lies on); fine Dirichlet velocity values count
-// as zero and the coarse Dirichlet velocity rows are zero.  16 lanes per
-// node, lane e the midpoint in direction e of every occurrence, occurrence
-// records in batches as in the interface rows above.
+// as zero and the coarse Dirichlet velocity rows are zero.  A group of 16 SL
+// lanes per node, lane l the midpoint in direction l mod 16 of the node's
+// occurrences l / 16, l / 16 + SL, ..., records in batches as in the
+// interface rows above.
+template <int SL>
 __global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, UList lst,
                                                               const double* __restrict__ rf,
                                                               double* __restrict__ rc) {
-  const int q = blockIdx.x * kIfNodes + (threadIdx.x / kIfGroup), e = threadIdx.x % kIfGroup;
+  constexpr int GW = kIfPts * SL;
+  const int q = blockIdx.x * if_nodes(SL) + (threadIdx.x / GW), l = threadIdx.x % GW, e = l % kIfPts;
   if (q >= lst.n) return;
   const int nc = Lc.n, nf = Lf.n;
   const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const bool lane_pt = e >= 1 && e < kUPoints;
   const int ee = lane_pt ? e : 1;
-  for (int base = 0; base < no; base += kIfGroup) {
-    // record of occurrence base + e: cell, coarse point, and the fine cell's
+  for (int base = 0; base < no; base += GW) {
+    // record of occurrence base + l: cell, coarse point, and the fine cell's
     // inside mask of the coarse class, ownership and Dirichlet masks
     int mc = 0, mp = 0;
     unsigned mi = 0u, mo = 0u, mb = 0u;
-    if (base + e < no) {
-      const int2 oc = lst.occ[o0 + base + e];
+    if (base + l < no) {
+      const int2 oc = lst.occ[o0 + base + l];
       int i, j, k;
       unpack(oc.y, i, j, k);
       const UCell* cs = Lf.cs + oc.x;
@@ -372,16 +389,17 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, 
       mo = cs->owned;
       mb = cs->bnd;
     }
-    const int cnt = min(kIfGroup, no - base);
-    for (int u = 0; u < cnt; ++u) {
-      const int cell = __shfl(mc, u, kIfGroup), pt = __shfl(mp, u, kIfGroup);
-      const unsigned ins = (unsigned)__shfl((int)mi, u, kIfGroup), own = (unsigned)__shfl((int)mo, u, kIfGroup),
-                     bnd = (unsigned)__shfl((int)mb, u, kIfGroup);
+    const int cnt = min(GW, no - base);
+    for (int u0 = 0; u0 < cnt; u0 += SL) {
+      const int u = u0 + l / kIfPts;
+      const int cell = __shfl(mc, u, GW), pt = __shfl(mp, u, GW);
+      const unsigned ins = (unsigned)__shfl((int)mi, u, GW), own = (unsigned)__shfl((int)mo, u, GW),
+                     bnd = (unsigned)__shfl((int)mb, u, GW);
       int i, j, k;
       unpack(pt, i, j, k);
       const int I = 2 * i + udir(ee, 0), J = 2 * j + udir(ee, 1), K = 2 * k + udir(ee, 2);
       const int mf = uclass(I, J, K, nf);
-      const bool take = lane_pt && ((ins >> e) & 1) && ((own >> mf) & 1);
+      const bool take = u < cnt && lane_pt && ((ins >> e) & 1) && ((own >> mf) & 1);
       const size_t sl = (size_t)cell * Lf.P + (take ? uslot(I, J, K, nf) : uslot(2 * i, 2 * j, 2 * k, nf));
       const bool fd = (bnd >> mf) & 1;
 #pragma unroll
@@ -392,14 +410,14 @@ __global__ void __launch_bounds__(kUBlock) k_u_restrict_iface(ULev Lf, ULev Lc, 
     }
   }
 #pragma unroll
-  for (int f = 0; f < 4; ++f) acc[f] = group_sum(acc[f]);
+  for (int f = 0; f < 4; ++f) acc[f] = group_sum<GW>(acc[f]);
   int i, j, k;
   unpack(lst.occ[o0].y, i, j, k);
   const size_t fown = (size_t)lst.occ[o0].x * Lf.P + uslot(2 * i, 2 * j, 2 * k, nf);
   const bool dir = q >= lst.nfree;
   double out[4];
   for (int f = 0; f < 4; ++f) out[f] = (f < 3 && dir) ? 0.0 : rf[f * Lf.vs + fown] + acc[f];
-  for (int o = o0 + e; o < o1; o += kIfGroup) {
+  for (int o = o0 + l; o < o1; o += GW) {
     const int2 oc = lst.occ[o];
     unpack(oc.y, i, j, k);
     const size_t sl = (size_t)oc.x * Lc.P + uslot(i, j, k, nc);
@@ -568,6 +586,20 @@ constexpr int kUPartials = 512;
 
 }  // namespace
 
+// Interface launch over n nodes: occurrence slots per node from the most
+// occurrences of one node (1: 16 lanes, 2: 32, more: 64, one wavefront),
+// f(std::integral_constant<int, SL>, grid).
+template <typename F>
+void if_launch(int maxocc, int n, F&& f) {
+  auto grid = [n](int sl) { return dim3((unsigned)((n + if_nodes(sl) - 1) / if_nodes(sl))); };
+  if (maxocc <= 1)
+    f(std::integral_constant<int, 1>{}, grid(1));
+  else if (maxocc <= 2)
+    f(std::integral_constant<int, 2>{}, grid(2));
+  else
+    f(std::integral_constant<int, 4>{}, grid(4));
+}
+
 void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList& lst, const double* x,
                          const double* b, double* y, int opmask, bool has_b, bool mass, bool wv, bool wp) {
   if (inner.n > 0) {
@@ -584,15 +616,17 @@ void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList&
   }
   if (lst.n > 0) {
     KScope ks(s, KF_IFACE, (double)lst.n);
-    const dim3 g((unsigned)((lst.n + kIfNodes - 1) / kIfNodes));
-    if (mass)
-      hipLaunchKernelGGL((k_u_apply_iface<false, true>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, 1, 1);
-    else if (has_b)
-      hipLaunchKernelGGL((k_u_apply_iface<true, false>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, (int)wv,
-                         (int)wp);
-    else
-      hipLaunchKernelGGL((k_u_apply_iface<false, false>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, (int)wv,
-                         (int)wp);
+    if_launch(lst.maxocc, lst.n, [&](auto sl, dim3 g) {
+      constexpr int SL = decltype(sl)::value;
+      if (mass)
+        hipLaunchKernelGGL((k_u_apply_iface<false, true, SL>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask, 1, 1);
+      else if (has_b)
+        hipLaunchKernelGGL((k_u_apply_iface<true, false, SL>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask,
+                           (int)wv, (int)wp);
+      else
+        hipLaunchKernelGGL((k_u_apply_iface<false, false, SL>), g, dim3(kUBlock), 0, s, L, lst, x, b, y, opmask,
+                           (int)wv, (int)wp);
+    });
   }
 }
 
@@ -602,12 +636,13 @@ void launch_u_gs_inner(hipStream_t s, const ULev& L, USegs seg, double* x, const
   hipLaunchKernelGGL(k_u_gs_inner, seg_grid(seg, L.ncell), dim3(kUBlock), 0, s, L, seg, x, b);
 }
 
-void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first, int count, double* x,
+void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first, int count, int maxocc, double* x,
                        const double* b) {
   if (count <= 0) return;
   KScope ks(s, KF_IFACE, (double)count);
-  hipLaunchKernelGGL(k_u_gs_iface, dim3((unsigned)((count + kIfNodes - 1) / kIfNodes)), dim3(kUBlock), 0, s, L, lst,
-                     first, count, x, b);
+  if_launch(maxocc, count, [&](auto sl, dim3 g) {
+    hipLaunchKernelGGL((k_u_gs_iface<decltype(sl)::value>), g, dim3(kUBlock), 0, s, L, lst, first, count, x, b);
+  });
 }
 
 void launch_u_pstep(hipStream_t s, const ULev& L, const double* dinv, double* x, const double* r, double omega) {
@@ -623,8 +658,9 @@ void launch_u_restrict(hipStream_t s, const ULev& Lf, const ULev& Lc, USegs inne
     hipLaunchKernelGGL(k_u_restrict_inner, seg_grid(inner_c, Lc.ncell), dim3(kUBlock), 0, s, Lf, Lc, inner_c, rf,
                        rc);
   if (lst_c.n > 0)
-    hipLaunchKernelGGL(k_u_restrict_iface, dim3((unsigned)((lst_c.n + kIfNodes - 1) / kIfNodes)), dim3(kUBlock), 0, s,
-                       Lf, Lc, lst_c, rf, rc);
+    if_launch(lst_c.maxocc, lst_c.n, [&](auto sl, dim3 g) {
+      hipLaunchKernelGGL((k_u_restrict_iface<decltype(sl)::value>), g, dim3(kUBlock), 0, s, Lf, Lc, lst_c, rf, rc);
+    });
 }
 
 void launch_u_prolong(hipStream_t s, const ULev& Lc, const ULev& Lf, USegs all_f, const double* xc, double* xf,

@@ -74,6 +74,7 @@ struct UList {
   const int2* occ;
   const double* ainv;  // 1 / assembled A diagonal, free nodes
   int nfree, n;
+  int maxocc;          // most occurrences of one node
 };
 
 // Row segments (i0, j, k, count) of up to lps points, one lane per point
@@ -92,6 +93,7 @@ struct ULevelData {
   int nnodes = 0;
   int ncol_if = 0;               // interface colours K (colours K..K+3: cell interiors)
   std::vector<int> col_off;      // K + 1 offsets into the free interface nodes
+  std::vector<int> col_maxocc;   // per interface colour: most occurrences of one of its nodes
   UList lst{};
   USegs all{}, inner{}, colour[4]{};
   double* dinv = nullptr;        // per slot: 1 / Schur diagonal of its node
@@ -113,7 +115,9 @@ struct ULevelData {
 void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList& lst, const double* x,
                          const double* b, double* y, int opmask, bool has_b, bool mass, bool wv, bool wp);
 void launch_u_gs_inner(hipStream_t s, const ULev& L, USegs seg, double* x, const double* b);
-void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first, int count, double* x,
+// Free interface nodes [first, first + count) of one colour; maxocc: the
+// most occurrences of one of them (sets the lanes per node).
+void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first, int count, int maxocc, double* x,
                        const double* b);
 void launch_u_pstep(hipStream_t s, const ULev& L, const double* dinv, double* x, const double* r, double omega);
 void launch_u_restrict(hipStream_t s, const ULev& Lf, const ULev& Lc, USegs inner_c, const UList& lst_c,
