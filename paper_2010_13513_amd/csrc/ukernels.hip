@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, con
 constexpr int kIfPts = 16;
 
 __host__ __device__ constexpr int if_nodes(int sl) { return kUBlock / (kIfPts * sl); }
+constexpr int kIfManyNodes = 8192;  // see if_launch
 
 template <int GW>
 __device__ __forceinline__ double group_sum(double v) {
@@ -588,13 +589,17 @@ constexpr int kUPartials = 512;
 
 // Interface launch over n nodes: occurrence slots per node from the most
 // occurrences of one node (1: 16 lanes, 2: 32, more: 64, one wavefront),
-// f(std::integral_constant<int, SL>, grid).
+// f(std::integral_constant<int, SL>, grid).  Launches of many nodes are
+// mostly face nodes (2 cells) and throughput-bound: 2 slots, whatever a few
+// edge and vertex nodes of T_0 need (cube benchmark, interface rows of a
+// level-7 apply: 4 slots 0.374 ms, 2 slots 0.245 ms; the level-6 FMG solve
+// 26.9 -> 26.4 ms with this rule at 8192 nodes, 26.5 at 4096, 26.6 at 32768).
 template <typename F>
 void if_launch(int maxocc, int n, F&& f) {
   auto grid = [n](int sl) { return dim3((unsigned)((n + if_nodes(sl) - 1) / if_nodes(sl))); };
   if (maxocc <= 1)
     f(std::integral_constant<int, 1>{}, grid(1));
-  else if (maxocc <= 2)
+  else if (maxocc <= 2 || n >= kIfManyNodes)
     f(std::integral_constant<int, 2>{}, grid(2));
   else
     f(std::integral_constant<int, 4>{}, grid(4));
