@@ -820,7 +820,7 @@ def bench_umesh(torch, hhg, dev, stream, ctx, args, L=6):
     fams = {hhg.KF_APPLY: "cell_interior_rows", hhg.KF_IFACE: "interface_nodes",
             hhg.KF_GS_VERTEX: "gs_interior_colour", hhg.KF_PSTEP: "uzawa_pressure_step",
             hhg.KF_RESTRICT: "restrict", hhg.KF_PROLONG: "prolong", hhg.KF_COARSE: "coarse_gemv",
-            hhg.KF_REDUCE: "reductions", hhg.KF_OTHER: "other"}
+            hhg.KF_REDUCE: "reductions", hhg.KF_OTHER: "other", hhg.KF_SMALL: "one_workgroup_smoothing"}
     rsteps = max(2, min(args.steps, 5))
     hhg.hhg_timer_start(sum(1 << f for f in fams))
     for _ in range(rsteps):

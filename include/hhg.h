@@ -417,7 +417,11 @@ hhg_status hhg_coarse_pair(hhg_hier h, const double* r, float* features, float* 
  * level vectors held in LDS when the levels up to the top fit in 128 KB.
  * Applies to V-cycles with the exact coarse solve (not with a network
  * attached, the recorder on or coarse_smooth > 0).  Default 800; 0 turns it
- * off. */
+ * off.  On an unstructured macro mesh the same bound is on a level's slots
+ * (cells times points per cell) and applies to every smoothing call
+ * (hhg_smooth and the smoothing inside cycles): one workgroup runs the whole
+ * call, every value computed as by the per-colour launches; default 300
+ * (the cube benchmark's level 1), meshes of at most 64 cells. */
 hhg_status hhg_hier_set_fused_sites(hhg_hier h, long max_sites);
 /* Not in the paper: bfloat16 storage on the coarse levels of float32
  * cycles.  The n coarsest levels (lmin .. lmin + n - 1, 0 <= n <= number of

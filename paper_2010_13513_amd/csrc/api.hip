@@ -136,6 +136,14 @@ struct hhg_ctx_s {
 constexpr size_t kScratchEpochs = 4096;
 constexpr size_t kScratchOrder = (size_t)1 << 21;
 constexpr size_t kScratchBytes = kScratchEpochs * sizeof(double) + kScratchOrder * sizeof(int);
+// Default bound of the one-workgroup smoothing calls on unstructured meshes
+// (slots of a level; hhg_hier_set_fused_sites).  An interface node's update
+// is three dependent round trips (records, rows, own value), so one
+// workgroup only wins where a colour is a single pass of its threads: on
+// the cube benchmark (24 cells) level 1 (240 slots) gains, level 2 (840)
+// loses (FMG solve: off 26.4 ms, up to level 1 25.8, up to level 2 28.2,
+// up to level 3 47.6).
+constexpr long kUFusedSlots = 300;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 // Macro mesh T_0 (host data): vertex coordinates, tetrahedra, and the number
@@ -187,6 +195,9 @@ struct hhg_hier_s {
   hhg::SmallLevel<float>* slv32 = nullptr;
   bool slv_stale = true;
   long fused_sites = 800;
+  // unstructured meshes: levels with at most ufused_slots slots (cells times
+  // points per cell) run each smoothing call in one workgroup (0: never)
+  long ufused_slots = kUFusedSlots;
   std::vector<int> lds_end64, lds_end32;  // LDS words of levels lmin..l (0: level not in LDS)
   // levels lmin .. lmin + bf16_levels - 1 hold bfloat16 values in their
   // float32 vectors (hhg_hier_set_bf16_levels)
@@ -706,6 +717,9 @@ void u_smooth(hhg_hier h, int l, double* x, const double* b, int iters, int gs, 
   ULevelData& U = UL(h, l);
   const int ncol = U.ncol_if + 4;
   double* r = h->L(l).r;
+  if ((long)U.L.ncell * U.L.P <= h->ufused_slots &&
+      launch_u_smooth_small(S(h), U, x, b, r, iters, xi, gs == HHG_GS_SYM, omega))
+    return;
   for (int it = 0; it < iters; ++it) {
     for (int s = 0; s < xi; ++s) {
       for (int c = 0; c < ncol; ++c) u_colour(h, l, c, x, b);
@@ -2270,6 +2284,7 @@ hhg_status hhg_hier_set_fused_sites(hhg_hier h, long max_sites) {
   return guard([&] {
     HHG_REQUIRE(h && max_sites >= 0, HHG_ERR_ARG, "bad arguments");
     h->fused_sites = max_sites;
+    h->ufused_slots = max_sites;
     if (h->fmg_exec) {  // a captured solve holds the old launch sequence
       HHG_CHECK_HIP(hipGraphExecDestroy(h->fmg_exec));
       h->fmg_exec = nullptr;

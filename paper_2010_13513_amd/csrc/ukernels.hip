@@ -47,19 +47,13 @@ __device__ __forceinline__ void stage_inner(const UCell* __restrict__ cs, double
 // ------------------------------------------------------------------ apply
 // opmask bits: 1 A, 2 B^T, 4 B, 8 C, 16 C with + sign (the C block alone);
 // wv / wp: write the velocity / pressure rows.
+// Interior point (i, j, k) of cell c, its rows w (class 0, staged in LDS).
 template <bool HB, bool MASS>
-__global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, const double* __restrict__ x,
-                                                           const double* __restrict__ b, double* __restrict__ y,
-                                                           int opmask, int wv, int wp) {
-  __shared__ double w[8][kUPoints];
-  const int c = blockIdx.y;
-  const UCell* cs = L.cs + c;
-  stage_inner(cs, w);
-  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
-  if (sid >= sg.n) return;
-  const int4 s = sg.s[sid];
-  if (lane >= s.w) return;
-  const int n = L.n, i = s.x + lane, j = s.y, k = s.z;
+__device__ __forceinline__ void apply_inner_pt(const ULev& L, int c, const double (*w)[kUPoints], double cf, int i,
+                                               int j, int k, const double* __restrict__ x,
+                                               const double* __restrict__ b, double* __restrict__ y, int opmask,
+                                               int wv, int wp) {
+  const int n = L.n;
   int off[kUPoints];
   offsets(i, j, k, n, off);
   const size_t t = (size_t)c * L.P + uslot(i, j, k, n);
@@ -99,7 +93,6 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, con
       if (dC) cp += w[0][e] * pe;
     }
   }
-  const double cf = cs->cfac;
   const double yp = bu + ((opmask & 16) ? cf * cp : -(cf * cp));
   if (wv)
 #pragma unroll
@@ -108,6 +101,21 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, con
       y[d * vs + t] = HB ? b[d * vs + t] - v : v;
     }
   if (wp) y[3 * vs + t] = HB ? b[3 * vs + t] - yp : yp;
+}
+
+template <bool HB, bool MASS>
+__global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, const double* __restrict__ x,
+                                                           const double* __restrict__ b, double* __restrict__ y,
+                                                           int opmask, int wv, int wp) {
+  __shared__ double w[8][kUPoints];
+  const int c = blockIdx.y;
+  const UCell* cs = L.cs + c;
+  stage_inner(cs, w);
+  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
+  if (sid >= sg.n) return;
+  const int4 s = sg.s[sid];
+  if (lane >= s.w) return;
+  apply_inner_pt<HB, MASS>(L, c, w, cs->cfac, s.x + lane, s.y, s.z, x, b, y, opmask, wv, wp);
 }
 
 // Interface nodes: a group of 16 SL lanes per node (SL = 1, 2 or 4 slots,
@@ -175,13 +183,14 @@ __device__ __forceinline__ long occ_slot(const ULev& L, const OccRec& r, int e, 
   return (long)r.cell * L.P + uslot(i + udir(ee, 0), j + udir(ee, 1), k + udir(ee, 2), L.n);
 }
 
+// Rows of interface node q, lane l of its group of 16 SL lanes (the whole
+// group calls it).
 template <bool HB, bool MASS, int SL>
-__global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, const double* __restrict__ x,
-                                                           const double* __restrict__ b, double* __restrict__ y,
-                                                           int opmask, int wv, int wp) {
+__device__ __forceinline__ void apply_iface_node(const ULev& L, const UList& lst, int q, int l,
+                                                 const double* __restrict__ x, const double* __restrict__ b,
+                                                 double* __restrict__ y, int opmask, int wv, int wp) {
   constexpr int GW = kIfPts * SL;
-  const int q = blockIdx.x * if_nodes(SL) + (threadIdx.x / GW), l = threadIdx.x % GW, e = l % kIfPts;
-  if (q >= lst.n) return;
+  const int e = l % kIfPts;
   const size_t vs = L.vs;
   const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, bp[3] = {0.0, 0.0, 0.0}, cp = 0.0;
@@ -246,20 +255,22 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, co
   }
 }
 
+template <bool HB, bool MASS, int SL>
+__global__ void __launch_bounds__(kUBlock) k_u_apply_iface(ULev L, UList lst, const double* __restrict__ x,
+                                                           const double* __restrict__ b, double* __restrict__ y,
+                                                           int opmask, int wv, int wp) {
+  constexpr int GW = kIfPts * SL;
+  const int q = blockIdx.x * if_nodes(SL) + (threadIdx.x / GW);
+  if (q >= lst.n) return;
+  apply_iface_node<HB, MASS, SL>(L, lst, q, threadIdx.x % GW, x, b, y, opmask, wv, wp);
+}
+
 // ----------------------------------------------------------- Gauss-Seidel
 // One interior colour: points (i, j, k) of the cell interiors with i + j + k
 // = colour (mod 4), segments of stride 4; u_d += (f_d - A u_d - B^T_d p) / a_00.
-__global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double* __restrict__ x,
-                                                        const double* __restrict__ b) {
-  __shared__ double w[8][kUPoints];
-  const int c = blockIdx.y;
-  const UCell* cs = L.cs + c;
-  stage_inner(cs, w);
-  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
-  if (sid >= sg.n) return;
-  const int4 s = sg.s[sid];
-  if (lane >= s.w) return;
-  const int n = L.n, i = s.x + 4 * lane, j = s.y, k = s.z;
+__device__ __forceinline__ void gs_inner_pt(const ULev& L, int c, const double (*w)[kUPoints], double ai, int i,
+                                            int j, int k, double* __restrict__ x, const double* __restrict__ b) {
+  const int n = L.n;
   int off[kUPoints];
   offsets(i, j, k, n, off);
   const size_t t = (size_t)c * L.P + uslot(i, j, k, n);
@@ -273,9 +284,21 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double
     r[1] -= w[0][e] * x[vs + t + off[e]] + w[2][e] * pe;
     r[2] -= w[0][e] * x[2 * vs + t + off[e]] + w[3][e] * pe;
   }
-  const double ai = cs->ainv0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) x[d * vs + t] += r[d] * ai;
+}
+
+__global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double* __restrict__ x,
+                                                        const double* __restrict__ b) {
+  __shared__ double w[8][kUPoints];
+  const int c = blockIdx.y;
+  const UCell* cs = L.cs + c;
+  stage_inner(cs, w);
+  const int sid = blockIdx.x * (kUBlock / sg.lps) + threadIdx.x / sg.lps, lane = threadIdx.x % sg.lps;
+  if (sid >= sg.n) return;
+  const int4 s = sg.s[sid];
+  if (lane >= s.w) return;
+  gs_inner_pt(L, c, w, cs->ainv0, s.x + 4 * lane, s.y, s.z, x, b);
 }
 
 // Free interface nodes [first, first + count) of one colour, a group of
@@ -283,12 +306,10 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_inner(ULev L, USegs sg, double
 // node's old value before any lane writes a copy (one wavefront, program
 // order).
 template <int SL>
-__global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int first, int count,
-                                                        double* __restrict__ x, const double* __restrict__ b) {
+__device__ __forceinline__ void gs_iface_node(const ULev& L, const UList& lst, int q, int l, double* __restrict__ x,
+                                              const double* __restrict__ b) {
   constexpr int GW = kIfPts * SL;
-  const int t = blockIdx.x * if_nodes(SL) + (threadIdx.x / GW), l = threadIdx.x % GW, e = l % kIfPts;
-  if (t >= count) return;
-  const int q = first + t;
+  const int e = l % kIfPts;
   const size_t vs = L.vs;
   const int o0 = lst.off[q], o1 = lst.off[q + 1], no = o1 - o0;
   double r[3] = {0.0, 0.0, 0.0};
@@ -318,6 +339,15 @@ __global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int f
     const size_t sl = occ_centre(L, lst.occ[o]);
     for (int d = 0; d < 3; ++d) x[d * vs + sl] = v[d];
   }
+}
+
+template <int SL>
+__global__ void __launch_bounds__(kUBlock) k_u_gs_iface(ULev L, UList lst, int first, int count,
+                                                        double* __restrict__ x, const double* __restrict__ b) {
+  constexpr int GW = kIfPts * SL;
+  const int t = blockIdx.x * if_nodes(SL) + (threadIdx.x / GW);
+  if (t >= count) return;
+  gs_iface_node<SL>(L, lst, first + t, threadIdx.x % GW, x, b);
 }
 
 // p -= omega r_p dinv on every real slot (copies stay equal: same inputs).
@@ -578,6 +608,125 @@ __global__ void __launch_bounds__(kUBlock) k_u_sync(ULev L, UList lst, double* _
 }
 
 unsigned ublocks(long n) { return (unsigned)((n + kUBlock - 1) / kUBlock); }
+
+// ---------------------------------------------------------- small levels
+// One workgroup runs a whole smoothing call (iters Uzawa iterations, Sec.
+// 3.2) on a small level: the phases of the launch-per-colour path -- every
+// interface colour, then the four interior colours (xi sweeps, each also
+// reversed for the symmetric variant), the pressure residual rows, the
+// pressure step -- each a block-strided loop over the same per-node and
+// per-point functions with the same lanes per node, phases separated by
+// workgroup barriers, so every value is computed as there.  The cells'
+// interior rows are staged in LDS once.  On the small levels a launch per
+// phase is almost all launch latency.
+constexpr int kUSmall = 1024;
+constexpr int kUSmallCells = 64;  // LDS: 8 x 15 words per cell
+
+struct USmallArgs {
+  ULev L;
+  UList lst;
+  USegs inner, colour[4];
+  const int* col_off;  // K + 1 offsets of the interface colours
+  const int* col_sl;   // K occurrence slots per interface colour
+  int K, list_sl;      // list_sl: occurrence slots of the whole list (residual rows)
+  const double* dinv;
+  double omega;
+  int iters, xi, sym;
+};
+
+template <int SL>
+__device__ void small_gs_iface(const ULev& L, const UList& lst, int first, int count, double* __restrict__ x,
+                               const double* __restrict__ b) {
+  constexpr int GW = kIfPts * SL;
+  for (int t0 = 0; t0 < count; t0 += kUSmall / GW) {
+    const int t = t0 + (int)threadIdx.x / GW;
+    if (t < count) gs_iface_node<SL>(L, lst, first + t, (int)threadIdx.x % GW, x, b);
+  }
+}
+template <int SL>
+__device__ void small_presid_iface(const ULev& L, const UList& lst, const double* __restrict__ x,
+                                   const double* __restrict__ b, double* __restrict__ r) {
+  constexpr int GW = kIfPts * SL;
+  for (int t0 = 0; t0 < lst.n; t0 += kUSmall / GW) {
+    const int q = t0 + (int)threadIdx.x / GW;
+    if (q < lst.n) apply_iface_node<true, false, SL>(L, lst, q, (int)threadIdx.x % GW, x, b, r, 12, 0, 1);
+  }
+}
+
+__global__ void __launch_bounds__(kUSmall) k_u_smooth_small(USmallArgs a, double* __restrict__ x,
+                                                            const double* __restrict__ b, double* __restrict__ r) {
+  extern __shared__ double wall[];  // [cell][8][15]: A, B^T (3), B (3), M of class 0
+  const ULev& L = a.L;
+  const int ncell = L.ncell;
+  for (int t = threadIdx.x; t < ncell * 8 * kUPoints; t += kUSmall) {
+    const int c = t / (8 * kUPoints), q = (t / kUPoints) % 8, e = t % kUPoints;
+    const UCell* cs = L.cs + c;
+    double v;
+    if (q == 0) v = cs->A[0][e];
+    else if (q < 4) v = cs->BT[0][e][q - 1];
+    else if (q < 7) v = cs->B[0][e][q - 4];
+    else v = cs->M[0][e];
+    wall[t] = v;
+  }
+  __syncthreads();
+  auto rows = [&](int c) { return reinterpret_cast<const double(*)[kUPoints]>(wall + c * 8 * kUPoints); };
+  auto colour = [&](int c) {
+    if (c < a.K) {
+      const int first = a.col_off[c], count = a.col_off[c + 1] - first, sl = a.col_sl[c];
+      if (sl == 1)
+        small_gs_iface<1>(L, a.lst, first, count, x, b);
+      else if (sl == 2)
+        small_gs_iface<2>(L, a.lst, first, count, x, b);
+      else
+        small_gs_iface<4>(L, a.lst, first, count, x, b);
+    } else {
+      const USegs sg = a.colour[c - a.K];
+      const int lps = sg.lps, tot = ncell * sg.n;
+      for (int w0 = 0; w0 < tot; w0 += kUSmall / lps) {
+        const int w = w0 + (int)threadIdx.x / lps, lane = (int)threadIdx.x % lps;
+        if (w < tot) {
+          const int cc = w / sg.n;
+          const int4 s = sg.s[w - cc * sg.n];
+          if (lane < s.w) gs_inner_pt(L, cc, rows(cc), L.cs[cc].ainv0, s.x + 4 * lane, s.y, s.z, x, b);
+        }
+      }
+    }
+    __syncthreads();
+  };
+  const int ncol = a.K + 4;
+  for (int it = 0; it < a.iters; ++it) {
+    for (int sw = 0; sw < a.xi; ++sw) {
+      for (int c = 0; c < ncol; ++c) colour(c);
+      if (a.sym)
+        for (int c = ncol - 1; c >= 0; --c) colour(c);
+    }
+    // r_p = g - B u + C p: interior points and interface nodes (disjoint slots)
+    {
+      const USegs sg = a.inner;
+      const int lps = sg.lps, tot = ncell * sg.n;
+      for (int w0 = 0; w0 < tot; w0 += kUSmall / lps) {
+        const int w = w0 + (int)threadIdx.x / lps, lane = (int)threadIdx.x % lps;
+        if (w < tot) {
+          const int cc = w / sg.n;
+          const int4 s = sg.s[w - cc * sg.n];
+          if (lane < s.w)
+            apply_inner_pt<true, false>(L, cc, rows(cc), L.cs[cc].cfac, s.x + lane, s.y, s.z, x, b, r, 12, 0, 1);
+        }
+      }
+    }
+    if (a.list_sl == 1)
+      small_presid_iface<1>(L, a.lst, x, b, r);
+    else if (a.list_sl == 2)
+      small_presid_iface<2>(L, a.lst, x, b, r);
+    else
+      small_presid_iface<4>(L, a.lst, x, b, r);
+    __syncthreads();
+    // p -= omega r_p D^-1 on every slot
+    const long ns = (long)ncell * L.P;
+    for (long t = threadIdx.x; t < ns; t += kUSmall) x[3 * L.vs + t] -= a.omega * r[3 * L.vs + t] * a.dinv[t];
+    __syncthreads();
+  }
+}
 dim3 seg_grid(const USegs& s, int ncell) {
   const int per = kUBlock / s.lps;
   return dim3((unsigned)((s.n + per - 1) / per), (unsigned)ncell);
@@ -587,19 +736,23 @@ constexpr int kUPartials = 512;
 
 }  // namespace
 
-// Interface launch over n nodes: occurrence slots per node from the most
-// occurrences of one node (1: 16 lanes, 2: 32, more: 64, one wavefront),
-// f(std::integral_constant<int, SL>, grid).  Launches of many nodes are
-// mostly face nodes (2 cells) and throughput-bound: 2 slots, whatever a few
-// edge and vertex nodes of T_0 need (cube benchmark, interface rows of a
-// level-7 apply: 4 slots 0.374 ms, 2 slots 0.245 ms; the level-6 FMG solve
-// 26.9 -> 26.4 ms with this rule at 8192 nodes, 26.5 at 4096, 26.6 at 32768).
+// Occurrence slots per node from the most occurrences of one node (1: 16
+// lanes, 2: 32, more: 64, one wavefront).  Launches of many nodes are mostly
+// face nodes (2 cells) and throughput-bound: 2 slots, whatever a few edge
+// and vertex nodes of T_0 need (cube benchmark, interface rows of a level-7
+// apply: 4 slots 0.374 ms, 2 slots 0.245 ms; the level-6 FMG solve 26.9 ->
+// 26.4 ms with this rule at 8192 nodes, 26.5 at 4096, 26.6 at 32768).
+int if_slots(int maxocc, int n) { return maxocc <= 1 ? 1 : ((maxocc <= 2 || n >= kIfManyNodes) ? 2 : 4); }
+
+// Interface launch over n nodes with if_slots slots per node:
+// f(std::integral_constant<int, SL>, grid).
 template <typename F>
 void if_launch(int maxocc, int n, F&& f) {
   auto grid = [n](int sl) { return dim3((unsigned)((n + if_nodes(sl) - 1) / if_nodes(sl))); };
-  if (maxocc <= 1)
+  const int sl = if_slots(maxocc, n);
+  if (sl == 1)
     f(std::integral_constant<int, 1>{}, grid(1));
-  else if (maxocc <= 2 || n >= kIfManyNodes)
+  else if (sl == 2)
     f(std::integral_constant<int, 2>{}, grid(2));
   else
     f(std::integral_constant<int, 4>{}, grid(4));
@@ -648,6 +801,30 @@ void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first
   if_launch(maxocc, count, [&](auto sl, dim3 g) {
     hipLaunchKernelGGL((k_u_gs_iface<decltype(sl)::value>), g, dim3(kUBlock), 0, s, L, lst, first, count, x, b);
   });
+}
+
+bool launch_u_smooth_small(hipStream_t s, const ULevelData& U, double* x, const double* b, double* r, int iters,
+                           int xi, bool sym, double omega) {
+  if (U.L.ncell > kUSmallCells || U.ncol_if > 64 || !U.col_off_d) return false;
+  if (iters <= 0) return true;
+  KScope ks(s, KF_SMALL, (double)real_slots(U.L));
+  USmallArgs a{};
+  a.L = U.L;
+  a.lst = U.lst;
+  a.inner = U.inner;
+  for (int c = 0; c < 4; ++c) a.colour[c] = U.colour[c];
+  a.col_off = U.col_off_d;
+  a.col_sl = U.col_sl_d;
+  a.K = U.ncol_if;
+  a.list_sl = if_slots(U.lst.maxocc, U.lst.n);
+  a.dinv = U.dinv;
+  a.omega = omega;
+  a.iters = iters;
+  a.xi = xi;
+  a.sym = sym;
+  const size_t lds = (size_t)U.L.ncell * 8 * kUPoints * sizeof(double);
+  hipLaunchKernelGGL(k_u_smooth_small, dim3(1), dim3(kUSmall), lds, s, a, x, b, r);
+  return true;
 }
 
 void launch_u_pstep(hipStream_t s, const ULev& L, const double* dinv, double* x, const double* r, double omega) {

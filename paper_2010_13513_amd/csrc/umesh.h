@@ -94,6 +94,8 @@ struct ULevelData {
   int ncol_if = 0;               // interface colours K (colours K..K+3: cell interiors)
   std::vector<int> col_off;      // K + 1 offsets into the free interface nodes
   std::vector<int> col_maxocc;   // per interface colour: most occurrences of one of its nodes
+  int* col_off_d = nullptr;      // device copies: col_off, occurrence slots per colour (if_slots)
+  int* col_sl_d = nullptr;
   UList lst{};
   USegs all{}, inner{}, colour[4]{};
   double* dinv = nullptr;        // per slot: 1 / Schur diagonal of its node
@@ -106,6 +108,10 @@ struct ULevelData {
   std::vector<int2> h_occ;
   std::vector<int> h_canon;
 };
+
+// Occurrence slots per interface node (1, 2 or 4: 16, 32 or 64 lanes) of a
+// launch over n nodes whose nodes lie in at most maxocc cells each.
+int if_slots(int maxocc, int n);
 
 // Launchers (ukernels.hip), float64, asynchronous on s.
 // y = [b -] op x at every node: opmask 1 A, 2 B^T (velocity rows), 4 B, 8 C
@@ -120,6 +126,13 @@ void launch_u_gs_inner(hipStream_t s, const ULev& L, USegs seg, double* x, const
 void launch_u_gs_iface(hipStream_t s, const ULev& L, const UList& lst, int first, int count, int maxocc, double* x,
                        const double* b);
 void launch_u_pstep(hipStream_t s, const ULev& L, const double* dinv, double* x, const double* r, double omega);
+// A whole smoothing call (iters Uzawa iterations: xi sweeps of every colour,
+// also reversed when sym, then r_p = g - B u + C p into r and the pressure
+// step) in one workgroup, every value computed as by the per-colour
+// launches; false (nothing launched) when the level has more cells or
+// colours than the kernel holds.
+bool launch_u_smooth_small(hipStream_t s, const ULevelData& U, double* x, const double* b, double* r, int iters,
+                           int xi, bool sym, double omega);
 void launch_u_restrict(hipStream_t s, const ULev& Lf, const ULev& Lc, USegs inner_c, const UList& lst_c,
                        const double* rf, double* rc);
 void launch_u_prolong(hipStream_t s, const ULev& Lc, const ULev& Lf, USegs all_f, const double* xc, double* xf,

@@ -634,9 +634,16 @@ UHier* u_build(const double* xyz, int nv, const int* tet, int nt, const std::vec
     lv.lst.maxocc = 0;
     for (int q = 0; q < H.nlist; ++q) lv.lst.maxocc = std::max(lv.lst.maxocc, lv.h_off[q + 1] - lv.h_off[q]);
     lv.col_maxocc.assign(lv.col_off.size() > 0 ? lv.col_off.size() - 1 : 0, 0);
-    for (size_t cc = 0; cc + 1 < lv.col_off.size(); ++cc)
+    std::vector<int> col_sl(lv.col_maxocc.size(), 1);
+    for (size_t cc = 0; cc + 1 < lv.col_off.size(); ++cc) {
       for (int q = lv.col_off[cc]; q < lv.col_off[cc + 1]; ++q)
         lv.col_maxocc[cc] = std::max(lv.col_maxocc[cc], lv.h_off[q + 1] - lv.h_off[q]);
+      col_sl[cc] = if_slots(lv.col_maxocc[cc], lv.col_off[cc + 1] - lv.col_off[cc]);
+    }
+    if (!lv.col_off.empty()) {
+      lv.col_off_d = upload(*u, lv.col_off);
+      if (!col_sl.empty()) lv.col_sl_d = upload(*u, col_sl);
+    }
     lv.dinv = upload(*u, H.dinv);
     lv.ml_own = upload(*u, H.mlown);
     lv.flags = upload(*u, H.flags);

@@ -131,6 +131,37 @@ def test_smooth(libs, oracle_levels, name, lmin, L, gs, xi):
     assert_blocks(lib, L, lib.to_lattice(L, dx), want, 1e-12, f"{name} smooth {gs}{xi}")
 
 
+@pytest.mark.parametrize("name,lmin,L", [("cube24", 0, 3), ("jittered", 0, 2), ("box2", 0, 2)])
+def test_smooth_one_workgroup(oracle_levels, name, lmin, L):
+    """A smoothing call run by one workgroup (hhg_hier_set_fused_sites above
+    the level's slots) computes every value as the per-colour launches do:
+    the two agree to rounding (the same per-node arithmetic), and both with
+    the oracle."""
+    lib = Lib(hhg.HHG_P1P1, lmin, L, mesh=MESHES[name]())     # own hierarchy: the bound is changed below
+    try:
+        S = oracle_levels(name, L)
+        U = osm.Uzawa(S, "sd")
+        x = _rand(S, 21)
+        bl = _rand(S, 22, zero_bnd=True)
+        b = lib.from_lattice(L, bl)
+        for gs, xi in (("f", 1), ("s", 2)):
+            mode = hhg.HHG_GS_FWD if gs == "f" else hhg.HHG_GS_SYM
+            out = []
+            for fused in (0, 10 ** 9):
+                hhg.hhg_hier_set_fused_sites(lib.h, fused)
+                dx = lib.from_lattice(L, x)
+                hhg.hhg_smooth(lib.h, L, dx, b, 3, mode, xi, 2.0)
+                out.append(dx)
+            diff = float((out[0] - out[1]).abs().max() / out[0].abs().max())
+            assert diff <= 1e-14, f"{name} {gs}{xi}: one workgroup vs launches {diff:.2e}"
+            want = x
+            for _ in range(3):
+                want = U.iterate(want, bl, gs, xi, 0.5)
+            assert_blocks(lib, L, lib.to_lattice(L, out[1]), want, 1e-12, f"{name} one-workgroup smooth {gs}{xi}")
+    finally:
+        lib.close()
+
+
 def test_smooth_ml_schur(oracle_levels):
     lib = Lib(hhg.HHG_P1P1, 0, 2, schur=hhg.HHG_SCHUR_ML, mesh=MESHES["jittered"]())
     try:
