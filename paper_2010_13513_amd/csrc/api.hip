@@ -727,7 +727,7 @@ void u_smooth(hhg_hier h, int l, double* x, const double* b, int iters, int gs, 
         for (int c = ncol - 1; c >= 0; --c) u_colour(h, l, c, x, b);
     }
     // r_p = g - B u + C p, then p -= omega D^{-1} r_p
-    launch_u_apply_rows(S(h), U.L, U.inner, U.lst, x, b, r, 12, true, false, false, true);
+    launch_u_apply_rows(S(h), U.L, U.inner, U.zitems, U.lst, x, b, r, 12, true, false, false, true);
     launch_u_pstep(S(h), U.L, U.dinv, x, r, omega);
   }
 }
@@ -822,7 +822,7 @@ void op_apply(hhg_hier h, int l, int opmask, const T* x, const T* b, T* y, bool 
   if (h->um) {
     u_f64<T>();
     ULevelData& U = UL(h, l);
-    launch_u_apply_rows(S(h), U.L, U.inner, U.lst, (const double*)x, (const double*)b, (double*)y, opmask, has_b,
+    launch_u_apply_rows(S(h), U.L, U.inner, U.zitems, U.lst, (const double*)x, (const double*)b, (double*)y, opmask, has_b,
                         false, vel, prs);
     return;
   }
@@ -1451,12 +1451,12 @@ double u_estimate_omega(hhg_hier h, int l, const double* v0, int iters) {
   launch_u_pscale(s, U.L, v + vs3, h->sums, 0);
   const int ncol = U.ncol_if + 4;
   for (int it = 0; it < iters; ++it) {
-    launch_u_apply_rows(s, U.L, U.inner, U.lst, v, nullptr, y, 2, false, false, true, false);  // B^T v
+    launch_u_apply_rows(s, U.L, U.inner, U.zitems, U.lst, v, nullptr, y, 2, false, false, true, false);  // B^T v
     launch_fill<double>(s, z, lv.vec_words, 0.0);
     for (int c = 0; c < ncol; ++c) u_colour(h, l, c, z, y);
     for (int c = ncol - 1; c >= 0; --c) u_colour(h, l, c, z, y);
     launch_scaled_copy<double>(s, z + vs3, v + vs3, nullptr, vs, -1.0);
-    launch_u_apply_rows(s, U.L, U.inner, U.lst, z, nullptr, y, 12, false, false, false, true);  // B z + C v
+    launch_u_apply_rows(s, U.L, U.inner, U.zitems, U.lst, z, nullptr, y, 12, false, false, false, true);  // B z + C v
     launch_scaled_copy<double>(s, v + vs3, y + vs3, U.dinv, vs, 1.0);
     launch_u_dot(s, U.L, U.flags, nullptr, v, v, 3, 1, h->partial, h->sums, 0);
     if (it + 1 < iters) launch_u_pscale(s, U.L, v + vs3, h->sums, 0);
@@ -1757,7 +1757,7 @@ hhg_status hhg_apply(hhg_hier h, int level, hhg_op op, const void* x, void* y, h
     if (mask < 0 && h->um) {
       HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
       ULevelData& U = UL(h, level);
-      launch_u_apply_rows(S(h), U.L, U.inner, U.lst, (const double*)x, nullptr, (double*)y, 0, false, true, true, true);
+      launch_u_apply_rows(S(h), U.L, U.inner, U.zitems, U.lst, (const double*)x, nullptr, (double*)y, 0, false, true, true, true);
       HHG_CHECK_HIP(hipGetLastError());
       return;
     }
@@ -1795,7 +1795,7 @@ hhg_status hhg_rhs(hhg_hier h, int level, const void* f, void* b, hhg_prec prec)
     if (h->um) {  // b = M I(f) on the free velocity rows, zero elsewhere
       HHG_REQUIRE(prec == HHG_F64, HHG_ERR_PREC, "unstructured macro meshes: float64 only");
       ULevelData& U = UL(h, level);
-      launch_u_apply_rows(S(h), U.L, U.inner, U.lst, (const double*)f, nullptr, (double*)b, 0, false, true, true, true);
+      launch_u_apply_rows(S(h), U.L, U.inner, U.zitems, U.lst, (const double*)f, nullptr, (double*)b, 0, false, true, true, true);
       launch_u_rhs_fix(S(h), U.L, U.flags, (double*)b);
       HHG_CHECK_HIP(hipGetLastError());
       return;

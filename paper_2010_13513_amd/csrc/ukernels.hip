@@ -10,6 +10,7 @@
 // the node.
 #include <type_traits>
 
+#include "lanes.h"
 #include "umesh.h"
 
 namespace hhg {
@@ -116,6 +117,102 @@ __global__ void __launch_bounds__(kUBlock) k_u_apply_inner(ULev L, USegs sg, con
   const int4 s = sg.s[sid];
   if (lane >= s.w) return;
   apply_inner_pt<HB, MASS>(L, c, w, cs->cfac, s.x + lane, s.y, s.z, x, b, y, opmask, wv, wp);
+}
+
+// k-marching apply of the interior rows (class 0) of cell c: a wavefront owns
+// the points (i0 - 1 .. i0 + 62, j) of one row j of the cell and the output
+// planes [ka, kb), and walks k = ka - 1 .. kb; at each plane it loads rows
+// j - 1, j, j + 1 of the four fields once (12 loads), takes the i -+ 1
+// neighbours from the adjacent lanes, and adds each word into the rows of
+// its lane's point at k - 1, k, k + 1 (three rotating accumulator planes);
+// the row at k - 1 is complete after plane k and is written.  Per interior
+// point this issues 12 loads per plane for 62 points instead of 60 gathers
+// per point.  Lanes outside the row load its nearest point: an interior row
+// only reads points inside the closed cell, so such words reach only rows
+// that are not written.  Same products as apply_inner_pt, summed in another
+// order.  Velocity row d: A u_d + B^T_d p; pressure row: B u -+ C p.
+template <int Q, bool HB>
+__device__ __forceinline__ void uzm_step(const ULev& L, const double (*w)[kUPoints], double csign, size_t base, int i,
+                                         int j, int kp, bool out, int ka, int kb, const double* __restrict__ x,
+                                         const double* __restrict__ b, double* __restrict__ y, bool dA, bool dBT,
+                                         bool dB, bool dC, int wv, int wp, double (&acc)[3][4]) {
+  const int n = L.n;
+  const size_t vs = L.vs;
+  // the rows are read from LDS at every plane: an opaque zero offset keeps
+  // the compiler from hoisting all 105 weights into registers for the loop
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  const double* wz = &w[0][0] + z;
+  double v[3][4];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int jj = max(j - 1 + r, kp);  // row j - 1 at plane j is not in the cell (its words reach row k = j only)
+    const size_t sl = base + uslot(min(max(i, jj), n), jj, kp, n);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v[r][f] = x[f * vs + sl];
+  }
+#pragma unroll
+  for (int e = 0; e < kUPoints; ++e) {
+    const int di = udir(e, 0), dj = udir(e, 1), dk = udir(e, 2);
+    const int sl = ((Q - dk) % 3 + 3) % 3;  // accumulator plane of the row at k = kp - dk
+    double u[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const double a = v[dj + 1][f];
+      u[f] = di < 0 ? gen::from_prev(a) : (di > 0 ? gen::from_next(a) : a);
+    }
+    auto W = [&](int q) { return wz[q * kUPoints + e]; };
+    if (dA)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) acc[sl][d] += W(0) * u[d];
+    if (dBT)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) acc[sl][d] += W(1 + d) * u[3];
+    if (dB) acc[sl][3] += W(4) * u[0] + W(5) * u[1] + W(6) * u[2];
+    if (dC) acc[sl][3] += csign * (W(0) * u[3]);
+  }
+  constexpr int S = (Q + 2) % 3;  // the row at k = kp - 1
+  const int kr = kp - 1;
+  if (out && kr >= ka && kr < kb) {
+    const size_t t = base + uslot(i, j, kr, n);
+    if (wv)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) y[d * vs + t] = HB ? b[d * vs + t] - acc[S][d] : acc[S][d];
+    if (wp) y[3 * vs + t] = HB ? b[3 * vs + t] - acc[S][3] : acc[S][3];
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) acc[S][f] = 0.0;
+}
+
+template <bool HB>
+__global__ void __launch_bounds__(kUBlock) k_u_apply_zm(ULev L, const int4* __restrict__ items, int nitems,
+                                                        const double* __restrict__ x, const double* __restrict__ b,
+                                                        double* __restrict__ y, int opmask, int wv, int wp) {
+  __shared__ double w[8][kUPoints];
+  const int c = blockIdx.y;
+  const UCell* cs = L.cs + c;
+  stage_inner(cs, w);
+  const int it = blockIdx.x * (kUBlock / 64) + (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  if (it >= nitems) return;  // whole wavefront
+  const int4 item = items[it];  // (j, i0, ka, kb)
+  const int j = item.x, ka = item.z, kb = item.w, n = L.n;
+  const int i = item.y - 1 + lane;
+  const bool out = lane >= 1 && lane <= 62 && i <= n - 1;
+  const bool dA = opmask & 1, dBT = opmask & 2, dB = opmask & 4, dC = opmask & 24;
+  const double csign = (opmask & 16) ? cs->cfac : -cs->cfac;
+  const size_t base = (size_t)c * L.P;
+  double acc[3][4];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[q][f] = 0.0;
+  const int nq = kb - ka + 2;
+  for (int q = 0; q < nq; q += 3) {
+    const int kp = ka - 1 + q;
+    uzm_step<0, HB>(L, w, csign, base, i, j, kp, out, ka, kb, x, b, y, dA, dBT, dB, dC, wv, wp, acc);
+    if (q + 1 < nq) uzm_step<1, HB>(L, w, csign, base, i, j, kp + 1, out, ka, kb, x, b, y, dA, dBT, dB, dC, wv, wp, acc);
+    if (q + 2 < nq) uzm_step<2, HB>(L, w, csign, base, i, j, kp + 2, out, ka, kb, x, b, y, dA, dBT, dB, dC, wv, wp, acc);
+  }
 }
 
 // Interface nodes: a group of 16 SL lanes per node (SL = 1, 2 or 4 slots,
@@ -758,9 +855,21 @@ void if_launch(int maxocc, int n, F&& f) {
     f(std::integral_constant<int, 4>{}, grid(4));
 }
 
-void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList& lst, const double* x,
+void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, USegs zitems, const UList& lst, const double* x,
                          const double* b, double* y, int opmask, bool has_b, bool mass, bool wv, bool wp) {
-  if (inner.n > 0) {
+  // k-marching from n = 64 on (cube benchmark FMG solve: from 32 26.2 ms,
+  // from 64 25.6, from 128 25.8, never 25.8; on the small levels its chains
+  // of dependent plane steps cost more than the row-segment gathers)
+  if (inner.n > 0 && !mass && zitems.n > 0 && L.n >= 64) {
+    KScope ks(s, KF_APPLY, (double)inner.pts * L.ncell);
+    const dim3 g((unsigned)((zitems.n + kUBlock / 64 - 1) / (kUBlock / 64)), (unsigned)L.ncell);
+    if (has_b)
+      hipLaunchKernelGGL((k_u_apply_zm<true>), g, dim3(kUBlock), 0, s, L, zitems.s, zitems.n, x, b, y, opmask, (int)wv,
+                         (int)wp);
+    else
+      hipLaunchKernelGGL((k_u_apply_zm<false>), g, dim3(kUBlock), 0, s, L, zitems.s, zitems.n, x, b, y, opmask,
+                         (int)wv, (int)wp);
+  } else if (inner.n > 0) {
     KScope ks(s, KF_APPLY, (double)inner.pts * L.ncell);
     const dim3 g = seg_grid(inner, L.ncell);
     if (mass)

@@ -98,6 +98,7 @@ struct ULevelData {
   int* col_sl_d = nullptr;
   UList lst{};
   USegs all{}, inner{}, colour[4]{};
+  USegs zitems{};                // k-marching items (j, i0, ka, kb) of the interior apply
   double* dinv = nullptr;        // per slot: 1 / Schur diagonal of its node
   double* ml_own = nullptr;      // per slot: lumped mass of its node at the owner slot, else 0
   unsigned char* flags = nullptr;  // per slot: bit 0 owner, bit 1 Dirichlet
@@ -118,7 +119,9 @@ int if_slots(int maxocc, int n);
 // (pressure rows B u - C p; 16: + C p instead), Dirichlet velocity rows zero;
 // mass: the consistent mass on all four fields (every row) instead.  wv / wp:
 // write the velocity / pressure rows (the others are left as they are).
-void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, const UList& lst, const double* x,
+// zitems: the k-marching items (j, i0, ka, kb) of the interior rows (used
+// unless mass; n = 0: the row-segment kernel).
+void launch_u_apply_rows(hipStream_t s, const ULev& L, USegs inner, USegs zitems, const UList& lst, const double* x,
                          const double* b, double* y, int opmask, bool has_b, bool mass, bool wv, bool wp);
 void launch_u_gs_inner(hipStream_t s, const ULev& L, USegs seg, double* x, const double* b);
 // Free interface nodes [first, first + count) of one colour; maxocc: the
