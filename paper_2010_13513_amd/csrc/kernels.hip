@@ -1647,13 +1647,16 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     // the 48-tet level-7 lattice: 8 -> 1.23 ms, 4 -> 1.16 ms, 3 -> 1.14 ms,
     // 2 -> 1.36 ms).  Unused dynamic LDS caps residency at 3 of the CU's
     // 160 KiB; float64 is already held to 4 by its registers and does not
-    // gain from fewer.  P1-P1 loads a third of the words per plane and needs
-    // the waves to hide their latency: no cap (same lattice, float32: 3
-    // workgroups 0.381 ms, 4 0.383, 6 0.278, uncapped 0.215).
+    // gain from fewer.  The cap pays on that lattice only (n1 = 257); on the
+    // smaller ones the columns in flight fit the L2 anyway (n1 = 65: 0.034 ->
+    // 0.028 ms uncapped; n1 = 129: 0.193 -> 0.188).  P1-P1 loads a third of
+    // the words per plane and needs the waves to hide their latency: no cap
+    // (n1 = 257, float32: 3 workgroups 0.381 ms, 4 0.383, 6 0.278, uncapped
+    // 0.215).
     // vel_rows false: the pressure rows only (the Uzawa pressure residual):
     // the velocity words are still loaded for B u, the velocity rows are
     // neither accumulated nor written and their b words not read
-    const unsigned dyn = sizeof(T) == 4 && g.G == 8 ? kZmF32Lds : 0;
+    const unsigned dyn = sizeof(T) == 4 && g.G == 8 && g.n1 >= 200 ? kZmF32Lds : 0;
     if (g.G == 1) {
       if (vel_rows)
         hipLaunchKernelGGL((k_apply_zm<T, 1, true>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
