@@ -6,6 +6,7 @@
 // along i, so every stencil neighbour load of a wavefront is a contiguous run.
 // Stencil weights are constant per row type (paper Sec. 2.1) and are read from
 // small device tables with wavefront-uniform addresses (scalar loads).
+#include <type_traits>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -430,21 +431,36 @@ struct ZmCol {
   T sv, sp;  // units of the accumulated velocity and pressure rows
 };
 
-template <typename T, int G, int D, int Q, bool VEL>
+template <typename T, int G, int D, int Q, bool VEL, bool HB>
 __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
-                                        const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol<T>& c, int q,
+                                        const T* __restrict__ b, T* __restrict__ y, const ZmCol<T>& c, int q,
                                         T (&acc)[3][G + 1], T (*pshare)[3][kZmCols]) {
   constexpr int S = (Q + 2) % 3;  // slot of the row plane completed by this step
   const int N = g.N, s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn, vs = g.vstride;
   const int kp = c.k0 - 1 + q;
+  const int kr = kp - 1;
   const int kps = min(max(kp, 0), N) * s2;
   const int vo[3] = {(c.nb[0] + kps) * (int)sizeof(T), (c.nb[1] + kps) * (int)sizeof(T),
                      (c.nb[2] + kps) * (int)sizeof(T)};
   const __amdgpu_buffer_rsrc_t ru = gen::make_rsrc(x + (size_t)D * vs, (unsigned)((size_t)vs * sizeof(T)));
   const __amdgpu_buffer_rsrc_t rp = gen::make_rsrc(x + (size_t)3 * vs, (unsigned)((size_t)nn * sizeof(T)));
+  // residual: the b words of the row this step completes are loaded before
+  // the plane's multiply-adds, so their latency hides behind them instead of
+  // adding a round trip before the stores (address clamped into the lattice;
+  // only the rows written use them)
+  T bv[G + 1];
+  if constexpr (HB) {
+    const int atc = c.nb[1] + min(max(kr, 0), N) * s2;
+#pragma unroll
+    for (int gr = 0; gr < G; ++gr) bv[gr] = VEL ? b[D * vs + gr * nn + atc] : T(0);
+    bv[G] = D == 0 ? b[3 * vs + atc] : T(0);
+  }
   zm_plane<T, G, D, Q>(ru, rp, vo, nn * (int)sizeof(T), c.rt, c.rc, acc);
+  if constexpr (HB) {
+#pragma unroll
+    for (int r = 0; r <= G; ++r) asm volatile("" : "+v"(bv[r]));  // keep the loads above (not sunk to the stores)
+  }
   (void)s1;
-  const int kr = kp - 1;
   const int lane = threadIdx.x & (kZmCols - 1);
   if (kr >= c.k0 && kr < c.k1) {  // uniform over the block
     const int at = c.col + kr * s2;
@@ -453,7 +469,7 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
       for (int gr = 0; gr < G; ++gr) {
         const int pos = D * vs + gr * nn + at;
         const T v = c.sv * acc[S][gr];
-        y[pos] = vel_interior<G>(gr, c.i, c.j, kr, N) ? (has_b ? b[pos] - v : v) : T(0);
+        y[pos] = vel_interior<G>(gr, c.i, c.j, kr, N) ? (HB ? bv[gr] - v : v) : T(0);
       }
     }
     pshare[q & 1][D][lane] = acc[S][G];
@@ -461,16 +477,16 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
     if (D == 0 && c.valid && c.i >= 1 && c.j >= 1 && kr >= 1 && c.i <= N - 1 && c.j <= N - 1 && kr <= N - 1) {
       const T v = c.sp * (pshare[q & 1][0][lane] + pshare[q & 1][1][lane] + pshare[q & 1][2][lane]);
       const int pp = 3 * vs + at;
-      y[pp] = has_b ? b[pp] - v : v;
+      y[pp] = HB ? bv[G] - v : v;
     }
   }
 #pragma unroll
   for (int r = 0; r <= G; ++r) acc[S][r] = T(0);
 }
 
-template <typename T, int G, int D, bool VEL>
+template <typename T, int G, int D, bool VEL, bool HB>
 __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
-                                       const T* __restrict__ b, T* __restrict__ y, int has_b, const ZmCol<T>& c,
+                                       const T* __restrict__ b, T* __restrict__ y, const ZmCol<T>& c,
                                        T (*pshare)[3][kZmCols]) {
   T acc[3][G + 1];
 #pragma unroll
@@ -479,19 +495,19 @@ __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, c
     for (int r = 0; r <= G; ++r) acc[s][r] = T(0);
   const int nq = c.k1 - c.k0 + 2;
   for (int q = 0; q < nq; q += 3) {
-    zm_step<T, G, D, 0, VEL>(g, lc, x, b, y, has_b, c, q, acc, pshare);
-    if (q + 1 < nq) zm_step<T, G, D, 1, VEL>(g, lc, x, b, y, has_b, c, q + 1, acc, pshare);
-    if (q + 2 < nq) zm_step<T, G, D, 2, VEL>(g, lc, x, b, y, has_b, c, q + 2, acc, pshare);
+    zm_step<T, G, D, 0, VEL, HB>(g, lc, x, b, y, c, q, acc, pshare);
+    if (q + 1 < nq) zm_step<T, G, D, 1, VEL, HB>(g, lc, x, b, y, c, q + 1, acc, pshare);
+    if (q + 2 < nq) zm_step<T, G, D, 2, VEL, HB>(g, lc, x, b, y, c, q + 2, acc, pshare);
   }
 }
 
-template <typename T, int G, bool VEL>
+template <typename T, int G, bool VEL, bool HB>
 __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
-                                                          const T* __restrict__ b, T* __restrict__ y, int has_b, int kc,
-                                                          int ncb, const int* __restrict__ bnd, int nbnd, int nmain) {
+                                                          const T* __restrict__ b, T* __restrict__ y, int kc, int ncb,
+                                                          const int* __restrict__ bnd, int nbnd, int nmain) {
   __shared__ T pshare[2][3][kZmCols];
   if ((int)blockIdx.x >= nmain) {
-    prow_bnd_block<T, G>(g, lc, x, b, y, G == 1 ? 15 : 7, has_b, bnd, nbnd, nmain, 3 * kZmCols);
+    prow_bnd_block<T, G>(g, lc, x, b, y, G == 1 ? 15 : 7, (int)HB, bnd, nbnd, nmain, 3 * kZmCols);
     return;
   }
   const int lin = xcd_block_of(nmain);
@@ -518,11 +534,11 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
   for (int dj = -1; dj <= 1; ++dj) c.nb[dj + 1] = min(max(c.col + dj * n1, 0), ncol - 1);
   const int wave = threadIdx.x / kZmCols;  // velocity component
   if (wave == 0)
-    zm_run<T, G, 0, VEL>(g, lc, x, b, y, has_b, c, pshare);
+    zm_run<T, G, 0, VEL, HB>(g, lc, x, b, y, c, pshare);
   else if (wave == 1)
-    zm_run<T, G, 1, VEL>(g, lc, x, b, y, has_b, c, pshare);
+    zm_run<T, G, 1, VEL, HB>(g, lc, x, b, y, c, pshare);
   else
-    zm_run<T, G, 2, VEL>(g, lc, x, b, y, has_b, c, pshare);
+    zm_run<T, G, 2, VEL, HB>(g, lc, x, b, y, c, pshare);
 }
 
 // Pressure rows at boundary nodes (list), boundary-class stencils.
@@ -1657,20 +1673,25 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     // the velocity words are still loaded for B u, the velocity rows are
     // neither accumulated nor written and their b words not read
     const unsigned dyn = sizeof(T) == 4 && g.G == 8 && g.n1 >= 200 ? kZmF32Lds : 0;
+    auto go = [&](auto gg, auto vel, auto hbc) {
+      constexpr int GG = decltype(gg)::value;
+      constexpr bool V = decltype(vel)::value, H = decltype(hbc)::value;
+      hipLaunchKernelGGL((k_apply_zm<T, GG, V, H>), grid, block, dyn, s, g, lc, x, b, y, kc, ncb, bnd, nb_bnd, nmain);
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I8 = std::integral_constant<int, 8>;
+    using BT = std::true_type;
+    using BF = std::false_type;
     if (g.G == 1) {
       if (vel_rows)
-        hipLaunchKernelGGL((k_apply_zm<T, 1, true>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
-                           nmain);
+        hb ? go(I1{}, BT{}, BT{}) : go(I1{}, BT{}, BF{});
       else
-        hipLaunchKernelGGL((k_apply_zm<T, 1, false>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
-                           nmain);
+        hb ? go(I1{}, BF{}, BT{}) : go(I1{}, BF{}, BF{});
     } else {
       if (vel_rows)
-        hipLaunchKernelGGL((k_apply_zm<T, 8, true>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
-                           nmain);
+        hb ? go(I8{}, BT{}, BT{}) : go(I8{}, BT{}, BF{});
       else
-        hipLaunchKernelGGL((k_apply_zm<T, 8, false>), grid, block, dyn, s, g, lc, x, b, y, hb, kc, ncb, bnd, nb_bnd,
-                           nmain);
+        hb ? go(I8{}, BF{}, BT{}) : go(I8{}, BF{}, BF{});
     }
   } else {
     const int nmain = (int)nblocks8(g.nn);
