@@ -273,6 +273,42 @@ def test_refusals(libs):
         hhg.hhg_mesh_destroy(mesh)
 
 
+# ------------------------------------------------------- k-marching rows
+# One jittered tetrahedron (not a Kuhn simplex) at level 6: n = 64, so its
+# interior rows run the k-marching kernel (levels with n >= 64), compared
+# with the oracle on all 47,905 nodes (the oracle builds it in about 30 s).
+ONE_TET = (np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.9, 1.1, 0.05], [1.05, 0.95, 1.2]]), np.array([[0, 1, 2, 3]]))
+
+
+@pytest.fixture(scope="module")
+def one_tet():
+    print("[umesh] one tetrahedron, level 6: oracle operator", flush=True)
+    S = Stokes(umesh.ULevel(*ONE_TET, 6))
+    lib = Lib(hhg.HHG_P1P1, 5, 6, mesh=ONE_TET)
+    yield lib, S
+    lib.close()
+
+
+@pytest.mark.parametrize("op", ["FULL", "A", "BT", "B", "C"])
+def test_k_marching_rows(one_tet, op):
+    lib, S = one_tet
+    x = _rand(S, 900)
+    dy = lib.empty(6)
+    code = {"FULL": hhg.HHG_OP_FULL, "A": hhg.HHG_OP_A, "BT": hhg.HHG_OP_BT, "B": hhg.HHG_OP_B, "C": hhg.HHG_OP_C}[op]
+    hhg.hhg_apply(lib.h, 6, code, lib.from_lattice(6, x), dy)
+    want = S.apply(x) if op == "FULL" else S.apply_block(x, op)
+    assert_blocks(lib, 6, lib.to_lattice(6, dy), want, 1e-12, f"one tet level 6 apply {op}")
+
+
+def test_k_marching_residual(one_tet):
+    lib, S = one_tet
+    x = _rand(S, 901)
+    b = _rand(S, 902, zero_bnd=True)
+    dr = lib.empty(6)
+    hhg.hhg_residual(lib.h, 6, lib.from_lattice(6, x), lib.from_lattice(6, b), dr)
+    assert_blocks(lib, 6, lib.to_lattice(6, dr), S.residual(x, b), 1e-12, "one tet level 6 residual")
+
+
 # ---------------------------------------------------------------- full size
 @pytest.fixture(scope="module")
 def big():
