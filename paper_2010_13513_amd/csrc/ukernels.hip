@@ -3,11 +3,13 @@
 // Cell interiors run as lattice kernels: a workgroup of four wavefronts
 // takes 256 / lps row segments of one cell (grid.y = cell), one lane per point,
 // with the cell's interior rows staged in LDS; neighbours are the 14
-// Freudenthal neighbours in the cell's packed slot order.  Interface nodes
-// (on vertices, edges and faces of T_0) run 16 lanes per node, one per
-// stencil point: the row is the sum, over the cells containing the node, of
-// that cell's row of the node's class, and the result goes to every copy of
-// the node.
+// Freudenthal neighbours in the cell's packed slot order.  On the large
+// levels the interior rows of the apply walk k instead (k_u_apply_zm).
+// Interface nodes (on vertices, edges and faces of T_0) run 16, 32 or 64
+// lanes per node, one per stencil point and occurrence slot: the row is the
+// sum, over the cells containing the node, of that cell's row of the node's
+// class, and the result goes to every copy of the node.  The smoothing calls
+// of the smallest levels run in one workgroup (k_u_smooth_small).
 #include <type_traits>
 
 #include "lanes.h"
