@@ -104,11 +104,15 @@ def sampled_rows(vo, N, rng, per_class=6, nu=None):
     return rows, bnd
 
 
-def check_rows(rows, bnd, xval, got, rtol=1e-12):
-    """Compare gathered outputs with the rows; xval maps input index -> value."""
-    for (yl, terms), g in zip(rows, got[:len(rows)]):
+def check_rows(rows, bnd, xval, got, rtol=1e-12, bval=None):
+    """Compare gathered outputs with the rows; xval maps input index -> value.
+    bval (residual): the right-hand side at each row's output, expected b -
+    row . x, error relative to |b| + sum |w x|."""
+    for q, ((yl, terms), g) in enumerate(zip(rows, got[:len(rows)])):
         want = sum(w * xval[i] for i, w in terms)
         scale = sum(abs(w * xval[i]) for i, w in terms)
+        if bval is not None:
+            want, scale = bval[q] - want, scale + abs(bval[q])
         assert abs(g - want) <= rtol * scale, (yl, g, want)
     assert np.all(got[len(rows):] == 0.0)
 
@@ -174,6 +178,50 @@ def test_apply_full_size_sampled_rows(disc, prec):
         xi = sorted({t[0] for r in rows for t in r[1]})
         xv = dict(zip(xi, lat.index_select(0, torch.tensor(xi, device=lib.dev)).cpu().numpy()))
         check_rows(rows, bnd, xv, got, rtol=1e-12 if prec == hhg.HHG_F64 else 3e-5)
+    finally:
+        lib.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("disc,prec", [(hhg.HHG_P2P1, hhg.HHG_F64), (hhg.HHG_P2P1, hhg.HHG_F32),
+                                       (hhg.HHG_P1P1, hhg.HHG_F32)])
+def test_residual_full_size_sampled_rows(disc, prec):
+    """r = b - calA x in the same launch configuration (the residual form of
+    the k-marching kernel, which loads b ahead of each plane's arithmetic):
+    sampled interior rows against b - (rescaled oracle row) . x, Dirichlet
+    velocity rows zero.  Tolerances as for the apply, relative to |b| +
+    sum |w x|."""
+    lib = Lib(disc, 6, 7, macro_refine=1)
+    torch = lib.torch
+    try:
+        vo = 2 if disc == hhg.HHG_P2P1 else 1
+        dt = torch.float64 if prec == hhg.HHG_F64 else torch.float32
+        N, nn, vw, lw = lib.layout(7)
+        print(f"residual full size: disc {disc}, prec {prec}, N {N}, {vw} words", flush=True)
+        gen = torch.Generator(device=lib.dev).manual_seed(13513 + 3002)
+        lat = torch.randn(lw, generator=gen, dtype=torch.float64, device=lib.dev)
+        blat = torch.randn(lw, generator=gen, dtype=torch.float64, device=lib.dev)
+        if prec == hhg.HHG_F32:
+            lat, blat = lat.float().double(), blat.float().double()
+        x = torch.zeros(vw, dtype=dt, device=lib.dev)
+        b = torch.zeros(vw, dtype=dt, device=lib.dev)
+        hhg.hhg_vec_from_lattice(lib.h, 7, lat, x, prec)
+        hhg.hhg_vec_from_lattice(lib.h, 7, blat, b, prec)
+        r = torch.empty_like(x)
+        hhg.hhg_residual(lib.h, 7, x, b, r, prec)
+        del x, b
+        rlat = torch.empty_like(lat)
+        hhg.hhg_vec_to_lattice(lib.h, 7, r, rlat, prec)
+        del r
+        torch.cuda.synchronize()
+
+        rows, bnd = sampled_rows(vo, N, np.random.default_rng(9))
+        out = torch.tensor([q[0] for q in rows] + bnd, device=lib.dev)
+        got = rlat.index_select(0, out).cpu().numpy()
+        bval = blat.index_select(0, out).cpu().numpy()[:len(rows)]
+        xi = sorted({t[0] for q in rows for t in q[1]})
+        xv = dict(zip(xi, lat.index_select(0, torch.tensor(xi, device=lib.dev)).cpu().numpy()))
+        check_rows(rows, bnd, xv, got, rtol=1e-12 if prec == hhg.HHG_F64 else 3e-5, bval=bval)
     finally:
         lib.close()
 
