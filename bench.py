@@ -321,6 +321,9 @@ def main():
     if traffic:
         roofline["traffic_source"] = traffic["source"]
 
+    # ---- P1-P1: a solve at discretisation accuracy within 10 work units
+    p1_solved = bench_p1_solved(torch, hhg, ctx, stream, steps=max(5, args.steps // 2))
+
     # ---- operator-apply HBM roofline at the throughput size (48 tets, level 7)
     apply_roofline = None
     if not args.no_apply_roofline:
@@ -340,6 +343,7 @@ def main():
         "alternatives": alternatives,
         "schur_ml": schur_ml,
         "relative_error": delta,
+        "p1p1_solved": p1_solved,
         "roofline": roofline,
     }
     if apply_roofline:
@@ -351,6 +355,61 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L, omega_inv)
     print(json.dumps(out), flush=True)
+
+
+# The least-work tuple of the 768-tuple search space whose P1-P1 level-6
+# result meets gamma_u, gamma_p <= 2 (the sweep's Tab. fmg-table row (2, 2))
+P1_SOLVED = (1, 0, 1, 1, 0, 4)
+
+
+def bench_p1_solved(torch, hhg, ctx, stream, steps=10, warmup=2, L=6):
+    """P1-P1 PSPG, 6 Kuhn macro-tets, level 6 (1,098,500 DoFs), paper cube
+    solution, coarsest level 0: FMG with P1_SOLVED (graph-replayed), its work
+    units and gammas (eq. gamma against a solve converged to 1e-12)."""
+    from paper_2010_13513_amd import study, workloads as W
+    from paper_2010_13513_amd.problem import Problem
+    prob = W.paper_cube()
+    P = Problem(torch, ctx, hhg.HHG_P1P1, 0, L)
+    try:
+        v0 = torch.from_numpy(W.normal_vector(W.SEED_BASE + 1000, (2 ** L + 1) ** 3)).to(P.dev)
+        om = hhg.hhg_estimate_omega(P.h, L, v0, 100)
+        bs = P.rhs(prob)
+        x0 = P.boundary(prob)
+        gev = study.GammaEvaluator(torch, P, prob)
+        try:
+            xd, _ = study.discrete_solution(P, bs, x0, om)
+            ed = gev.errors(xd)
+            prm = hhg.solver_params(*P1_SOLVED, om)
+            x = torch.empty_like(x0)
+
+            def step():
+                x.copy_(x0)
+                hhg.hhg_fmg_solve(P.h, x, bs, prm, want_stats=False)
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            eu, ep = gev.errors(x)
+            wu = hhg.hhg_fmg_solve(P.h, x0.clone(), bs, prm).work_units
+            dofs = P.dofs(L)
+            res = {"workload": f"P1-P1 PSPG Stokes, unit cube, 6 Kuhn macro-tets, level {L} ({dofs} DoFs), paper "
+                               "cube solution, coarsest level 0",
+                   "fmg": _tname(P1_SOLVED), "work_units": round(wu, 3), "omega_inv": om,
+                   "gamma_u": round(eu / ed[0], 4), "gamma_p": round(ep / ed[1], 4), "ms_per_solve": round(ms, 4),
+                   "dofs_per_s": dofs / (ms * 1e-3)}
+            log(f"[bench] P1-P1 level {L} FMG{_tname(P1_SOLVED)} ({wu:.2f} WU): {ms:.3f} ms, "
+                f"{res['dofs_per_s']:.3e} DoF/s, gamma ({res['gamma_u']:.3f}, {res['gamma_p']:.3f})")
+            return res
+        finally:
+            gev.close()
+    finally:
+        P.close()
 
 
 def bench_apply(torch, hhg, dev, stream, ctx, level=7, reps=20):
