@@ -1277,11 +1277,24 @@ __device__ __forceinline__ T prow_bnd_table(const Geom& g, const Tables<T>* __re
   const T* p = x + 3 * g.vstride;
   T acc = 0;
   if (opmask & 4) {
+    // four entries per pass into four partial sums: the entries' table and
+    // vector loads are independent, so a pass waits for memory once
     const DStencil<T> s = tb->B[cls];
-    for (int e = 0; e < s.n; ++e) {
-      const int o = node + s.off[e];
-      acc += s.w[3 * e] * u0[o] + s.w[3 * e + 1] * u1[o] + s.w[3 * e + 2] * u2[o];
+    T a4[4] = {0, 0, 0, 0};
+    int e = 0;
+    for (; e + 4 <= s.n; e += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = node + s.off[e + q];
+        const T* w = s.w + 3 * (e + q);
+        a4[q] += w[0] * u0[o] + w[1] * u1[o] + w[2] * u2[o];
+      }
     }
+    for (; e < s.n; ++e) {
+      const int o = node + s.off[e];
+      a4[0] += s.w[3 * e] * u0[o] + s.w[3 * e + 1] * u1[o] + s.w[3 * e + 2] * u2[o];
+    }
+    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   }
   if (opmask & 8) {
     const DStencil<T> s = tb->C[cls];
