@@ -399,6 +399,69 @@ void emit_restriction(FILE* f, const char* D, int vorder) {
   std::fprintf(f, "  return a;\n}\n// %zu entries\n\n", pres.size());
 }
 
+// k-marching velocity restriction (P2-P1): a wavefront owns 64 consecutive
+// coarse columns (i, j) of one component and walks the coarse planes; step q
+// (coarse plane kq) loads the fine planes 2 kq (P = 0) and 2 kq + 1 (P = 1).
+// A lane holds the fine words at 2 i (even) and 2 i + 1 (odd) of every fine
+// row 2 j + dj (dj = -2 .. 1) and fine group the plane's entries use; the
+// offsets di = -1, -2 are the previous lane's odd and even words.  An entry
+// (coarse group gc, fine group g, di, dj, dk) of a plane of parity P = dk mod
+// 2 adds to coarse plane kq (dk >= 0, accumulator slot Q) or kq + 1 (dk < 0,
+// slot 1 - Q).  ro_e / ro_o: byte offsets of the even / odd word of fine row
+// dj + 2 in the plane, group g at soffset g nnb.
+void emit_restriction_zm(FILE* f, const char* D, int vorder) {
+  std::vector<std::vector<RestrictEntry>> vel;
+  std::vector<RestrictEntry> pres;
+  restriction_entries(vorder, vel, pres);
+  const int G = (int)vel.size();
+  for (int P = 0; P < 2; ++P)
+    for (int Q = 0; Q < 2; ++Q) {
+      std::fprintf(f,
+                   "template <typename T>\n__device__ __forceinline__ void %s_Rzm_p%d_q%d(__amdgpu_buffer_rsrc_t ru, "
+                   "const int (&ro_e)[4], const int (&ro_o)[4], int nnb, T (&acc)[2][%d]) {\n",
+                   D, P, Q, G);
+      // the (fine group, row) pairs this plane parity uses, in a fixed order
+      std::vector<std::pair<int, int>> pairs;
+      for (int g = 0; g < 8; ++g)
+        for (int dj = -2; dj <= 1; ++dj) {
+          bool any = false;
+          for (int gc = 0; gc < G; ++gc)
+            for (auto& e : vel[gc]) any |= e.g == g && e.dj == dj && (((e.dk % 2) + 2) % 2) == P;
+          if (any) pairs.push_back({g, dj});
+        }
+      for (size_t w = 0; w < pairs.size(); ++w)
+        std::fprintf(f,
+                     "  const T e%zu = buffer_word<T>(ru, ro_e[%d], %d * nnb);\n"
+                     "  const T o%zu = buffer_word<T>(ru, ro_o[%d], %d * nnb);\n",
+                     w, pairs[w].second + 2, pairs[w].first, w, pairs[w].second + 2, pairs[w].first);
+      for (size_t w = 0; w < pairs.size(); ++w) {
+        const int g = pairs[w].first, dj = pairs[w].second;
+        bool need[4] = {false, false, false, false};  // di + 2
+        for (int gc = 0; gc < G; ++gc)
+          for (auto& e : vel[gc])
+            if (e.g == g && e.dj == dj && (((e.dk % 2) + 2) % 2) == P) need[e.di + 2] = true;
+        std::fprintf(f, "  {\n");
+        if (need[0]) std::fprintf(f, "    const T m2 = from_prev(e%zu);\n", w);
+        if (need[1]) std::fprintf(f, "    const T m1 = from_prev(o%zu);\n", w);
+        for (int gc = 0; gc < G; ++gc)
+          for (auto& e : vel[gc]) {
+            if (!(e.g == g && e.dj == dj && (((e.dk % 2) + 2) % 2) == P)) continue;
+            const char* word = e.di == -2 ? "m2" : (e.di == -1 ? "m1" : nullptr);
+            char buf[32];
+            if (!word) {
+              std::snprintf(buf, sizeof buf, "%c%zu", e.di == 0 ? 'e' : 'o', w);
+              word = buf;
+            }
+            const int slot = e.dk >= 0 ? Q : 1 - Q;
+            std::fprintf(f, "    acc[%d][%d] = fma(T(%s), %s, acc[%d][%d]);\n", slot, gc, lit(e.w).c_str(), word, slot,
+                         gc);
+          }
+        std::fprintf(f, "  }\n");
+      }
+      std::fprintf(f, "}\n// %zu word pairs per plane\n\n", pairs.size());
+    }
+}
+
 double diag_of(const Row& r, int g) {
   for (auto& e : r)
     if (e.g == g && e.di == 0 && e.dj == 0 && e.dk == 0) return e.w[0];
@@ -448,6 +511,7 @@ int main(int argc, char** argv) {
     emit_zm(f, es, D, G);
     emit_boundary_rows(f, es, D, G);
     emit_restriction(f, D, vorder);
+    if (vorder == 2) emit_restriction_zm(f, D, vorder);
   }
   std::fprintf(f, "}  // namespace gen\n}  // namespace hhg\n");
   std::fclose(f);

@@ -820,10 +820,99 @@ __device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, co
   rc[(size_t)d * gc.vstride + gr * gc.nn + t] = a0;
 }
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const T* __restrict__ rf, T* __restrict__ rc) {
+__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const T* __restrict__ rf, T* __restrict__ rc,
+                                                     int sl0) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= gc.nn) return;
-  restrict_site<T, G>(gf, gc, rf, rc, t, blockIdx.y);
+  restrict_site<T, G>(gf, gc, rf, rc, t, sl0 + (int)blockIdx.y);
+}
+
+// k-marching velocity restriction, P2-P1: a block is three wavefronts (the
+// velocity components) over the same 64 consecutive coarse columns (linear
+// index i + n1 j) of one chunk of coarse planes [k0, k1).  Step q (coarse
+// plane kq = k0 - 1 + q) loads the fine planes 2 kq and 2 kq + 1: each lane
+// the fine words at 2 i and 2 i + 1 of the fine rows 2 j - 2 .. 2 j + 1 of
+// every fine group the plane's restriction entries use (one batch of loads,
+// coalesced pairs instead of one gather per entry), the offsets 2 i - 1 and
+// 2 i - 2 from the previous lane; the entries add into coarse planes kq and
+// kq + 1 (two rotating accumulator planes), and plane kq is complete after
+// step q and written.  Windows overlap by two columns (the end lanes lack a
+// neighbour); clamped words reach only boundary coarse rows, which are
+// written as zero.  Same entries as restrict_site, summed in another order.
+constexpr int kRzmCols = 64;
+#ifndef HHG_RZM_KC
+#define HHG_RZM_KC 8  // coarse planes per chunk
+#endif
+template <typename T, int Q>
+__device__ __forceinline__ void rzm_step(const Geom& gf, const Geom& gc, __amdgpu_buffer_rsrc_t ru, int fcol_e,
+                                         int fcol_o, const int (&frow)[4], int kq, int k0, int k1, bool valid, int ic,
+                                         int jc, int col, T* __restrict__ rc, int d, T (&acc)[2][8]) {
+  const int n1f = gf.n1, s2f = n1f * n1f, nnb = gf.nn * (int)sizeof(T);
+#pragma unroll
+  for (int P = 0; P < 2; ++P) {
+    const int F = min(max(2 * kq + P, 0), n1f - 1) * s2f;
+    int ro_e[4], ro_o[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ro_e[r] = (F + frow[r] + fcol_e) * (int)sizeof(T);
+      ro_o[r] = (F + frow[r] + fcol_o) * (int)sizeof(T);
+    }
+    if (P == 0) {
+      if constexpr (Q == 0) gen::p2_Rzm_p0_q0<T>(ru, ro_e, ro_o, nnb, acc);
+      else gen::p2_Rzm_p0_q1<T>(ru, ro_e, ro_o, nnb, acc);
+    } else {
+      if constexpr (Q == 0) gen::p2_Rzm_p1_q0<T>(ru, ro_e, ro_o, nnb, acc);
+      else gen::p2_Rzm_p1_q1<T>(ru, ro_e, ro_o, nnb, acc);
+    }
+    // keep the next plane's loads below this plane's multiply-adds (left
+    // alone, the compiler issues both planes' 106 words at once: 256 VGPRs)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int g = 0; g < 8; ++g) asm volatile("" : "+v"(acc[q][g]));
+  }
+  if (valid && kq >= k0 && kq < k1) {
+    const int at = col + kq * gc.n1 * gc.n1;
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      rc[(size_t)d * gc.vstride + g * gc.nn + at] = vel_interior<8>(g, ic, jc, kq, gc.N) ? acc[Q][g] : T(0);
+  }
+#pragma unroll
+  for (int g = 0; g < 8; ++g) acc[Q][g] = T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(3 * kRzmCols) k_restrict_zm(Geom gf, Geom gc, const T* __restrict__ rf,
+                                                              T* __restrict__ rc, int kc, int ncb, int nmain) {
+  const int lin = xcd_block_of(nmain);
+  const int cb = lin % ncb, chunk = lin / ncb;
+  const int k0 = chunk * kc;
+  if (k0 >= gc.n1) return;  // whole block: grid padding
+  const int k1 = min(k0 + kc, gc.n1);
+  const int lane = threadIdx.x & (kRzmCols - 1), d = threadIdx.x / kRzmCols;
+  const int ncol = gc.n1 * gc.n1;
+  const int col = cb * (kRzmCols - 2) - 1 + lane;
+  const bool valid = lane >= 1 && lane <= kRzmCols - 2 && col < ncol;
+  const int cc = min(max(col, 0), ncol - 1);
+  const int ic = cc % gc.n1, jc = cc / gc.n1;
+  const int n1f = gf.n1;
+  const int fcol_e = 2 * ic, fcol_o = min(2 * ic + 1, n1f - 1);
+  int frow[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) frow[r] = min(max(2 * jc - 2 + r, 0), n1f - 1) * n1f;
+  const __amdgpu_buffer_rsrc_t ru =
+      gen::make_rsrc(rf + (size_t)d * gf.vstride, (unsigned)((size_t)gf.vstride * sizeof(T)));
+  T acc[2][8];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int g = 0; g < 8; ++g) acc[q][g] = T(0);
+  const int nq = k1 - k0 + 1;
+  for (int q = 0; q < nq; q += 2) {
+    rzm_step<T, 0>(gf, gc, ru, fcol_e, fcol_o, frow, k0 - 1 + q, k0, k1, valid, ic, jc, col, rc, d, acc);
+    if (q + 1 < nq)
+      rzm_step<T, 1>(gf, gc, ru, fcol_e, fcol_o, frow, k0 + q, k0, k1, valid, ic, jc, col, rc, d, acc);
+  }
 }
 
 // Prolongation: a fine thread evaluates the coarse function at its site of
@@ -1876,10 +1965,24 @@ void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const Transf
   KScope ks(s, KF_RESTRICT, p_sites(gf));
   (void)tt;
   // grid.y: (velocity group, component) slices and the pressure
-  if (gc.G == 1)
-    hipLaunchKernelGGL((k_restrict<T, 1>), dim3(nblocks(gc.nn), 4), dim3(kBlock), 0, s, gf, gc, rf, rc);
-  else
-    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 25), dim3(kBlock), 0, s, gf, gc, rf, rc);
+  if (gc.G == 1) {
+    hipLaunchKernelGGL((k_restrict<T, 1>), dim3(nblocks(gc.nn), 4), dim3(kBlock), 0, s, gf, gc, rf, rc, 0);
+  } else if (gc.n1 >= 33) {
+    // velocity: the k-marching form; the pressure slice as before.  From a
+    // coarse lattice of 33 nodes per edge on (48-tet cube, level 7 -> 6:
+    // 3.52 -> 1.05 ms in float64, 13.5 % -> 45 % of HBM; level 6 -> 5 0.350
+    // -> 0.147 ms); on the FMG's small levels the per-site gather is as fast
+    // (6-tet cube, FMG to level 5 with it on every level: 4.21 -> 4.25 ms)
+    const int ncb = (gc.n1 * gc.n1 + kRzmCols - 3) / (kRzmCols - 2);
+    int kc = std::min(HHG_RZM_KC, gc.n1);
+    while (kc > 2 && ncb * ((gc.n1 + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
+    const int nch = (gc.n1 + kc - 1) / kc;
+    const int nmain = (ncb * nch + 7) & ~7;
+    hipLaunchKernelGGL((k_restrict_zm<T>), dim3(nmain), dim3(3 * kRzmCols), 0, s, gf, gc, rf, rc, kc, ncb, nmain);
+    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 1), dim3(kBlock), 0, s, gf, gc, rf, rc, 24);
+  } else {
+    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 25), dim3(kBlock), 0, s, gf, gc, rf, rc, 0);
+  }
 }
 
 template <typename T>

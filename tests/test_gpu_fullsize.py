@@ -227,6 +227,41 @@ def test_residual_full_size_sampled_rows(disc, prec):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("prec", [hhg.HHG_F64, hhg.HHG_F32])
+def test_restriction_adjoint_full_size(prec):
+    """The restriction at the throughput size (48 tets, level 7 -> 6, the
+    k-marching velocity form) is the transpose of the interpolation (Sec.
+    3.3): <R r, x_c>_u = <r, P x_c>_u for random r and a coarse x_c with zero
+    boundary velocity (x_c = R r2), velocity parts.  Tolerance: 1e-12
+    (float64) / 1e-5 (float32) of sum |terms|, bounded by |r| |P x_c|."""
+    lib = Lib(hhg.HHG_P2P1, 6, 7, macro_refine=1)
+    torch = lib.torch
+    try:
+        dt = torch.float64 if prec == hhg.HHG_F64 else torch.float32
+        _, _, vwf, _ = lib.layout(7)
+        _, _, vwc, _ = lib.layout(6)
+        print(f"restriction adjoint full size: prec {prec}, {vwf} fine words", flush=True)
+        gen = torch.Generator(device=lib.dev).manual_seed(13513 + 3003)
+        r = torch.randn(vwf, generator=gen, dtype=torch.float64, device=lib.dev).to(dt)
+        r2 = torch.randn(vwf, generator=gen, dtype=torch.float64, device=lib.dev).to(dt)
+        rc = torch.zeros(vwc, dtype=dt, device=lib.dev)
+        xc = torch.zeros(vwc, dtype=dt, device=lib.dev)
+        hhg.hhg_restrict(lib.h, 7, r, rc, prec)
+        hhg.hhg_restrict(lib.h, 7, r2, xc, prec)
+        pxc = torch.zeros(vwf, dtype=dt, device=lib.dev)
+        hhg.hhg_prolong_add(lib.h, 6, xc, pxc, prec)
+        lhs, _ = hhg.hhg_dots(lib.h, 6, rc, xc, prec)
+        rhs, _ = hhg.hhg_dots(lib.h, 7, r, pxc, prec)
+        un, _ = hhg.hhg_dots(lib.h, 7, r, r, prec)
+        pn, _ = hhg.hhg_dots(lib.h, 7, pxc, pxc, prec)
+        scale = float(np.sqrt(un * pn))
+        tol = 1e-12 if prec == hhg.HHG_F64 else 1e-5
+        assert abs(lhs - rhs) <= tol * scale, (lhs, rhs, scale)
+    finally:
+        lib.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("disc", [hhg.HHG_P2P1, hhg.HHG_P1P1])
 def test_variable_viscosity_apply_full_size_sampled_rows(disc):
     """The mixed-precision workload's operator: 6 macro-tets, level 7
