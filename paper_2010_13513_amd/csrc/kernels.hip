@@ -957,19 +957,16 @@ __device__ __forceinline__ void prolong_slice(const Geom& gc, const Geom& gf, co
   const int pos = d * gf.vstride + gr * gf.nn + t;
   xf[pos] = add ? xf[pos] + a : a;
 }
-// Every slice of one fine site, the three components of a group together
-// (the one-workgroup V-cycle's form: same sums as prolong_slice).
+// One velocity group of one fine site, its three components together (one
+// table walk for the three).
 template <typename T, int G>
-__device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, const TransferTables<T>* __restrict__ tt,
-                                             const T* __restrict__ xc, T* __restrict__ xf, int add, int skip_boundary,
-                                             int t) {
-  int i, j, k;
-  decode(t, gf.n1, i, j, k);
+__device__ __forceinline__ void prolong_group(const Geom& gc, const Geom& gf, const TransferTables<T>* __restrict__ tt,
+                                              const T* __restrict__ xc, T* __restrict__ xf, int add, int skip_boundary,
+                                              int t, int i, int j, int k, int gr) {
   const int Nf = gf.N;
-#pragma unroll
-  for (int gr = 0; gr < G; ++gr) {
-    if (!vel_exists<G>(gr, i, j, k, Nf)) continue;
-    if (skip_boundary && !vel_interior<G>(gr, i, j, k, Nf)) continue;
+  {
+    if (!vel_exists<G>(gr, i, j, k, Nf)) return;
+    if (skip_boundary && !vel_interior<G>(gr, i, j, k, Nf)) return;
     int cls, base;
     if (G == 1) {
       cls = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
@@ -993,7 +990,32 @@ __device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, con
     xf[gf.vstride + pos] = add ? xf[gf.vstride + pos] + a1 : a1;
     xf[2 * gf.vstride + pos] = add ? xf[2 * gf.vstride + pos] + a2 : a2;
   }
+}
+// Every slice of one fine site (the one-workgroup V-cycle's form: same sums
+// as prolong_slice).
+template <typename T, int G>
+__device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, const TransferTables<T>* __restrict__ tt,
+                                             const T* __restrict__ xc, T* __restrict__ xf, int add, int skip_boundary,
+                                             int t) {
+  int i, j, k;
+  decode(t, gf.n1, i, j, k);
+#pragma unroll
+  for (int gr = 0; gr < G; ++gr) prolong_group<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, gr);
   prolong_slice<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, 3 * G);
+}
+// grid.y: the G velocity groups (three components each) and the pressure
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_prolong_g(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
+                                                      const T* __restrict__ xc, T* __restrict__ xf, int add,
+                                                      int skip_boundary) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gf.nn) return;
+  int i, j, k;
+  decode(t, gf.n1, i, j, k);
+  if ((int)blockIdx.y < G)
+    prolong_group<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, blockIdx.y);
+  else
+    prolong_slice<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, 3 * G);
 }
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
@@ -1991,8 +2013,16 @@ void launch_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const Transfe
   KScope ks(s, KF_PROLONG, p_sites(gf));
   // grid.y: (velocity group, component) slices and the pressure
   const dim3 block(kBlock);
+  // P2-P1 from a fine lattice of 65 nodes per edge on: a thread per (fine
+  // site, group), the three components sharing one table walk (48-tet cube,
+  // level 6 -> 7: float64 5.00 -> 4.05 ms, float32 2.91 -> 2.20 ms); on the
+  // FMG's small levels the per-component slices keep the latency chains
+  // shorter (6-tet FMG to level 5 with groups everywhere: 4.18 -> 4.20 ms)
   if (gf.G == 1)
     hipLaunchKernelGGL((k_prolong<T, 1>), dim3(nblocks(gf.nn), 4), block, 0, s, gc, gf, tt, xc, xf, (int)add,
+                       (int)skip_boundary);
+  else if (gf.n1 >= 65)
+    hipLaunchKernelGGL((k_prolong_g<T, 8>), dim3(nblocks(gf.nn), 9), block, 0, s, gc, gf, tt, xc, xf, (int)add,
                        (int)skip_boundary);
   else
     hipLaunchKernelGGL((k_prolong<T, 8>), dim3(nblocks(gf.nn), 25), block, 0, s, gc, gf, tt, xc, xf, (int)add,
