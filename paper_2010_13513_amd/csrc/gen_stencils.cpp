@@ -462,6 +462,53 @@ void emit_restriction_zm(FILE* f, const char* D, int vorder) {
     }
 }
 
+// Interpolation by coarse cubes: the coarse element functions of cube (i, j,
+// k) at its fine sites 2 (i, j, k) + (pi, pj, pk) of fine group g.  c holds
+// the coarse words at the doubled positions (a, b, c) in {0, 1, 2}^3 of the
+// cube, index a + 3 b + 9 c (coarse group of parity (a & 1, b & 1, c & 1) at
+// coarse index (i, j, k) + (a, b, c) / 2; P1 uses the corners a, b, c in {0,
+// 2} only); v[pi + 2 pj + 4 pk] receives the eight values.
+void emit_prolongation_cube(FILE* f, const char* D, int vorder) {
+  const int G = vorder == 1 ? 1 : 8;
+  const int vq = vorder == 1 ? 2 : 4;  // fine positions per coarse cube edge
+  int dir[8][3] = {};  // parity of each group
+  for (int p = 0; p < 8; ++p) {
+    const int g = group_of_parity(p & 1, (p >> 1) & 1, p >> 2);
+    for (int d = 0; d < 3; ++d) dir[g][d] = (p >> d) & 1;
+  }
+  for (int g = 0; g < G; ++g) {
+    std::fprintf(f, "template <typename T>\n__device__ __forceinline__ void %s_Pc_g%d(const T (&c)[27], T (&v)[8]) {\n",
+                 D, g);
+    for (int p = 0; p < 8; ++p) {
+      double t[3];
+      for (int d = 0; d < 3; ++d) {
+        const int par = (p >> d) & 1;
+        t[d] = (double)(vorder == 2 ? 2 * par + dir[g][d] : par) / vq;
+      }
+      std::string sum;
+      for (auto& w : interp_weights(vorder, t)) {
+        const int gc = std::get<0>(w);
+        const int o[3] = {std::get<1>(w), std::get<2>(w), std::get<3>(w)};
+        int idx = 0, mul = 1;
+        for (int d = 0; d < 3; ++d, mul *= 3) idx += mul * (2 * o[d] + (vorder == 2 ? dir[gc][d] : 0));
+        if (!sum.empty()) sum += " + ";
+        sum += "T(" + lit(std::get<4>(w)) + ") * c[" + std::to_string(idx) + "]";
+      }
+      std::fprintf(f, "  v[%d] = %s;\n", p, sum.empty() ? "T(0)" : sum.c_str());
+    }
+    std::fprintf(f, "}\n");
+  }
+  std::fprintf(f, "template <typename T>\n__device__ __forceinline__ void %s_Pc(int g, const T (&c)[27], T (&v)[8]) {\n",
+               D);
+  if (G == 1) {
+    std::fprintf(f, "  (void)g;\n  %s_Pc_g0(c, v);\n}\n\n", D);
+    return;
+  }
+  std::fprintf(f, "  switch (g) {\n");
+  for (int g = 0; g < G; ++g) std::fprintf(f, "    case %d: %s_Pc_g%d(c, v); break;\n", g, D, g);
+  std::fprintf(f, "    default: break;\n  }\n}\n\n");
+}
+
 double diag_of(const Row& r, int g) {
   for (auto& e : r)
     if (e.g == g && e.di == 0 && e.dj == 0 && e.dk == 0) return e.w[0];
@@ -512,6 +559,7 @@ int main(int argc, char** argv) {
     emit_boundary_rows(f, es, D, G);
     emit_restriction(f, D, vorder);
     if (vorder == 2) emit_restriction_zm(f, D, vorder);
+    emit_prolongation_cube(f, D, vorder);
   }
   std::fprintf(f, "}  // namespace gen\n}  // namespace hhg\n");
   std::fclose(f);

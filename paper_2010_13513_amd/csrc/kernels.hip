@@ -1003,20 +1003,6 @@ __device__ __forceinline__ void prolong_site(const Geom& gc, const Geom& gf, con
   for (int gr = 0; gr < G; ++gr) prolong_group<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, gr);
   prolong_slice<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, 3 * G);
 }
-// grid.y: the G velocity groups (three components each) and the pressure
-template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_prolong_g(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
-                                                      const T* __restrict__ xc, T* __restrict__ xf, int add,
-                                                      int skip_boundary) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= gf.nn) return;
-  int i, j, k;
-  decode(t, gf.n1, i, j, k);
-  if ((int)blockIdx.y < G)
-    prolong_group<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, blockIdx.y);
-  else
-    prolong_slice<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, 3 * G);
-}
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const TransferTables<T>* __restrict__ tt,
                                                     const T* __restrict__ xc, T* __restrict__ xf, int add,
@@ -1026,6 +1012,86 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Geom gc, Geom gf, const Tran
   int i, j, k;
   decode(t, gf.n1, i, j, k);
   prolong_slice<T, G>(gc, gf, tt, xc, xf, add, skip_boundary, t, i, j, k, blockIdx.y);
+}
+
+// Prolongation by coarse cubes (large levels): a thread owns coarse cube (i,
+// j, k) and one slice -- velocity component blockIdx.y < 3, or the pressure
+// (blockIdx.y == 3, the P1 function on the vertex lattice) -- loads the
+// cube's coarse words once (27 for P2, its 8 corners for P1) and writes the
+// fine sites 2 (i, j, k) + {0, 1}^3 of every fine group with the generated
+// interpolation (no table walk, no per-site class).  A fine group's eight
+// words are read as one batch before its eight stores; a word's address is
+// clamped to the cube's own site when the site is not written, so every load
+// is in bounds and unconditional.
+template <typename T, int G, bool ADD>
+__global__ void __launch_bounds__(kBlock) k_prolong_cube(Geom gc, Geom gf, const T* __restrict__ xc,
+                                                         T* __restrict__ xf, int skip_boundary) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= gc.nn) return;
+  int i, j, k;
+  decode(t, gc.n1, i, j, k);
+  const int sl = blockIdx.y;
+  const bool pres = sl == 3;
+  const int n1c = gc.n1;
+  const int oi = min(i + 1, n1c - 1) - i, oj = (min(j + 1, n1c - 1) - j) * n1c,
+            ok = (min(k + 1, n1c - 1) - k) * n1c * n1c;
+  const T* src = xc + (size_t)(pres ? 3 : sl) * gc.vstride + t;
+  T c[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) c[q] = T(0);
+  if (G == 8 && !pres) {
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int a = q % 3, b = (q / 3) % 3, e = q / 9;
+      const int gr = (a & 1) + 2 * (b & 1) + 4 * (e & 1);  // parity -> group below
+      constexpr int kGroupOfParity[8] = {0, 1, 2, 4, 3, 5, 6, 7};
+      c[q] = src[kGroupOfParity[gr] * gc.nn + (a == 2 ? oi : 0) + (b == 2 ? oj : 0) + (e == 2 ? ok : 0)];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int a = q & 1, b = (q >> 1) & 1, e = q >> 2;
+      c[2 * a + 6 * b + 18 * e] = src[(a ? oi : 0) + (b ? oj : 0) + (e ? ok : 0)];
+    }
+  }
+  const int n1f = gf.n1, Nf = gf.N;
+  const int fi = 2 * i, fj = 2 * j, fk = 2 * k;
+  T* dst = xf + (size_t)(pres ? 3 : sl) * gf.vstride + (fi + n1f * (fj + n1f * fk));
+  if (pres || G == 1) {
+    T v[8], old[8];
+    gen::p1_Pc_g0<T>(c, v);
+    bool w[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int pi = p & 1, pj = (p >> 1) & 1, pk = p >> 2;
+      w[p] = fi + pi <= Nf && fj + pj <= Nf && fk + pk <= Nf &&
+             (pres || !skip_boundary || vel_interior<1>(0, fi + pi, fj + pj, fk + pk, Nf));
+      if (ADD) old[p] = dst[w[p] ? pi + n1f * (pj + n1f * pk) : 0];
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (w[p]) dst[(p & 1) + n1f * (((p >> 1) & 1) + n1f * (p >> 2))] = ADD ? old[p] + v[p] : v[p];
+    return;
+  }
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    T v[8], old[8];
+    gen::p2_Pc<T>(g, c, v);
+    bool w[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int pi = p & 1, pj = (p >> 1) & 1, pk = p >> 2;
+      w[p] = vel_exists<8>(g, fi + pi, fj + pj, fk + pk, Nf) &&
+             (!skip_boundary || vel_interior<8>(g, fi + pi, fj + pj, fk + pk, Nf));
+      if (ADD) old[p] = dst[g * gf.nn + (w[p] ? pi + n1f * (pj + n1f * pk) : 0)];
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (w[p]) {
+        const int o = g * gf.nn + (p & 1) + n1f * (((p >> 1) & 1) + n1f * (p >> 2));
+        dst[o] = ADD ? old[p] + v[p] : v[p];
+      }
+  }
 }
 
 // Boundary velocity values of the coarse level from the coincident fine nodes.
@@ -2011,18 +2077,27 @@ template <typename T>
 void launch_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, const T* xc, T* xf,
                     bool add, bool skip_boundary) {
   KScope ks(s, KF_PROLONG, p_sites(gf));
-  // grid.y: (velocity group, component) slices and the pressure
   const dim3 block(kBlock);
-  // P2-P1 from a fine lattice of 65 nodes per edge on: a thread per (fine
-  // site, group), the three components sharing one table walk (48-tet cube,
-  // level 6 -> 7: float64 5.00 -> 4.05 ms, float32 2.91 -> 2.20 ms); on the
-  // FMG's small levels the per-component slices keep the latency chains
-  // shorter (6-tet FMG to level 5 with groups everywhere: 4.18 -> 4.20 ms)
-  if (gf.G == 1)
+  // From a fine lattice of 65 nodes per edge on: a thread per (coarse cube,
+  // slice), generated interpolation (48-tet cube, level 6 -> 7, float64:
+  // P2-P1 4.06 -> 1.47 ms, 22 % -> 61 % of 8 TB/s; P1-P1 0.73 -> 0.25 ms);
+  // on the FMG's small levels the per-site slices keep more threads in
+  // flight (6-tet FMG to level 5 with cubes everywhere: 4.20 -> 4.27 ms)
+  if (gf.n1 >= 65) {
+    const dim3 grid(nblocks(gc.nn), 4);
+    if (gf.G == 1) {
+      if (add)
+        hipLaunchKernelGGL((k_prolong_cube<T, 1, true>), grid, block, 0, s, gc, gf, xc, xf, (int)skip_boundary);
+      else
+        hipLaunchKernelGGL((k_prolong_cube<T, 1, false>), grid, block, 0, s, gc, gf, xc, xf, (int)skip_boundary);
+    } else {
+      if (add)
+        hipLaunchKernelGGL((k_prolong_cube<T, 8, true>), grid, block, 0, s, gc, gf, xc, xf, (int)skip_boundary);
+      else
+        hipLaunchKernelGGL((k_prolong_cube<T, 8, false>), grid, block, 0, s, gc, gf, xc, xf, (int)skip_boundary);
+    }
+  } else if (gf.G == 1)
     hipLaunchKernelGGL((k_prolong<T, 1>), dim3(nblocks(gf.nn), 4), block, 0, s, gc, gf, tt, xc, xf, (int)add,
-                       (int)skip_boundary);
-  else if (gf.n1 >= 65)
-    hipLaunchKernelGGL((k_prolong_g<T, 8>), dim3(nblocks(gf.nn), 9), block, 0, s, gc, gf, tt, xc, xf, (int)add,
                        (int)skip_boundary);
   else
     hipLaunchKernelGGL((k_prolong<T, 8>), dim3(nblocks(gf.nn), 25), block, 0, s, gc, gf, tt, xc, xf, (int)add,

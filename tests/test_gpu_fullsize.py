@@ -293,3 +293,82 @@ def test_variable_viscosity_apply_full_size_sampled_rows(disc):
         check_rows(rows, bnd, xv, got)
     finally:
         lib.close()
+
+
+def _lattice_xyz(torch, dev, M):
+    """Coordinates of the (M+1)^3 lattice in plain order X + (M+1)(Y + (M+1) Z)."""
+    g = torch.arange(M + 1, dtype=torch.float64, device=dev) / M
+    z, y, x = torch.meshgrid(g, g, g, indexing="ij")
+    return x.reshape(-1), y.reshape(-1), z.reshape(-1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("disc,prec,lmin,L,refine", [
+    (hhg.HHG_P2P1, hhg.HHG_F64, 6, 7, 1), (hhg.HHG_P2P1, hhg.HHG_F32, 6, 7, 1),
+    (hhg.HHG_P1P1, hhg.HHG_F64, 6, 7, 1), (hhg.HHG_P2P1, hhg.HHG_F64, 5, 6, 0)])
+def test_prolongation_reproduces_polynomials_full_size(disc, prec, lmin, L, refine):
+    """Prolong-add at the throughput size (48 tets, level 6 -> 7, the
+    coarse-cube form; and 6 tets, level 5 -> 6, its smallest lattice): the
+    interpolation is the embedding of the coarse element spaces (Sec. 3.3), so
+    coarse nodal values of a quadratic velocity (P2; linear for P1) and a
+    linear pressure arrive as the fine nodal values of the same polynomials,
+    added to a random fine vector at the unknown velocity sites and at every
+    pressure node; Dirichlet boundary velocity words keep their values
+    exactly.  Tolerance: 1e-13 (float64) / 2e-6 (float32) of the largest
+    polynomial value plus the random word."""
+    lib = Lib(disc, lmin, L, macro_refine=refine)
+    torch = lib.torch
+    try:
+        dev = lib.dev
+        vo = 2 if disc == hhg.HHG_P2P1 else 1
+        dt = torch.float64 if prec == hhg.HHG_F64 else torch.float32
+        Nf, _, vwf, lwf = lib.layout(L)
+        Nc, _, vwc, lwc = lib.layout(L - 1)
+        assert Nf == 2 * Nc and Nf >= 64
+        print(f"prolongation polynomials: disc {disc} prec {prec} N {Nc} -> {Nf}", flush=True)
+
+        def fields(N):
+            x, y, z = _lattice_xyz(torch, dev, vo * N)
+            if vo == 2:
+                u = [0.3 + x - 2 * y + 0.5 * z + 3 * x * y - y * z + 2 * z * z - x * x,
+                     -1 + 0.25 * x + y * y - 2 * x * z + 1.5 * y * z,
+                     2 - x + 0.75 * y - z + x * z - 3 * y * y + 0.5 * x * y]
+            else:
+                u = [0.3 + x - 2 * y + 0.5 * z, -1 + 0.25 * x + 1.5 * z, 2 - x + 0.75 * y - z]
+            bnd = (x == 0) | (x == 1) | (y == 0) | (y == 1) | (z == 0) | (z == 1)
+            del x, y, z
+            px, py, pz = _lattice_xyz(torch, dev, N)
+            p = 0.5 - px + 2 * py + 0.25 * pz
+            return u, p, bnd
+
+        u, p, _ = fields(Nc)
+        src = torch.cat(u + [p])
+        del u, p
+        assert src.numel() == lwc
+        xc = torch.zeros(vwc, dtype=dt, device=dev)
+        hhg.hhg_vec_from_lattice(lib.h, L - 1, src, xc, prec)
+        del src
+        gen = torch.Generator(device=dev).manual_seed(13513 + 3004)
+        rnd = torch.randn(lwf, generator=gen, dtype=torch.float64, device=dev)
+        xf = torch.zeros(vwf, dtype=dt, device=dev)
+        hhg.hhg_vec_from_lattice(lib.h, L, rnd, xf, prec)
+        before = torch.empty(lwf, dtype=torch.float64, device=dev)
+        hhg.hhg_vec_to_lattice(lib.h, L, xf, before, prec)  # the random words as stored
+        del rnd
+        hhg.hhg_prolong_add(lib.h, L - 1, xc, xf, prec)
+        got = torch.empty(lwf, dtype=torch.float64, device=dev)
+        hhg.hhg_vec_to_lattice(lib.h, L, xf, got, prec)
+        torch.cuda.synchronize()
+        u, p, bnd = fields(Nf)
+        m3 = (vo * Nf + 1) ** 3
+        tol = (1e-13 if prec == hhg.HHG_F64 else 2e-6) * (max(float(t.abs().max()) for t in u + [p]) +
+                                                         float(before.abs().max()))
+        for d in range(3):
+            g, b0 = got[d * m3:(d + 1) * m3], before[d * m3:(d + 1) * m3]
+            assert torch.equal(g[bnd], b0[bnd]), f"boundary velocity words changed, component {d}"
+            err = float((g - b0 - u[d])[~bnd].abs().max())
+            assert err <= tol, (d, err, tol)
+        err = float((got[3 * m3:] - before[3 * m3:] - p).abs().max())
+        assert err <= tol, ("p", err, tol)
+    finally:
+        lib.close()
