@@ -870,12 +870,25 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
     }
     // r_p = g - B u + C p, then p -= omega D^{-1} r_p.  With constant
     // coefficients the k-marching apply in its pressure-rows-only form (a
-    // few loads per lattice point, no velocity rows written).
-    if (!lv.nu64)
-      op_apply<T>(h, l, full_mask(h), x, b, r, true, false, true);
-    else
-      op_apply<T>(h, l, full_mask(h) & 12, x, b, r, true, false, true);
-    launch_pressure_step<T>(S(h), lv.g, dinv<T>(lv), x, r, (T)omega);
+    // few loads per lattice point, no velocity rows written).  Taylor-Hood
+    // pressure rows read no p (C = 0): the step is applied in place by the
+    // residual launch itself (no residual stored, one launch less per
+    // iteration), except where the residual is rounded to bfloat16 first.
+    const bool bf16_level = std::is_same<T, float>::value && l - h->lmin < h->bf16_levels;
+    if (!lv.nu64 && h->disc == HHG_P2P1 && !bf16_level) {
+      PStep<T> ps;
+      ps.p = x + 3 * (size_t)lv.g.vstride;
+      ps.dinv = dinv<T>(lv);
+      ps.omega = (T)omega;
+      launch_apply<T>(S(h), lv.g, lconst<T>(lv), tables<T>(lv), x, b, r, full_mask(h), true, false, true, lv.bnd,
+                      lv.nbnd, ps);
+    } else {
+      if (!lv.nu64)
+        op_apply<T>(h, l, full_mask(h), x, b, r, true, false, true);
+      else
+        op_apply<T>(h, l, full_mask(h) & 12, x, b, r, true, false, true);
+      launch_pressure_step<T>(S(h), lv.g, dinv<T>(lv), x, r, (T)omega);
+    }
     round_out<T>(h, l, x, 0, 3 * (size_t)lv.g.vstride, lv.g.nn, 1);
   }
 }

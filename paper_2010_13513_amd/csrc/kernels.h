@@ -161,10 +161,23 @@ void launch_vcycle_small(hipStream_t s, const SmallLevel<T>* lv, const SmallCycl
 // Allow kSmallLdsBytes of dynamic LDS for the one-workgroup V-cycle kernels.
 void small_kernel_attributes();
 
+// Uzawa pressure step fused into the pressure rows of a residual launch:
+// with p set, a pressure row's residual r_k is not stored but applied as
+// p_k -= omega dinv_k r_k (eq. uzawa-pressure).  Only for operators whose
+// pressure rows do not read p (no C block: Taylor-Hood), so that the update
+// in place races with no read.
+template <typename T>
+struct PStep {
+  T* p = nullptr;
+  const T* dinv = nullptr;
+  T omega = T(0);
+};
+
 // Launchers (kernels.hip).  All asynchronous on `s`.
 template <typename T>
 void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const Tables<T>* tb, const T* x, const T* b,
-                  T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd);
+                  T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd,
+                  const PStep<T>& ps = PStep<T>{});
 template <typename T>
 void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* x, const T* b, int colour);
 template <typename T>

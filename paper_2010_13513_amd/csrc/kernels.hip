@@ -249,7 +249,8 @@ __device__ __forceinline__ int xcd_block_of(int nmain) {
 template <typename T, int G>
 __device__ __forceinline__ void prow_bnd_block(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                               const int* __restrict__ bnd, int nbnd, int nmain, int bs);
+                                               const int* __restrict__ bnd, int nbnd, int nmain, int bs,
+                                               PStep<T> ps);
 
 // Pressure row value at any node t = (i, j, k): interior rows from the
 // generated interior stencils, boundary rows from the generated per-class
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_apply(Geom g, LevelConst<T> lc, cons
                                                   int vel_rows, int p_rows, const int* __restrict__ bnd, int nbnd,
                                                   int nmain) {
   if ((int)blockIdx.x >= nmain) {
-    prow_bnd_block<T, G>(g, lc, x, b, y, opmask, has_b, bnd, nbnd, nmain, kBlock);
+    prow_bnd_block<T, G>(g, lc, x, b, y, opmask, has_b, bnd, nbnd, nmain, kBlock, PStep<T>{});
     return;
   }
   const int t = xcd_block_of(nmain) * kBlock + threadIdx.x;
@@ -434,7 +435,7 @@ struct ZmCol {
 template <typename T, int G, int D, int Q, bool VEL, bool HB>
 __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
                                         const T* __restrict__ b, T* __restrict__ y, const ZmCol<T>& c, int q,
-                                        T (&acc)[3][G + 1], T (*pshare)[3][kZmCols]) {
+                                        T (&acc)[3][G + 1], T (*pshare)[3][kZmCols], const PStep<T>& ps) {
   constexpr int S = (Q + 2) % 3;  // slot of the row plane completed by this step
   const int N = g.N, s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn, vs = g.vstride;
   const int kp = c.k0 - 1 + q;
@@ -477,7 +478,11 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
     if (D == 0 && c.valid && c.i >= 1 && c.j >= 1 && kr >= 1 && c.i <= N - 1 && c.j <= N - 1 && kr <= N - 1) {
       const T v = c.sp * (pshare[q & 1][0][lane] + pshare[q & 1][1][lane] + pshare[q & 1][2][lane]);
       const int pp = 3 * vs + at;
-      y[pp] = HB ? bv[G] - v : v;
+      const T r = HB ? bv[G] - v : v;
+      if (HB && !VEL && ps.p)
+        ps.p[at] -= ps.omega * ps.dinv[at] * r;
+      else
+        y[pp] = r;
     }
   }
 #pragma unroll
@@ -487,7 +492,7 @@ __device__ __forceinline__ void zm_step(const Geom& g, const LevelConst<T>& lc, 
 template <typename T, int G, int D, bool VEL, bool HB>
 __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
                                        const T* __restrict__ b, T* __restrict__ y, const ZmCol<T>& c,
-                                       T (*pshare)[3][kZmCols]) {
+                                       T (*pshare)[3][kZmCols], const PStep<T>& ps) {
   T acc[3][G + 1];
 #pragma unroll
   for (int s = 0; s < 3; ++s)
@@ -495,19 +500,20 @@ __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, c
     for (int r = 0; r <= G; ++r) acc[s][r] = T(0);
   const int nq = c.k1 - c.k0 + 2;
   for (int q = 0; q < nq; q += 3) {
-    zm_step<T, G, D, 0, VEL, HB>(g, lc, x, b, y, c, q, acc, pshare);
-    if (q + 1 < nq) zm_step<T, G, D, 1, VEL, HB>(g, lc, x, b, y, c, q + 1, acc, pshare);
-    if (q + 2 < nq) zm_step<T, G, D, 2, VEL, HB>(g, lc, x, b, y, c, q + 2, acc, pshare);
+    zm_step<T, G, D, 0, VEL, HB>(g, lc, x, b, y, c, q, acc, pshare, ps);
+    if (q + 1 < nq) zm_step<T, G, D, 1, VEL, HB>(g, lc, x, b, y, c, q + 1, acc, pshare, ps);
+    if (q + 2 < nq) zm_step<T, G, D, 2, VEL, HB>(g, lc, x, b, y, c, q + 2, acc, pshare, ps);
   }
 }
 
 template <typename T, int G, bool VEL, bool HB>
 __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
                                                           const T* __restrict__ b, T* __restrict__ y, int kc, int ncb,
-                                                          const int* __restrict__ bnd, int nbnd, int nmain) {
+                                                          const int* __restrict__ bnd, int nbnd, int nmain,
+                                                          PStep<T> ps) {
   __shared__ T pshare[2][3][kZmCols];
   if ((int)blockIdx.x >= nmain) {
-    prow_bnd_block<T, G>(g, lc, x, b, y, G == 1 ? 15 : 7, (int)HB, bnd, nbnd, nmain, 3 * kZmCols);
+    prow_bnd_block<T, G>(g, lc, x, b, y, G == 1 ? 15 : 7, (int)HB, bnd, nbnd, nmain, 3 * kZmCols, ps);
     return;
   }
   const int lin = xcd_block_of(nmain);
@@ -534,18 +540,19 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
   for (int dj = -1; dj <= 1; ++dj) c.nb[dj + 1] = min(max(c.col + dj * n1, 0), ncol - 1);
   const int wave = threadIdx.x / kZmCols;  // velocity component
   if (wave == 0)
-    zm_run<T, G, 0, VEL, HB>(g, lc, x, b, y, c, pshare);
+    zm_run<T, G, 0, VEL, HB>(g, lc, x, b, y, c, pshare, ps);
   else if (wave == 1)
-    zm_run<T, G, 1, VEL, HB>(g, lc, x, b, y, c, pshare);
+    zm_run<T, G, 1, VEL, HB>(g, lc, x, b, y, c, pshare, ps);
   else
-    zm_run<T, G, 2, VEL, HB>(g, lc, x, b, y, c, pshare);
+    zm_run<T, G, 2, VEL, HB>(g, lc, x, b, y, c, pshare, ps);
 }
 
 // Pressure rows at boundary nodes (list), boundary-class stencils.
 template <typename T, int G>
 __device__ __forceinline__ void prow_bnd_block(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ y, int opmask, int has_b,
-                                               const int* __restrict__ bnd, int nbnd, int nmain, int bs) {
+                                               const int* __restrict__ bnd, int nbnd, int nmain, int bs,
+                                               PStep<T> ps) {
   const int q = ((int)blockIdx.x - nmain) * bs + (int)threadIdx.x;
   if (q >= nbnd) return;
   const int t = bnd[q];
@@ -553,7 +560,11 @@ __device__ __forceinline__ void prow_bnd_block(const Geom& g, const LevelConst<T
   decode(t, g.n1, i, j, k);
   const T acc = prow_value<T, G>(g, lc, x, opmask, t, i, j, k);
   const int pp = 3 * g.vstride + t;
-  y[pp] = has_b ? b[pp] - acc : acc;
+  const T r = has_b ? b[pp] - acc : acc;
+  if (ps.p)
+    ps.p[t] -= ps.omega * ps.dinv[t] * r;
+  else
+    y[pp] = r;
 }
 
 
@@ -1827,7 +1838,8 @@ static double p_sites(const Geom& g) {
 
 template <typename T>
 void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const Tables<T>* tb, const T* x, const T* b,
-                  T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd) {
+                  T* y, int opmask, bool has_b, bool vel_rows, bool p_rows, const int* bnd, int nbnd,
+                  const PStep<T>& ps) {
   if (!(vel_rows || p_rows)) return;
   KScope ks(s, KF_APPLY, p_sites(g));
   const int hb = has_b, vr = vel_rows, pr = p_rows;
@@ -1863,10 +1875,13 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     // the velocity words are still loaded for B u, the velocity rows are
     // neither accumulated nor written and their b words not read
     const unsigned dyn = sizeof(T) == 4 && g.G == 8 && g.n1 >= 200 ? kZmF32Lds : 0;
+    // the fused pressure step: the pressure-residual form only
+    const bool fused = ps.p && !vel_rows && has_b;
     auto go = [&](auto gg, auto vel, auto hbc) {
       constexpr int GG = decltype(gg)::value;
       constexpr bool V = decltype(vel)::value, H = decltype(hbc)::value;
-      hipLaunchKernelGGL((k_apply_zm<T, GG, V, H>), grid, block, dyn, s, g, lc, x, b, y, kc, ncb, bnd, nb_bnd, nmain);
+      hipLaunchKernelGGL((k_apply_zm<T, GG, V, H>), grid, block, dyn, s, g, lc, x, b, y, kc, ncb, bnd, nb_bnd, nmain,
+                         fused ? ps : PStep<T>{});
     };
     using I1 = std::integral_constant<int, 1>;
     using I8 = std::integral_constant<int, 8>;
@@ -1883,6 +1898,8 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
       else
         hb ? go(I8{}, BF{}, BT{}) : go(I8{}, BF{}, BF{});
     }
+    if (ps.p && !fused)
+      HHG_LAUNCH((k_pstep<T>), nblocks(g.nn), s, g.nn, ps.dinv, ps.p, y + 3 * (size_t)g.vstride, ps.omega);
   } else {
     const int nmain = (int)nblocks8(g.nn);
     const unsigned nb = (unsigned)(nmain + (nb_bnd + kBlock - 1) / kBlock);
@@ -1897,6 +1914,8 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
       else
         HHG_LAUNCH((k_apply<T, 8, false>), nb, s, g, lc, x, b, y, opmask, hb, vr, pr, bnd, nb_bnd, nmain);
     }
+    if (ps.p)  // the per-site form stores the residual; the step follows
+      HHG_LAUNCH((k_pstep<T>), nblocks(g.nn), s, g.nn, ps.dinv, ps.p, y + 3 * (size_t)g.vstride, ps.omega);
   }
   (void)tb;
 }
@@ -2273,7 +2292,7 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
 
 #define HHG_INSTANTIATE(T)                                                                                          \
   template void launch_apply<T>(hipStream_t, const Geom&, const LevelConst<T>&, const Tables<T>*, const T*,        \
-                                const T*, T*, int, bool, bool, bool, const int*, int);                              \
+                                const T*, T*, int, bool, bool, bool, const int*, int, const PStep<T>&);             \
   template void launch_gs_colour<T>(hipStream_t, const Geom&, const LevelConst<T>&, T*, const T*, int);             \
   template void launch_pressure_step<T>(hipStream_t, const Geom&, const T*, T*, const T*, T);                       \
   template void launch_schur_diag<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, int, T*,                 \
