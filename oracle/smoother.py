@@ -7,12 +7,16 @@ forward and one backward sweep.
 
 Orderings.  The paper relaxes in lexicographic order; here every Gauss-Seidel
 sweep visits colour classes that have no coupling inside a class, so each
-class can be updated at once.  P1 nodes (I,J,K): colour (I+J+K) mod 4.  P2
-nodes on the doubled lattice (X,Y,Z): vertex nodes take ((X+Y+Z)/2) mod 4,
-edge nodes take 4 + the index of their parity class in mesh.EDGE_DIRS.  A
-forward sweep visits colours in ascending order, a backward sweep in
-descending order.  Inside a colour every update reads the state at the start
-of that colour.
+class can be updated at once.  P1 nodes (I,J,K): colour (I+J+K) mod 2.  P2
+nodes on the doubled lattice (X,Y,Z): vertex nodes take ((X+Y+Z)/2) mod 2,
+edge nodes take 2 + the index of their parity class in mesh.EDGE_DIRS.  Two
+vertex classes suffice because the stiffness of a Kuhn tetrahedron couples
+two vertex functions through grad(lambda_i) . grad(lambda_j) (P1 and the P2
+vertex functions alike), which vanishes for every edge off the lattice axes
+(face and body diagonals), so vertex nodes are coupled only to their six axis
+neighbours.  A forward sweep visits colours in ascending order, a backward
+sweep in descending order.  Inside a colour every update reads the state at
+the start of that colour.
 
 Pressure Schur approximation: S_hat = omega^{-1} D with a positive diagonal
 D, so the pressure step is p <- p - omega D^{-1} (g - B u + C p), and
@@ -40,19 +44,19 @@ def colours(lev):
         return lev.colour
     c = lev.vcoords
     if lev.vorder == 1:
-        return (c.sum(axis=1)) % 4
+        return (c.sum(axis=1)) % 2
     par = c % 2
     out = np.full(c.shape[0], -1, dtype=np.int64)
     isv = np.all(par == 0, axis=1)
-    out[isv] = (c[isv].sum(axis=1) // 2) % 4
+    out[isv] = (c[isv].sum(axis=1) // 2) % 2
     for g, d in enumerate(mesh.EDGE_DIRS):
         sel = np.all(par == np.array(d), axis=1)
-        out[sel] = 4 + g
+        out[sel] = 2 + g
     return out
 
 
 def n_colours(vorder):
-    return 4 if vorder == 1 else 11
+    return 2 if vorder == 1 else 9
 
 
 def schur_diagonal(stokes, mode):

@@ -413,7 +413,7 @@ void build_neumann(hhg_hier h, const ElementSet& es) {
     const Geom& g = lv.g;
     const int N = g.N, n1 = g.n1, nn = g.nn;
     const int M = G == 1 ? N : 2 * N;
-    const int ncol = G == 1 ? 4 : 11;
+    const int ncol = gs_colours(G);
     std::vector<std::vector<std::pair<int, int>>> bycol(ncol);  // (pos, slot)
     std::vector<char> used(kNeuSlots, 0);
     for (int gr = 0; gr < G; ++gr)
@@ -434,7 +434,7 @@ void build_neumann(hhg_hier h, const ElementSet& es) {
               mul *= 3;
             }
             if (!exists || faces == 0 || (faces & ~h->nf)) continue;
-            const int colour = gr == 0 ? (i + j + k) % 4 : 3 + gr;
+            const int colour = gr == 0 ? (i + j + k) % kGsVertexColours : kGsVertexColours - 1 + gr;
             bycol[colour].push_back({gr * nn + lin(i, j, k, n1), gr * 27 + cls});
             used[gr * 27 + cls] = 1;
           }
@@ -456,8 +456,14 @@ void build_neumann(hhg_hier h, const ElementSet& es) {
       const int ci = rep[cls % 3], cj = rep[(cls / 3) % 3], ck = rep[cls / 9];
       HostStencil A, BT;
       double diag = 0.0;
-      for (auto& e : row_stencil(es, 'A', gr, ci, cj, ck, 4)) {
-        if (e.w[0] == 0.0) continue;
+      // entries that vanish mathematically (vertex pairs off the lattice
+      // axes) carry rounding residue of the element sums: dropped, as in the
+      // generated interior rows, so no Gauss-Seidel colour reads its own sites
+      const auto arow = row_stencil(es, 'A', gr, ci, cj, ck, 4);
+      double amax = 0.0;
+      for (auto& e : arow) amax = std::max(amax, std::fabs(e.w[0]));
+      for (auto& e : arow) {
+        if (std::fabs(e.w[0]) <= 1e-13 * amax) continue;
         A.off.push_back((e.g - gr) * nn + lin(e.di, e.dj, e.dk, n1));
         A.w.push_back(e.w[0] * sA);
         if (e.g == gr && e.di == 0 && e.dj == 0 && e.dk == 0) diag = e.w[0] * sA;
@@ -854,13 +860,14 @@ void op_smooth(hhg_hier h, int l, T* x, const T* b, int iters, int gs, int xi, d
     return;
   }
   Level& lv = h->L(l);
-  const int ncol = h->G == 1 ? 4 : 11;
+  const int ncol = gs_colours(h->G);
   T* r = rbuf<T>(lv);
-  auto colour = [&](int c) {  // colour c < 4 writes the vertex group, c >= 4 the edge group c - 3
+  auto colour = [&](int c) {  // a vertex colour writes the vertex group, the others edge group c - 1
     launch_gs_colour<T>(S(h), lv.g, lconst<T>(lv), x, b, c);
     if (lv.neu_n)
       launch_neu_gs<T>(S(h), lv.g, neutab<T>(lv), lv.neu(), lv.neu_coff[c], lv.neu_coff[c + 1] - lv.neu_coff[c], x, b);
-    round_out<T>(h, l, x, lv.g.vstride, c < 4 ? 0 : (size_t)(c - 3) * lv.g.nn, lv.g.nn, 3);
+    round_out<T>(h, l, x, lv.g.vstride, c < kGsVertexColours ? 0 : (size_t)(c - kGsVertexColours + 1) * lv.g.nn,
+                 lv.g.nn, 3);
   };
   for (int it = 0; it < iters; ++it) {
     for (int s = 0; s < xi; ++s) {
@@ -1920,7 +1927,7 @@ hhg_status hhg_estimate_omega(hhg_hier h, int level, const double* v0, int iters
       launch_scale<double>(s, v + vs3, g.nn, h->sums, 0);
     };
     normalise();
-    const int ncol = h->G == 1 ? 4 : 11;
+    const int ncol = gs_colours(h->G);
     for (int it = 0; it < iters; ++it) {
       op_apply<double>(h, level, 2, v, nullptr, y, false, true, false);   // B^T v
       launch_fill<double>(s, z, lv.vec_words, 0.0);

@@ -13,6 +13,15 @@ struct Geom {
   int N, n1, nn, G, vstride, nf;
 };
 
+// Gauss-Seidel colours of the lattice velocity: the vertex group (P1: every
+// node) in two classes by (i + j + k) mod 2, then one colour per P2 edge
+// group.  Two vertex classes suffice: on the Kuhn lattice the stiffness
+// couples two vertex nodes only along a lattice axis (for the other edges of
+// a Kuhn tetrahedron the barycentric gradients are orthogonal, so their
+// entries vanish).
+constexpr int kGsVertexColours = 2;
+__host__ __device__ constexpr int gs_colours(int G) { return G == 1 ? kGsVertexColours : kGsVertexColours + 7; }
+
 // Outflow-face velocity rows (Sec. 2, natural boundary condition): sites on
 // Neumann faces (off the closed Dirichlet part) are unknowns whose rows are
 // the element sums inside the cube, i.e. the boundary-class rows of their

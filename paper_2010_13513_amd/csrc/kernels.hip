@@ -596,19 +596,19 @@ __device__ __forceinline__ void gs_update(const Geom& g, const LevelConst<T>& lc
   ud[pos] += (b[d * g.vstride + pos] - lc.a * a0 - lc.b * c) * ai;
 }
 
-// One colour of the vertex group: interior nodes with (i+j+k) mod 4 == c.
+// One colour of the vertex group: interior nodes with (i+j+k) mod 2 == c.
 // u_d += (f_d - (A u_d) - (B^T p)_d) / a_gg.
 __host__ __device__ __forceinline__ int gs_vertex_count(const Geom& g) {
-  const int nr = g.N - 1, ni = (nr + 3) >> 2;
+  const int nr = g.N - 1, ni = (nr + 1) >> 1;
   return ni * nr * nr;
 }
 template <typename T, int G, bool VAR>
 __device__ __forceinline__ void gs_vertex_site(const Geom& g, const LevelConst<T>& lc, T* __restrict__ x,
                                                const T* __restrict__ b, int c, int t, int d) {
-  const int N = g.N, nr = N - 1, ni = (nr + 3) >> 2;
+  const int N = g.N, nr = N - 1, ni = (nr + 1) >> 1;
   const int ip = t % ni, row = t / ni;
   const int j = 1 + row % nr, k = 1 + row / nr;
-  const int i = 1 + ((((c - 1 - j - k) % 4) + 4) & 3) + 4 * ip;
+  const int i = 1 + ((c + 1 + j + k) & 1) + 2 * ip;
   if (i > N - 1) return;
   gs_update<T, G, VAR>(g, lc, x, b, 0, i + g.n1 * j + g.n1 * g.n1 * k, d);
 }
@@ -1569,25 +1569,26 @@ __device__ void small_apply(const SmallLevel<T>& L, int opmask, V x, V b, V y, i
 
 template <typename T, int G, bool VAR, typename V>
 __device__ void small_colour(const SmallLevel<T>& L, V x, V b, int c, bool q16) {
-  if (c < 4) {
+  if (c < kGsVertexColours) {
     const int n = gs_vertex_count(L.g);
     for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock)
       gs_vertex_site<T, G, VAR>(L.g, L.lc, (T*)x, (const T*)b, c, w % n, w / n);
   } else {
     if constexpr (G == 8) {
-      const int gr = c - 3, n = gs_edge_count(L.g, gr);
+      const int gr = c - kGsVertexColours + 1, n = gs_edge_count(L.g, gr);
       for (int w = threadIdx.x; w < 3 * n; w += kSmallBlock)
         gs_edge_site<T, VAR>(L.g, L.lc, (T*)x, (const T*)b, gr, w % n, w / n);
     }
   }
   __syncthreads();
-  small_round<T>(q16, x, L.g.vstride, c < 4 ? 0 : (c - 3) * L.g.nn, L.g.nn, 3);  // the group the colour wrote
+  small_round<T>(q16, x, L.g.vstride, c < kGsVertexColours ? 0 : (c - kGsVertexColours + 1) * L.g.nn, L.g.nn,
+                 3);  // the group the colour wrote
 }
 
 template <typename T, int G, bool VAR, typename V>
 __device__ void small_smooth(const SmallCycle<T>& sc, const SmallLevel<T>& L, V x, V b, V r, int iters, bool q16) {
   if (L.g.N < 2) return;
-  const int ncol = G == 1 ? 4 : 11;
+  constexpr int ncol = gs_colours(G);
   for (int it = 0; it < iters; ++it) {
     for (int s = 0; s < sc.xi; ++s) {
       for (int c = 0; c < ncol; ++c) small_colour<T, G, VAR>(L, x, b, c, q16);
@@ -1933,14 +1934,14 @@ template <typename T>
 void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* x, const T* b, int colour) {
   const int N = g.N;
   if (N < 2) return;
-  if (colour < 4) {
-    const int nr = N - 1, ni = (nr + 3) / 4;
+  if (colour < kGsVertexColours) {
+    const int nr = N - 1, ni = (nr + 1) / 2;
     double cnt = 0;
     if (timer().mask & (1u << KF_GS_VERTEX))
       for (int k = 1; k <= nr; ++k)
         for (int j = 1; j <= nr; ++j) {
-          const int i0 = 1 + (((colour - 1 - j - k) % 4) + 4) % 4;
-          if (i0 <= nr) cnt += (nr - i0) / 4 + 1;
+          const int i0 = 1 + ((colour + 1 + j + k) & 1);
+          if (i0 <= nr) cnt += (nr - i0) / 2 + 1;
         }
     KScope ks(s, KF_GS_VERTEX, cnt, true);
     const dim3 grid(nblocks((size_t)ni * nr * nr), 3), block(kBlock);
@@ -1956,7 +1957,7 @@ void launch_gs_colour(hipStream_t s, const Geom& g, const LevelConst<T>& lc, T* 
         launch_timed(ks, k_gs_vertex<T, 8, false>, grid, block, s, g, lc, x, b, colour);
     }
   } else {
-    const int gr = colour - 3;
+    const int gr = colour - kGsVertexColours + 1;
     const size_t n = (size_t)gs_edge_count(g, gr);
     KScope ks(s, KF_GS_EDGE, (double)n, true);
     const dim3 grid(nblocks(n), 3), block(kBlock);
