@@ -387,12 +387,20 @@ void build_level_tables(hhg_hier h, Level& lv, const ElementSet& es) {
   lv.tb32 = a.alloc<Tables<float>>(1);
   HHG_CHECK_HIP(hipMemcpy(lv.tb64, &t64, sizeof(t64), hipMemcpyHostToDevice));
   HHG_CHECK_HIP(hipMemcpy(lv.tb32, &t32, sizeof(t32), hipMemcpyHostToDevice));
-  // boundary pressure nodes
-  std::vector<int> bnd;
+  // boundary pressure nodes, grouped by boundary class (lattice order inside
+  // a class): each node's row is the generated row of its class, so a
+  // wavefront of one class runs one branch instead of several
+  std::vector<std::pair<int, int>> bcl;
+  auto bc3 = [&](int c) { return c == 0 ? 0 : (c == g.N ? 2 : 1); };
   for (int k = 0; k < n1; ++k)
     for (int j = 0; j < n1; ++j)
       for (int i = 0; i < n1; ++i)
-        if (i == 0 || j == 0 || k == 0 || i == g.N || j == g.N || k == g.N) bnd.push_back(lin(i, j, k, n1));
+        if (i == 0 || j == 0 || k == 0 || i == g.N || j == g.N || k == g.N)
+          bcl.push_back({bc3(i) + 3 * bc3(j) + 9 * bc3(k), lin(i, j, k, n1)});
+  std::stable_sort(bcl.begin(), bcl.end(),
+                   [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+  std::vector<int> bnd;
+  for (auto& e : bcl) bnd.push_back(e.second);
   lv.nbnd = (int)bnd.size();
   lv.bnd = a.upload(bnd);
 }
