@@ -345,6 +345,22 @@ Row pruned_at(const ElementSet& es, char kind, int ci, int cj, int ck, int nw) {
   }
   return out;
 }
+// One velocity component's part of a boundary-class pressure row.
+void emit_pv_comp(FILE* f, const char* name, const Row& r, int d) {
+  std::fprintf(f,
+               "template <typename T>\n__device__ __forceinline__ void %s(const T* __restrict__ ud, int pos, int s1, "
+               "int s2, int nn, T& a) {\n",
+               name);
+  size_t n = 0;
+  for (auto& e : r) {
+    if (e.w[d] == 0.0) continue;
+    std::string o = "pos + " + off_expr(e, 0, true);
+    std::fprintf(f, "  a += T(%s) * ud[%s];\n", lit(e.w[d]).c_str(), o.c_str());
+    ++n;
+  }
+  std::fprintf(f, "}\n// %zu entries\n\n", n);
+}
+
 void emit_boundary_rows(FILE* f, const ElementSet& es, const char* D, int G) {
   const int rep[3] = {0, 2, 4};
   for (int cls = 0; cls < 27; ++cls) {
@@ -352,7 +368,12 @@ void emit_boundary_rows(FILE* f, const ElementSet& es, const char* D, int G) {
     const int ci = rep[cls % 3], cj = rep[(cls / 3) % 3], ck = rep[cls / 9];
     char name[64];
     std::snprintf(name, sizeof name, "%s_Bc%d", D, cls);
-    emit_pv(f, name, pruned_at(es, 'B', ci, cj, ck, 3));
+    const Row brow = pruned_at(es, 'B', ci, cj, ck, 3);
+    emit_pv(f, name, brow);
+    for (int d = 0; d < 3; ++d) {
+      std::snprintf(name, sizeof name, "%s_Bc%d_d%d", D, cls, d);
+      emit_pv_comp(f, name, brow, d);
+    }
     if (G == 1) {
       std::snprintf(name, sizeof name, "%s_Cc%d", D, cls);
       emit_pp(f, name, pruned_at(es, 'C', ci, cj, ck, 1));

@@ -269,6 +269,9 @@ __device__ __forceinline__ void prow_bnd_block(const Geom& g, const LevelConst<T
   }
 #define HHG_BROW(D, C) gen::D##_Bc##C<T>(u0, u1, u2, t, s1, s2, nn, ab)
 #define HHG_CROW(D, C) gen::D##_Cc##C<T>(p, t, s1, s2, ac)
+#define HHG_BROW_D0(D, C) gen::D##_Bc##C##_d0<T>(ud, t, s1, s2, nn, ab)
+#define HHG_BROW_D1(D, C) gen::D##_Bc##C##_d1<T>(ud, t, s1, s2, nn, ab)
+#define HHG_BROW_D2(D, C) gen::D##_Bc##C##_d2<T>(ud, t, s1, s2, nn, ab)
 template <typename T, int G>
 __device__ __forceinline__ T prow_value(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x, int opmask,
                                         int t, int i, int j, int k) {
@@ -296,7 +299,6 @@ __device__ __forceinline__ T prow_value(const Geom& g, const LevelConst<T>& lc, 
   return lc.b * ab + ((opmask & 16) ? lc.c * ac : -lc.c * ac);
 }
 #undef HHG_BROW
-#undef HHG_CROW
 
 // One velocity row type (group GR) of the apply at array index t.
 template <typename T, int G, int GR, bool VAR>
@@ -506,6 +508,12 @@ __device__ __forceinline__ void zm_run(const Geom& g, const LevelConst<T>& lc, c
   }
 }
 
+template <typename T, int G>
+__device__ __forceinline__ void prow_bnd_split(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                               const T* __restrict__ b, T* __restrict__ y, int has_b,
+                                               const int* __restrict__ bnd, int nbnd, int nmain, PStep<T> ps,
+                                               T (*red)[kZmCols]);
+
 template <typename T, int G, bool VEL, bool HB>
 __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> lc, const T* __restrict__ x,
                                                           const T* __restrict__ b, T* __restrict__ y, int kc, int ncb,
@@ -513,7 +521,7 @@ __global__ void __launch_bounds__(3 * kZmCols) k_apply_zm(Geom g, LevelConst<T> 
                                                           PStep<T> ps) {
   __shared__ T pshare[2][3][kZmCols];
   if ((int)blockIdx.x >= nmain) {
-    prow_bnd_block<T, G>(g, lc, x, b, y, G == 1 ? 15 : 7, (int)HB, bnd, nbnd, nmain, 3 * kZmCols, ps);
+    prow_bnd_split<T, G>(g, lc, x, b, y, (int)HB, bnd, nbnd, nmain, ps, pshare[0]);
     return;
   }
   const int lin = xcd_block_of(nmain);
@@ -568,6 +576,69 @@ __device__ __forceinline__ void prow_bnd_block(const Geom& g, const LevelConst<T
 }
 
 
+
+// The boundary pressure rows of a k-marching launch, one component per
+// wavefront: the block's three wavefronts take the same 64 nodes, wavefront d
+// sums the B_d part of each node's class row, and wavefront 0 adds the three
+// partial sums (and C p for PSPG) after a block barrier -- a third of the
+// loads of a whole row per thread.  red: 3 x 64 words of LDS.
+template <typename T, int G>
+__device__ __forceinline__ void prow_bnd_split(const Geom& g, const LevelConst<T>& lc, const T* __restrict__ x,
+                                               const T* __restrict__ b, T* __restrict__ y, int has_b,
+                                               const int* __restrict__ bnd, int nbnd, int nmain, PStep<T> ps,
+                                               T (*red)[kZmCols]) {
+  const int lane = (int)threadIdx.x % kZmCols, d = (int)threadIdx.x / kZmCols;
+  const int q = ((int)blockIdx.x - nmain) * kZmCols + lane;
+  const int N = g.N, s1 = g.n1, s2 = g.n1 * g.n1, nn = g.nn;
+  int t = 0, cls = 0;
+  T ab = 0;
+  if (q < nbnd) {
+    t = bnd[q];
+    int i, j, k;
+    decode(t, g.n1, i, j, k);
+    cls = bcls3(i, N) + 3 * bcls3(j, N) + 9 * bcls3(k, N);
+    const T* __restrict__ ud = x + (size_t)d * g.vstride;
+    if (d == 0) {
+      if constexpr (G == 1) {
+        HHG_BCLS_CASES(p1, HHG_BROW_D0)
+      } else {
+        HHG_BCLS_CASES(p2, HHG_BROW_D0)
+      }
+    } else if (d == 1) {
+      if constexpr (G == 1) {
+        HHG_BCLS_CASES(p1, HHG_BROW_D1)
+      } else {
+        HHG_BCLS_CASES(p2, HHG_BROW_D1)
+      }
+    } else {
+      if constexpr (G == 1) {
+        HHG_BCLS_CASES(p1, HHG_BROW_D2)
+      } else {
+        HHG_BCLS_CASES(p2, HHG_BROW_D2)
+      }
+    }
+  }
+  red[d][lane] = ab;
+  __syncthreads();
+  if (d != 0 || q >= nbnd) return;
+  T ac = 0;
+  if constexpr (G == 1) {
+    const T* __restrict__ p = x + 3 * (size_t)g.vstride;
+    HHG_BCLS_CASES(p1, HHG_CROW)
+  }
+  // opmask of the k-marching launch: B and -C p (PSPG) / B only (Taylor-Hood)
+  const T acc = lc.b * (red[0][lane] + red[1][lane] + red[2][lane]) - lc.c * ac;
+  const int pp = 3 * g.vstride + t;
+  const T r = has_b ? b[pp] - acc : acc;
+  if (ps.p)
+    ps.p[t] -= ps.omega * ps.dinv[t] * r;
+  else
+    y[pp] = r;
+}
+#undef HHG_CROW
+#undef HHG_BROW_D0
+#undef HHG_BROW_D1
+#undef HHG_BROW_D2
 
 // ---------------------------------------------------------- Gauss-Seidel
 // The generated row functions accumulate three components at once; the
@@ -1858,7 +1929,7 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     while (kc > 2 && ncb * ((g.n1 + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
     const int nch = (g.n1 + kc - 1) / kc;
     const int nmain = (ncb * nch + 7) & ~7;
-    const int nextra = (nb_bnd + 3 * kZmCols - 1) / (3 * kZmCols);
+    const int nextra = (nb_bnd + kZmCols - 1) / kZmCols;  // 64 boundary nodes per block
     const dim3 grid(nmain + nextra), block(3 * kZmCols);
     // float32 P2-P1: the kernel's registers allow 8 resident workgroups per
     // CU, but the columns of more than 3 workgroups in flight evict each
