@@ -392,7 +392,7 @@ constexpr int kZmCols = 64;
 #define HHG_ZM_KC 20  // k-planes per chunk (the chunk re-reads 2 halo planes); 20 measured best of 8..48
 #endif
 constexpr int kZmOut = kZmCols - 2;  // columns written per window
-constexpr unsigned kZmF32Lds = 50000;  // dynamic LDS of the float32 launch: 3 workgroups per CU
+constexpr unsigned kZmF32Lds = 50000;  // dynamic LDS of the large-lattice P2-P1 launch: 3 workgroups per CU
 
 template <typename T, int G, int D, int Q>
 __device__ __forceinline__ void zm_plane(__amdgpu_buffer_rsrc_t ru, __amdgpu_buffer_rsrc_t rp, const int (&vo)[3],
@@ -1936,8 +1936,7 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     // other's j-neighbour rows from L2 before they are re-read (measured on
     // the 48-tet level-7 lattice: 8 -> 1.23 ms, 4 -> 1.16 ms, 3 -> 1.14 ms,
     // 2 -> 1.36 ms).  Unused dynamic LDS caps residency at 3 of the CU's
-    // 160 KiB; float64 is already held to 4 by its registers and does not
-    // gain from fewer.  The cap pays on that lattice only (n1 = 257); on the
+    // 160 KiB, for float64 too (below).  The cap pays on that lattice only (n1 = 257); on the
     // smaller ones the columns in flight fit the L2 anyway (n1 = 65: 0.034 ->
     // 0.028 ms uncapped; n1 = 129: 0.193 -> 0.188).  P1-P1 loads a third of
     // the words per plane and needs the waves to hide their latency: no cap
@@ -1946,7 +1945,9 @@ void launch_apply(hipStream_t s, const Geom& g, const LevelConst<T>& lc, const T
     // vel_rows false: the pressure rows only (the Uzawa pressure residual):
     // the velocity words are still loaded for B u, the velocity rows are
     // neither accumulated nor written and their b words not read
-    const unsigned dyn = sizeof(T) == 4 && g.G == 8 && g.n1 >= 200 ? kZmF32Lds : 0;
+    // float64 at 114 VGPRs would hold 5 workgroups per CU; the same cap to 3
+    // measured 2.158 -> 2.102 ms on the n1 = 257 lattice (4: 2.135 ms)
+    const unsigned dyn = g.G == 8 && g.n1 >= 200 ? kZmF32Lds : 0;
     // the fused pressure step: the pressure-residual form only
     const bool fused = ps.p && !vel_rows && has_b;
     auto go = [&](auto gg, auto vel, auto hbc) {
