@@ -1630,7 +1630,9 @@ template <typename T, int G, bool VAR, typename V>
 __device__ void small_apply(const SmallLevel<T>& L, int opmask, V x, V b, V y, int vel_rows) {
   for (int t = threadIdx.x; t < L.g.nn; t += kSmallBlock)
     apply_site<T, G, VAR>(L.g, L.lc, (const T*)x, (const T*)b, (T*)y, opmask, 1, vel_rows, 1, t);
-  for (int q = threadIdx.x; q < L.nbnd; q += kSmallBlock) {
+  // boundary pressure rows from the last thread down: on the levels where
+  // nn < kSmallBlock they go to the threads the loop above left idle
+  for (int q = kSmallBlock - 1 - (int)threadIdx.x; q < L.nbnd; q += kSmallBlock) {
     const int t = L.bnd[q];
     const int pp = 3 * L.g.vstride + t;
     y[pp] = b[pp] - prow_bnd_table<T>(L.g, L.tb, (const T*)x, opmask, t);
