@@ -56,7 +56,7 @@ TRAFFIC = {
                        "source": "profiles/fmg_p2p1_level5_cube.md: FETCH_SIZE x 2 + WRITE_SIZE per k_gs_edge "
                                  "dispatch, weighted with the solve's launch mix over levels 3-5"},
 }
-APPLY_TRAFFIC = {"f64": 10.80e9, "f32": 4.66e9}   # profiles/apply_p2p1_48tets_level7.md
+APPLY_TRAFFIC = {"f64": 10.81e9, "f32": 4.66e9}   # profiles/apply_p2p1_48tets_level7.md
 # algorithmic bytes per work unit (float64 words), see the design doc
 WORDS = {
     "apply_p2": 6.25,        # y = calA x per P2 site
