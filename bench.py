@@ -93,8 +93,8 @@ def main():
                     help="profiler runs: setup, the timed headline solves and a 1 GiB calibration copy only")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -523,7 +523,8 @@ def bench_c3(torch, hhg, dev, stream, ctx, levels=(5, 6, 7), reps=5):
                 torch.cuda.synchronize()
                 hhg.hhg_hier_destroy(H)
     return {"mode": "c3", "workload": "48 macro-tets (one Bey step of the Kuhn cube), N(0,1) inputs, "
-                                      "algorithmic bytes per site as in the survey's table", "rows": rows}
+                                      "algorithmic words per site: apply 6.25 / 8, residual 9.375 / 12, Uzawa 9.125 xi + 3.375 / "
+                                      "10 xi + 6 (P2-P1 / P1-P1), transfers per fine site", "rows": rows}
 
 
 def bench_learned(torch, hhg, ctx, args, L=6, lmin=2):
