@@ -938,8 +938,9 @@ void op_mean_zero(hhg_hier h, int l, T* x) {
 }
 
 template <typename T>
-void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
+void op_restrict(hhg_hier h, int lf, const T* rf, T* rc, T* zero_x = nullptr) {
   if (h->um) {
+    if (zero_x) launch_fill<T>(S(h), zero_x, h->L(lf - 1).vec_words, T(0));
     u_f64<T>();
     ULevelData& F = UL(h, lf);
     ULevelData& C = UL(h, lf - 1);
@@ -952,7 +953,7 @@ void op_restrict(hhg_hier h, int lf, const T* rf, T* rc) {
   }
   Level& f = h->L(lf);
   Level& c = h->L(lf - 1);
-  launch_restrict<T>(S(h), f.g, c.g, ttables<T>(f), rf, rc);
+  launch_restrict<T>(S(h), f.g, c.g, ttables<T>(f), rf, rc, zero_x);
   if (c.neu_n) launch_neu_restrict<T>(S(h), f.g, c.g, neutab<T>(c), c.neu(), c.neu_n, rf, rc);
   round_out<T>(h, lf - 1, rc, 0, 0, c.vec_words, 1);
   if (h->nf) return;  // no null vector: no compatibility shift
@@ -1154,8 +1155,7 @@ void vcycle_t(hhg_hier h, int lf, int l, T* x, const T* b, const hhg_solver_para
   T* r = rbuf<T>(lv);
   op_smooth<T>(h, l, x, b, p.nu_pre + (lf - l) * p.nu_inc, p.gs, p.xi, om);
   op_apply<T>(h, l, full_mask(h), x, b, r, true, true, true);
-  op_restrict<T>(h, l, r, cbbuf<T>(lc));
-  launch_fill<T>(S(h), cxbuf<T>(lc), lc.vec_words, T(0));
+  op_restrict<T>(h, l, r, cbbuf<T>(lc), cxbuf<T>(lc));  // and the coarse start value 0
   vcycle_t<T>(h, lf, l - 1, cxbuf<T>(lc), cbbuf<T>(lc), p);
   op_prolong<T>(h, l - 1, cxbuf<T>(lc), x, true, true);
   op_smooth<T>(h, l, x, b, p.nu_post + (lf - l) * p.nu_inc, p.gs, p.xi, om);

@@ -223,7 +223,10 @@ void launch_mass(hipStream_t s, const Geom& g, const Tables<T>* tb, const T* x, 
 template <typename T>
 void launch_dot(hipStream_t s, const T* x, const T* y, size_t n, double* partial, double* out);
 template <typename T>
-void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc);
+// zero_x (optional): a coarse vector set to zero word for word by the same
+// threads (the coarse correction's start value), every word of the level.
+void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc,
+                     T* zero_x = nullptr);
 template <typename T>
 void launch_prolong(hipStream_t s, const Geom& gc, const Geom& gf, const TransferTables<T>* tt, const T* xc, T* xf,
                     bool add, bool skip_boundary);

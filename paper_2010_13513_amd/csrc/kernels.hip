@@ -876,7 +876,7 @@ __global__ void __launch_bounds__(kBlock) k_dot(const T* __restrict__ x, const T
 // loads.  Coarse boundary velocity rows are zero.
 template <typename T, int G>
 __device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, const T* __restrict__ rf,
-                                              T* __restrict__ rc, int t, int sl) {
+                                              T* __restrict__ rc, int t, int sl, T* __restrict__ zx = nullptr) {
   int i, j, k;
   decode(t, gc.n1, i, j, k);
   const int fb = 2 * i + gf.n1 * (2 * j + gf.n1 * 2 * k);
@@ -885,6 +885,7 @@ __device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, co
     const T* pf = rf + 3 * (size_t)vs;
     rc[3 * gc.vstride + t] = G == 1 ? gen::p1_RP<T>(pf, fb, 2 * i, 2 * j, 2 * k, gf.N, s1, s2)
                                     : gen::p2_RP<T>(pf, fb, 2 * i, 2 * j, 2 * k, gf.N, s1, s2);
+    if (zx) zx[3 * gc.vstride + t] = T(0);
     return;
   }
   const int gr = sl / 3, d = sl - 3 * gr;
@@ -900,13 +901,14 @@ __device__ __forceinline__ void restrict_site(const Geom& gf, const Geom& gc, co
   }
   (void)a1, (void)a2;
   rc[(size_t)d * gc.vstride + gr * gc.nn + t] = a0;
+  if (zx) zx[(size_t)d * gc.vstride + gr * gc.nn + t] = T(0);
 }
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, const T* __restrict__ rf, T* __restrict__ rc,
-                                                     int sl0) {
+                                                     int sl0, T* __restrict__ zx) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= gc.nn) return;
-  restrict_site<T, G>(gf, gc, rf, rc, t, sl0 + (int)blockIdx.y);
+  restrict_site<T, G>(gf, gc, rf, rc, t, sl0 + (int)blockIdx.y, zx);
 }
 
 // k-marching velocity restriction, P2-P1: a block is three wavefronts (the
@@ -928,7 +930,8 @@ constexpr int kRzmCols = 64;
 template <typename T, int Q>
 __device__ __forceinline__ void rzm_step(const Geom& gf, const Geom& gc, __amdgpu_buffer_rsrc_t ru, int fcol_e,
                                          int fcol_o, const int (&frow)[4], int kq, int k0, int k1, bool valid, int ic,
-                                         int jc, int col, T* __restrict__ rc, int d, T (&acc)[2][8]) {
+                                         int jc, int col, T* __restrict__ rc, int d, T (&acc)[2][8],
+                                         T* __restrict__ zx) {
   const int n1f = gf.n1, s2f = n1f * n1f, nnb = gf.nn * (int)sizeof(T);
 #pragma unroll
   for (int P = 0; P < 2; ++P) {
@@ -958,6 +961,9 @@ __device__ __forceinline__ void rzm_step(const Geom& gf, const Geom& gc, __amdgp
 #pragma unroll
     for (int g = 0; g < 8; ++g)
       rc[(size_t)d * gc.vstride + g * gc.nn + at] = vel_interior<8>(g, ic, jc, kq, gc.N) ? acc[Q][g] : T(0);
+    if (zx)
+#pragma unroll
+      for (int g = 0; g < 8; ++g) zx[(size_t)d * gc.vstride + g * gc.nn + at] = T(0);
   }
 #pragma unroll
   for (int g = 0; g < 8; ++g) acc[Q][g] = T(0);
@@ -965,7 +971,8 @@ __device__ __forceinline__ void rzm_step(const Geom& gf, const Geom& gc, __amdgp
 
 template <typename T>
 __global__ void __launch_bounds__(3 * kRzmCols) k_restrict_zm(Geom gf, Geom gc, const T* __restrict__ rf,
-                                                              T* __restrict__ rc, int kc, int ncb, int nmain) {
+                                                              T* __restrict__ rc, int kc, int ncb, int nmain,
+                                                              T* __restrict__ zx) {
   const int lin = xcd_block_of(nmain);
   const int cb = lin % ncb, chunk = lin / ncb;
   const int k0 = chunk * kc;
@@ -991,9 +998,9 @@ __global__ void __launch_bounds__(3 * kRzmCols) k_restrict_zm(Geom gf, Geom gc, 
     for (int g = 0; g < 8; ++g) acc[q][g] = T(0);
   const int nq = k1 - k0 + 1;
   for (int q = 0; q < nq; q += 2) {
-    rzm_step<T, 0>(gf, gc, ru, fcol_e, fcol_o, frow, k0 - 1 + q, k0, k1, valid, ic, jc, col, rc, d, acc);
+    rzm_step<T, 0>(gf, gc, ru, fcol_e, fcol_o, frow, k0 - 1 + q, k0, k1, valid, ic, jc, col, rc, d, acc, zx);
     if (q + 1 < nq)
-      rzm_step<T, 1>(gf, gc, ru, fcol_e, fcol_o, frow, k0 + q, k0, k1, valid, ic, jc, col, rc, d, acc);
+      rzm_step<T, 1>(gf, gc, ru, fcol_e, fcol_o, frow, k0 + q, k0, k1, valid, ic, jc, col, rc, d, acc, zx);
   }
 }
 
@@ -2143,12 +2150,13 @@ void launch_dot(hipStream_t s, const T* x, const T* y, size_t n, double* partial
 }
 
 template <typename T>
-void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc) {
+void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const TransferTables<T>* tt, const T* rf, T* rc,
+                     T* zero_x) {
   KScope ks(s, KF_RESTRICT, p_sites(gf));
   (void)tt;
   // grid.y: (velocity group, component) slices and the pressure
   if (gc.G == 1) {
-    hipLaunchKernelGGL((k_restrict<T, 1>), dim3(nblocks(gc.nn), 4), dim3(kBlock), 0, s, gf, gc, rf, rc, 0);
+    hipLaunchKernelGGL((k_restrict<T, 1>), dim3(nblocks(gc.nn), 4), dim3(kBlock), 0, s, gf, gc, rf, rc, 0, zero_x);
   } else if (gc.n1 >= 33) {
     // velocity: the k-marching form; the pressure slice as before.  From a
     // coarse lattice of 33 nodes per edge on (48-tet cube, level 7 -> 6:
@@ -2160,10 +2168,11 @@ void launch_restrict(hipStream_t s, const Geom& gf, const Geom& gc, const Transf
     while (kc > 2 && ncb * ((gc.n1 + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
     const int nch = (gc.n1 + kc - 1) / kc;
     const int nmain = (ncb * nch + 7) & ~7;
-    hipLaunchKernelGGL((k_restrict_zm<T>), dim3(nmain), dim3(3 * kRzmCols), 0, s, gf, gc, rf, rc, kc, ncb, nmain);
-    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 1), dim3(kBlock), 0, s, gf, gc, rf, rc, 24);
+    hipLaunchKernelGGL((k_restrict_zm<T>), dim3(nmain), dim3(3 * kRzmCols), 0, s, gf, gc, rf, rc, kc, ncb, nmain,
+                       zero_x);
+    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 1), dim3(kBlock), 0, s, gf, gc, rf, rc, 24, zero_x);
   } else {
-    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 25), dim3(kBlock), 0, s, gf, gc, rf, rc, 0);
+    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nblocks(gc.nn), 25), dim3(kBlock), 0, s, gf, gc, rf, rc, 0, zero_x);
   }
 }
 
@@ -2384,7 +2393,8 @@ void launch_axpy(hipStream_t s, T* y, const T* x, size_t n, T a) {
   template void launch_rhs<T>(hipStream_t, const Geom&, const LevelConst<T>&, const T*, T*);                        \
   template void launch_mass<T>(hipStream_t, const Geom&, const Tables<T>*, const T*, T*);                           \
   template void launch_dot<T>(hipStream_t, const T*, const T*, size_t, double*, double*);                           \
-  template void launch_restrict<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*);  \
+  template void launch_restrict<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*,  \
+                                   T*);                                                                             \
   template void launch_prolong<T>(hipStream_t, const Geom&, const Geom&, const TransferTables<T>*, const T*, T*,    \
                                   bool, bool);                                                                      \
   template void launch_inject_boundary<T>(hipStream_t, const Geom&, const Geom&, const T*, T*);                     \
