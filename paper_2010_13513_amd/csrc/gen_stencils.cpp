@@ -572,6 +572,10 @@ int main(int argc, char** argv) {
     Row B = pruned(es, 'B', 0, 3);
     std::snprintf(name, sizeof name, "%s_B", D);
     emit_pv(f, name, B);
+    for (int d = 0; d < 3; ++d) {
+      std::snprintf(name, sizeof name, "%s_B_d%d", D, d);
+      emit_pv_comp(f, name, B, d);
+    }
     if (vorder == 1) {
       Row C = pruned(es, 'C', 0, 1);
       emit_pp(f, "p1_C", C);
