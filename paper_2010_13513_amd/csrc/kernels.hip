@@ -1405,36 +1405,53 @@ constexpr int kMeanBlock = 1024;
 template <typename T>
 __global__ void __launch_bounds__(kMeanBlock) k_mean_zero_1b(Geom g, const Tables<T>* __restrict__ tb,
                                                              T* __restrict__ p, double* __restrict__ sums, int mode) {
-  __shared__ double sa[kMeanBlock], sb[kMeanBlock];
+  constexpr int kWaves = kMeanBlock / 64;
+  __shared__ double mc[27], sa[kWaves], sb[kWaves], smean;
+  if (mode == 0 && threadIdx.x < 27) mc[threadIdx.x] = (double)tb->mclass[threadIdx.x];
+  __syncthreads();
+  // (i, j, k) from t by float reciprocals: exact for the one-block sizes
+  // (n1 <= 40, t < 65536: the quotients stay far from integer boundaries)
+  const float inv = 1.0f / (float)g.n1;
   double a = 0.0, bsum = 0.0;
   for (int t = threadIdx.x; t < g.nn; t += kMeanBlock) {
     const double v = (double)p[t];
     if (mode == 0) {
-      int i, j, k;
-      decode(t, g.n1, i, j, k);
-      const double m = (double)tb->mclass[bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N)];
+      const int r = (int)(((float)t + 0.5f) * inv);
+      const int i = t - r * g.n1;
+      const int k = (int)(((float)r + 0.5f) * inv);
+      const int j = r - k * g.n1;
+      const double m = mc[bcls3(i, g.N) + 3 * bcls3(j, g.N) + 9 * bcls3(k, g.N)];
       a += m * v;
       bsum += m;
     } else {
       a += v;
     }
   }
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = bsum;
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o);
+    bsum += __shfl_down(bsum, o);
+  }
+  const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  if (lane == 0) {
+    sa[w] = a;
+    sb[w] = bsum;
+  }
   __syncthreads();
-  for (int s = kMeanBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sa[threadIdx.x] += sa[threadIdx.x + s];
-      sb[threadIdx.x] += sb[threadIdx.x + s];
+  if (w == 0) {
+    double x = lane < kWaves ? sa[lane] : 0.0, y = lane < kWaves ? sb[lane] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+      x += __shfl_down(x, o);
+      y += __shfl_down(y, o);
     }
-    __syncthreads();
+    if (lane == 0) {
+      smean = mode == 0 ? x / y : x / (double)g.nn;
+      sums[0] = x;
+      sums[1] = y;
+    }
   }
-  const double mean = mode == 0 ? sa[0] / sb[0] : sa[0] / (double)g.nn;
+  __syncthreads();
+  const double mean = smean;
   for (int t = threadIdx.x; t < g.nn; t += kMeanBlock) p[t] = (T)((double)p[t] - mean);
-  if (threadIdx.x == 0) {
-    sums[0] = sa[0];
-    sums[1] = sb[0];
-  }
 }
 
 // x *= 1 / sqrt(sums[slot])
